@@ -1,0 +1,251 @@
+/* mlbm.h -- C-ABI of the MI355X (gfx950) Meshless Lattice Boltzmann library.
+ *
+ * The method (Strzelczyk & Matyka, arXiv 2306.01525, after Lin et al.): a
+ * D2Q9 BGK lattice Boltzmann model on an irregular point cloud whose streaming
+ * step is semi-Lagrangian. The population k arriving at node x_i departs from
+ * the Lagrangian point x_i - e_k dx (Sec. 2.3), where it is interpolated from
+ * the post-collision populations of a stencil of K nodes with precomputed
+ * shape vectors of a cubic polyharmonic RBF augmented with complete
+ * polynomials of degree m (Sec. 2.2, eqs. rbf_interp_set_augmented,
+ * shape_vector, poly_sets). Collision is BGK (Sec. 2.1, eqs. LBM_collision,
+ * feq), optionally with the body-force term of Sec. 3.
+ *
+ * Conventions shared by every entry point:
+ *  - Memory. The caller owns every device byte (typically torch tensors). The
+ *    library never allocates device memory: sizes come from the *_query calls
+ *    and the caller passes buffers of at least that size. The only host
+ *    allocation is the small opaque mlbm_plan object.
+ *  - Pointers. "device" pointers must be addressable by the current HIP
+ *    device; "host" pointers are ordinary CPU memory.
+ *  - Streams. Work is enqueued on the given stream and is asynchronous unless
+ *    stated. Argument checks are synchronous and return an error code.
+ *  - Errors. Every call returns an mlbm_status; on failure mlbm_last_error()
+ *    returns a thread-local message. No exception crosses the ABI.
+ *  - Node order. Inputs and outputs that carry a per-node value use the
+ *    caller's node order ("user order"). The state arrays g are internal: the
+ *    library reorders nodes along a Hilbert curve and keeps g in that order.
+ *  - Units. Coordinates and dx are in the cloud's units. Populations,
+ *    velocities, densities and forces are in lattice units (dx = dt = 1).
+ */
+#ifndef MLBM_H
+#define MLBM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    MLBM_OK = 0,
+    MLBM_EINVAL = -1,        /* bad argument (size, parameter range, null)      */
+    MLBM_ESINGULAR = -2,     /* a local RBF system is numerically singular      */
+    MLBM_EHIP = -3,          /* a HIP runtime call failed                       */
+    MLBM_ESMALLBUF = -4,     /* caller buffer smaller than the queried size     */
+    MLBM_EUNSUPPORTED = -5   /* valid request this library does not implement   */
+} mlbm_status;
+
+enum { MLBM_FP32_DEV = 0, MLBM_FP64 = 1 };          /* mlbm_params.precision    */
+enum { MLBM_STENCIL_PAPER = 0, MLBM_STENCIL_OWN = 1 }; /* mlbm_params.stencil_mode */
+
+/* One point cloud (Sec. 2.2: the set X of Eulerian nodes). */
+typedef struct {
+    int32_t n;                  /* number of nodes, >= K                          */
+    const double *x, *y;        /* device, [n] coordinates, user order            */
+    const uint8_t *node_type;   /* device, [n]: 0 fluid, 1 wall; NULL = all fluid */
+    double period_x, period_y;  /* > 0: periodic with that period, coordinates in
+                                   [0, period); 0: open along that axis          */
+} mlbm_cloud;
+
+/* Simulation parameters of one cloud (Algorithm 1: "simulation parameters"). */
+typedef struct {
+    double dx;              /* streaming distance dx_ML (Sec. 2.3), cloud units    */
+    int32_t K;              /* stencil size N_L (Sec. 2.2), 6 <= K <= 48, K >= M   */
+    int32_t degree;         /* polynomial augmentation degree m in {2,3,4}
+                               (eq. poly_sets; m < 2 is rejected, Sec. 3)          */
+    int32_t stencil_mode;   /* MLBM_STENCIL_PAPER: a departure point is
+                               interpolated on the stencil of its closest node
+                               (Sec. 2.3, Algorithm 1). MLBM_STENCIL_OWN: on the
+                               stencil of the arriving node itself                 */
+    int32_t precision;      /* MLBM_FP32_DEV: populations stored and streamed in
+                               FP32 as deviations from w_k rho0; MLBM_FP64: plain
+                               FP64 populations. Weights are always built in FP64 */
+    double tau;             /* BGK relaxation time, > 0.5 (eq. LBM_collision)     */
+    double rho0;            /* reference density (initial density when none given) */
+    int32_t force_kind;     /* 0 none; 1 constant azimuthal acceleration about the
+                               origin (Sec. 3), magnitude force_mag (lattice units) */
+    double force_mag;
+    int32_t wall_kind;      /* 0 none; 1 wall nodes (node_type 1) hold the rest
+                               equilibrium feq(rho_wall, 0) after every stream     */
+    double rho_wall;
+    int32_t with_adjoint;   /* 1: also build the transposed streaming operator
+                               used by mlbm_step_adjoint (8K entries per node)     */
+} mlbm_params;
+
+typedef struct mlbm_plan mlbm_plan;  /* opaque host object; refers to the
+                                        caller's plan buffer                    */
+
+/* Read-only description of a built plan. */
+typedef struct {
+    int32_t n_clouds;
+    int64_t n_total;          /* sum of n over clouds                             */
+    int32_t K, degree, stencil_mode, precision;   /* of cloud 0                    */
+    size_t state_bytes;       /* bytes of one state array g (9 populations)        */
+    int64_t tile_nodes;       /* nodes per workgroup of the step kernel            */
+} mlbm_plan_info;
+
+/* ---- weight build (Sec. 2.2-2.3; Algorithm 1, initialisation loop) -------- */
+
+/* Sizes of the device plan buffer and of the temporary workspace needed by
+ * mlbm_build_weights for these clouds and parameters. Synchronous, no device
+ * work. n_clouds >= 1; clouds and params are host arrays of n_clouds entries. */
+mlbm_status mlbm_weights_query(const mlbm_cloud *clouds, const mlbm_params *params,
+                               int32_t n_clouds, size_t *plan_bytes,
+                               size_t *workspace_bytes);
+
+/* Build stencils, owners and shape vectors on the GPU:
+ *  1. order nodes along a Hilbert curve of a uniform cell grid;
+ *  2. stencil X^L of every node: itself, then its K-1 closest nodes by
+ *     (squared distance, user index), minimum image when periodic (Sec. 2.2);
+ *  3. owner of every departure point x_i - e_k dx: its closest node, ties to
+ *     the lower user index (paper mode), or node i (own mode) (Sec. 2.3);
+ *  4. shape vectors w_L(p) = first K entries of Phi^{-1} phi_L(p) with Phi the
+ *     (K+M)x(K+M) collocation matrix of r^3 plus monomials, solved in FP64 by
+ *     Gaussian elimination with partial pivoting (Sec. 2.2-2.3).
+ * plan_buf (device, plan_bytes) must stay allocated while the plan is used;
+ * workspace (device, workspace_bytes) is free again when the stream reaches
+ * the end of this call's work. *out receives a host object to release with
+ * mlbm_plan_destroy. When the stream is not being captured, the call waits
+ * for the build and returns MLBM_ESINGULAR if a local system was singular
+ * (mlbm_last_error names the node); under capture, the status is left in the
+ * device error word (mlbm_device_error). */
+mlbm_status mlbm_build_weights(const mlbm_cloud *clouds, const mlbm_params *params,
+                               int32_t n_clouds, void *plan_buf, size_t plan_bytes,
+                               void *workspace, size_t workspace_bytes, mlbm_plan **out,
+                               hipStream_t stream);
+
+/* Test hook: a plan built from host arrays instead of the GPU build, for one
+ * periodic or open cloud. x, y: host [n]; nbr: host int32 [n][K] stencils in
+ * user indices (centre first); owner: host int32 [n][9] owner node per
+ * direction (user indices); W: host FP64 [n][9][K] shape vectors. Node order
+ * is taken as given (no reordering). Same buffer rules as mlbm_build_weights;
+ * synchronous. */
+mlbm_status mlbm_import_query(int32_t n, const mlbm_params *params, size_t *plan_bytes);
+mlbm_status mlbm_import_weights(int32_t n, const double *x, const double *y,
+                                const uint8_t *node_type, const int32_t *nbr,
+                                const int32_t *owner, const double *W,
+                                const mlbm_params *params, void *plan_buf,
+                                size_t plan_bytes, mlbm_plan **out, hipStream_t stream);
+
+mlbm_status mlbm_plan_get_info(const mlbm_plan *plan, mlbm_plan_info *info);
+
+/* Copy an internal plan array to host memory (synchronous), for inspection:
+ * what = 0 perm int32 [n] (internal position -> user index),
+ *        1 nbr int32 [n][K] (user indices, node-major, user order),
+ *        2 owner int32 [n][9] (user indices, user order),
+ *        3 W FP64 [n][9][K] (user order; k = 0 is the identity).
+ * Cloud `cloud`; dst_bytes must match exactly. */
+mlbm_status mlbm_plan_export(const mlbm_plan *plan, int32_t cloud, int32_t what, void *dst,
+                             size_t dst_bytes);
+
+mlbm_status mlbm_plan_destroy(mlbm_plan *plan);   /* frees the host object only */
+
+/* ---- time stepping (Algorithm 1, time loop) ------------------------------- */
+
+/* Initial state: populations at equilibrium with the given macroscopic fields
+ * (Algorithm 1; Sec. 3), then one collision, so that g holds post-collision
+ * populations. rho: device FP64 [n_total] or NULL (uniform rho0); ux, uy:
+ * device FP64 [n_total] or NULL (zero), user order. g: device, state_bytes. */
+mlbm_status mlbm_init(const mlbm_plan *plan, const double *rho, const double *ux,
+                      const double *uy, void *g, hipStream_t stream);
+
+/* n_steps fused timesteps. Each step, per node: stream (interpolate the
+ * post-collision populations at the departure points), apply the wall rule,
+ * take the moments, collide (with force), write the new post-collision
+ * populations. Ping-pong between g_a and g_b (device, state_bytes each);
+ * *result_in_b (host) is set to 1 if the final state is in g_b, else 0. */
+mlbm_status mlbm_step(const mlbm_plan *plan, void *g_a, void *g_b, int32_t n_steps,
+                      int32_t *result_in_b, hipStream_t stream);
+
+/* Density and velocity (eq. macro_var) of the pre-collision populations that
+ * gave the post-collision state g (collision conserves mass and momentum; the
+ * force contribution is removed). Outputs: device FP64 [n_total] each, user
+ * order; any may be NULL. */
+mlbm_status mlbm_moments(const mlbm_plan *plan, const void *g, double *rho, double *ux,
+                         double *uy, hipStream_t stream);
+
+/* Diagnostics: sums over all nodes (FP64, device out[4]) of
+ * (u - u*)^2 + (v - v*)^2, u*^2 + v*^2, (u - u*)^2, u*^2 for the velocity of
+ * state g against a target field (device FP64 [n_total], user order). The L2
+ * norm of eq. L2norm is sqrt(out[2] / out[3]) for the u-component and
+ * sqrt(out[0] / out[1]) for the vector. out is overwritten. */
+mlbm_status mlbm_l2_sums(const mlbm_plan *plan, const void *g, const double *ux_t,
+                         const double *uy_t, double *out, hipStream_t stream);
+
+/* ---- differentiation (no walls, no force) ----------------------------------- */
+
+/* Forward steps that also record the pre-collision populations f^n of every
+ * step n = 1..n_steps into f_rec (device, n_steps * state_bytes, in the
+ * state's precision and layout). */
+mlbm_status mlbm_step_record(const mlbm_plan *plan, void *g_a, void *g_b, int32_t n_steps,
+                             void *f_rec, int32_t *result_in_b, hipStream_t stream);
+
+/* Pre-collision populations f^0 = feq(rho0, u0) (the state before the first
+ * collision). Same inputs and layout as mlbm_init. */
+mlbm_status mlbm_init_f(const mlbm_plan *plan, const double *rho, const double *ux,
+                        const double *uy, void *f, hipStream_t stream);
+
+/* Collision only: g = C(f) for a pre-collision state f (same layout), so a
+ * recorded or checkpointed f can restart the post-collision time loop. */
+mlbm_status mlbm_collide(const mlbm_plan *plan, const void *f, void *g, hipStream_t stream);
+
+/* Seed of the adjoint for J = 1/2 sum_i |u_i(f_T) - u*_i|^2: lamf_T = dJ/df_T.
+ * f_T: pre-collision state (device, state precision and layout); ux_t, uy_t:
+ * device FP64 [n_total] user order; lamf_T: device, state_bytes, adjoint
+ * populations in the state precision and layout; J: device FP64 [1],
+ * overwritten. Plans with walls or a body force return MLBM_EUNSUPPORTED. */
+mlbm_status mlbm_loss_seed(const mlbm_plan *plan, const void *f_T, const double *ux_t,
+                           const double *uy_t, void *lamf_T, double *J,
+                           hipStream_t stream);
+
+/* One reversed step. The forward step maps f^n to f^{n+1} = S(C(f^n)) (C
+ * collision, S streaming). Given the adjoint lamf_next of f^{n+1} and the
+ * recorded pre-collision f^n, computes lamf_n = C'(f^n)^T S^T lamf_next: a
+ * gather over the transposed streaming weights (built when the plan was made
+ * with_adjoint), then the transposed BGK Jacobian at f^n. Adds this step's
+ * dJ/dtau = (S^T lamf_next) . dC/dtau (f^n) into dJ_dtau (device FP64 [1],
+ * accumulated). lamf_*: device, state_bytes, state precision and layout. */
+mlbm_status mlbm_step_adjoint(const mlbm_plan *plan, const void *f_n, const void *lamf_next,
+                              void *lamf_n, double *dJ_dtau, hipStream_t stream);
+
+/* dJ/du0 = (d feq(rho0, u0) / d u0)^T lamf_0, with f^0 = feq(rho0, u0) the
+ * state before the first collision. u0x, u0y: device FP64 [n_total], user
+ * order (NULL = 0); outputs device FP64 [n_total] each, user order. */
+mlbm_status mlbm_init_adjoint(const mlbm_plan *plan, const double *u0x, const double *u0y,
+                              const void *lamf_0, double *dJ_du0x, double *dJ_du0y,
+                              hipStream_t stream);
+
+/* ---- graphs ------------------------------------------------------------- */
+
+/* Capture n_steps steps on (g_a, g_b) into a HIP graph owned by the plan
+ * (replaces a previous one). mlbm_graph_launch replays it on `stream`.
+ * The graph is destroyed by mlbm_plan_destroy. */
+mlbm_status mlbm_graph_create(mlbm_plan *plan, void *g_a, void *g_b, int32_t n_steps,
+                              hipStream_t stream);
+mlbm_status mlbm_graph_launch(mlbm_plan *plan, hipStream_t stream);
+
+/* ---- errors --------------------------------------------------------------- */
+
+const char *mlbm_last_error(void);
+
+/* Sticky device error word of the plan, read synchronously: 0 none; > 0 the
+ * 1-based user index of the first node whose local system was singular. */
+int32_t mlbm_device_error(const mlbm_plan *plan);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MLBM_H */

@@ -1,0 +1,320 @@
+// Discrete adjoint of the MLBM time loop on gfx950 (periodic, no walls, no
+// force). The forward step is f^{n+1} = S(C(f^n)): C the BGK collision
+// (eqs. LBM_collision, feq), S the semi-Lagrangian streaming through the
+// shape vectors (Sec. 2.3). Its adjoint is lam^n = C'(f^n)^T S^T lam^{n+1}.
+//
+// S^T is applied as a gather, not a scatter: for every direction k and source
+// node m, the list of (arriving node i, weight) pairs whose stencil reads m is
+// stored as a CSR row sorted by i. Each lane owns one source node and sums its
+// row in that fixed order, so the adjoint needs no atomics and is
+// deterministic. The weights are the ones the forward step uses (FP32 after
+// the partition-of-unity correction, or FP64).
+#include "common.h"
+
+namespace mlbm {
+namespace {
+
+__device__ __forceinline__ int stencil_owner(const int32_t *owner, int mode, int k, int n,
+                                             int i) {
+    return mode == MLBM_STENCIL_OWN ? i : owner[(int64_t)(k - 1) * n + i];
+}
+
+__global__ void k_tr_count(int n, int K, int mode, const int32_t *__restrict__ nbr,
+                           const int32_t *__restrict__ owner, int32_t *__restrict__ cnt) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    for (int k = 1; k < kQ; ++k) {
+        const int s = stencil_owner(owner, mode, k, n, i);
+        for (int j = 0; j < K; ++j) {
+            const int m = nbr[(int64_t)j * n + s];
+            atomicAdd(&cnt[(int64_t)(k - 1) * n + m], 1);
+        }
+    }
+}
+
+template <class T>
+__global__ void k_tr_fill(int n, int K, int mode, const int32_t *__restrict__ nbr,
+                          const int32_t *__restrict__ owner, const float *__restrict__ W32,
+                          const double *__restrict__ W64, const int32_t *__restrict__ ptr,
+                          int32_t *__restrict__ cur, int32_t *__restrict__ col,
+                          T *__restrict__ val) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    for (int k = 1; k < kQ; ++k) {
+        const int s = stencil_owner(owner, mode, k, n, i);
+        for (int j = 0; j < K; ++j) {
+            const int m = nbr[(int64_t)j * n + s];
+            const int64_t row = (int64_t)(k - 1) * n + m;
+            const int pos = ptr[row] + atomicAdd(&cur[row], 1);
+            col[pos] = i;
+            T w;
+            if (W64)
+                w = (T)W64[((int64_t)(k - 1) * K + j) * n + i];
+            else
+                w = (T)W32[(((int64_t)j * 2 + ((k - 1) >> 2)) * n + i) * 4 + ((k - 1) & 3)];
+            val[pos] = w;
+        }
+    }
+}
+
+// Sort each CSR row by arriving node (rows hold about K entries).
+template <class T>
+__global__ void k_tr_sort(int64_t rows, const int32_t *__restrict__ ptr,
+                          int32_t *__restrict__ col, T *__restrict__ val) {
+    int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= rows) return;
+    const int b = ptr[r], e = ptr[r + 1];
+    for (int a = b + 1; a < e; ++a) {
+        const int c = col[a];
+        const T v = val[a];
+        int q = a - 1;
+        while (q >= b && col[q] > c) {
+            col[q + 1] = col[q];
+            val[q + 1] = val[q];
+            --q;
+        }
+        col[q + 1] = c;
+        val[q + 1] = v;
+    }
+}
+
+__global__ void k_set_i32(int32_t *p, int32_t v) { *p = v; }
+
+// Workgroup sum of one double per lane into part[blockIdx.x].
+__device__ __forceinline__ void block_sum_to(double v, double *part) {
+    __shared__ double sh[256];
+    sh[threadIdx.x] = v;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
+}
+
+__global__ __launch_bounds__(256) void k_sum_final(int64_t nparts, const double *__restrict__ part,
+                                                   double *__restrict__ out, int accumulate) {
+    __shared__ double sh[256];
+    double a = 0.0;
+    for (int64_t b = threadIdx.x; b < nparts; b += 256) a += part[b];
+    sh[threadIdx.x] = a;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *out = accumulate ? *out + sh[0] : sh[0];
+}
+
+template <class T>
+__device__ __forceinline__ void moments_of(const T *f, int n, int p, int dev, double rho0,
+                                           T (&fk)[kQ], T &rho, T &ux, T &uy, T &drho) {
+    T r = 0, jx = 0, jy = 0;
+#pragma unroll
+    for (int k = 0; k < kQ; ++k) {
+        fk[k] = f[(int64_t)k * n + p];
+        r += fk[k];
+        jx += fk[k] * (T)lat_ex(k);
+        jy += fk[k] * (T)lat_ey(k);
+    }
+    rho = dev ? (T)rho0 + r : r;
+    drho = dev ? r : r - (T)rho0;
+    ux = jx / rho;
+    uy = jy / rho;
+}
+
+// lam_n = C'(f^n)^T (S^T lam_next); part[block] = sum of (S^T lam).(dC/dtau).
+//   d feq_a / d rho = w_a [1 - 4.5 (e_a.u)^2 + 1.5 u^2]
+//   d feq_a / d j   = w_a [3 e_a + 9 (e_a.u) e_a - 3 u]
+//   C_a = f_a - (f_a - feq_a)/tau, so
+//   lam_b = (1 - 1/tau) lg_b + (1/tau) (A + B . e_b),
+//   A = sum_a lg_a d feq_a / d rho, B = sum_a lg_a d feq_a / d j,
+//   d C_a / d tau = (f_a - feq_a) / tau^2.
+template <class T>
+__global__ __launch_bounds__(256) void k_adj_step(
+    int n, const T *__restrict__ fn, const T *__restrict__ lam_next, T *__restrict__ lam_n,
+    const int32_t *__restrict__ ptr, const int32_t *__restrict__ col, const T *__restrict__ val,
+    double rtau, double rho0, int dev, double *__restrict__ part) {
+    const int m = blockIdx.x * blockDim.x + threadIdx.x;
+    double dt = 0.0;
+    if (m < n) {
+        T lg[kQ];
+        lg[0] = lam_next[m];
+#pragma unroll
+        for (int k = 1; k < kQ; ++k) {
+            const int64_t row = (int64_t)(k - 1) * n + m;
+            const int b = ptr[row], e = ptr[row + 1];
+            const T *lk = lam_next + (int64_t)k * n;
+            T acc = 0;
+            for (int q = b; q < e; ++q) acc += val[q] * lk[col[q]];
+            lg[k] = acc;
+        }
+        T fk[kQ], rho, ux, uy, drho;
+        moments_of<T>(fn, n, m, dev, rho0, fk, rho, ux, uy, drho);
+        const T uu = ux * ux + uy * uy;
+        T A = 0, Bx = 0, By = 0;
+        double dtl = 0.0;
+#pragma unroll
+        for (int a = 0; a < kQ; ++a) {
+            const T ex = (T)lat_ex(a), ey = (T)lat_ey(a), w = (T)lat_w(a);
+            const T eu = ex * ux + ey * uy;
+            A += lg[a] * w * ((T)1 - (T)4.5 * eu * eu + (T)1.5 * uu);
+            Bx += lg[a] * w * ((T)3 * ex + (T)9 * eu * ex - (T)3 * ux);
+            By += lg[a] * w * ((T)3 * ey + (T)9 * eu * ey - (T)3 * uy);
+            const T poly = (T)3 * eu + (T)4.5 * eu * eu - (T)1.5 * uu;
+            const T fneq = dev ? fk[a] - w * (drho + rho * poly)
+                               : fk[a] - w * rho * ((T)1 + poly);
+            dtl += (double)lg[a] * (double)fneq;
+        }
+        dt = dtl * rtau * rtau;
+        const T rt = (T)rtau;
+#pragma unroll
+        for (int b = 0; b < kQ; ++b)
+            lam_n[(int64_t)b * n + m] =
+                ((T)1 - rt) * lg[b] + rt * (A + Bx * (T)lat_ex(b) + By * (T)lat_ey(b));
+    }
+    block_sum_to(dt, part);
+}
+
+// dJ/df_b for J = 1/2 sum |u - u*|^2: (r . (e_b - u)) / rho, r = u - u*.
+template <class T>
+__global__ __launch_bounds__(256) void k_loss_seed(int n, const int32_t *__restrict__ perm,
+                                                   const T *__restrict__ fT,
+                                                   const double *__restrict__ uxt,
+                                                   const double *__restrict__ uyt,
+                                                   T *__restrict__ lam, double rho0, int dev,
+                                                   double *__restrict__ part) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    double jl = 0.0;
+    if (p < n) {
+        T fk[kQ], rho, ux, uy, drho;
+        moments_of<T>(fT, n, p, dev, rho0, fk, rho, ux, uy, drho);
+        const int u = perm[p];
+        const double rx = (double)ux - uxt[u], ry = (double)uy - uyt[u];
+        jl = 0.5 * (rx * rx + ry * ry);
+#pragma unroll
+        for (int b = 0; b < kQ; ++b)
+            lam[(int64_t)b * n + p] =
+                (T)((rx * ((double)lat_ex(b) - (double)ux) + ry * ((double)lat_ey(b) - (double)uy)) /
+                    (double)rho);
+    }
+    block_sum_to(jl, part);
+}
+
+// dJ/du0 = sum_k lam_k d feq_k(rho0, u0) / d u0.
+template <class T>
+__global__ void k_init_adjoint(int n, const int32_t *__restrict__ perm,
+                               const double *__restrict__ u0x, const double *__restrict__ u0y,
+                               const T *__restrict__ lam, double rho0, double *__restrict__ gx,
+                               double *__restrict__ gy) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= n) return;
+    const int u = perm[p];
+    const double ux = u0x ? u0x[u] : 0.0, uy = u0y ? u0y[u] : 0.0;
+    double sx = 0.0, sy = 0.0;
+    for (int k = 0; k < kQ; ++k) {
+        const double l = (double)lam[(int64_t)k * n + p];
+        const double eu = lat_ex(k) * ux + lat_ey(k) * uy;
+        sx += l * lat_w(k) * rho0 * (3.0 * lat_ex(k) + 9.0 * eu * lat_ex(k) - 3.0 * ux);
+        sy += l * lat_w(k) * rho0 * (3.0 * lat_ey(k) + 9.0 * eu * lat_ey(k) - 3.0 * uy);
+    }
+    gx[u] = sx;
+    gy[u] = sy;
+}
+
+}  // namespace
+
+size_t transpose_temp_bytes(int n, int K) {
+    (void)K;
+    const size_t rows = (size_t)8 * n;
+    return ((rows * sizeof(int32_t) + 255) & ~size_t(255)) + scan_temp_bytes((int)rows) + 256;
+}
+
+hipError_t launch_transpose(const CloudPlan &cp, int precision, void *tmp, size_t tmp_bytes,
+                            hipStream_t s) {
+    const int n = cp.n, K = cp.K, mode = cp.prm.stencil_mode;
+    const int64_t rows = (int64_t)8 * n;
+    int32_t *cnt = (int32_t *)tmp;
+    const size_t cnt_bytes = ((size_t)rows * sizeof(int32_t) + 255) & ~size_t(255);
+    void *scan_tmp = (char *)tmp + cnt_bytes;
+    const size_t scan_bytes = tmp_bytes - cnt_bytes;
+    hipError_t e = launch_fill_i32(cnt, 0, rows, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_tr_count, dim3(blocks_for(n, 256)), dim3(256), 0, s, n, K, mode, cp.nbr,
+                       cp.owner, cnt);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if ((e = exclusive_scan(scan_tmp, scan_bytes, cnt, cp.tr_ptr, (int)rows, s)) != hipSuccess)
+        return e;
+    hipLaunchKernelGGL(k_set_i32, dim3(1), dim3(1), 0, s, cp.tr_ptr + rows,
+                       (int32_t)(rows * K));
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if ((e = launch_fill_i32(cnt, 0, rows, s)) != hipSuccess) return e;
+    if (precision == MLBM_FP64) {
+        hipLaunchKernelGGL(k_tr_fill<double>, dim3(blocks_for(n, 256)), dim3(256), 0, s, n, K,
+                           mode, cp.nbr, cp.owner, (const float *)nullptr, cp.W64, cp.tr_ptr, cnt,
+                           cp.tr_col, (double *)cp.tr_val);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        hipLaunchKernelGGL(k_tr_sort<double>, dim3(blocks_for(rows, 256)), dim3(256), 0, s, rows,
+                           cp.tr_ptr, cp.tr_col, (double *)cp.tr_val);
+    } else {
+        hipLaunchKernelGGL(k_tr_fill<float>, dim3(blocks_for(n, 256)), dim3(256), 0, s, n, K,
+                           mode, cp.nbr, cp.owner, cp.W32, (const double *)nullptr, cp.tr_ptr,
+                           cnt, cp.tr_col, (float *)cp.tr_val);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        hipLaunchKernelGGL(k_tr_sort<float>, dim3(blocks_for(rows, 256)), dim3(256), 0, s, rows,
+                           cp.tr_ptr, cp.tr_col, (float *)cp.tr_val);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_loss_seed(const CloudPlan &cp, int precision, const void *fT,
+                            const double *uxt, const double *uyt, void *lam, double *J,
+                            double *part, hipStream_t s) {
+    const int n = cp.n;
+    const int64_t nb = blocks_for(n, 256);
+    if (precision == MLBM_FP64)
+        hipLaunchKernelGGL(k_loss_seed<double>, dim3(nb), dim3(256), 0, s, n, cp.perm,
+                           (const double *)fT, uxt, uyt, (double *)lam, cp.prm.rho0, 0, part);
+    else
+        hipLaunchKernelGGL(k_loss_seed<float>, dim3(nb), dim3(256), 0, s, n, cp.perm,
+                           (const float *)fT, uxt, uyt, (float *)lam, cp.prm.rho0, 1, part);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_sum_final, dim3(1), dim3(256), 0, s, nb, (const double *)part, J, 0);
+    return hipGetLastError();
+}
+
+hipError_t launch_step_adjoint(const CloudPlan &cp, int precision, const void *fn,
+                               const void *lam_next, void *lam_n, double *dtau, double *part,
+                               hipStream_t s) {
+    const int n = cp.n;
+    const int64_t nb = blocks_for(n, 256);
+    const double rtau = 1.0 / cp.prm.tau;
+    if (precision == MLBM_FP64)
+        hipLaunchKernelGGL(k_adj_step<double>, dim3(nb), dim3(256), 0, s, n, (const double *)fn,
+                           (const double *)lam_next, (double *)lam_n, cp.tr_ptr, cp.tr_col,
+                           (const double *)cp.tr_val, rtau, cp.prm.rho0, 0, part);
+    else
+        hipLaunchKernelGGL(k_adj_step<float>, dim3(nb), dim3(256), 0, s, n, (const float *)fn,
+                           (const float *)lam_next, (float *)lam_n, cp.tr_ptr, cp.tr_col,
+                           (const float *)cp.tr_val, rtau, cp.prm.rho0, 1, part);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_sum_final, dim3(1), dim3(256), 0, s, nb, (const double *)part, dtau, 1);
+    return hipGetLastError();
+}
+
+hipError_t launch_init_adjoint(const CloudPlan &cp, int precision, const double *u0x,
+                               const double *u0y, const void *lam0, double *gx, double *gy,
+                               hipStream_t s) {
+    const int n = cp.n;
+    if (precision == MLBM_FP64)
+        hipLaunchKernelGGL(k_init_adjoint<double>, dim3(blocks_for(n, 256)), dim3(256), 0, s, n,
+                           cp.perm, u0x, u0y, (const double *)lam0, cp.prm.rho0, gx, gy);
+    else
+        hipLaunchKernelGGL(k_init_adjoint<float>, dim3(blocks_for(n, 256)), dim3(256), 0, s, n,
+                           cp.perm, u0x, u0y, (const float *)lam0, cp.prm.rho0, gx, gy);
+    return hipGetLastError();
+}
+
+}  // namespace mlbm

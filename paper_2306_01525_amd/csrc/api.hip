@@ -1,0 +1,630 @@
+// Host side of the MLBM C-ABI: argument checks, buffer layout, build
+// orchestration, stepping, graphs and errors. Every entry point returns an
+// mlbm_status; no exception leaves this file.
+#include <algorithm>
+#include <climits>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "common.h"
+
+namespace mlbm {
+
+namespace {
+thread_local std::string g_error;
+}
+
+void set_error(const std::string &msg) { g_error = msg; }
+
+mlbm_status fail(mlbm_status st, const std::string &msg) {
+    g_error = msg;
+    return st;
+}
+
+mlbm_status hip_fail(hipError_t e, const char *what) {
+    g_error = std::string(what) + ": " + hipGetErrorString(e);
+    return MLBM_EHIP;
+}
+
+namespace {
+
+// Power of two nearest to v (at least 1).
+int pow2_near(double v) {
+    if (v <= 1.0) return 1;
+    int e = (int)std::lround(std::log2(v));
+    return 1 << std::max(0, std::min(e, 15));
+}
+
+// Uniform search grid with about two nodes per cell.
+void choose_grid(int n, double Lx, double Ly, int &gx, int &gy, int &hb) {
+    double aspect = (Lx > 0 && Ly > 0) ? Lx / Ly : 1.0;
+    double cells = std::max(1.0, n / 2.0);
+    gx = pow2_near(std::sqrt(cells * aspect));
+    gy = pow2_near(std::sqrt(cells / aspect));
+    hb = 0;
+    while ((1 << hb) < std::max(gx, gy)) ++hb;
+}
+
+mlbm_status check_params(const mlbm_cloud &c, const mlbm_params &p, bool device_cloud) {
+    if (c.n <= 0) return fail(MLBM_EINVAL, "cloud has no nodes");
+    if (device_cloud && (!c.x || !c.y)) return fail(MLBM_EINVAL, "cloud coordinates are null");
+    if (p.degree < 2 || p.degree > 4)
+        return fail(MLBM_EINVAL, "polynomial degree must be 2, 3 or 4");
+    const int M = poly_count(p.degree);
+    if (p.K < 6 || p.K > kMaxK) return fail(MLBM_EINVAL, "stencil size K must be in [6, 48]");
+    if (p.K < M) return fail(MLBM_EINVAL, "stencil size K is smaller than the polynomial count");
+    if (p.K + M > 64) return fail(MLBM_EUNSUPPORTED, "K + M > 64 is not supported");
+    if (c.n < p.K) return fail(MLBM_EINVAL, "cloud has fewer nodes than the stencil size");
+    if (!(p.tau > 0.5)) return fail(MLBM_EINVAL, "tau must exceed 0.5");
+    if (!(p.dx > 0.0)) return fail(MLBM_EINVAL, "dx must be positive");
+    if ((c.period_x > 0 && !(p.dx < 0.5 * c.period_x)) ||
+        (c.period_y > 0 && !(p.dx < 0.5 * c.period_y)))
+        return fail(MLBM_EINVAL, "dx must be below half the period");
+    if (c.period_x < 0 || c.period_y < 0) return fail(MLBM_EINVAL, "negative period");
+    if (p.precision != MLBM_FP32_DEV && p.precision != MLBM_FP64)
+        return fail(MLBM_EINVAL, "unknown precision");
+    if (p.stencil_mode != MLBM_STENCIL_PAPER && p.stencil_mode != MLBM_STENCIL_OWN)
+        return fail(MLBM_EINVAL, "unknown stencil mode");
+    if (p.force_kind != 0 && p.force_kind != 1) return fail(MLBM_EINVAL, "unknown force kind");
+    if (p.wall_kind != 0 && p.wall_kind != 1) return fail(MLBM_EINVAL, "unknown wall kind");
+    if (!(p.rho0 > 0.0)) return fail(MLBM_EINVAL, "rho0 must be positive");
+    if (p.wall_kind == 1 && !(p.rho_wall > 0.0)) return fail(MLBM_EINVAL, "rho_wall must be positive");
+    if (p.with_adjoint && (p.force_kind != 0 || p.wall_kind != 0))
+        return fail(MLBM_EUNSUPPORTED, "the adjoint supports periodic clouds without walls or force");
+    return MLBM_OK;
+}
+
+struct BuildWs {
+    uint32_t *keys = nullptr, *skeys = nullptr;
+    int32_t *vals = nullptr;
+    int32_t *cstart = nullptr, *cend = nullptr;
+    void *sort_tmp = nullptr;
+    size_t sort_bytes = 0;
+    void *tr_tmp = nullptr;
+    size_t tr_bytes = 0;
+    int gx = 1, gy = 1, hb = 0;
+};
+
+// Plan layout of one cloud. With null bases only the sizes are computed.
+void layout_cloud(const mlbm_cloud &c, const mlbm_params &p, int precision, Carve &pl,
+                  Carve *ws, CloudPlan &cp, BuildWs *bw) {
+    const int n = c.n, K = p.K;
+    cp.n = n;
+    cp.prm = p;
+    cp.K = K;
+    cp.m = p.degree;
+    cp.M = poly_count(p.degree);
+    cp.Lx = c.period_x;
+    cp.Ly = c.period_y;
+    cp.has_walls = p.wall_kind == 1;
+    cp.geo = pl.take<Geo>(1);
+    cp.xs = pl.take<double>(n);
+    cp.ys = pl.take<double>(n);
+    cp.perm = pl.take<int32_t>(n);
+    cp.iperm = pl.take<int32_t>(n);
+    cp.ntype = pl.take<uint8_t>(n);
+    cp.nbr = pl.take<int32_t>((size_t)K * n);
+    cp.owner = p.stencil_mode == MLBM_STENCIL_PAPER ? pl.take<int32_t>((size_t)8 * n) : nullptr;
+    cp.W64 = pl.take<double>((size_t)8 * K * n);
+    cp.W32 = precision == MLBM_FP32_DEV ? pl.take<float>((size_t)8 * K * n) : nullptr;
+    if (p.force_kind) {
+        cp.force64 = pl.take<double>((size_t)2 * n);
+        cp.force32 = precision == MLBM_FP32_DEV ? pl.take<float>((size_t)2 * n) : nullptr;
+    }
+    if (p.with_adjoint) {
+        cp.tr_ptr = pl.take<int32_t>((size_t)8 * n + 1);
+        cp.tr_col = pl.take<int32_t>((size_t)8 * K * n);
+        cp.tr_val = precision == MLBM_FP64 ? (void *)pl.take<double>((size_t)8 * K * n)
+                                           : (void *)pl.take<float>((size_t)8 * K * n);
+    }
+    if (ws && bw) {
+        choose_grid(n, c.period_x, c.period_y, bw->gx, bw->gy, bw->hb);
+        const size_t ncells = (size_t)bw->gx * bw->gy;
+        bw->keys = ws->take<uint32_t>(n);
+        bw->skeys = ws->take<uint32_t>(n);
+        bw->vals = ws->take<int32_t>(n);
+        bw->cstart = ws->take<int32_t>(ncells);
+        bw->cend = ws->take<int32_t>(ncells);
+        bw->sort_bytes = sort_pairs_temp_bytes(n);
+        bw->sort_tmp = ws->take<char>(bw->sort_bytes);
+        if (p.with_adjoint) {
+            bw->tr_bytes = transpose_temp_bytes(n, K);
+            bw->tr_tmp = ws->take<char>(bw->tr_bytes);
+        }
+    }
+}
+
+void layout_common(Carve &pl, mlbm_plan &plan, int64_t n_total) {
+    plan.dev_err = pl.take<int32_t>(64);
+    plan.scratch64 = pl.take<double>(16 + (size_t)blocks_for(n_total, 256) * 4);
+}
+
+bool capturing(hipStream_t s) {
+    hipStreamCaptureStatus st = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(s, &st) != hipSuccess) return false;
+    return st != hipStreamCaptureStatusNone;
+}
+
+mlbm_status check_singular(mlbm_plan *plan, hipStream_t s) {
+    if (capturing(s)) return MLBM_OK;
+    MLBM_HIP(hipStreamSynchronize(s));
+    int32_t v = 0;
+    MLBM_HIP(hipMemcpy(&v, plan->dev_err, sizeof(v), hipMemcpyDeviceToHost));
+    if (v != INT_MAX)
+        return fail(MLBM_ESINGULAR, "local RBF system is numerically singular at node " +
+                                        std::to_string(v - 1) + " (user index)");
+    return MLBM_OK;
+}
+
+const CloudPlan *single(const mlbm_plan *plan) {
+    if (!plan || plan->c.empty()) {
+        set_error("null plan");
+        return nullptr;
+    }
+    return &plan->c[0];
+}
+
+}  // namespace
+}  // namespace mlbm
+
+using namespace mlbm;
+
+extern "C" {
+
+const char *mlbm_last_error(void) { return g_error.c_str(); }
+
+mlbm_status mlbm_weights_query(const mlbm_cloud *clouds, const mlbm_params *params,
+                               int32_t n_clouds, size_t *plan_bytes, size_t *workspace_bytes) {
+    if (!clouds || !params || !plan_bytes || !workspace_bytes || n_clouds < 1)
+        return fail(MLBM_EINVAL, "null argument or n_clouds < 1");
+    if (n_clouds != 1) return fail(MLBM_EUNSUPPORTED, "use mlbm_batch_* for several clouds");
+    mlbm_status st = check_params(clouds[0], params[0], false);
+    if (st != MLBM_OK) return st;
+    Carve pl(nullptr), ws(nullptr);
+    CloudPlan cp;
+    BuildWs bw;
+    mlbm_plan tmp;
+    layout_cloud(clouds[0], params[0], params[0].precision, pl, &ws, cp, &bw);
+    layout_common(pl, tmp, clouds[0].n);
+    *plan_bytes = pl.used + 256;
+    *workspace_bytes = ws.used + 256;
+    return MLBM_OK;
+}
+
+mlbm_status mlbm_build_weights(const mlbm_cloud *clouds, const mlbm_params *params,
+                               int32_t n_clouds, void *plan_buf, size_t plan_bytes,
+                               void *workspace, size_t workspace_bytes, mlbm_plan **out,
+                               hipStream_t s) {
+    if (!out) return fail(MLBM_EINVAL, "null output pointer");
+    *out = nullptr;
+    size_t need_p = 0, need_w = 0;
+    mlbm_status st = mlbm_weights_query(clouds, params, n_clouds, &need_p, &need_w);
+    if (st != MLBM_OK) return st;
+    if (!clouds[0].x || !clouds[0].y) return fail(MLBM_EINVAL, "cloud coordinates are null");
+    if (!plan_buf || !workspace) return fail(MLBM_EINVAL, "null plan buffer or workspace");
+    if (plan_bytes < need_p || workspace_bytes < need_w)
+        return fail(MLBM_ESMALLBUF, "plan or workspace buffer smaller than queried");
+    const mlbm_cloud &c = clouds[0];
+    const mlbm_params &p = params[0];
+    mlbm_plan *plan = new (std::nothrow) mlbm_plan();
+    if (!plan) return fail(MLBM_EINVAL, "out of host memory");
+    plan->precision = p.precision;
+    plan->n_total = c.n;
+    Carve pl(plan_buf), ws(workspace);
+    CloudPlan cp;
+    BuildWs bw;
+    layout_cloud(c, p, p.precision, pl, &ws, cp, &bw);
+    layout_common(pl, *plan, c.n);
+    plan->c.push_back(cp);
+    const int n = c.n;
+    auto cleanup = [&](mlbm_status r) {
+        delete plan;
+        return r;
+    };
+#define STEP(call)                                                      \
+    do {                                                                \
+        hipError_t e_ = (call);                                         \
+        if (e_ != hipSuccess) return cleanup(hip_fail(e_, #call));      \
+    } while (0)
+    if (c.period_x > 0 && c.period_y > 0)
+        STEP(launch_geo_periodic(cp.geo, c.period_x, c.period_y, bw.gx, bw.gy, bw.hb, s));
+    else if (c.period_x > 0 || c.period_y > 0)
+        return cleanup(fail(MLBM_EUNSUPPORTED, "clouds periodic along one axis only"));
+    else
+        STEP(launch_geo_bbox(cp.geo, c.x, c.y, n, bw.gx, bw.gy, bw.hb, s));
+    STEP(launch_keys(cp.geo, c.x, c.y, n, bw.keys, bw.vals, s));
+    STEP(sort_pairs(bw.sort_tmp, bw.sort_bytes, bw.keys, bw.skeys, bw.vals, cp.perm, n,
+                    std::max(1, 2 * bw.hb), s));
+    STEP(launch_scatter_sorted(cp.geo, c.x, c.y, c.node_type, cp.perm, bw.skeys, n, cp.xs,
+                               cp.ys, cp.ntype, cp.iperm, bw.cstart, bw.cend, bw.gx * bw.gy, s));
+    STEP(launch_knn(cp.geo, cp.xs, cp.ys, cp.perm, cp.iperm, bw.cstart, bw.cend, n, p.K, cp.nbr, s));
+    if (p.stencil_mode == MLBM_STENCIL_PAPER)
+        STEP(launch_owner(cp.geo, cp.xs, cp.ys, cp.perm, cp.iperm, bw.cstart, bw.cend, n, p.dx,
+                          cp.owner, s));
+    STEP(launch_fill_i32(plan->dev_err, INT_MAX, 1, s));
+    STEP(launch_rbf(cp.geo, cp.xs, cp.ys, cp.perm, cp.nbr, cp.owner, n, p.K, p.degree, p.dx,
+                    p.stencil_mode, cp.ntype, cp.W64, plan->dev_err, s));
+    if (cp.W32) STEP(launch_pack_w32(cp.W64, n, p.K, cp.W32, s));
+    STEP(launch_force(cp.xs, cp.ys, cp.ntype, n, p.force_kind, p.force_mag, cp.force32,
+                      cp.force64, s));
+    if (p.with_adjoint) STEP(launch_transpose(cp, p.precision, bw.tr_tmp, bw.tr_bytes, s));
+#undef STEP
+    st = check_singular(plan, s);
+    if (st != MLBM_OK) return cleanup(st);
+    *out = plan;
+    return MLBM_OK;
+}
+
+mlbm_status mlbm_import_query(int32_t n, const mlbm_params *params, size_t *plan_bytes) {
+    if (!params || !plan_bytes) return fail(MLBM_EINVAL, "null argument");
+    mlbm_cloud c{};
+    c.n = n;
+    mlbm_status st = check_params(c, *params, false);
+    if (st != MLBM_OK) return st;
+    Carve pl(nullptr);
+    CloudPlan cp;
+    mlbm_plan tmp;
+    mlbm_params p = *params;
+    layout_cloud(c, p, p.precision, pl, nullptr, cp, nullptr);
+    layout_common(pl, tmp, n);
+    *plan_bytes = pl.used + 256;
+    return MLBM_OK;
+}
+
+mlbm_status mlbm_import_weights(int32_t n, const double *x, const double *y,
+                                const uint8_t *node_type, const int32_t *nbr,
+                                const int32_t *owner, const double *W,
+                                const mlbm_params *params, void *plan_buf, size_t plan_bytes,
+                                mlbm_plan **out, hipStream_t s) {
+    if (!out) return fail(MLBM_EINVAL, "null output pointer");
+    *out = nullptr;
+    size_t need = 0;
+    mlbm_status st = mlbm_import_query(n, params, &need);
+    if (st != MLBM_OK) return st;
+    if (!x || !y || !nbr || !owner || !W || !plan_buf)
+        return fail(MLBM_EINVAL, "null input array");
+    if (plan_bytes < need) return fail(MLBM_ESMALLBUF, "plan buffer smaller than queried");
+    const mlbm_params &p = *params;
+    const int K = p.K;
+    for (int64_t i = 0; i < (int64_t)n * K; ++i)
+        if (nbr[i] < 0 || nbr[i] >= n) return fail(MLBM_EINVAL, "stencil index out of range");
+    for (int64_t i = 0; i < (int64_t)n * 9; ++i)
+        if (owner[i] < 0 || owner[i] >= n) return fail(MLBM_EINVAL, "owner index out of range");
+    mlbm_plan *plan = new (std::nothrow) mlbm_plan();
+    if (!plan) return fail(MLBM_EINVAL, "out of host memory");
+    plan->precision = p.precision;
+    plan->n_total = n;
+    mlbm_cloud c{};
+    c.n = n;
+    Carve pl(plan_buf);
+    CloudPlan cp;
+    layout_cloud(c, p, p.precision, pl, nullptr, cp, nullptr);
+    layout_common(pl, *plan, n);
+    cp.imported = true;
+    bool any_wall = false;
+    std::vector<int32_t> ident(n), hn((size_t)K * n), ho;
+    std::vector<uint8_t> nt(n, 0);
+    std::vector<double> hw((size_t)8 * K * n);
+    for (int i = 0; i < n; ++i) ident[i] = i;
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j < K; ++j) hn[(size_t)j * n + i] = nbr[(size_t)i * K + j];
+    if (cp.owner) {
+        ho.resize((size_t)8 * n);
+        for (int i = 0; i < n; ++i)
+            for (int k = 1; k < 9; ++k) ho[(size_t)(k - 1) * n + i] = owner[(size_t)i * 9 + k];
+    }
+    for (int i = 0; i < n; ++i)
+        for (int k = 1; k < 9; ++k)
+            for (int j = 0; j < K; ++j)
+                hw[((size_t)(k - 1) * K + j) * n + i] = W[((size_t)i * 9 + k) * K + j];
+    if (node_type)
+        for (int i = 0; i < n; ++i) {
+            nt[i] = node_type[i];
+            any_wall |= nt[i] != 0;
+        }
+    cp.has_walls = p.wall_kind == 1;
+    auto cleanup = [&](mlbm_status r) {
+        delete plan;
+        return r;
+    };
+#define STEP(call)                                                      \
+    do {                                                                \
+        hipError_t e_ = (call);                                         \
+        if (e_ != hipSuccess) return cleanup(hip_fail(e_, #call));      \
+    } while (0)
+    STEP(hipMemcpyAsync(cp.xs, x, sizeof(double) * n, hipMemcpyHostToDevice, s));
+    STEP(hipMemcpyAsync(cp.ys, y, sizeof(double) * n, hipMemcpyHostToDevice, s));
+    STEP(hipMemcpyAsync(cp.perm, ident.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice, s));
+    STEP(hipMemcpyAsync(cp.iperm, ident.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice, s));
+    STEP(hipMemcpyAsync(cp.ntype, nt.data(), n, hipMemcpyHostToDevice, s));
+    STEP(hipMemcpyAsync(cp.nbr, hn.data(), sizeof(int32_t) * hn.size(), hipMemcpyHostToDevice, s));
+    if (cp.owner)
+        STEP(hipMemcpyAsync(cp.owner, ho.data(), sizeof(int32_t) * ho.size(),
+                            hipMemcpyHostToDevice, s));
+    STEP(hipMemcpyAsync(cp.W64, hw.data(), sizeof(double) * hw.size(), hipMemcpyHostToDevice, s));
+    if (cp.W32) STEP(launch_pack_w32(cp.W64, n, K, cp.W32, s));
+    STEP(launch_force(cp.xs, cp.ys, cp.ntype, n, p.force_kind, p.force_mag, cp.force32,
+                      cp.force64, s));
+    STEP(launch_fill_i32(plan->dev_err, INT_MAX, 1, s));
+    (void)any_wall;
+    if (p.with_adjoint) {
+        // This path has no workspace argument, so the transposed operator is
+        // assembled on the host (rows filled in ascending arriving node, which
+        // is the order the GPU build sorts to) and copied in.
+        std::vector<int32_t> cnt((size_t)8 * n, 0), ptr((size_t)8 * n + 1, 0), col;
+        std::vector<double> v64;
+        std::vector<float> v32;
+        const size_t nnz = (size_t)8 * K * n;
+        col.resize(nnz);
+        if (p.precision == MLBM_FP64) v64.resize(nnz);
+        else v32.resize(nnz);
+        std::vector<float> w32;
+        if (p.precision != MLBM_FP64) {
+            w32.resize((size_t)8 * K * n);
+            STEP(hipMemcpyAsync(w32.data(), cp.W32, sizeof(float) * w32.size(),
+                                hipMemcpyDeviceToHost, s));
+            STEP(hipStreamSynchronize(s));
+        }
+        auto src = [&](int i, int k, int j) {
+            int sidx = p.stencil_mode == MLBM_STENCIL_OWN ? i : owner[(size_t)i * 9 + k];
+            return nbr[(size_t)sidx * K + j];
+        };
+        for (int i = 0; i < n; ++i)
+            for (int k = 1; k < 9; ++k)
+                for (int j = 0; j < K; ++j) cnt[(size_t)(k - 1) * n + src(i, k, j)]++;
+        for (size_t r = 0; r < (size_t)8 * n; ++r) ptr[r + 1] = ptr[r] + cnt[r];
+        std::vector<int32_t> cur(ptr.begin(), ptr.end() - 1);
+        for (int i = 0; i < n; ++i)   // ascending i: rows come out sorted by arriving node
+            for (int k = 1; k < 9; ++k)
+                for (int j = 0; j < K; ++j) {
+                    size_t r = (size_t)(k - 1) * n + src(i, k, j);
+                    int pos = cur[r]++;
+                    col[pos] = i;
+                    if (p.precision == MLBM_FP64)
+                        v64[pos] = hw[((size_t)(k - 1) * K + j) * n + i];
+                    else
+                        v32[pos] = w32[(((size_t)j * 2 + ((k - 1) >> 2)) * n + i) * 4 + ((k - 1) & 3)];
+                }
+        STEP(hipMemcpyAsync(cp.tr_ptr, ptr.data(), sizeof(int32_t) * ptr.size(),
+                            hipMemcpyHostToDevice, s));
+        STEP(hipMemcpyAsync(cp.tr_col, col.data(), sizeof(int32_t) * nnz, hipMemcpyHostToDevice, s));
+        if (p.precision == MLBM_FP64)
+            STEP(hipMemcpyAsync(cp.tr_val, v64.data(), sizeof(double) * nnz, hipMemcpyHostToDevice, s));
+        else
+            STEP(hipMemcpyAsync(cp.tr_val, v32.data(), sizeof(float) * nnz, hipMemcpyHostToDevice, s));
+    }
+    STEP(hipStreamSynchronize(s));
+#undef STEP
+    plan->c.push_back(cp);
+    *out = plan;
+    return MLBM_OK;
+}
+
+mlbm_status mlbm_plan_get_info(const mlbm_plan *plan, mlbm_plan_info *info) {
+    const CloudPlan *cp = single(plan);
+    if (!cp || !info) return fail(MLBM_EINVAL, "null argument");
+    info->n_clouds = (int32_t)plan->c.size();
+    info->n_total = plan->n_total;
+    info->K = cp->K;
+    info->degree = cp->m;
+    info->stencil_mode = cp->prm.stencil_mode;
+    info->precision = plan->precision;
+    info->state_bytes = (size_t)9 * plan->n_total * state_elem_bytes(plan->precision);
+    info->tile_nodes = kTile;
+    return MLBM_OK;
+}
+
+mlbm_status mlbm_plan_export(const mlbm_plan *plan, int32_t cloud, int32_t what, void *dst,
+                             size_t dst_bytes) {
+    if (!plan || cloud < 0 || cloud >= (int32_t)plan->c.size() || !dst)
+        return fail(MLBM_EINVAL, "bad plan, cloud or destination");
+    const CloudPlan &cp = plan->c[cloud];
+    const int n = cp.n, K = cp.K;
+    size_t need = what == 0 ? sizeof(int32_t) * n
+                : what == 1 ? sizeof(int32_t) * (size_t)n * K
+                : what == 2 ? sizeof(int32_t) * (size_t)n * 9
+                : what == 3 ? sizeof(double) * (size_t)n * 9 * K : 0;
+    if (need == 0) return fail(MLBM_EINVAL, "unknown export item");
+    if (dst_bytes != need) return fail(MLBM_ESMALLBUF, "export size mismatch");
+    MLBM_HIP(hipDeviceSynchronize());
+    std::vector<int32_t> perm(n), iperm(n);
+    MLBM_HIP(hipMemcpy(perm.data(), cp.perm, sizeof(int32_t) * n, hipMemcpyDeviceToHost));
+    for (int p = 0; p < n; ++p) iperm[perm[p]] = p;
+    if (what == 0) {
+        std::memcpy(dst, perm.data(), need);
+        return MLBM_OK;
+    }
+    if (what == 1) {
+        std::vector<int32_t> nb((size_t)K * n);
+        MLBM_HIP(hipMemcpy(nb.data(), cp.nbr, sizeof(int32_t) * nb.size(), hipMemcpyDeviceToHost));
+        int32_t *o = (int32_t *)dst;
+        for (int u = 0; u < n; ++u)
+            for (int j = 0; j < K; ++j) o[(size_t)u * K + j] = perm[nb[(size_t)j * n + iperm[u]]];
+        return MLBM_OK;
+    }
+    if (what == 2) {
+        std::vector<int32_t> ow;
+        if (cp.owner) {
+            ow.resize((size_t)8 * n);
+            MLBM_HIP(hipMemcpy(ow.data(), cp.owner, sizeof(int32_t) * ow.size(), hipMemcpyDeviceToHost));
+        }
+        int32_t *o = (int32_t *)dst;
+        for (int u = 0; u < n; ++u) {
+            o[(size_t)u * 9] = u;
+            for (int k = 1; k < 9; ++k)
+                o[(size_t)u * 9 + k] = cp.owner ? perm[ow[(size_t)(k - 1) * n + iperm[u]]] : u;
+        }
+        return MLBM_OK;
+    }
+    std::vector<double> w((size_t)8 * K * n);
+    MLBM_HIP(hipMemcpy(w.data(), cp.W64, sizeof(double) * w.size(), hipMemcpyDeviceToHost));
+    double *o = (double *)dst;
+    for (int u = 0; u < n; ++u) {
+        const int p = iperm[u];
+        for (int j = 0; j < K; ++j) o[((size_t)u * 9) * K + j] = j == 0 ? 1.0 : 0.0;
+        for (int k = 1; k < 9; ++k)
+            for (int j = 0; j < K; ++j)
+                o[((size_t)u * 9 + k) * K + j] = w[((size_t)(k - 1) * K + j) * n + p];
+    }
+    return MLBM_OK;
+}
+
+mlbm_status mlbm_plan_destroy(mlbm_plan *plan) {
+    if (!plan) return MLBM_OK;
+    if (plan->graph_exec) (void)hipGraphExecDestroy(plan->graph_exec);
+    if (plan->graph) (void)hipGraphDestroy(plan->graph);
+    delete plan;
+    return MLBM_OK;
+}
+
+int32_t mlbm_device_error(const mlbm_plan *plan) {
+    if (!plan || !plan->dev_err) return 0;
+    int32_t v = INT_MAX;
+    if (hipDeviceSynchronize() != hipSuccess) return -1;
+    if (hipMemcpy(&v, plan->dev_err, sizeof(v), hipMemcpyDeviceToHost) != hipSuccess) return -1;
+    return v == INT_MAX ? 0 : v;
+}
+
+mlbm_status mlbm_init(const mlbm_plan *plan, const double *rho, const double *ux,
+                      const double *uy, void *g, hipStream_t s) {
+    const CloudPlan *cp = single(plan);
+    if (!cp || !g) return fail(MLBM_EINVAL, "null plan or state");
+    MLBM_HIP(launch_init(*cp, plan->precision, rho, ux, uy, g, true, s));
+    return MLBM_OK;
+}
+
+mlbm_status mlbm_init_f(const mlbm_plan *plan, const double *rho, const double *ux,
+                        const double *uy, void *f, hipStream_t s) {
+    const CloudPlan *cp = single(plan);
+    if (!cp || !f) return fail(MLBM_EINVAL, "null plan or state");
+    MLBM_HIP(launch_init(*cp, plan->precision, rho, ux, uy, f, false, s));
+    return MLBM_OK;
+}
+
+mlbm_status mlbm_collide(const mlbm_plan *plan, const void *f, void *g, hipStream_t s) {
+    const CloudPlan *cp = single(plan);
+    if (!cp || !f || !g) return fail(MLBM_EINVAL, "null plan or state");
+    if (f == g) return fail(MLBM_EINVAL, "collide needs distinct input and output");
+    MLBM_HIP(launch_collide(*cp, plan->precision, f, g, s));
+    return MLBM_OK;
+}
+
+mlbm_status mlbm_step(const mlbm_plan *plan, void *g_a, void *g_b, int32_t n_steps,
+                      int32_t *result_in_b, hipStream_t s) {
+    const CloudPlan *cp = single(plan);
+    if (!cp || !g_a || !g_b || n_steps < 0) return fail(MLBM_EINVAL, "bad step arguments");
+    if (g_a == g_b) return fail(MLBM_EINVAL, "ping-pong buffers must differ");
+    void *cur = g_a, *nxt = g_b;
+    for (int t = 0; t < n_steps; ++t) {
+        MLBM_HIP(launch_step(*cp, plan->precision, cur, nxt, nullptr, s));
+        std::swap(cur, nxt);
+    }
+    if (result_in_b) *result_in_b = (n_steps & 1) ? 1 : 0;
+    return MLBM_OK;
+}
+
+mlbm_status mlbm_step_record(const mlbm_plan *plan, void *g_a, void *g_b, int32_t n_steps,
+                             void *f_rec, int32_t *result_in_b, hipStream_t s) {
+    const CloudPlan *cp = single(plan);
+    if (!cp || !g_a || !g_b || !f_rec || n_steps < 0)
+        return fail(MLBM_EINVAL, "bad step arguments");
+    if (g_a == g_b) return fail(MLBM_EINVAL, "ping-pong buffers must differ");
+    const size_t sb = (size_t)9 * plan->n_total * state_elem_bytes(plan->precision);
+    void *cur = g_a, *nxt = g_b;
+    for (int t = 0; t < n_steps; ++t) {
+        MLBM_HIP(launch_step(*cp, plan->precision, cur, nxt, (char *)f_rec + sb * t, s));
+        std::swap(cur, nxt);
+    }
+    if (result_in_b) *result_in_b = (n_steps & 1) ? 1 : 0;
+    return MLBM_OK;
+}
+
+mlbm_status mlbm_moments(const mlbm_plan *plan, const void *g, double *rho, double *ux,
+                         double *uy, hipStream_t s) {
+    const CloudPlan *cp = single(plan);
+    if (!cp || !g) return fail(MLBM_EINVAL, "null plan or state");
+    MLBM_HIP(launch_moments(*cp, plan->precision, g, rho, ux, uy, true, s));
+    return MLBM_OK;
+}
+
+mlbm_status mlbm_l2_sums(const mlbm_plan *plan, const void *g, const double *ux_t,
+                         const double *uy_t, double *out, hipStream_t s) {
+    const CloudPlan *cp = single(plan);
+    if (!cp || !g || !ux_t || !uy_t || !out) return fail(MLBM_EINVAL, "null argument");
+    MLBM_HIP(launch_l2(*cp, plan->precision, g, ux_t, uy_t, out, plan->scratch64, s));
+    return MLBM_OK;
+}
+
+mlbm_status mlbm_loss_seed(const mlbm_plan *plan, const void *f_T, const double *ux_t,
+                           const double *uy_t, void *lamf_T, double *J, hipStream_t s) {
+    const CloudPlan *cp = single(plan);
+    if (!cp || !f_T || !ux_t || !uy_t || !lamf_T || !J) return fail(MLBM_EINVAL, "null argument");
+    if (cp->prm.force_kind || cp->has_walls)
+        return fail(MLBM_EUNSUPPORTED, "adjoint without walls or force only");
+    MLBM_HIP(launch_loss_seed(*cp, plan->precision, f_T, ux_t, uy_t, lamf_T, J,
+                              plan->scratch64, s));
+    return MLBM_OK;
+}
+
+mlbm_status mlbm_step_adjoint(const mlbm_plan *plan, const void *f_n, const void *lamf_next,
+                              void *lamf_n, double *dJ_dtau, hipStream_t s) {
+    const CloudPlan *cp = single(plan);
+    if (!cp || !f_n || !lamf_next || !lamf_n || !dJ_dtau) return fail(MLBM_EINVAL, "null argument");
+    if (!cp->tr_ptr) return fail(MLBM_EINVAL, "plan was built without with_adjoint");
+    if (lamf_next == lamf_n) return fail(MLBM_EINVAL, "adjoint buffers must differ");
+    MLBM_HIP(launch_step_adjoint(*cp, plan->precision, f_n, lamf_next, lamf_n, dJ_dtau,
+                                 plan->scratch64, s));
+    return MLBM_OK;
+}
+
+mlbm_status mlbm_init_adjoint(const mlbm_plan *plan, const double *u0x, const double *u0y,
+                              const void *lamf_0, double *dJ_du0x, double *dJ_du0y,
+                              hipStream_t s) {
+    const CloudPlan *cp = single(plan);
+    if (!cp || !lamf_0 || !dJ_du0x || !dJ_du0y) return fail(MLBM_EINVAL, "null argument");
+    MLBM_HIP(launch_init_adjoint(*cp, plan->precision, u0x, u0y, lamf_0, dJ_du0x, dJ_du0y, s));
+    return MLBM_OK;
+}
+
+mlbm_status mlbm_graph_create(mlbm_plan *plan, void *g_a, void *g_b, int32_t n_steps,
+                              hipStream_t s) {
+    const CloudPlan *cp = single(plan);
+    if (!cp || !g_a || !g_b || n_steps < 1) return fail(MLBM_EINVAL, "bad graph arguments");
+    if (!s) return fail(MLBM_EINVAL, "graph capture needs a non-default stream");
+    if (plan->graph_exec) {
+        (void)hipGraphExecDestroy(plan->graph_exec);
+        plan->graph_exec = nullptr;
+    }
+    if (plan->graph) {
+        (void)hipGraphDestroy(plan->graph);
+        plan->graph = nullptr;
+    }
+    MLBM_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+    void *cur = g_a, *nxt = g_b;
+    hipError_t err = hipSuccess;
+    for (int t = 0; t < n_steps && err == hipSuccess; ++t) {
+        err = launch_step(*cp, plan->precision, cur, nxt, nullptr, s);
+        std::swap(cur, nxt);
+    }
+    hipGraph_t graph = nullptr;
+    hipError_t e2 = hipStreamEndCapture(s, &graph);
+    if (err != hipSuccess) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return hip_fail(err, "step launch under capture");
+    }
+    if (e2 != hipSuccess) return hip_fail(e2, "hipStreamEndCapture");
+    plan->graph = graph;
+    MLBM_HIP(hipGraphInstantiate(&plan->graph_exec, graph, nullptr, nullptr, 0));
+    return MLBM_OK;
+}
+
+mlbm_status mlbm_graph_launch(mlbm_plan *plan, hipStream_t s) {
+    if (!plan || !plan->graph_exec) return fail(MLBM_EINVAL, "no graph on this plan");
+    MLBM_HIP(hipGraphLaunch(plan->graph_exec, s));
+    return MLBM_OK;
+}
+
+}  // extern "C"

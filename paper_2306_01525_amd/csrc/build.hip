@@ -1,0 +1,675 @@
+// Weight build of the MLBM on gfx950: space-filling-curve ordering, stencil
+// and owner searches on a uniform cell grid, and the FP64 local RBF solves.
+//
+// This translation unit is compiled with -ffp-contract=off: squared distances
+// are rounded exactly as written, so stencil ties are decided on bitwise equal
+// distances and then by user index, as in the definition of the stencil.
+#include <cfloat>
+#include <climits>
+
+#include "common.h"
+
+namespace mlbm {
+namespace {
+
+__device__ __forceinline__ double min_image(double d, double L) {
+    if (L > 0.0) {
+        if (d > 0.5 * L) d -= L;
+        else if (d < -0.5 * L) d += L;
+    }
+    return d;
+}
+
+__device__ __forceinline__ double dist2(double ax, double ay, double bx, double by,
+                                        double Lx, double Ly) {
+    double dx = min_image(bx - ax, Lx);
+    double dy = min_image(by - ay, Ly);
+    return dx * dx + dy * dy;
+}
+
+// Index of cell (x, y) along the Hilbert curve of a 2^order x 2^order grid
+// (the classic quadrant-rotation construction).
+__device__ uint32_t hilbert_index(uint32_t x, uint32_t y, int order) {
+    uint32_t d = 0;
+    const uint32_t side = 1u << order;
+    for (uint32_t s = side >> 1; s > 0; s >>= 1) {
+        uint32_t rx = (x & s) ? 1u : 0u;
+        uint32_t ry = (y & s) ? 1u : 0u;
+        d += s * s * ((3u * rx) ^ ry);
+        if (ry == 0) {
+            if (rx == 1) {
+                x = side - 1 - x;
+                y = side - 1 - y;
+            }
+            uint32_t t = x;
+            x = y;
+            y = t;
+        }
+    }
+    return d;
+}
+
+__device__ __forceinline__ void cell_of(const Geo &g, double x, double y, int &cx, int &cy) {
+    double fx = floor((x - g.x0) / g.cw);
+    double fy = floor((y - g.y0) / g.ch);
+    cx = fx < 0 ? 0 : (fx >= g.gx ? g.gx - 1 : (int)fx);
+    cy = fy < 0 ? 0 : (fy >= g.gy ? g.gy - 1 : (int)fy);
+}
+
+__global__ void k_geo_periodic(Geo *geo, double Lx, double Ly, int gx, int gy, int hb) {
+    Geo g;
+    g.x0 = 0.0;
+    g.y0 = 0.0;
+    g.cw = Lx / gx;
+    g.ch = Ly / gy;
+    g.Lx = Lx;
+    g.Ly = Ly;
+    g.gx = gx;
+    g.gy = gy;
+    g.hb = hb;
+    g.pad = 0;
+    *geo = g;
+}
+
+// Bounding box of an open cloud (one workgroup).
+__global__ __launch_bounds__(1024) void k_geo_bbox(Geo *geo, const double *x, const double *y,
+                                                   int n, int gx, int gy, int hb) {
+    __shared__ double s[4][1024];
+    double mnx = DBL_MAX, mny = DBL_MAX, mxx = -DBL_MAX, mxy = -DBL_MAX;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+        mnx = fmin(mnx, x[i]);
+        mxx = fmax(mxx, x[i]);
+        mny = fmin(mny, y[i]);
+        mxy = fmax(mxy, y[i]);
+    }
+    s[0][threadIdx.x] = mnx;
+    s[1][threadIdx.x] = mxx;
+    s[2][threadIdx.x] = mny;
+    s[3][threadIdx.x] = mxy;
+    __syncthreads();
+    for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) {
+            s[0][threadIdx.x] = fmin(s[0][threadIdx.x], s[0][threadIdx.x + w]);
+            s[1][threadIdx.x] = fmax(s[1][threadIdx.x], s[1][threadIdx.x + w]);
+            s[2][threadIdx.x] = fmin(s[2][threadIdx.x], s[2][threadIdx.x + w]);
+            s[3][threadIdx.x] = fmax(s[3][threadIdx.x], s[3][threadIdx.x + w]);
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        double ex = s[1][0] - s[0][0], ey = s[3][0] - s[2][0];
+        double e = fmax(fmax(ex, ey), 1e-300);
+        Geo g;
+        g.x0 = s[0][0] - 1e-9 * e;
+        g.y0 = s[2][0] - 1e-9 * e;
+        g.cw = (ex + 2e-9 * e) / gx;
+        g.ch = (ey + 2e-9 * e) / gy;
+        if (!(g.cw > 0)) g.cw = 1.0;
+        if (!(g.ch > 0)) g.ch = 1.0;
+        g.Lx = 0.0;
+        g.Ly = 0.0;
+        g.gx = gx;
+        g.gy = gy;
+        g.hb = hb;
+        g.pad = 0;
+        *geo = g;
+    }
+}
+
+__global__ void k_keys(const Geo *__restrict__ geo, const double *__restrict__ x,
+                       const double *__restrict__ y, int n, uint32_t *keys, int32_t *vals) {
+    int u = blockIdx.x * blockDim.x + threadIdx.x;
+    if (u >= n) return;
+    Geo g = *geo;
+    int cx, cy;
+    cell_of(g, x[u], y[u], cx, cy);
+    keys[u] = hilbert_index((uint32_t)cx, (uint32_t)cy, g.hb);
+    vals[u] = u;
+}
+
+__global__ void k_scatter_sorted(const Geo *__restrict__ geo, const double *__restrict__ x,
+                                 const double *__restrict__ y, const uint8_t *__restrict__ nt,
+                                 const int32_t *__restrict__ perm,
+                                 const uint32_t *__restrict__ skeys, int n, double *xs,
+                                 double *ys, uint8_t *ntype, int32_t *iperm, int32_t *cstart,
+                                 int32_t *cend) {
+    int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= n) return;
+    Geo g = *geo;
+    int u = perm[p];
+    double px = x[u], py = y[u];
+    xs[p] = px;
+    ys[p] = py;
+    ntype[p] = nt ? nt[u] : (uint8_t)0;
+    iperm[u] = p;
+    int cx, cy;
+    cell_of(g, px, py, cx, cy);
+    int c = cy * g.gx + cx;
+    uint32_t k = skeys[p];
+    if (p == 0 || skeys[p - 1] != k) cstart[c] = p;
+    if (p == n - 1 || skeys[p + 1] != k) cend[c] = p + 1;
+}
+
+__global__ void k_fill_i32(int32_t *p, int32_t v, int64_t n) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+// Ordered insertion of (d, u) into the ascending list held in registers. The
+// live entries occupy the tail of the array; the head holds sentinels with
+// distance -1 that nothing displaces, so the worst live entry is always the
+// last element.
+template <int KMAX>
+__device__ __forceinline__ void topk_insert(double (&bd)[KMAX], int (&bu)[KMAX], double d,
+                                            int u) {
+    if (!(d < bd[KMAX - 1] || (d == bd[KMAX - 1] && u < bu[KMAX - 1]))) return;
+    bool placed = false;
+#pragma unroll
+    for (int q = KMAX - 1; q >= 0; --q) {
+        if (!placed) {
+            bool before = false;
+            if (q > 0) before = d < bd[q - 1] || (d == bd[q - 1] && u < bu[q - 1]);
+            if (before) {
+                bd[q] = bd[q - 1];
+                bu[q] = bu[q - 1];
+            } else {
+                bd[q] = d;
+                bu[q] = u;
+                placed = true;
+            }
+        }
+    }
+}
+
+// Scan the cells of Chebyshev ring r around (cx, cy); `body(q)` runs for every
+// node q in those cells. Periodic axes wrap; cells outside open axes are skipped.
+template <class F>
+__device__ __forceinline__ void for_ring(const Geo &g, const int32_t *__restrict__ cstart,
+                                         const int32_t *__restrict__ cend, int cx, int cy,
+                                         int r, F &&body) {
+    const int span = 2 * r + 1;
+    const int count = r == 0 ? 1 : 8 * r;
+    for (int t = 0; t < count; ++t) {
+        int dx, dy;
+        if (r == 0) {
+            dx = 0;
+            dy = 0;
+        } else if (t < span) {        // bottom row
+            dx = t - r;
+            dy = -r;
+        } else if (t < 2 * span) {    // top row
+            dx = t - span - r;
+            dy = r;
+        } else {                      // left and right columns without corners
+            int u = t - 2 * span;
+            dx = (u & 1) ? r : -r;
+            dy = (u >> 1) - r + 1;
+        }
+        int ix = cx + dx, iy = cy + dy;
+        if (g.Lx > 0.0) ix = (ix % g.gx + g.gx) % g.gx;
+        else if (ix < 0 || ix >= g.gx) continue;
+        if (g.Ly > 0.0) iy = (iy % g.gy + g.gy) % g.gy;
+        else if (iy < 0 || iy >= g.gy) continue;
+        int c = iy * g.gx + ix;
+        int e = cend[c];
+        for (int q = cstart[c]; q < e; ++q) body(q);
+    }
+}
+
+// Stencil of node p: p itself, then the K-1 closest other nodes by
+// (squared distance, user index). Rings of cells are scanned outwards until
+// every unscanned node is provably farther than the current (K-1)-th.
+template <int KMAX>
+__global__ __launch_bounds__(256) void k_knn(const Geo *__restrict__ geo,
+                                             const double *__restrict__ xs,
+                                             const double *__restrict__ ys,
+                                             const int32_t *__restrict__ perm,
+                                             const int32_t *__restrict__ iperm,
+                                             const int32_t *__restrict__ cstart,
+                                             const int32_t *__restrict__ cend, int n, int K,
+                                             int32_t *__restrict__ nbr) {
+    int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= n) return;
+    const Geo g = *geo;
+    const int live = K - 1, first = KMAX - live;
+    double bd[KMAX];
+    int bu[KMAX];
+#pragma unroll
+    for (int q = 0; q < KMAX; ++q) {
+        bd[q] = q < first ? -1.0 : DBL_MAX;
+        bu[q] = q < first ? -1 : INT_MAX;
+    }
+    const double px = xs[p], py = ys[p];
+    int cx, cy;
+    cell_of(g, px, py, cx, cy);
+    const double cmin = fmin(g.cw, g.ch);
+    for (int r = 0;; ++r) {
+        bool wraps = (g.Lx > 0.0 && 2 * r + 1 > g.gx) || (g.Ly > 0.0 && 2 * r + 1 > g.gy);
+        if (wraps) {  // tiny periodic grid: rings would revisit cells, scan all nodes
+#pragma unroll
+            for (int q = first; q < KMAX; ++q) {
+                bd[q] = DBL_MAX;
+                bu[q] = INT_MAX;
+            }
+            for (int q = 0; q < n; ++q)
+                if (q != p) topk_insert<KMAX>(bd, bu, dist2(px, py, xs[q], ys[q], g.Lx, g.Ly), perm[q]);
+            break;
+        }
+        for_ring(g, cstart, cend, cx, cy, r, [&](int q) {
+            if (q != p) topk_insert<KMAX>(bd, bu, dist2(px, py, xs[q], ys[q], g.Lx, g.Ly), perm[q]);
+        });
+        double reach = r * cmin;
+        if (bd[KMAX - 1] < reach * reach) break;
+        if (r > g.gx && r > g.gy) break;
+    }
+    nbr[p] = p;
+#pragma unroll
+    for (int q = 0; q < KMAX; ++q)
+        if (q >= first) nbr[(int64_t)(q - first + 1) * n + p] = iperm[bu[q]];
+}
+
+// Owner of each departure point x_p - e_k dx (k = 1..8): the closest node,
+// ties to the lower user index.
+__global__ __launch_bounds__(256) void k_owner(const Geo *__restrict__ geo,
+                                               const double *__restrict__ xs,
+                                               const double *__restrict__ ys,
+                                               const int32_t *__restrict__ perm,
+                                               const int32_t *__restrict__ iperm,
+                                               const int32_t *__restrict__ cstart,
+                                               const int32_t *__restrict__ cend, int n,
+                                               double dx, int32_t *__restrict__ owner) {
+    int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= n) return;
+    const Geo g = *geo;
+    const double cmin = fmin(g.cw, g.ch);
+    for (int k = 1; k < kQ; ++k) {
+        double qx = xs[p] - lat_ex(k) * dx;
+        double qy = ys[p] - lat_ey(k) * dx;
+        // cell of the departure point (wrapped into the periodic box)
+        double wx = qx, wy = qy;
+        if (g.Lx > 0.0) wx = wx - g.Lx * floor(wx / g.Lx);
+        if (g.Ly > 0.0) wy = wy - g.Ly * floor(wy / g.Ly);
+        int cx, cy;
+        cell_of(g, wx, wy, cx, cy);
+        double bd = DBL_MAX;
+        int bu = INT_MAX;
+        auto take = [&](int q) {
+            double d = dist2(qx, qy, xs[q], ys[q], g.Lx, g.Ly);
+            int u = perm[q];
+            if (d < bd || (d == bd && u < bu)) {
+                bd = d;
+                bu = u;
+            }
+        };
+        for (int r = 0;; ++r) {
+            bool wraps = (g.Lx > 0.0 && 2 * r + 1 > g.gx) || (g.Ly > 0.0 && 2 * r + 1 > g.gy);
+            if (wraps) {
+                bd = DBL_MAX;
+                bu = INT_MAX;
+                for (int q = 0; q < n; ++q) take(q);
+                break;
+            }
+            for_ring(g, cstart, cend, cx, cy, r, take);
+            double reach = r * cmin;
+            if (bd < reach * reach) break;
+            if (r > g.gx && r > g.gy) break;
+        }
+        owner[(int64_t)(k - 1) * n + p] = iperm[bu];
+    }
+}
+
+__device__ __forceinline__ double readlane_d(double v, int l) {
+    long long b = __double_as_longlong(v);
+    int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), l);
+    int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+    return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+
+// Monomial q of eq. poly_sets (order 1, x, y, x^2, xy, y^2, x^3, x^2y, xy^2,
+// y^3, x^4, x^3y, x^2y^2, xy^3, y^4) at (x, y).
+__device__ __forceinline__ double monomial(int q, double x, double y) {
+    switch (q) {
+        case 0: return 1.0;
+        case 1: return x;
+        case 2: return y;
+        case 3: return x * x;
+        case 4: return x * y;
+        case 5: return y * y;
+        case 6: return x * x * x;
+        case 7: return x * x * y;
+        case 8: return x * y * y;
+        case 9: return y * y * y;
+        case 10: return x * x * x * x;
+        case 11: return x * x * x * y;
+        case 12: return x * x * y * y;
+        case 13: return x * y * y * y;
+        case 14: return y * y * y * y;
+        default: return 0.0;
+    }
+}
+
+__device__ __forceinline__ double cube_dist(double ax, double ay, double bx, double by) {
+    double dx = ax - bx, dy = ay - by;
+    double r = sqrt(dx * dx + dy * dy);
+    return r * r * r;
+}
+
+// One wavefront solves one local system Phi w = phi(p) (eqs.
+// rbf_interp_set_augmented and shape_vector) for R right-hand sides by
+// Gaussian elimination with partial pivoting. Lane r holds row r of the
+// system (K RBF rows, M polynomial rows, then identity rows that pad the
+// system to NB unknowns). Rows are never moved: the pivot of column k is the
+// not-yet-used lane with the largest |a_k| (ties: lowest lane), broadcast by
+// readlane; elimination leaves an upper-triangular system in pivot order that
+// is solved backwards. R = 8: own-node stencil, the eight departure points of
+// node p. R = 1: paper stencil, one departure point (p, k) on the stencil of
+// its owner.
+template <int NB, int R>
+__global__ __launch_bounds__(256) void k_rbf(const Geo *__restrict__ geo,
+                                             const double *__restrict__ xs,
+                                             const double *__restrict__ ys,
+                                             const int32_t *__restrict__ perm,
+                                             const int32_t *__restrict__ nbr,
+                                             const int32_t *__restrict__ owner, int n, int K,
+                                             int m, double dx, double *__restrict__ W64,
+                                             int32_t *__restrict__ dev_err) {
+    const int lane = threadIdx.x & 63;
+    const int64_t wave = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    int p, kdir;
+    if (R == 8) {
+        if (wave >= n) return;
+        p = (int)wave;
+        kdir = 1;
+    } else {
+        if (wave >= (int64_t)n * 8) return;
+        p = (int)(wave >> 3);
+        kdir = (int)(wave & 7) + 1;
+    }
+    const Geo g = *geo;
+    const int M = (m + 1) * (m + 2) / 2;
+    const int nn = K + M;
+    const int s = (R == 8) ? p : owner[(int64_t)(kdir - 1) * n + p];
+
+    // stencil member coordinates relative to the centre s, then scaled by the
+    // stencil radius (the interpolant is invariant to this; it helps the
+    // conditioning)
+    double rx = 0.0, ry = 0.0;
+    if (lane < K) {
+        int q = nbr[(int64_t)lane * n + s];
+        rx = min_image(xs[q] - xs[s], g.Lx);
+        ry = min_image(ys[q] - ys[s], g.Ly);
+    }
+    double rad = sqrt(rx * rx + ry * ry);
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) rad = fmax(rad, __shfl_xor(rad, off));
+    if (!(rad > 0.0)) rad = 1.0;
+    const double sx = rx / rad, sy = ry / rad;
+
+    // departure points (scaled, relative to s)
+    double qx[R], qy[R];
+#pragma unroll
+    for (int t = 0; t < R; ++t) {
+        int k = (R == 8) ? t + 1 : kdir;
+        if (R == 8) {
+            qx[t] = (-lat_ex(k) * dx) / rad;
+            qy[t] = (-lat_ey(k) * dx) / rad;
+        } else {
+            qx[t] = min_image(xs[p] - lat_ex(k) * dx - xs[s], g.Lx) / rad;
+            qy[t] = min_image(ys[p] - lat_ey(k) * dx - ys[s], g.Ly) / rad;
+        }
+    }
+
+    // row `lane` of the padded system and its right-hand sides
+    double a[NB], b[R];
+    const bool rbf_row = lane < K;
+    const bool poly_row = lane >= K && lane < nn;
+    const int qrow = lane - K;
+#pragma unroll
+    for (int c = 0; c < NB; ++c) {
+        double cxv = readlane_d(sx, c < 64 ? c : 0);
+        double cyv = readlane_d(sy, c < 64 ? c : 0);
+        double v = 0.0;
+        if (rbf_row) {
+            if (c < K) v = cube_dist(sx, sy, cxv, cyv);
+            else if (c < nn) v = monomial(c - K, sx, sy);
+        } else if (poly_row) {
+            if (c < K) v = monomial(qrow, cxv, cyv);
+        } else if (lane < NB) {
+            v = (c == lane) ? 1.0 : 0.0;
+        }
+        a[c] = v;
+    }
+#pragma unroll
+    for (int t = 0; t < R; ++t) {
+        double v = 0.0;
+        if (rbf_row) v = cube_dist(sx, sy, qx[t], qy[t]);
+        else if (poly_row) v = monomial(qrow, qx[t], qy[t]);
+        b[t] = v;
+    }
+
+    // infinity norm for the singularity threshold
+    double rs = 0.0;
+#pragma unroll
+    for (int c = 0; c < NB; ++c) rs += fabs(a[c]);
+    if (lane >= NB) rs = 0.0;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) rs = fmax(rs, __shfl_xor(rs, off));
+    const double tiny = 1e3 * DBL_EPSILON * rs;
+
+    bool used = lane >= NB;   // lanes beyond the system never pivot
+    int pstep = NB;           // elimination step at which this lane was the pivot
+    int plane[NB];
+    bool singular = false;
+#pragma unroll
+    for (int k = 0; k < NB; ++k) {
+        double v = used ? -1.0 : fabs(a[k]);
+        int idx = lane;
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) {
+            double ov = __shfl_xor(v, off);
+            int oi = __shfl_xor(idx, off);
+            if (ov > v || (ov == v && oi < idx)) {
+                v = ov;
+                idx = oi;
+            }
+        }
+        const int pl = __builtin_amdgcn_readfirstlane(idx);
+        plane[k] = pl;
+        if (!(v > tiny)) singular = true;
+        const double pk = readlane_d(a[k], pl);
+        const double l = (!used && lane != pl) ? a[k] / pk : 0.0;
+#pragma unroll
+        for (int c = k + 1; c < NB; ++c) a[c] = a[c] - l * readlane_d(a[c], pl);
+#pragma unroll
+        for (int t = 0; t < R; ++t) b[t] = b[t] - l * readlane_d(b[t], pl);
+        if (lane == pl) {
+            used = true;
+            pstep = k;
+        }
+    }
+    double xo[R];
+#pragma unroll
+    for (int t = 0; t < R; ++t) xo[t] = 0.0;
+#pragma unroll
+    for (int k = NB - 1; k >= 0; --k) {
+        const int pl = plane[k];
+        const double ukk = readlane_d(a[k], pl);
+#pragma unroll
+        for (int t = 0; t < R; ++t) {
+            const double xk = readlane_d(b[t], pl) / ukk;
+            if (pstep < k) b[t] = b[t] - a[k] * xk;
+            if (lane == k) xo[t] = xk;
+        }
+    }
+    if (lane < K) {
+#pragma unroll
+        for (int t = 0; t < R; ++t) {
+            int k = (R == 8) ? t + 1 : kdir;
+            W64[((int64_t)(k - 1) * K + lane) * n + p] = xo[t];
+        }
+    }
+    if (singular && lane == 0) atomicMin(dev_err, perm[p] + 1);
+}
+
+// FP32 copy of the shape vectors in the streaming layout [K][2][n][4]
+// (directions 1..4 and 5..8 as float4). After rounding, the weights of each
+// (node, direction) no longer sum to one; the defect 1 - sum (evaluated in
+// FP64) is added to one weight, the smallest in magnitude among those at least
+// 64 times larger than the defect, so the rounded weights keep the partition
+// of unity that the deviation-stored populations rely on.
+__global__ void k_pack_w32(const double *__restrict__ W64, int n, int K, float *__restrict__ W32) {
+    int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= n) return;
+    for (int k = 1; k < kQ; ++k) {
+        const double *w = W64 + (int64_t)(k - 1) * K * n + p;
+        double sum = 0.0;
+        for (int j = 0; j < K; ++j) sum += (double)(float)w[(int64_t)j * n];
+        const double defect = 1.0 - sum;
+        int jstar = -1;
+        double best = DBL_MAX;
+        for (int j = 0; j < K; ++j) {
+            double a = fabs(w[(int64_t)j * n]);
+            if (a >= 64.0 * fabs(defect) && a < best) {
+                best = a;
+                jstar = j;
+            }
+        }
+        const int h = (k - 1) >> 2, c = (k - 1) & 3;
+        for (int j = 0; j < K; ++j) {
+            double v = w[(int64_t)j * n];
+            float f = (float)v;
+            if (j == jstar) f = (float)((double)f + defect);
+            W32[(((int64_t)j * 2 + h) * n + p) * 4 + c] = f;
+        }
+    }
+}
+
+// Constant azimuthal acceleration about the origin (Sec. 3): a = g (-y, x)/r at
+// fluid nodes, zero at wall nodes.
+__global__ void k_force(const double *__restrict__ xs, const double *__restrict__ ys,
+                        const uint8_t *__restrict__ nt, int n, double mag, float *f32,
+                        double *f64) {
+    int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= n) return;
+    double x = xs[p], y = ys[p];
+    double r = sqrt(x * x + y * y);
+    double ax = 0.0, ay = 0.0;
+    if (!(nt && nt[p]) && r > 0.0) {
+        ax = -mag * y / r;
+        ay = mag * x / r;
+    }
+    if (f32) {
+        f32[p] = (float)ax;
+        f32[n + p] = (float)ay;
+    }
+    if (f64) {
+        f64[p] = ax;
+        f64[n + p] = ay;
+    }
+}
+
+}  // namespace
+
+hipError_t launch_geo_periodic(Geo *geo, double Lx, double Ly, int gx, int gy, int hb,
+                               hipStream_t s) {
+    hipLaunchKernelGGL(k_geo_periodic, dim3(1), dim3(1), 0, s, geo, Lx, Ly, gx, gy, hb);
+    return hipGetLastError();
+}
+
+hipError_t launch_geo_bbox(Geo *geo, const double *x, const double *y, int n, int gx, int gy,
+                           int hb, hipStream_t s) {
+    hipLaunchKernelGGL(k_geo_bbox, dim3(1), dim3(1024), 0, s, geo, x, y, n, gx, gy, hb);
+    return hipGetLastError();
+}
+
+hipError_t launch_keys(const Geo *geo, const double *x, const double *y, int n,
+                       uint32_t *keys, int32_t *vals, hipStream_t s) {
+    hipLaunchKernelGGL(k_keys, dim3(blocks_for(n, 256)), dim3(256), 0, s, geo, x, y, n, keys,
+                       vals);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_i32(int32_t *p, int32_t v, int64_t n, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fill_i32, dim3(blocks_for(n, 256)), dim3(256), 0, s, p, v, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_scatter_sorted(const Geo *geo, const double *x, const double *y,
+                                 const uint8_t *nt, const int32_t *perm,
+                                 const uint32_t *skeys, int n, double *xs, double *ys,
+                                 uint8_t *ntype, int32_t *iperm, int32_t *cstart,
+                                 int32_t *cend, int ncells, hipStream_t s) {
+    hipError_t e = launch_fill_i32(cstart, 0, ncells, s);
+    if (e != hipSuccess) return e;
+    e = launch_fill_i32(cend, 0, ncells, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_scatter_sorted, dim3(blocks_for(n, 256)), dim3(256), 0, s, geo, x, y,
+                       nt, perm, skeys, n, xs, ys, ntype, iperm, cstart, cend);
+    return hipGetLastError();
+}
+
+hipError_t launch_knn(const Geo *geo, const double *xs, const double *ys,
+                      const int32_t *perm, const int32_t *iperm, const int32_t *cstart,
+                      const int32_t *cend, int n, int K, int32_t *nbr, hipStream_t s) {
+    dim3 grid(blocks_for(n, 256)), block(256);
+    if (K - 1 <= 16)
+        hipLaunchKernelGGL(k_knn<16>, grid, block, 0, s, geo, xs, ys, perm, iperm, cstart, cend, n, K, nbr);
+    else if (K - 1 <= 32)
+        hipLaunchKernelGGL(k_knn<32>, grid, block, 0, s, geo, xs, ys, perm, iperm, cstart, cend, n, K, nbr);
+    else
+        hipLaunchKernelGGL(k_knn<48>, grid, block, 0, s, geo, xs, ys, perm, iperm, cstart, cend, n, K, nbr);
+    return hipGetLastError();
+}
+
+hipError_t launch_owner(const Geo *geo, const double *xs, const double *ys,
+                        const int32_t *perm, const int32_t *iperm, const int32_t *cstart,
+                        const int32_t *cend, int n, double dx, int32_t *owner,
+                        hipStream_t s) {
+    hipLaunchKernelGGL(k_owner, dim3(blocks_for(n, 256)), dim3(256), 0, s, geo, xs, ys, perm,
+                       iperm, cstart, cend, n, dx, owner);
+    return hipGetLastError();
+}
+
+template <int NB>
+static hipError_t launch_rbf_nb(const Geo *geo, const double *xs, const double *ys,
+                                const int32_t *perm, const int32_t *nbr, const int32_t *owner,
+                                int n, int K, int m, double dx, int mode, double *W64,
+                                int32_t *dev_err, hipStream_t s) {
+    const int64_t waves = mode == MLBM_STENCIL_OWN ? (int64_t)n : (int64_t)n * 8;
+    dim3 grid(blocks_for(waves, 4)), block(256);
+    if (mode == MLBM_STENCIL_OWN)
+        hipLaunchKernelGGL((k_rbf<NB, 8>), grid, block, 0, s, geo, xs, ys, perm, nbr, owner, n, K,
+                           m, dx, W64, dev_err);
+    else
+        hipLaunchKernelGGL((k_rbf<NB, 1>), grid, block, 0, s, geo, xs, ys, perm, nbr, owner, n, K,
+                           m, dx, W64, dev_err);
+    return hipGetLastError();
+}
+
+hipError_t launch_rbf(const Geo *geo, const double *xs, const double *ys,
+                      const int32_t *perm, const int32_t *nbr, const int32_t *owner,
+                      int n, int K, int m, double dx, int mode, const uint8_t *ntype,
+                      double *W64, int32_t *dev_err, hipStream_t s) {
+    (void)ntype;
+    const int nn = K + poly_count(m);
+    if (nn <= 24) return launch_rbf_nb<24>(geo, xs, ys, perm, nbr, owner, n, K, m, dx, mode, W64, dev_err, s);
+    if (nn <= 32) return launch_rbf_nb<32>(geo, xs, ys, perm, nbr, owner, n, K, m, dx, mode, W64, dev_err, s);
+    if (nn <= 48) return launch_rbf_nb<48>(geo, xs, ys, perm, nbr, owner, n, K, m, dx, mode, W64, dev_err, s);
+    return launch_rbf_nb<64>(geo, xs, ys, perm, nbr, owner, n, K, m, dx, mode, W64, dev_err, s);
+}
+
+hipError_t launch_pack_w32(const double *W64, int n, int K, float *W32, hipStream_t s) {
+    hipLaunchKernelGGL(k_pack_w32, dim3(blocks_for(n, 256)), dim3(256), 0, s, W64, n, K, W32);
+    return hipGetLastError();
+}
+
+hipError_t launch_force(const double *xs, const double *ys, const uint8_t *ntype, int n,
+                        int kind, double mag, float *f32, double *f64, hipStream_t s) {
+    if (kind == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_force, dim3(blocks_for(n, 256)), dim3(256), 0, s, xs, ys, ntype, n,
+                       mag, f32, f64);
+    return hipGetLastError();
+}
+
+}  // namespace mlbm

@@ -1,0 +1,186 @@
+// Internal declarations of the MLBM HIP library (gfx950). Not part of the ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/mlbm.h"
+
+namespace mlbm {
+
+// ---------------------------------------------------------------------------
+// D2Q9 lattice (Sec. 2.1): directions k = 0..8 in the paper's order
+// (0,0),(1,0),(0,1),(-1,0),(0,-1),(1,1),(-1,1),(-1,-1),(1,-1); weights 4/9,
+// 1/9 (axes), 1/36 (diagonals); c_s^2 = 1/3.
+// ---------------------------------------------------------------------------
+__host__ __device__ constexpr int lat_ex(int k) {
+    return (k == 1 || k == 5 || k == 8) ? 1 : (k == 3 || k == 6 || k == 7) ? -1 : 0;
+}
+__host__ __device__ constexpr int lat_ey(int k) {
+    return (k == 2 || k == 5 || k == 6) ? 1 : (k == 4 || k == 7 || k == 8) ? -1 : 0;
+}
+__host__ __device__ constexpr double lat_w(int k) {
+    return k == 0 ? 4.0 / 9.0 : (k <= 4 ? 1.0 / 9.0 : 1.0 / 36.0);
+}
+
+constexpr int kQ = 9;
+constexpr int kMaxK = 48;       // largest stencil supported
+constexpr int kTile = 256;      // nodes per workgroup in the step kernels
+
+inline int poly_count(int m) { return (m + 1) * (m + 2) / 2; }
+
+// Geometry of the uniform search grid of one cloud (device resident).
+struct Geo {
+    double x0, y0;      // grid origin
+    double cw, ch;      // cell width and height
+    double Lx, Ly;      // periods (0 = open)
+    int gx, gy;         // cells per axis (powers of two)
+    int hb;             // Hilbert order: grid side 2^hb >= max(gx, gy)
+    int pad;
+};
+
+// One cloud inside a plan. Pointers are device addresses inside the caller's
+// plan buffer; arrays are in internal (Hilbert) node order unless stated.
+struct CloudPlan {
+    int64_t off = 0;          // offset of this cloud's nodes in state arrays
+    int32_t n = 0;
+    mlbm_params prm{};
+    int K = 0, m = 0, M = 0;
+    double Lx = 0, Ly = 0;
+    bool has_walls = false;
+    bool imported = false;
+    Geo *geo = nullptr;       // device
+    double *xs = nullptr, *ys = nullptr;     // [n]
+    int32_t *perm = nullptr;  // [n] internal -> user index
+    int32_t *iperm = nullptr; // [n] user -> internal
+    uint8_t *ntype = nullptr; // [n]
+    int32_t *nbr = nullptr;   // [K][n], internal indices, centre first
+    int32_t *owner = nullptr; // [8][n] for k = 1..8 (paper mode only)
+    double *W64 = nullptr;    // [8][K][n] FP64 shape vectors, k = 1..8
+    float *W32 = nullptr;     // [K][2][n][4] FP32 shape vectors, k = 1..8
+    float *force32 = nullptr; // [2][n] body force (lattice units), FP32 state
+    double *force64 = nullptr;// [2][n] body force, FP64 state
+    // transposed streaming (adjoint): per direction k = 1..8, CSR over the
+    // source node m of (arriving node i, weight)
+    int32_t *tr_ptr = nullptr;  // [8][n+1]
+    int32_t *tr_col = nullptr;  // [8][K*n]
+    void *tr_val = nullptr;     // [8][K*n] float (FP32 plans) or double (FP64)
+};
+
+// Bump allocator over a caller buffer (a null base computes sizes only).
+struct Carve {
+    char *base;
+    size_t used = 0;
+    explicit Carve(void *b) : base(static_cast<char *>(b)) {}
+    template <class T>
+    T *take(size_t count) {
+        used = (used + 255) & ~size_t(255);
+        T *p = base ? reinterpret_cast<T *>(base + used) : nullptr;
+        used += count * sizeof(T);
+        return p;
+    }
+};
+
+}  // namespace mlbm
+
+struct mlbm_plan {
+    std::vector<mlbm::CloudPlan> c;
+    int64_t n_total = 0;
+    int precision = MLBM_FP32_DEV;
+    int32_t *dev_err = nullptr;     // device word: 0 or 1 + user index
+    double *scratch64 = nullptr;    // device, small reductions
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t graph_exec = nullptr;
+};
+
+namespace mlbm {
+
+// Thread-local error message.
+void set_error(const std::string &msg);
+mlbm_status fail(mlbm_status st, const std::string &msg);
+mlbm_status hip_fail(hipError_t e, const char *what);
+
+#define MLBM_HIP(call)                                      \
+    do {                                                    \
+        hipError_t e_ = (call);                             \
+        if (e_ != hipSuccess) return ::mlbm::hip_fail(e_, #call); \
+    } while (0)
+
+inline size_t state_elem_bytes(int precision) {
+    return precision == MLBM_FP64 ? sizeof(double) : sizeof(float);
+}
+
+// Grid sizes for launches.
+inline unsigned blocks_for(int64_t n, int threads) {
+    return static_cast<unsigned>((n + threads - 1) / threads);
+}
+
+// ---- build stages (build.hip) ----
+hipError_t launch_geo_periodic(Geo *geo, double Lx, double Ly, int gx, int gy, int hb,
+                               hipStream_t s);
+hipError_t launch_geo_bbox(Geo *geo, const double *x, const double *y, int n, int gx,
+                           int gy, int hb, hipStream_t s);
+hipError_t launch_keys(const Geo *geo, const double *x, const double *y, int n,
+                       uint32_t *keys, int32_t *vals, hipStream_t s);
+hipError_t launch_scatter_sorted(const Geo *geo, const double *x, const double *y,
+                                 const uint8_t *nt, const int32_t *perm,
+                                 const uint32_t *skeys, int n, double *xs, double *ys,
+                                 uint8_t *ntype, int32_t *iperm, int32_t *cstart,
+                                 int32_t *cend, int ncells, hipStream_t s);
+hipError_t launch_knn(const Geo *geo, const double *xs, const double *ys,
+                      const int32_t *perm, const int32_t *iperm, const int32_t *cstart,
+                      const int32_t *cend, int n, int K, int32_t *nbr, hipStream_t s);
+hipError_t launch_owner(const Geo *geo, const double *xs, const double *ys,
+                        const int32_t *perm, const int32_t *iperm, const int32_t *cstart,
+                        const int32_t *cend, int n, double dx, int32_t *owner,
+                        hipStream_t s);
+hipError_t launch_rbf(const Geo *geo, const double *xs, const double *ys,
+                      const int32_t *perm, const int32_t *nbr, const int32_t *owner,
+                      int n, int K, int m, double dx, int mode, const uint8_t *ntype,
+                      double *W64, int32_t *dev_err, hipStream_t s);
+hipError_t launch_pack_w32(const double *W64, int n, int K, float *W32, hipStream_t s);
+hipError_t launch_force(const double *xs, const double *ys, const uint8_t *ntype, int n,
+                        int kind, double mag, float *f32, double *f64, hipStream_t s);
+hipError_t launch_fill_i32(int32_t *p, int32_t v, int64_t n, hipStream_t s);
+
+// ---- sort / scan (sort.hip) ----
+size_t sort_pairs_temp_bytes(int n);
+hipError_t sort_pairs(void *tmp, size_t tmp_bytes, const uint32_t *kin, uint32_t *kout,
+                      const int32_t *vin, int32_t *vout, int n, int end_bit, hipStream_t s);
+size_t scan_temp_bytes(int n);
+hipError_t exclusive_scan(void *tmp, size_t tmp_bytes, const int32_t *in, int32_t *out,
+                          int n, hipStream_t s);
+
+// ---- stepping (step.hip) ----
+hipError_t launch_init(const CloudPlan &cp, int precision, const double *rho,
+                       const double *ux, const double *uy, void *g, bool collide,
+                       hipStream_t s);
+hipError_t launch_step(const CloudPlan &cp, int precision, const void *gin, void *gout,
+                       void *frec, hipStream_t s);
+hipError_t launch_moments(const CloudPlan &cp, int precision, const void *g, double *rho,
+                          double *ux, double *uy, bool post_collision, hipStream_t s);
+hipError_t launch_l2(const CloudPlan &cp, int precision, const void *g, const double *uxt,
+                     const double *uyt, double *out, double *part, hipStream_t s);
+hipError_t launch_collide(const CloudPlan &cp, int precision, const void *f, void *g,
+                          hipStream_t s);
+
+// ---- adjoint (adjoint.hip) ----
+// workspace of the transpose build: counts/cursors [8n] + scan temp
+size_t transpose_temp_bytes(int n, int K);
+hipError_t launch_transpose(const CloudPlan &cp, int precision, void *tmp, size_t tmp_bytes,
+                            hipStream_t s);
+hipError_t launch_loss_seed(const CloudPlan &cp, int precision, const void *fT,
+                            const double *uxt, const double *uyt, void *lam, double *J,
+                            double *part, hipStream_t s);
+hipError_t launch_step_adjoint(const CloudPlan &cp, int precision, const void *fn,
+                               const void *lam_next, void *lam_n, double *dtau, double *part,
+                               hipStream_t s);
+hipError_t launch_init_adjoint(const CloudPlan &cp, int precision, const double *u0x,
+                               const double *u0y, const void *lam0, double *gx, double *gy,
+                               hipStream_t s);
+
+}  // namespace mlbm

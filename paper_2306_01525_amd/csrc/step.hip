@@ -1,0 +1,473 @@
+// Time stepping of the MLBM on gfx950: initial equilibrium, the fused
+// stream + collide step, moments and error reductions.
+//
+// One lane owns one node. Per step and node the kernel
+//   1. interpolates every moving population k = 1..8 at its departure point:
+//      f_k(i) = sum_j W[k][j][i] * g_k(nbr[j][s]), s the stencil owner
+//      (Sec. 2.3; Appendix A, STREAM); k = 0 departs from the node itself;
+//   2. imposes the wall rule at wall nodes;
+//   3. takes the moments (eq. macro_var) and applies BGK collision with the
+//      optional body force (eqs. LBM_collision, feq; Sec. 3);
+//   4. writes the post-collision populations g for the next step.
+// The state g is kept post-collision, so one kernel per step reads each
+// population once and writes it once; this is the paper's COLLIDE-STREAM order
+// shifted by half a step.
+//
+// The FP32 form stores every population as its deviation from w_k rho0 (the
+// populations are O(1) while the flow lives in O(u) corrections); the weights
+// reproduce constants, so the streamed deviation is the interpolated
+// deviation. The FP64 form stores plain populations.
+//
+// Memory: the stencil weights dominate the traffic (8K per node per step); they
+// are read once, unit-stride across the lanes of a wavefront. The populations
+// gathered through nbr are re-used by neighbouring nodes and are served from
+// L2; nodes are in Hilbert order so the gathers of a workgroup stay local.
+#include "common.h"
+
+namespace mlbm {
+namespace {
+
+constexpr float kW0 = 4.0f / 9.0f, kW1 = 1.0f / 9.0f, kW5 = 1.0f / 36.0f;
+
+__device__ __forceinline__ float wk32(int k) { return k == 0 ? kW0 : (k <= 4 ? kW1 : kW5); }
+
+// Workgroup -> tile map that gives each XCD a contiguous range of tiles (the
+// hardware deals workgroups round-robin over the 8 XCDs, each with its own
+// L2), so neighbouring tiles, which share stencil members, share an L2.
+__device__ __forceinline__ int64_t xcd_tile(int64_t nblocks) {
+    const int64_t b = blockIdx.x;
+    const int64_t per = (nblocks + 7) / 8;
+    return (b & 7) * per + (b >> 3);
+}
+
+inline unsigned xcd_grid(int64_t nblocks) { return (unsigned)(((nblocks + 7) / 8) * 8); }
+
+// ------------------------------------------------------------------------
+// FP32, deviation-stored populations
+// ------------------------------------------------------------------------
+template <int MODE, bool FORCE, bool WALL, bool REC>
+__global__ __launch_bounds__(kTile) void k_step32(
+    int n, int K, int64_t nblocks, const float *__restrict__ g, float *__restrict__ go,
+    const float4 *__restrict__ W, const int32_t *__restrict__ nbr,
+    const int32_t *__restrict__ owner, const float *__restrict__ force,
+    const uint8_t *__restrict__ ntype, float rtau, float rho0, float rho_w,
+    float *__restrict__ frec) {
+    const int64_t tile = xcd_tile(nblocks);
+    if (tile >= nblocks) return;
+    const int64_t p64 = tile * kTile + threadIdx.x;
+    if (p64 >= n) return;
+    const int p = (int)p64;
+
+    float acc[8];
+#pragma unroll
+    for (int d = 0; d < 8; ++d) acc[d] = 0.0f;
+    int s[8];
+#pragma unroll
+    for (int d = 0; d < 8; ++d) s[d] = MODE == MLBM_STENCIL_OWN ? p : owner[(int64_t)d * n + p];
+
+#pragma unroll 2
+    for (int j = 0; j < K; ++j) {
+        const float4 wa = W[((int64_t)j * 2) * n + p];
+        const float4 wb = W[((int64_t)j * 2 + 1) * n + p];
+        const float w[8] = {wa.x, wa.y, wa.z, wa.w, wb.x, wb.y, wb.z, wb.w};
+        if (MODE == MLBM_STENCIL_OWN) {
+            const int q = nbr[(int64_t)j * n + p];
+#pragma unroll
+            for (int d = 0; d < 8; ++d) acc[d] += w[d] * g[(int64_t)(d + 1) * n + q];
+        } else {
+#pragma unroll
+            for (int d = 0; d < 8; ++d) {
+                const int q = nbr[(int64_t)j * n + s[d]];
+                acc[d] += w[d] * g[(int64_t)(d + 1) * n + q];
+            }
+        }
+    }
+    float f[9];
+    f[0] = g[p];
+#pragma unroll
+    for (int d = 0; d < 8; ++d) f[d + 1] = acc[d];
+
+    if (WALL && ntype[p]) {
+#pragma unroll
+        for (int k = 0; k < kQ; ++k) {
+            const float v = wk32(k) * (rho_w - rho0);
+            go[(int64_t)k * n + p] = v;
+            if (REC) frec[(int64_t)k * n + p] = v;
+        }
+        return;
+    }
+    float drho = 0.0f, jx = 0.0f, jy = 0.0f;
+#pragma unroll
+    for (int k = 0; k < kQ; ++k) {
+        drho += f[k];
+        jx += f[k] * (float)lat_ex(k);
+        jy += f[k] * (float)lat_ey(k);
+    }
+    const float rho = rho0 + drho;
+    const float ux = jx / rho, uy = jy / rho;
+    const float uu = ux * ux + uy * uy;
+    float ax = 0.0f, ay = 0.0f;
+    if (FORCE) {
+        ax = force[p];
+        ay = force[n + p];
+    }
+#pragma unroll
+    for (int k = 0; k < kQ; ++k) {
+        const float eu = (float)lat_ex(k) * ux + (float)lat_ey(k) * uy;
+        const float feq = wk32(k) * (drho + rho * (3.0f * eu + 4.5f * eu * eu - 1.5f * uu));
+        float v = f[k] - (f[k] - feq) * rtau;
+        if (FORCE) v += 3.0f * wk32(k) * ((float)lat_ex(k) * ax + (float)lat_ey(k) * ay);
+        go[(int64_t)k * n + p] = v;
+        if (REC) frec[(int64_t)k * n + p] = f[k];
+    }
+}
+
+// ------------------------------------------------------------------------
+// FP64, plain populations
+// ------------------------------------------------------------------------
+template <int MODE, bool FORCE, bool WALL, bool REC>
+__global__ __launch_bounds__(kTile) void k_step64(
+    int n, int K, int64_t nblocks, const double *__restrict__ g, double *__restrict__ go,
+    const double *__restrict__ W, const int32_t *__restrict__ nbr,
+    const int32_t *__restrict__ owner, const double *__restrict__ force,
+    const uint8_t *__restrict__ ntype, double rtau, double rho_w, double *__restrict__ frec) {
+    const int64_t tile = xcd_tile(nblocks);
+    if (tile >= nblocks) return;
+    const int64_t p64 = tile * kTile + threadIdx.x;
+    if (p64 >= n) return;
+    const int p = (int)p64;
+
+    double acc[8];
+#pragma unroll
+    for (int d = 0; d < 8; ++d) acc[d] = 0.0;
+    int s[8];
+#pragma unroll
+    for (int d = 0; d < 8; ++d) s[d] = MODE == MLBM_STENCIL_OWN ? p : owner[(int64_t)d * n + p];
+    for (int j = 0; j < K; ++j) {
+        int qo = 0;
+        if (MODE == MLBM_STENCIL_OWN) qo = nbr[(int64_t)j * n + p];
+#pragma unroll
+        for (int d = 0; d < 8; ++d) {
+            const double w = W[((int64_t)d * K + j) * n + p];
+            const int q = MODE == MLBM_STENCIL_OWN ? qo : nbr[(int64_t)j * n + s[d]];
+            acc[d] += w * g[(int64_t)(d + 1) * n + q];
+        }
+    }
+    double f[9];
+    f[0] = g[p];
+#pragma unroll
+    for (int d = 0; d < 8; ++d) f[d + 1] = acc[d];
+    if (WALL && ntype[p]) {
+#pragma unroll
+        for (int k = 0; k < kQ; ++k) {
+            const double v = lat_w(k) * rho_w;
+            go[(int64_t)k * n + p] = v;
+            if (REC) frec[(int64_t)k * n + p] = v;
+        }
+        return;
+    }
+    double rho = 0.0, jx = 0.0, jy = 0.0;
+#pragma unroll
+    for (int k = 0; k < kQ; ++k) {
+        rho += f[k];
+        jx += f[k] * lat_ex(k);
+        jy += f[k] * lat_ey(k);
+    }
+    const double ux = jx / rho, uy = jy / rho;
+    const double uu = ux * ux + uy * uy;
+    double ax = 0.0, ay = 0.0;
+    if (FORCE) {
+        ax = force[p];
+        ay = force[n + p];
+    }
+#pragma unroll
+    for (int k = 0; k < kQ; ++k) {
+        const double eu = lat_ex(k) * ux + lat_ey(k) * uy;
+        const double feq = lat_w(k) * rho * (1.0 + 3.0 * eu + 4.5 * eu * eu - 1.5 * uu);
+        double v = f[k] - (f[k] - feq) * rtau;
+        if (FORCE) v += 3.0 * lat_w(k) * (lat_ex(k) * ax + lat_ey(k) * ay);
+        go[(int64_t)k * n + p] = v;
+        if (REC) frec[(int64_t)k * n + p] = f[k];
+    }
+}
+
+// ------------------------------------------------------------------------
+// Initial state, moments, L2 sums
+// ------------------------------------------------------------------------
+template <class T>
+__global__ void k_init(int n, const int32_t *__restrict__ perm, const double *__restrict__ rho,
+                       const double *__restrict__ ux, const double *__restrict__ uy,
+                       const uint8_t *__restrict__ ntype, const double *__restrict__ force,
+                       double rho0, double rho_w, int wall, int dev, int collide,
+                       T *__restrict__ g) {
+    int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= n) return;
+    const int u = perm[p];
+    double r = rho ? rho[u] : rho0;
+    double vx = ux ? ux[u] : 0.0, vy = uy ? uy[u] : 0.0;
+    const bool is_wall = wall && ntype && ntype[p];
+    if (is_wall) {
+        r = rho_w;
+        vx = vy = 0.0;
+    }
+    const double uu = vx * vx + vy * vy;
+    for (int k = 0; k < kQ; ++k) {
+        const double eu = lat_ex(k) * vx + lat_ey(k) * vy;
+        // feq - w rho0 = w [(rho - rho0) + rho (3 eu + 4.5 eu^2 - 1.5 u^2)]
+        double v = dev ? lat_w(k) * ((r - rho0) + r * (3.0 * eu + 4.5 * eu * eu - 1.5 * uu))
+                       : lat_w(k) * r * (1.0 + 3.0 * eu + 4.5 * eu * eu - 1.5 * uu);
+        if (collide && force && !is_wall)
+            v += 3.0 * lat_w(k) * (lat_ex(k) * force[p] + lat_ey(k) * force[n + p]);
+        g[(int64_t)k * n + p] = (T)v;
+    }
+}
+
+template <class T>
+__global__ void k_moments(int n, const int32_t *__restrict__ perm, const T *__restrict__ g,
+                          const float *__restrict__ f32, const double *__restrict__ f64,
+                          const uint8_t *__restrict__ ntype, double rho0, int dev,
+                          double *__restrict__ rho, double *__restrict__ ux,
+                          double *__restrict__ uy) {
+    int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= n) return;
+    double r = 0.0, jx = 0.0, jy = 0.0;
+    for (int k = 0; k < kQ; ++k) {
+        const double v = (double)g[(int64_t)k * n + p];
+        r += v;
+        jx += v * lat_ex(k);
+        jy += v * lat_ey(k);
+    }
+    if (dev) r += rho0;
+    if (!(ntype && ntype[p])) {   // the force term added momentum a at fluid nodes
+        if (f32) {
+            jx -= (double)f32[p];
+            jy -= (double)f32[n + p];
+        } else if (f64) {
+            jx -= f64[p];
+            jy -= f64[n + p];
+        }
+    }
+    const int u = perm[p];
+    if (rho) rho[u] = r;
+    if (ux) ux[u] = jx / r;
+    if (uy) uy[u] = jy / r;
+}
+
+// Per-block partial sums, then a single workgroup adds the partials in a fixed
+// order (deterministic, no floating-point atomics).
+template <class T>
+__global__ __launch_bounds__(256) void k_l2_partial(
+    int n, const int32_t *__restrict__ perm, const T *__restrict__ g,
+    const float *__restrict__ f32, const double *__restrict__ f64,
+    const uint8_t *__restrict__ ntype, double rho0, int dev, const double *__restrict__ uxt,
+    const double *__restrict__ uyt, double *__restrict__ part) {
+    __shared__ double sh[4][256];
+    int p = blockIdx.x * blockDim.x + threadIdx.x;
+    double a0 = 0, a1 = 0, a2 = 0, a3 = 0;
+    if (p < n) {
+        double r = 0.0, jx = 0.0, jy = 0.0;
+        for (int k = 0; k < kQ; ++k) {
+            const double v = (double)g[(int64_t)k * n + p];
+            r += v;
+            jx += v * lat_ex(k);
+            jy += v * lat_ey(k);
+        }
+        if (dev) r += rho0;
+        if (!(ntype && ntype[p])) {
+            if (f32) {
+                jx -= (double)f32[p];
+                jy -= (double)f32[n + p];
+            } else if (f64) {
+                jx -= f64[p];
+                jy -= f64[n + p];
+            }
+        }
+        const int u = perm[p];
+        const double ex = jx / r - uxt[u], ey = jy / r - uyt[u];
+        a0 = ex * ex + ey * ey;
+        a1 = uxt[u] * uxt[u] + uyt[u] * uyt[u];
+        a2 = ex * ex;
+        a3 = uxt[u] * uxt[u];
+    }
+    sh[0][threadIdx.x] = a0;
+    sh[1][threadIdx.x] = a1;
+    sh[2][threadIdx.x] = a2;
+    sh[3][threadIdx.x] = a3;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w)
+            for (int c = 0; c < 4; ++c) sh[c][threadIdx.x] += sh[c][threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x < 4) part[(int64_t)blockIdx.x * 4 + threadIdx.x] = sh[threadIdx.x][0];
+}
+
+__global__ __launch_bounds__(256) void k_l2_final(int64_t nparts, const double *__restrict__ part,
+                                                  double *__restrict__ out) {
+    __shared__ double sh[4][256];
+    double a[4] = {0, 0, 0, 0};
+    for (int64_t b = threadIdx.x; b < nparts; b += 256)
+        for (int c = 0; c < 4; ++c) a[c] += part[b * 4 + c];
+    for (int c = 0; c < 4; ++c) sh[c][threadIdx.x] = a[c];
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w)
+            for (int c = 0; c < 4; ++c) sh[c][threadIdx.x] += sh[c][threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x < 4) out[threadIdx.x] = sh[threadIdx.x][0];
+}
+
+// Collision only (g = C(f)), same arithmetic as the fused step after its
+// streaming part.
+template <class T>
+__global__ void k_collide(int n, const T *__restrict__ f, T *__restrict__ g,
+                          const double *__restrict__ force, const uint8_t *__restrict__ ntype,
+                          int wall, double rtau, double rho0, double rho_w, int dev) {
+    int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= n) return;
+    if (wall && ntype && ntype[p]) {
+        for (int k = 0; k < kQ; ++k)
+            g[(int64_t)k * n + p] = (T)(dev ? lat_w(k) * (rho_w - rho0) : lat_w(k) * rho_w);
+        return;
+    }
+    T fk[kQ];
+    T drho = 0, jx = 0, jy = 0;
+    for (int k = 0; k < kQ; ++k) {
+        fk[k] = f[(int64_t)k * n + p];
+        drho += fk[k];
+        jx += fk[k] * (T)lat_ex(k);
+        jy += fk[k] * (T)lat_ey(k);
+    }
+    const T rho = dev ? (T)rho0 + drho : drho;
+    const T ux = jx / rho, uy = jy / rho, uu = ux * ux + uy * uy;
+    for (int k = 0; k < kQ; ++k) {
+        const T eu = (T)lat_ex(k) * ux + (T)lat_ey(k) * uy;
+        const T w = (T)lat_w(k);
+        const T poly = (T)3 * eu + (T)4.5 * eu * eu - (T)1.5 * uu;
+        const T feq = dev ? w * (drho + rho * poly) : w * rho * ((T)1 + poly);
+        T v = fk[k] - (fk[k] - feq) * (T)rtau;
+        if (force)
+            v += (T)(3.0 * lat_w(k) * (lat_ex(k) * force[p] + lat_ey(k) * force[n + p]));
+        g[(int64_t)k * n + p] = v;
+    }
+}
+
+template <int MODE, bool FORCE, bool WALL, bool REC>
+hipError_t step_variant(const CloudPlan &cp, int precision, const void *gin, void *gout,
+                        void *frec, hipStream_t s) {
+    const int n = cp.n;
+    const int64_t nblocks = (n + kTile - 1) / kTile;
+    dim3 grid(xcd_grid(nblocks)), block(kTile);
+    if (precision == MLBM_FP64) {
+        hipLaunchKernelGGL((k_step64<MODE, FORCE, WALL, REC>), grid, block, 0, s, n, cp.K,
+                           nblocks, (const double *)gin, (double *)gout, cp.W64, cp.nbr,
+                           cp.owner, cp.force64, cp.ntype, 1.0 / cp.prm.tau, cp.prm.rho_wall,
+                           (double *)frec);
+    } else {
+        hipLaunchKernelGGL((k_step32<MODE, FORCE, WALL, REC>), grid, block, 0, s, n, cp.K,
+                           nblocks, (const float *)gin, (float *)gout,
+                           (const float4 *)cp.W32, cp.nbr, cp.owner, cp.force32, cp.ntype,
+                           (float)(1.0 / cp.prm.tau), (float)cp.prm.rho0,
+                           (float)cp.prm.rho_wall, (float *)frec);
+    }
+    return hipGetLastError();
+}
+
+template <int MODE, bool FORCE, bool WALL>
+hipError_t step_rec(const CloudPlan &cp, int precision, const void *gin, void *gout,
+                    void *frec, hipStream_t s) {
+    return frec ? step_variant<MODE, FORCE, WALL, true>(cp, precision, gin, gout, frec, s)
+                : step_variant<MODE, FORCE, WALL, false>(cp, precision, gin, gout, frec, s);
+}
+
+template <int MODE, bool FORCE>
+hipError_t step_wall(const CloudPlan &cp, int precision, const void *gin, void *gout,
+                     void *frec, hipStream_t s) {
+    return cp.has_walls ? step_rec<MODE, FORCE, true>(cp, precision, gin, gout, frec, s)
+                        : step_rec<MODE, FORCE, false>(cp, precision, gin, gout, frec, s);
+}
+
+template <int MODE>
+hipError_t step_force(const CloudPlan &cp, int precision, const void *gin, void *gout,
+                      void *frec, hipStream_t s) {
+    return cp.prm.force_kind ? step_wall<MODE, true>(cp, precision, gin, gout, frec, s)
+                             : step_wall<MODE, false>(cp, precision, gin, gout, frec, s);
+}
+
+}  // namespace
+
+hipError_t launch_step(const CloudPlan &cp, int precision, const void *gin, void *gout,
+                       void *frec, hipStream_t s) {
+    return cp.prm.stencil_mode == MLBM_STENCIL_OWN
+               ? step_force<MLBM_STENCIL_OWN>(cp, precision, gin, gout, frec, s)
+               : step_force<MLBM_STENCIL_PAPER>(cp, precision, gin, gout, frec, s);
+}
+
+hipError_t launch_init(const CloudPlan &cp, int precision, const double *rho,
+                       const double *ux, const double *uy, void *g, bool collide,
+                       hipStream_t s) {
+    const int n = cp.n;
+    const int wall = cp.has_walls ? 1 : 0;
+    if (precision == MLBM_FP64)
+        hipLaunchKernelGGL(k_init<double>, dim3(blocks_for(n, 256)), dim3(256), 0, s, n,
+                           cp.perm, rho, ux, uy, cp.ntype, cp.force64, cp.prm.rho0,
+                           cp.prm.rho_wall, wall, 0, collide ? 1 : 0, (double *)g);
+    else
+        hipLaunchKernelGGL(k_init<float>, dim3(blocks_for(n, 256)), dim3(256), 0, s, n,
+                           cp.perm, rho, ux, uy, cp.ntype, cp.force64, cp.prm.rho0,
+                           cp.prm.rho_wall, wall, 1, collide ? 1 : 0, (float *)g);
+    return hipGetLastError();
+}
+
+hipError_t launch_moments(const CloudPlan &cp, int precision, const void *g, double *rho,
+                          double *ux, double *uy, bool post_collision, hipStream_t s) {
+    const int n = cp.n;
+    const float *f32 = post_collision && precision != MLBM_FP64 ? cp.force32 : nullptr;
+    const double *f64 = post_collision && precision == MLBM_FP64 ? cp.force64 : nullptr;
+    if (precision == MLBM_FP64)
+        hipLaunchKernelGGL(k_moments<double>, dim3(blocks_for(n, 256)), dim3(256), 0, s, n,
+                           cp.perm, (const double *)g, f32, f64, cp.ntype, cp.prm.rho0, 0, rho,
+                           ux, uy);
+    else
+        hipLaunchKernelGGL(k_moments<float>, dim3(blocks_for(n, 256)), dim3(256), 0, s, n,
+                           cp.perm, (const float *)g, f32, f64, cp.ntype, cp.prm.rho0, 1, rho,
+                           ux, uy);
+    return hipGetLastError();
+}
+
+hipError_t launch_l2(const CloudPlan &cp, int precision, const void *g, const double *uxt,
+                     const double *uyt, double *out, double *part, hipStream_t s) {
+    const int n = cp.n;
+    const int64_t nb = blocks_for(n, 256);
+    const float *f32 = precision != MLBM_FP64 ? cp.force32 : nullptr;
+    const double *f64 = precision == MLBM_FP64 ? cp.force64 : nullptr;
+    if (precision == MLBM_FP64)
+        hipLaunchKernelGGL(k_l2_partial<double>, dim3(nb), dim3(256), 0, s, n, cp.perm,
+                           (const double *)g, f32, f64, cp.ntype, cp.prm.rho0, 0, uxt, uyt, part);
+    else
+        hipLaunchKernelGGL(k_l2_partial<float>, dim3(nb), dim3(256), 0, s, n, cp.perm,
+                           (const float *)g, f32, f64, cp.ntype, cp.prm.rho0, 1, uxt, uyt, part);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_l2_final, dim3(1), dim3(256), 0, s, nb, (const double *)part, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_collide(const CloudPlan &cp, int precision, const void *f, void *g,
+                          hipStream_t s) {
+    const int n = cp.n;
+    const int wall = cp.has_walls ? 1 : 0;
+    const double *force = cp.prm.force_kind ? cp.force64 : nullptr;
+    if (precision == MLBM_FP64)
+        hipLaunchKernelGGL(k_collide<double>, dim3(blocks_for(n, 256)), dim3(256), 0, s, n,
+                           (const double *)f, (double *)g, force, cp.ntype, wall,
+                           1.0 / cp.prm.tau, cp.prm.rho0, cp.prm.rho_wall, 0);
+    else
+        hipLaunchKernelGGL(k_collide<float>, dim3(blocks_for(n, 256)), dim3(256), 0, s, n,
+                           (const float *)f, (float *)g, force, cp.ntype, wall,
+                           1.0 / cp.prm.tau, cp.prm.rho0, cp.prm.rho_wall, 1);
+    return hipGetLastError();
+}
+
+}  // namespace mlbm

@@ -1,0 +1,255 @@
+"""Thin Python binding of the MLBM C-ABI on top of PyTorch device memory.
+
+Every computation runs in the HIP library; this module only allocates torch
+buffers of the queried sizes, passes their addresses and the current stream,
+and converts status codes into exceptions.
+"""
+from __future__ import annotations
+
+import ctypes
+from dataclasses import dataclass
+
+import torch
+
+from . import _lib
+from ._lib import MLBM_FP32_DEV, MLBM_FP64, MLBM_STENCIL_OWN, MLBM_STENCIL_PAPER  # noqa: F401
+from ._lib import MLBMError, check
+
+
+def _ptr(t):
+    """Address of a tensor. The caller must hold a reference to `t` until the
+    enqueued work has consumed it (a temporary freed here would be handed to
+    the next allocation on the same stream)."""
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream=None):
+    s = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _order(stream, *tensors):
+    """Inputs staged on torch's current stream are consumed on `stream`: make
+    `stream` wait for their copies and keep their memory until it is done."""
+    if stream is None:
+        return
+    cur = torch.cuda.current_stream()
+    if stream != cur:
+        stream.wait_stream(cur)
+        for t in tensors:
+            if t is not None:
+                t.record_stream(stream)
+
+
+def _f64(t, device):
+    if t is None:
+        return None
+    t = torch.as_tensor(t, dtype=torch.float64, device=device)
+    return t.contiguous()
+
+
+@dataclass
+class Params:
+    dx: float
+    K: int
+    degree: int
+    tau: float
+    stencil_mode: int = MLBM_STENCIL_PAPER
+    precision: int = MLBM_FP32_DEV
+    rho0: float = 1.0
+    force_kind: int = 0
+    force_mag: float = 0.0
+    wall_kind: int = 0
+    rho_wall: float = 1.0
+    with_adjoint: int = 0
+
+    def to_c(self) -> _lib.Params:
+        return _lib.Params(self.dx, self.K, self.degree, self.stencil_mode, self.precision,
+                           self.tau, self.rho0, self.force_kind, self.force_mag,
+                           self.wall_kind, self.rho_wall, self.with_adjoint)
+
+
+class Plan:
+    """A built MLBM plan: stencils, owners and shape vectors of one cloud."""
+
+    def __init__(self, handle, plan_buf, params: Params, n: int, device):
+        self._h = handle
+        self._buf = plan_buf          # keeps the caller-owned plan memory alive
+        self.params = params
+        self.n = n
+        self.device = device
+        info = _lib.PlanInfo()
+        check(_lib.load().mlbm_plan_get_info(self._h, ctypes.byref(info)))
+        self.info = info
+        self.state_dtype = torch.float64 if params.precision == MLBM_FP64 else torch.float32
+
+    # ---- construction ----------------------------------------------------
+    @classmethod
+    def build(cls, x, y, period, params: Params, node_type=None, device="cuda",
+              stream=None):
+        L = _lib.load()
+        x = _f64(x, device)
+        y = _f64(y, device)
+        nt = None
+        if node_type is not None:
+            nt = torch.as_tensor(node_type, dtype=torch.uint8, device=device).contiguous()
+        n = int(x.shape[0])
+        _order(stream, x, y, nt)
+        cloud = _lib.Cloud(n, x.data_ptr(), y.data_ptr(), nt.data_ptr() if nt is not None else None,
+                           float(period[0]), float(period[1]))
+        cp = params.to_c()
+        pb, wb = ctypes.c_size_t(), ctypes.c_size_t()
+        check(L.mlbm_weights_query(ctypes.byref(cloud), ctypes.byref(cp), 1, ctypes.byref(pb),
+                                   ctypes.byref(wb)))
+        plan_buf = torch.empty(pb.value, dtype=torch.uint8, device=device)
+        ws = torch.empty(wb.value, dtype=torch.uint8, device=device)
+        h = ctypes.c_void_p()
+        check(L.mlbm_build_weights(ctypes.byref(cloud), ctypes.byref(cp), 1, _ptr(plan_buf),
+                                   pb.value, _ptr(ws), wb.value, ctypes.byref(h),
+                                   _stream(stream)))
+        torch.cuda.current_stream().synchronize() if stream is None else stream.synchronize()
+        del ws
+        return cls(h, plan_buf, params, n, device)
+
+    @classmethod
+    def from_arrays(cls, x, y, nbr, owner, W, params: Params, node_type=None, device="cuda"):
+        """Plan from host arrays (test hook): nbr [n][K], owner [n][9] (user
+        indices), W [n][9][K] FP64; no reordering."""
+        import numpy as np
+        L = _lib.load()
+        x = np.ascontiguousarray(x, dtype=np.float64)
+        y = np.ascontiguousarray(y, dtype=np.float64)
+        nbr = np.ascontiguousarray(nbr, dtype=np.int32)
+        owner = np.ascontiguousarray(owner, dtype=np.int32)
+        W = np.ascontiguousarray(W, dtype=np.float64)
+        n = x.shape[0]
+        nt = None if node_type is None else np.ascontiguousarray(node_type, dtype=np.uint8)
+        cp = params.to_c()
+        pb = ctypes.c_size_t()
+        check(L.mlbm_import_query(n, ctypes.byref(cp), ctypes.byref(pb)))
+        plan_buf = torch.empty(pb.value, dtype=torch.uint8, device=device)
+        h = ctypes.c_void_p()
+        a = lambda arr: None if arr is None else arr.ctypes.data_as(ctypes.c_void_p)
+        check(L.mlbm_import_weights(n, a(x), a(y), a(nt), a(nbr), a(owner), a(W),
+                                    ctypes.byref(cp), _ptr(plan_buf), pb.value,
+                                    ctypes.byref(h), _stream()))
+        return cls(h, plan_buf, params, n, device)
+
+    def close(self):
+        if self._h:
+            _lib.load().mlbm_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ---- state ---------------------------------------------------------------
+    def new_state(self):
+        return torch.empty((9, self.n), dtype=self.state_dtype, device=self.device)
+
+    def init(self, ux=None, uy=None, rho=None, g=None, stream=None):
+        g = self.new_state() if g is None else g
+        rho, ux, uy = (_f64(a, self.device) for a in (rho, ux, uy))
+        _order(stream, rho, ux, uy)
+        check(_lib.load().mlbm_init(self._h, _ptr(rho), _ptr(ux), _ptr(uy), _ptr(g),
+                                    _stream(stream)))
+        return g
+
+    def init_f(self, ux=None, uy=None, rho=None, f=None, stream=None):
+        f = self.new_state() if f is None else f
+        rho, ux, uy = (_f64(a, self.device) for a in (rho, ux, uy))
+        _order(stream, rho, ux, uy)
+        check(_lib.load().mlbm_init_f(self._h, _ptr(rho), _ptr(ux), _ptr(uy), _ptr(f),
+                                      _stream(stream)))
+        return f
+
+    def collide(self, f, g=None, stream=None):
+        g = self.new_state() if g is None else g
+        check(_lib.load().mlbm_collide(self._h, _ptr(f), _ptr(g), _stream(stream)))
+        return g
+
+    def step(self, g_a, g_b, n_steps: int, stream=None):
+        """Advance n_steps; returns the buffer that holds the result."""
+        rb = ctypes.c_int32()
+        check(_lib.load().mlbm_step(self._h, _ptr(g_a), _ptr(g_b), int(n_steps),
+                                    ctypes.byref(rb), _stream(stream)))
+        return g_b if rb.value else g_a
+
+    def step_record(self, g_a, g_b, n_steps: int, f_rec, stream=None):
+        rb = ctypes.c_int32()
+        check(_lib.load().mlbm_step_record(self._h, _ptr(g_a), _ptr(g_b), int(n_steps),
+                                           _ptr(f_rec), ctypes.byref(rb), _stream(stream)))
+        return g_b if rb.value else g_a
+
+    def moments(self, g, stream=None):
+        rho = torch.empty(self.n, dtype=torch.float64, device=self.device)
+        ux = torch.empty_like(rho)
+        uy = torch.empty_like(rho)
+        check(_lib.load().mlbm_moments(self._h, _ptr(g), _ptr(rho), _ptr(ux), _ptr(uy),
+                                       _stream(stream)))
+        return rho, ux, uy
+
+    def l2_sums(self, g, ux_t, uy_t, stream=None):
+        out = torch.empty(4, dtype=torch.float64, device=self.device)
+        ux_t, uy_t = _f64(ux_t, self.device), _f64(uy_t, self.device)
+        _order(stream, ux_t, uy_t)
+        check(_lib.load().mlbm_l2_sums(self._h, _ptr(g), _ptr(ux_t), _ptr(uy_t), _ptr(out),
+                                       _stream(stream)))
+        return out
+
+    def l2(self, g, ux_t, uy_t):
+        """(L2 of the u-component, L2 of the velocity vector), eq. L2norm."""
+        s = self.l2_sums(g, ux_t, uy_t).cpu().tolist()
+        return (s[2] / s[3]) ** 0.5, (s[0] / s[1]) ** 0.5
+
+    # ---- adjoint ---------------------------------------------------------------
+    def loss_seed(self, f_T, ux_t, uy_t, stream=None):
+        lam = self.new_state()
+        J = torch.empty(1, dtype=torch.float64, device=self.device)
+        ux_t, uy_t = _f64(ux_t, self.device), _f64(uy_t, self.device)
+        _order(stream, ux_t, uy_t)
+        check(_lib.load().mlbm_loss_seed(self._h, _ptr(f_T), _ptr(ux_t), _ptr(uy_t), _ptr(lam),
+                                         _ptr(J), _stream(stream)))
+        return lam, J
+
+    def step_adjoint(self, f_n, lam_next, lam_n, dtau, stream=None):
+        check(_lib.load().mlbm_step_adjoint(self._h, _ptr(f_n), _ptr(lam_next), _ptr(lam_n),
+                                            _ptr(dtau), _stream(stream)))
+        return lam_n
+
+    def init_adjoint(self, u0x, u0y, lam0, stream=None):
+        gx = torch.empty(self.n, dtype=torch.float64, device=self.device)
+        gy = torch.empty_like(gx)
+        u0x, u0y = _f64(u0x, self.device), _f64(u0y, self.device)
+        _order(stream, u0x, u0y)
+        check(_lib.load().mlbm_init_adjoint(self._h, _ptr(u0x), _ptr(u0y), _ptr(lam0),
+                                            _ptr(gx), _ptr(gy), _stream(stream)))
+        return gx, gy
+
+    # ---- graphs ----------------------------------------------------------------
+    def graph_create(self, g_a, g_b, n_steps: int, stream):
+        check(_lib.load().mlbm_graph_create(self._h, _ptr(g_a), _ptr(g_b), int(n_steps),
+                                            _stream(stream)))
+
+    def graph_launch(self, stream):
+        check(_lib.load().mlbm_graph_launch(self._h, _stream(stream)))
+
+    # ---- inspection --------------------------------------------------------------
+    def export(self, what: str):
+        """Internal arrays in user order: 'perm', 'nbr' [n][K], 'owner' [n][9],
+        'W' [n][9][K] (FP64)."""
+        import numpy as np
+        code = {"perm": 0, "nbr": 1, "owner": 2, "W": 3}[what]
+        K = self.params.K
+        shape, dt = {0: ((self.n,), np.int32), 1: ((self.n, K), np.int32),
+                     2: ((self.n, 9), np.int32), 3: ((self.n, 9, K), np.float64)}[code]
+        out = np.empty(shape, dtype=dt)
+        check(_lib.load().mlbm_plan_export(self._h, 0, code, out.ctypes.data_as(ctypes.c_void_p),
+                                           out.nbytes))
+        return out
+
+    def device_error(self) -> int:
+        return int(_lib.load().mlbm_device_error(self._h))

@@ -1,0 +1,73 @@
+"""Shared setup of the GPU parity tests: seeded clouds, oracle references and
+tolerances. Importing this module does not touch the GPU."""
+from __future__ import annotations
+
+import math
+import sys
+
+import numpy as np
+
+import oracle
+from synth import annulus_poisson, jittered_lattice, tgv_initial_velocity
+
+EPS32 = 2.0 ** -24
+
+# FP64 GPU path vs FP64 oracle: both evaluate the same formulas in double
+# precision; they differ in summation order and in the local solver (pivoted
+# elimination with implicit row order vs explicit row swaps). Per step the
+# relative difference of the populations is a few ulps times the Lebesgue
+# constant of the stencil (sum |w| <= ~5), so after n steps it stays below
+# n * 1e-14 with a margin; 1e-11 covers the 200-step runs here.
+TOL_FP64 = 1e-11
+# Shape vectors: the local systems have condition numbers up to ~1e7 after
+# scaling, so the FP64 solutions agree to about 1e-16 * cond.
+TOL_W = 1e-9
+
+
+def tol_fp32(steps: int) -> float:
+    """Relative L2 bound on the velocity of the FP32 deviation path against
+    the FP64 oracle. Each step adds rounding of the stored deviations and of
+    the FP32 weights, at most ~8 ulps of FP32 relative to the velocity scale
+    (sum |w| <= 5 times a few operations); errors add linearly in the worst
+    case: 8 * 2^-24 * steps, plus a floor of 64 ulps for the initial
+    rounding."""
+    return 8.0 * EPS32 * steps + 64 * EPS32
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def tgv_case(n_side, K, m, mode, seed=1, u0=0.01, length=2 * math.pi, jitter=0.3,
+             ny=None, length_y=None):
+    c = jittered_lattice(n_side, length=length, seed=seed, jitter=jitter, ny=ny,
+                         length_y=length_y)
+    ux, uy = tgv_initial_velocity(c.x, c.y, c.period[0], u0)
+    return c, ux, uy
+
+
+def oracle_run(c, dx, K, m, mode, tau, ux, uy, steps_list, force=0.0, rho_w=1.0):
+    """Oracle plan and velocities after each step count in steps_list."""
+    nbr, own, W = oracle.build_plan(c, dx, K, m, mode)
+    f = oracle.equilibrium(np.ones(c.n), ux, uy)
+    ax = ay = None
+    if force:
+        ax, ay = oracle.azimuthal_force(c.x, c.y, force, c.node_type)
+    out = {}
+    done = 0
+    for s in sorted(steps_list):
+        f = oracle.run(f, nbr, own, W, tau, s - done, ax, ay, c.node_type, rho_w)
+        done = s
+        out[s] = oracle.moments(f)
+    return (nbr, own, W), out
+
+
+def rel_l2(a, b):
+    a = np.asarray(a)
+    b = np.asarray(b)
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def annulus_case(h=0.1, seed=3):
+    return annulus_poisson(1.0, 2.0, h, seed=seed)

@@ -1,0 +1,74 @@
+"""GPU weight build (stencils, owners, shape vectors) against the oracle."""
+import numpy as np
+import pytest
+
+import oracle
+from gpu_common import TOL_W, annulus_case, say, tgv_case
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _build(c, dx, K, m, mode, precision=0):
+    from paper_2306_01525_amd import Params, Plan
+    p = Params(dx=dx, K=K, degree=m, tau=0.8, stencil_mode=mode, precision=precision)
+    return Plan.build(c.x, c.y, c.period, p, node_type=c.node_type)
+
+
+CASES = [
+    # (label, cloud factory, dx factor, K, m, mode)
+    ("tgv40-K12-m2-own", lambda: tgv_case(40, 12, 2, 1)[0], 1.0, 12, 2, 1),
+    ("tgv40-K25-m2-paper", lambda: tgv_case(40, 25, 2, 0)[0], 1.0, 25, 2, 0),
+    ("tgv37x41-K30-m4-paper", lambda: tgv_case(37, 30, 4, 0, ny=41, length_y=7.0)[0], 1.0, 30, 4, 0),
+    ("tgv23-K20-m3-own", lambda: tgv_case(23, 20, 3, 1, seed=7)[0], 0.7, 20, 3, 1),
+    ("annulus-h0.1-K15-m2-paper", lambda: annulus_case(0.1), None, 15, 2, 0),
+    ("lattice16-K12-m2-paper", lambda: tgv_case(16, 12, 2, 0, jitter=0.0, length=16.0)[0], 1.0, 12, 2, 0),
+]
+
+
+@pytest.mark.parametrize("label,make,dxf,K,m,mode", CASES, ids=[c[0] for c in CASES])
+def test_build_matches_oracle(label, make, dxf, K, m, mode):
+    c = make()
+    dx = 0.1 if dxf is None else dxf * c.h
+    say("case", label, "n", c.n)
+    plan = _build(c, dx, K, m, mode)
+    nbr_g = plan.export("nbr")
+    own_g = plan.export("owner")
+    W_g = plan.export("W")
+    perm = plan.export("perm")
+    assert sorted(perm.tolist()) == list(range(c.n))
+    nbr_o = oracle.knn(c.x, c.y, c.period, K)
+    own_o = oracle.owners(c.x, c.y, c.period, dx, mode)
+    np.testing.assert_array_equal(nbr_g, nbr_o)
+    np.testing.assert_array_equal(own_g, own_o)
+    W_o = oracle.weights(c.x, c.y, c.period, dx, K, m, nbr_o, own_o)
+    err = np.abs(W_g[:, 1:, :] - W_o[:, 1:, :]).max()
+    say("  max |W_gpu - W_oracle| =", err)
+    assert err < TOL_W
+    # k = 0 is the identity on both sides
+    np.testing.assert_allclose(W_o[:, 0, 0], 1.0, atol=1e-10)
+    plan.close()
+
+
+def test_build_rejects_bad_parameters():
+    from paper_2306_01525_amd import MLBMError, Params, Plan
+    c, _, _ = tgv_case(10, 12, 2, 0)
+    for kw in (dict(K=5, degree=2), dict(K=12, degree=1), dict(K=8, degree=3),
+               dict(K=12, degree=2, tau=0.5)):
+        p = Params(dx=c.h, tau=kw.pop("tau", 0.8), **kw)
+        with pytest.raises(MLBMError):
+            Plan.build(c.x, c.y, c.period, p)
+
+
+def test_singular_stencil_is_reported():
+    """Nodes on a straight line make every local system singular
+    (the quadratic monomials are not unisolvent)."""
+    from paper_2306_01525_amd import MLBMError, Params, Plan
+    n = 40
+    x = np.linspace(0.0, 1.0, n)
+    y = 2.0 * x + 0.5
+    p = Params(dx=0.01, K=12, degree=2, tau=0.8, stencil_mode=1)
+    with pytest.raises(MLBMError) as ei:
+        Plan.build(x, y, (0.0, 0.0), p)
+    assert ei.value.status == -2

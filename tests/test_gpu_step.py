@@ -1,0 +1,142 @@
+"""GPU time stepping against the oracle: on imported oracle weights (isolates
+the step kernel) and end to end (GPU build + GPU steps)."""
+import numpy as np
+import pytest
+
+import oracle
+from gpu_common import (TOL_FP64, annulus_case, oracle_run, rel_l2, say, tgv_case,
+                        tol_fp32)
+from synth import tgv_initial_velocity
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _params(dx, K, m, mode, precision, tau, **kw):
+    from paper_2306_01525_amd import Params
+    return Params(dx=dx, K=K, degree=m, tau=tau, stencil_mode=mode, precision=precision, **kw)
+
+
+def _gpu_run(plan, ux, uy, steps_list, rho=None):
+    g = plan.init(ux, uy, rho=rho)
+    other = plan.new_state()
+    out = {}
+    done = 0
+    for s in sorted(steps_list):
+        res = plan.step(g, other, s - done)
+        if res is other:
+            g, other = other, g
+        done = s
+        rho_g, ux_g, uy_g = plan.moments(g)
+        out[s] = (rho_g.cpu().numpy(), ux_g.cpu().numpy(), uy_g.cpu().numpy())
+    return out
+
+
+def _compare(ref, got, tol, label):
+    for s in sorted(ref):
+        r_o, u_o, v_o = ref[s]
+        r_g, u_g, v_g = got[s]
+        eu = rel_l2(np.stack([u_g, v_g]), np.stack([u_o, v_o]))
+        er = float(np.abs(r_g - r_o).max())
+        say("  %s step %d: rel L2 velocity %.3e, max |drho| %.3e (tol %.1e)" % (label, s, eu, er, tol(s)))
+        assert eu < tol(s), (label, s, eu)
+        assert er < tol(s), (label, s, er)
+
+
+STEP_CASES = [
+    ("c1-own", 40, 12, 2, 1, 0.8),
+    ("paper-K25-m2", 40, 25, 2, 0, 0.8),
+    ("paper-K30-m4-tau0.6", 33, 30, 4, 0, 0.6),
+    ("own-K20-m3", 29, 20, 3, 1, 0.7),
+]
+
+
+@pytest.mark.parametrize("label,nside,K,m,mode,tau", STEP_CASES, ids=[c[0] for c in STEP_CASES])
+def test_step_on_imported_weights(label, nside, K, m, mode, tau):
+    """Oracle stencils and weights imported into the GPU plan: the step kernel
+    alone is compared with the oracle after 1, 10 and 200 steps."""
+    from paper_2306_01525_amd import Plan
+    c, ux, uy = tgv_case(nside, K, m, mode)
+    steps = [1, 10, 200]
+    (nbr, own, W), ref = oracle_run(c, c.h, K, m, mode, tau, ux, uy, steps)
+    for prec, tol in ((1, lambda s: TOL_FP64), (0, tol_fp32)):
+        say("case", label, "precision", prec, "n", c.n)
+        plan = Plan.from_arrays(c.x, c.y, nbr, own, W, _params(c.h, K, m, mode, prec, tau))
+        got = _gpu_run(plan, ux, uy, steps)
+        _compare(ref, got, tol, "%s/%s" % (label, "fp64" if prec else "fp32"))
+        plan.close()
+
+
+E2E_CASES = [
+    ("c1-own", 40, 12, 2, 1, 0.8, 200),
+    ("paper-K30-m4", 48, 30, 4, 0, 0.6, 100),
+    ("ragged-rect-paper-K20-m3", None, 20, 3, 0, 0.7, 50),
+]
+
+
+@pytest.mark.parametrize("label,nside,K,m,mode,tau,steps", E2E_CASES, ids=[c[0] for c in E2E_CASES])
+def test_end_to_end_matches_oracle(label, nside, K, m, mode, tau, steps):
+    from paper_2306_01525_amd import Plan
+    if nside is None:
+        c, ux, uy = tgv_case(31, K, m, mode, ny=23, length_y=2 * np.pi * 23 / 31)
+        ux, uy = tgv_initial_velocity(c.x, c.y, c.period[0], 0.01)
+    else:
+        c, ux, uy = tgv_case(nside, K, m, mode)
+    _, ref = oracle_run(c, c.h, K, m, mode, tau, ux, uy, [1, steps])
+    for prec, tol in ((1, lambda s: TOL_FP64), (0, tol_fp32)):
+        say("case", label, "precision", prec, "n", c.n)
+        plan = Plan.build(c.x, c.y, c.period, _params(c.h, K, m, mode, prec, tau))
+        got = _gpu_run(plan, ux, uy, [1, steps])
+        _compare(ref, got, tol, "%s/%s" % (label, "fp64" if prec else "fp32"))
+        plan.close()
+
+
+def test_annulus_walls_and_force_match_oracle():
+    """Open cloud, equilibrium walls, azimuthal body force (Sec. 3)."""
+    from paper_2306_01525_amd import Plan
+    c = annulus_case(0.1)
+    dx, K, m, tau, g = 0.1, 15, 2, 1.0, 1e-4
+    zeros = np.zeros(c.n)
+    _, ref = oracle_run(c, dx, K, m, 0, tau, zeros, zeros, [1, 20, 300], force=g)
+    for prec, tol in ((1, lambda s: TOL_FP64), (0, lambda s: 4 * tol_fp32(s))):
+        say("case annulus precision", prec, "n", c.n)
+        p = _params(dx, K, m, 0, prec, tau, force_kind=1, force_mag=g, wall_kind=1, rho_wall=1.0)
+        plan = Plan.build(c.x, c.y, c.period, p, node_type=c.node_type)
+        got = _gpu_run(plan, zeros, zeros, [1, 20, 300])
+        _compare(ref, got, tol, "annulus/%s" % ("fp64" if prec else "fp32"))
+        plan.close()
+
+
+def test_graph_replay_equals_eager():
+    from paper_2306_01525_amd import Plan
+    c, ux, uy = tgv_case(24, 20, 3, 0)
+    plan = Plan.build(c.x, c.y, c.period, _params(c.h, 20, 3, 0, 0, 0.8))
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        g0 = plan.init(ux, uy, stream=s)
+        a = g0.clone()
+        b = plan.new_state()
+        ea = g0.clone()
+        eb = plan.new_state()
+        plan.graph_create(a, b, 10, s)
+        for rep in range(3):
+            plan.graph_launch(s)                   # 10 steps: result back in a
+            res = plan.step(ea, eb, 10, stream=s)  # eager reference
+            assert res is ea
+            s.synchronize()
+            say("graph replay", rep)
+            assert torch.equal(a, ea)
+    plan.close()
+
+
+def test_fp32_mass_conservation():
+    """Periodic, no force: the corrected FP32 weights keep the partition of
+    unity, so total mass drifts only by rounding."""
+    from paper_2306_01525_amd import Plan
+    c, ux, uy = tgv_case(64, 30, 4, 0)
+    plan = Plan.build(c.x, c.y, c.period, _params(c.h, 30, 4, 0, 0, 0.6))
+    got = _gpu_run(plan, ux, uy, [500])
+    drift = abs(got[500][0].sum() - c.n) / c.n
+    say("fp32 mass drift after 500 steps", drift)
+    assert drift < 1e-6
