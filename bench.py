@@ -1,0 +1,275 @@
+"""MLBM node-update throughput on one MI355X.
+
+Workload (the Taylor-Green configuration at full size): a 512 x 512 lattice on
+[0, 2 pi)^2 with every coordinate jittered by U[-0.3 h, 0.3 h] (seed 2),
+N = 262,144 nodes, D2Q9 BGK, tau = 0.6, u0 = 0.01, streaming distance dx = h,
+r^3 RBF with degree-4 polynomial augmentation on K = 30 stencils, the paper's
+stencil rule (closest node of each departure point), FP32 deviation-stored
+populations. A timed step is one fused stream+collide pass over all nodes;
+the weight build is timed separately.
+
+Also reported: the same step in plain FP64, the adjoint/forward cost of a
+checkpointed reverse sweep, L2 errors against the analytic decay, the
+roofline position of the step kernel, and the FP64 CPU oracle timed on the
+host cores on a bounded sample of the same workload.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "MLBM node-updates/s FP32 vs FP64 + adjoint/forward cost, at stated L2 vs oracle"
+HBM_PEAK_GBS = 8000.0
+PROFILE_PMC = os.path.join(ROOT, "profiles", "step_fp32_tgv512_pmc.json")
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def bytes_per_update(K: int, precision: str, paper_mode: bool) -> int:
+    """Algorithmic HBM bytes of one node-update: 8K weights, K stencil
+    indices, 9 populations read and 9 written (gathers counted once), plus 8
+    owner indices with the paper's stencil rule."""
+    if precision == "f32":
+        b = 4 * (8 * K + K + 9 + 9)
+    else:
+        b = 8 * 8 * K + 4 * K + 8 * 18
+    return b + (32 if paper_mode else 0)
+
+
+def step_kernel_hash() -> str:
+    h = hashlib.sha256()
+    for f in ("step.hip", "common.h"):
+        with open(os.path.join(ROOT, "paper_2306_01525_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def time_steps(plan, g, steps, warmup, stream):
+    """W eager warm-up steps, then K steps replayed from a HIP graph, bracketed
+    by synchronisation and timed with events on the launch stream."""
+    import torch
+    other = plan.new_state()
+    with torch.cuda.stream(stream):
+        res = plan.step(g, other, warmup, stream=stream)
+        if res is other:
+            g, other = other, g
+        plan.graph_create(g, other, steps, stream)
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        plan.graph_launch(stream)
+        e1.record(stream)
+        torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    final = other if steps % 2 else g
+    return ms, final
+
+
+def run_gpu(args):
+    import numpy as np
+    import torch
+    from paper_2306_01525_amd import MLBM_FP32_DEV, MLBM_FP64, Params, Plan
+    from paper_2306_01525_amd import targets
+    from paper_2306_01525_amd.autograd import Rollout
+    from synth import jittered_lattice, tgv_initial_velocity
+
+    n_side, K, m, tau, u0, seed = 512, 30, 4, 0.6, 0.01, 2
+    c = jittered_lattice(n_side, seed=seed)
+    L = c.period[0]
+    ux, uy = tgv_initial_velocity(c.x, c.y, L, u0)
+    dev = torch.device("cuda:0")
+    xt = torch.tensor(c.x, device=dev)
+    yt = torch.tensor(c.y, device=dev)
+    uxt = torch.tensor(ux, device=dev)
+    uyt = torch.tensor(uy, device=dev)
+    stream = torch.cuda.Stream()
+    out = {}
+
+    def build(precision, with_adjoint=0):
+        p = Params(dx=c.h, K=K, degree=m, tau=tau, stencil_mode=0, precision=precision,
+                   with_adjoint=with_adjoint)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        plan = Plan.build(xt, yt, c.period, p, stream=stream)
+        torch.cuda.synchronize()
+        return plan, (time.perf_counter() - t0) * 1e3
+
+    # FP32 deviation form: the headline
+    log("building FP32 plan, N =", c.n)
+    plan32, build_ms = build(MLBM_FP32_DEV)
+    log("build %.1f ms; timing %d FP32 steps after %d warm-up" % (build_ms, args.steps, args.warmup))
+    g = plan32.init(uxt, uyt)
+    torch.cuda.synchronize()
+    ms32, g32 = time_steps(plan32, g, args.steps, args.warmup, stream)
+    total = args.steps + args.warmup
+    tx, ty = targets.tgv_velocity(c.x, c.y, L, u0, tau, c.h, total)
+    tx_t, ty_t = torch.tensor(tx, device=dev), torch.tensor(ty, device=dev)
+    l2u32, l2v32 = plan32.l2(g32, tx_t, ty_t)
+    _, u32, v32 = plan32.moments(g32)
+    out.update(ms32=ms32, build_ms=build_ms, l2_32=(l2u32, l2v32))
+    log("FP32: %.3f ms/step, L2(u) vs analytic %.3e" % (ms32 / args.steps, l2u32))
+
+    # FP64 plain form, same number of steps
+    if not args.skip_fp64:
+        plan64, build64_ms = build(MLBM_FP64)
+        g = plan64.init(uxt, uyt)
+        ms64, g64 = time_steps(plan64, g, args.steps, args.warmup, stream)
+        l2u64, l2v64 = plan64.l2(g64, tx_t, ty_t)
+        _, u64, v64 = plan64.moments(g64)
+        d = torch.sqrt(((u32 - u64) ** 2 + (v32 - v64) ** 2).sum() / (u64 ** 2 + v64 ** 2).sum())
+        out.update(ms64=ms64, l2_64=(l2u64, l2v64), fp32_vs_fp64=float(d))
+        log("FP64: %.3f ms/step, L2(u) vs analytic %.3e, FP32 vs FP64 %.3e"
+            % (ms64 / args.steps, l2u64, float(d)))
+        plan64.close()
+        del plan64
+
+    # adjoint / forward cost: one segment of C steps forward vs recompute + reverse
+    if not args.skip_adjoint:
+        C = 50
+        planA, _ = build(MLBM_FP32_DEV, with_adjoint=1)
+        with torch.cuda.stream(stream):
+            ro = Rollout(planA, C, C)
+            ro.forward(uxt, uyt, stream=stream)      # warm
+            ro.loss(tx_t, ty_t, stream=stream)
+            ro.backward(stream=stream)
+            torch.cuda.synchronize()
+            e = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+            e[0].record(stream)
+            ro.forward(uxt, uyt, stream=stream)
+            ro.loss(tx_t, ty_t, stream=stream)
+            e[1].record(stream)
+            ro.backward(stream=stream)
+            e[2].record(stream)
+            torch.cuda.synchronize()
+        fwd = e[0].elapsed_time(e[1])
+        bwd = e[1].elapsed_time(e[2])
+        out.update(adj_ratio=bwd / fwd, adj_fwd_ms=fwd, adj_bwd_ms=bwd)
+        log("adjoint: forward %.2f ms, recompute+reverse %.2f ms, ratio %.2f" % (fwd, bwd, bwd / fwd))
+        planA.close()
+    out["n"] = c.n
+    out["K"] = K
+    plan32.close()
+    return out
+
+
+def cpu_baseline(budget_s: float):
+    """The FP64 CPU oracle on a bounded sample of the same workload: a
+    128 x 128 cloud of the same kind (16,384 nodes, same jitter, K, degree,
+    tau, stencil rule), stepped until about budget_s seconds of CPU time."""
+    import numpy as np
+    import oracle
+    from synth import jittered_lattice, tgv_initial_velocity
+    c = jittered_lattice(128, seed=2)
+    nbr, own, W = oracle.build_plan(c, c.h, 30, 4, mode=0)
+    ux, uy = tgv_initial_velocity(c.x, c.y, c.period[0], 0.01)
+    f = oracle.equilibrium(np.ones(c.n), ux, uy)
+    f = oracle.run(f, nbr, own, W, 0.6, 2)    # warm
+    steps = 0
+    t0 = time.perf_counter()
+    while time.perf_counter() - t0 < budget_s:
+        f = oracle.run(f, nbr, own, W, 0.6, 10)
+        steps += 10
+    dt = time.perf_counter() - t0
+    return {"value": c.n * steps / dt, "unit": "node-updates/s", "cores": oracle.threads(),
+            "kind": "oracle",
+            "sample": "FP64 oracle on a 128x128 jittered TGV cloud (16,384 nodes, K 30, degree 4, "
+                      "tau 0.6, paper stencils), %d steps in %.1f s after setup" % (steps, dt)}
+
+
+def load_traffic(nodes, steps):
+    """HBM bytes per step-kernel launch from committed rocprofv3 counters,
+    only when they were taken on the current kernel source."""
+    try:
+        with open(PROFILE_PMC) as fh:
+            d = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if d.get("kernel_hash") != step_kernel_hash():
+        return None
+    return d.get("bytes_per_launch")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--skip-fp64", action="store_true")
+    ap.add_argument("--skip-adjoint", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-budget", type=float, default=15.0)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(--gpus %d requested)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+    if int(os.environ.get("RANK", "0")) != 0:
+        sys.exit(0)
+
+    r = run_gpu(args)
+    n, K, steps = r["n"], r["K"], args.steps
+    ms_step = r["ms32"] / steps
+    value = n * steps / (r["ms32"] / 1e3)
+    bpu = bytes_per_update(K, "f32", True)
+    achieved = bpu * n / (ms_step / 1e3) / 1e9
+    traffic = load_traffic(n, steps)
+    line = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "node-updates/s",
+        "n_gpus": 1,
+        "steps": steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": "TGV-512: 262,144 nodes (512x512 lattice on [0,2pi)^2 jittered by "
+                        "U[-0.3h,0.3h], seed 2), D2Q9 BGK tau 0.6, u0 0.01, dx = h, r^3 RBF + "
+                        "degree-4 polynomials, K 30, paper stencil rule, FP32 deviation state",
+            "nodes": n, "K": K, "degree": 4, "tau": 0.6, "stencil": "paper",
+        },
+        "roofline": {
+            "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS,
+            "traffic": traffic,
+            "bytes_per_update": bpu,
+        },
+        "l2_vs_analytic": {"fp32_u": r["l2_32"][0], "fp32_vec": r["l2_32"][1]},
+        "build_ms": r["build_ms"],
+    }
+    if "ms64" in r:
+        line["fp64"] = {
+            "value": n * steps / (r["ms64"] / 1e3), "ms_per_step": r["ms64"] / steps,
+            "roofline_frac": bytes_per_update(K, "f64", True) * n / (r["ms64"] / steps / 1e3)
+            / 1e9 / HBM_PEAK_GBS,
+            "l2_vs_analytic_u": r["l2_64"][0],
+        }
+        line["fp32_speedup_over_fp64"] = r["ms64"] / r["ms32"]
+        line["fp32_vs_fp64_rel_l2"] = r["fp32_vs_fp64"]
+    if "adj_ratio" in r:
+        line["adjoint_over_forward"] = r["adj_ratio"]
+    if not args.no_cpu_baseline:
+        log("timing the CPU oracle (%.0f s budget)" % args.cpu_budget)
+        line["cpu_baseline"] = cpu_baseline(args.cpu_budget)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -153,6 +153,11 @@ mlbm_status mlbm_plan_export(const mlbm_plan *plan, int32_t cloud, int32_t what,
 
 mlbm_status mlbm_plan_destroy(mlbm_plan *plan);   /* frees the host object only */
 
+/* Change the relaxation time tau (> 0.5) of every cloud of the plan. The
+ * shape vectors do not depend on tau, so nothing is rebuilt; a graph created
+ * earlier is dropped (it holds the old value). */
+mlbm_status mlbm_plan_set_tau(mlbm_plan *plan, double tau);
+
 /* ---- time stepping (Algorithm 1, time loop) ------------------------------- */
 
 /* Initial state: populations at equilibrium with the given macroscopic fields

@@ -56,6 +56,7 @@ SIGNATURES = {
     "mlbm_plan_get_info": (_c_i32, [_c_p, _P(PlanInfo)]),
     "mlbm_plan_export": (_c_i32, [_c_p, _c_i32, _c_i32, _c_p, _c_sz]),
     "mlbm_plan_destroy": (_c_i32, [_c_p]),
+    "mlbm_plan_set_tau": (_c_i32, [_c_p, _c_d]),
     "mlbm_init": (_c_i32, [_c_p, _c_p, _c_p, _c_p, _c_p, _c_p]),
     "mlbm_init_f": (_c_i32, [_c_p, _c_p, _c_p, _c_p, _c_p, _c_p]),
     "mlbm_collide": (_c_i32, [_c_p, _c_p, _c_p, _c_p]),

@@ -480,6 +480,21 @@ mlbm_status mlbm_plan_destroy(mlbm_plan *plan) {
     return MLBM_OK;
 }
 
+mlbm_status mlbm_plan_set_tau(mlbm_plan *plan, double tau) {
+    if (!plan || plan->c.empty()) return fail(MLBM_EINVAL, "null plan");
+    if (!(tau > 0.5)) return fail(MLBM_EINVAL, "tau must exceed 0.5");
+    for (auto &cp : plan->c) cp.prm.tau = tau;
+    if (plan->graph_exec) {
+        (void)hipGraphExecDestroy(plan->graph_exec);
+        plan->graph_exec = nullptr;
+    }
+    if (plan->graph) {
+        (void)hipGraphDestroy(plan->graph);
+        plan->graph = nullptr;
+    }
+    return MLBM_OK;
+}
+
 int32_t mlbm_device_error(const mlbm_plan *plan) {
     if (!plan || !plan->dev_err) return 0;
     int32_t v = INT_MAX;

@@ -251,5 +251,9 @@ class Plan:
                                            out.nbytes))
         return out
 
+    def set_tau(self, tau: float):
+        check(_lib.load().mlbm_plan_set_tau(self._h, float(tau)))
+        self.params.tau = float(tau)
+
     def device_error(self) -> int:
         return int(_lib.load().mlbm_device_error(self._h))

@@ -1,0 +1,89 @@
+"""GPU adjoint (checkpointed recompute + transposed gather + BGK VJP) against
+the oracle's discrete adjoint, complex-step and finite differences."""
+import numpy as np
+import pytest
+
+import oracle
+from gpu_common import rel_l2, say
+from synth import jittered_lattice, tgv_initial_velocity
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _setup(n_side=10, K=20, m=3, mode=0, seed=21):
+    c = jittered_lattice(n_side, seed=seed, length=float(n_side))
+    u0x, u0y = tgv_initial_velocity(c.x, c.y, float(n_side), 0.02)
+    tx, ty = tgv_initial_velocity(c.x, c.y, float(n_side), 0.015)
+    return c, u0x, u0y, tx, ty, K, m, mode
+
+
+def _gpu_grad(plan, u0x, u0y, tx, ty, steps, segment):
+    from paper_2306_01525_amd.autograd import Rollout
+    ro = Rollout(plan, steps, segment)
+    ro.forward(u0x, u0y)
+    J = ro.loss(tx, ty)
+    gx, gy, gt = ro.backward()
+    return float(J.item()), gx.cpu().numpy(), gy.cpu().numpy(), float(gt.item())
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+@pytest.mark.parametrize("precision", [1, 0])
+def test_adjoint_on_imported_weights(mode, precision):
+    """Same weights on both sides: FP64 GPU gradient to 1e-10, FP32 to 1e-4."""
+    from paper_2306_01525_amd import Params, Plan
+    c, u0x, u0y, tx, ty, K, m, _ = _setup(mode=mode)
+    tau, steps, seg = 0.7, 12, 5
+    nbr, own, W = oracle.build_plan(c, 1.0, K, m, mode)
+    J_o, gx_o, gy_o, gt_o = oracle.adjoint(nbr, own, W, tau, steps, 1.0, u0x, u0y, tx, ty)
+    p = Params(dx=1.0, K=K, degree=m, tau=tau, stencil_mode=mode, precision=precision,
+               with_adjoint=1)
+    plan = Plan.from_arrays(c.x, c.y, nbr, own, W, p)
+    J, gx, gy, gt = _gpu_grad(plan, u0x, u0y, tx, ty, steps, seg)
+    tol = 1e-10 if precision == 1 else 1e-4
+    eg = rel_l2(np.concatenate([gx, gy]), np.concatenate([gx_o, gy_o]))
+    say("mode %d prec %d: J %.6e vs %.6e, grad u0 rel %.2e, dtau %.6e vs %.6e"
+        % (mode, precision, J, J_o, eg, gt, gt_o))
+    assert abs(J - J_o) <= tol * abs(J_o)
+    assert eg < tol
+    assert abs(gt - gt_o) <= tol * abs(gt_o) + 1e-300
+    plan.close()
+
+
+def test_adjoint_end_to_end_gpu_build_and_autograd():
+    """GPU-built weights, autograd.Function, against the oracle gradient and
+    central finite differences of the GPU forward in FP64."""
+    from paper_2306_01525_amd import Params, Plan
+    from paper_2306_01525_amd.autograd import rollout_loss
+    c, u0x, u0y, tx, ty, K, m, mode = _setup(n_side=14, K=25, m=2, seed=5)
+    steps, seg = 20, 8
+    nbr, own, W = oracle.build_plan(c, 1.0, K, m, mode)
+    J_o, gx_o, gy_o, gt_o = oracle.adjoint(nbr, own, W, 0.8, steps, 1.0, u0x, u0y, tx, ty)
+    p = Params(dx=1.0, K=K, degree=m, tau=0.8, stencil_mode=mode, precision=1, with_adjoint=1)
+    plan = Plan.build(c.x, c.y, c.period, p)
+    dev = torch.device("cuda")
+    ux = torch.tensor(u0x, device=dev, requires_grad=True)
+    uy = torch.tensor(u0y, device=dev, requires_grad=True)
+    tau = torch.tensor(0.8, dtype=torch.float64, device=dev, requires_grad=True)
+    txt, tyt = torch.tensor(tx, device=dev), torch.tensor(ty, device=dev)
+    J = rollout_loss(plan, ux, uy, tau, steps, txt, tyt, seg)
+    J.backward()
+    eg = rel_l2(np.concatenate([ux.grad.cpu().numpy(), uy.grad.cpu().numpy()]),
+                np.concatenate([gx_o, gy_o]))
+    say("e2e: J %.8e vs oracle %.8e; grad rel %.2e; dtau %.8e vs %.8e"
+        % (J.item(), J_o, eg, tau.grad.item(), gt_o))
+    assert abs(J.item() - J_o) < 1e-8 * abs(J_o)
+    assert eg < 1e-7
+    assert abs(tau.grad.item() - gt_o) < 1e-7 * abs(gt_o)
+    # central finite difference of the GPU forward with respect to tau
+    h = 1e-5
+    with torch.no_grad():
+        jp = rollout_loss(plan, ux, uy, torch.tensor(0.8 + h, dtype=torch.float64), steps,
+                          txt, tyt, seg).item()
+        jm = rollout_loss(plan, ux, uy, torch.tensor(0.8 - h, dtype=torch.float64), steps,
+                          txt, tyt, seg).item()
+    fd = (jp - jm) / (2 * h)
+    say("fd dJ/dtau %.8e vs adjoint %.8e" % (fd, tau.grad.item()))
+    assert abs(fd - tau.grad.item()) < 1e-5 * abs(fd)
+    plan.close()
