@@ -95,6 +95,10 @@ typedef struct {
     int32_t K, degree, stencil_mode, precision;   /* of cloud 0                    */
     size_t state_bytes;       /* bytes of one state array g (9 populations)        */
     int64_t tile_nodes;       /* nodes per workgroup of the step kernel            */
+    int32_t step_lds_bytes;   /* LDS per workgroup of the FP32 step (0: the step
+                                 gathers from global memory only)                  */
+    int32_t fallback_tiles;   /* tiles whose gather tables exceed the LDS caps and
+                                 gather from global memory (-1: not known)         */
 } mlbm_plan_info;
 
 /* ---- weight build (Sec. 2.2-2.3; Algorithm 1, initialisation loop) -------- */
@@ -146,7 +150,13 @@ mlbm_status mlbm_plan_get_info(const mlbm_plan *plan, mlbm_plan_info *info);
  * what = 0 perm int32 [n] (internal position -> user index),
  *        1 nbr int32 [n][K] (user indices, node-major, user order),
  *        2 owner int32 [n][9] (user indices, user order),
- *        3 W FP64 [n][9][K] (user order; k = 0 is the identity).
+ *        3 W FP64 [n][9][K] (user order; k = 0 is the identity),
+ *        4 tile descriptors int32 [ntiles][2] (|O_t|, |H_t|; 0 = global path),
+ *        5 halo lists int32 [ntiles][hcap] (internal indices),
+ *        6 local stencils uint16 [ntiles][ocap][K],
+ *        7 local owners uint16 [8][n] (internal order; paper mode),
+ *        8 capacities int32 [2] (ocap, hcap).
+ * Items 4-8 describe the gather tables of the FP32 step (internal layout).
  * Cloud `cloud`; dst_bytes must match exactly. */
 mlbm_status mlbm_plan_export(const mlbm_plan *plan, int32_t cloud, int32_t what, void *dst,
                              size_t dst_bytes);

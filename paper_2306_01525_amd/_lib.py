@@ -41,7 +41,7 @@ class Params(ctypes.Structure):
 class PlanInfo(ctypes.Structure):
     _fields_ = [("n_clouds", _c_i32), ("n_total", _c_i64), ("K", _c_i32), ("degree", _c_i32),
                 ("stencil_mode", _c_i32), ("precision", _c_i32), ("state_bytes", _c_sz),
-                ("tile_nodes", _c_i64)]
+                ("tile_nodes", _c_i64), ("step_lds_bytes", _c_i32), ("fallback_tiles", _c_i32)]
 
 
 _P = ctypes.POINTER

@@ -10,7 +10,7 @@ CSRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "_lib", "libmlbm.so")
 
-SOURCES = ["api.hip", "build.hip", "step.hip", "adjoint.hip", "sort.hip"]
+SOURCES = ["api.hip", "build.hip", "step.hip", "adjoint.hip", "sort.hip", "tiles.hip"]
 ARCH = "gfx950"
 
 COMMON = ["-O3", "--offload-arch=" + ARCH, "-std=c++17", "-fPIC",

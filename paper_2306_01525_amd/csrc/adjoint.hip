@@ -80,6 +80,22 @@ __global__ void k_tr_sort(int64_t rows, const int32_t *__restrict__ ptr,
 
 __global__ void k_set_i32(int32_t *p, int32_t v) { *p = v; }
 
+// Slot-major copy of the first lw entries of every sorted CSR row.
+template <class T>
+__global__ void k_ell_fill(int n, int lw, const int32_t *__restrict__ ptr,
+                           const int32_t *__restrict__ col, const T *__restrict__ val,
+                           int32_t *__restrict__ ecol, T *__restrict__ eval) {
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= (int64_t)8 * n) return;
+    const int64_t k = r / n, m = r - k * n;
+    const int b = ptr[r], len = ptr[r + 1] - b;
+    for (int e = 0; e < lw; ++e) {
+        const int64_t dst = (k * lw + e) * n + m;
+        ecol[dst] = e < len ? col[b + e] : (int32_t)m;
+        eval[dst] = e < len ? val[b + e] : (T)0;
+    }
+}
+
 // Workgroup sum of one double per lane into part[blockIdx.x].
 __device__ __forceinline__ void block_sum_to(double v, double *part) {
     __shared__ double sh[256];
@@ -134,7 +150,8 @@ template <class T>
 __global__ __launch_bounds__(256) void k_adj_step(
     int n, const T *__restrict__ fn, const T *__restrict__ lam_next, T *__restrict__ lam_n,
     const int32_t *__restrict__ ptr, const int32_t *__restrict__ col, const T *__restrict__ val,
-    double rtau, double rho0, int dev, double *__restrict__ part) {
+    int lw, const int32_t *__restrict__ ecol, const T *__restrict__ eval, double rtau,
+    double rho0, int dev, double *__restrict__ part) {
     const int m = blockIdx.x * blockDim.x + threadIdx.x;
     double dt = 0.0;
     if (m < n) {
@@ -143,10 +160,15 @@ __global__ __launch_bounds__(256) void k_adj_step(
 #pragma unroll
         for (int k = 1; k < kQ; ++k) {
             const int64_t row = (int64_t)(k - 1) * n + m;
-            const int b = ptr[row], e = ptr[row + 1];
+            const int b = ptr[row], len = ptr[row + 1] - b;
             const T *lk = lam_next + (int64_t)k * n;
+            const int32_t *ec = ecol + (int64_t)(k - 1) * lw * n + m;
+            const T *ev = eval + (int64_t)(k - 1) * lw * n + m;
+            const int head = len < lw ? len : lw;
             T acc = 0;
-            for (int q = b; q < e; ++q) acc += val[q] * lk[col[q]];
+            // the row in its sorted order: slot-major head, then the CSR tail
+            for (int e = 0; e < head; ++e) acc += ev[(int64_t)e * n] * lk[ec[(int64_t)e * n]];
+            for (int e = lw; e < len; ++e) acc += val[b + e] * lk[col[b + e]];
             lg[k] = acc;
         }
         T fk[kQ], rho, ux, uy, drho;
@@ -264,6 +286,20 @@ hipError_t launch_transpose(const CloudPlan &cp, int precision, void *tmp, size_
         hipLaunchKernelGGL(k_tr_sort<float>, dim3(blocks_for(rows, 256)), dim3(256), 0, s, rows,
                            cp.tr_ptr, cp.tr_col, (float *)cp.tr_val);
     }
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    return launch_ell_fill(cp, precision, s);
+}
+
+hipError_t launch_ell_fill(const CloudPlan &cp, int precision, hipStream_t s) {
+    const int64_t rows = (int64_t)8 * cp.n;
+    if (precision == MLBM_FP64)
+        hipLaunchKernelGGL(k_ell_fill<double>, dim3(blocks_for(rows, 256)), dim3(256), 0, s, cp.n,
+                           cp.tr_lw, cp.tr_ptr, cp.tr_col, (const double *)cp.tr_val, cp.ell_col,
+                           (double *)cp.ell_val);
+    else
+        hipLaunchKernelGGL(k_ell_fill<float>, dim3(blocks_for(rows, 256)), dim3(256), 0, s, cp.n,
+                           cp.tr_lw, cp.tr_ptr, cp.tr_col, (const float *)cp.tr_val, cp.ell_col,
+                           (float *)cp.ell_val);
     return hipGetLastError();
 }
 
@@ -293,11 +329,13 @@ hipError_t launch_step_adjoint(const CloudPlan &cp, int precision, const void *f
     if (precision == MLBM_FP64)
         hipLaunchKernelGGL(k_adj_step<double>, dim3(nb), dim3(256), 0, s, n, (const double *)fn,
                            (const double *)lam_next, (double *)lam_n, cp.tr_ptr, cp.tr_col,
-                           (const double *)cp.tr_val, rtau, cp.prm.rho0, 0, part);
+                           (const double *)cp.tr_val, cp.tr_lw, cp.ell_col,
+                           (const double *)cp.ell_val, rtau, cp.prm.rho0, 0, part);
     else
         hipLaunchKernelGGL(k_adj_step<float>, dim3(nb), dim3(256), 0, s, n, (const float *)fn,
                            (const float *)lam_next, (float *)lam_n, cp.tr_ptr, cp.tr_col,
-                           (const float *)cp.tr_val, rtau, cp.prm.rho0, 1, part);
+                           (const float *)cp.tr_val, cp.tr_lw, cp.ell_col,
+                           (const float *)cp.ell_val, rtau, cp.prm.rho0, 1, part);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_sum_final, dim3(1), dim3(256), 0, s, nb, (const double *)part, dtau, 1);

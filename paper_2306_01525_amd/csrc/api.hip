@@ -114,11 +114,25 @@ void layout_cloud(const mlbm_cloud &c, const mlbm_params &p, int precision, Carv
         cp.force64 = pl.take<double>((size_t)2 * n);
         cp.force32 = precision == MLBM_FP32_DEV ? pl.take<float>((size_t)2 * n) : nullptr;
     }
+    if (precision == MLBM_FP32_DEV) {
+        const int ntiles = (n + kTile - 1) / kTile;
+        cp.hcap = 1024;
+        cp.ocap = std::min(512, ((65536 - 8 * cp.hcap * 4) / (2 * K)) & ~1);
+        cp.tdesc = pl.take<int32_t>((size_t)2 * ntiles);
+        if (p.stencil_mode == MLBM_STENCIL_PAPER) cp.ownerL = pl.take<uint16_t>((size_t)8 * n);
+        cp.nbrL = pl.take<uint16_t>((size_t)ntiles * cp.ocap * K);
+        cp.hlist = pl.take<int32_t>((size_t)ntiles * cp.hcap);
+    }
     if (p.with_adjoint) {
         cp.tr_ptr = pl.take<int32_t>((size_t)8 * n + 1);
         cp.tr_col = pl.take<int32_t>((size_t)8 * K * n);
         cp.tr_val = precision == MLBM_FP64 ? (void *)pl.take<double>((size_t)8 * K * n)
                                            : (void *)pl.take<float>((size_t)8 * K * n);
+        cp.tr_lw = K + 4;
+        cp.ell_col = pl.take<int32_t>((size_t)8 * cp.tr_lw * n);
+        cp.ell_val = precision == MLBM_FP64
+                         ? (void *)pl.take<double>((size_t)8 * cp.tr_lw * n)
+                         : (void *)pl.take<float>((size_t)8 * cp.tr_lw * n);
     }
     if (ws && bw) {
         choose_grid(n, c.period_x, c.period_y, bw->gx, bw->gy, bw->hb);
@@ -156,6 +170,26 @@ mlbm_status check_singular(mlbm_plan *plan, hipStream_t s) {
     if (v != INT_MAX)
         return fail(MLBM_ESINGULAR, "local RBF system is numerically singular at node " +
                                         std::to_string(v - 1) + " (user index)");
+    return MLBM_OK;
+}
+
+// Tile tables of the LDS-staged step; when the stream is not captured, the
+// launch LDS size is the largest tile's need, else the capacity bound.
+mlbm_status build_tiles(mlbm_plan *plan, CloudPlan &cp, hipStream_t s) {
+    if (!cp.tdesc) return MLBM_OK;
+    int32_t *stats = plan->dev_err + 1;
+    MLBM_HIP(launch_fill_i32(stats, 0, 2, s));
+    MLBM_HIP(launch_tiles(cp, stats, s));
+    if (capturing(s)) {
+        cp.lds_bytes = (unsigned)(8 * cp.hcap * 4 + cp.ocap * cp.K * 2);
+        cp.fallback_tiles = -1;
+        return MLBM_OK;
+    }
+    int32_t h[2] = {0, 0};
+    MLBM_HIP(hipStreamSynchronize(s));
+    MLBM_HIP(hipMemcpy(h, stats, sizeof(h), hipMemcpyDeviceToHost));
+    cp.lds_bytes = (unsigned)h[0];
+    cp.fallback_tiles = h[1];
     return MLBM_OK;
 }
 
@@ -252,6 +286,9 @@ mlbm_status mlbm_build_weights(const mlbm_cloud *clouds, const mlbm_params *para
                       cp.force64, s));
     if (p.with_adjoint) STEP(launch_transpose(cp, p.precision, bw.tr_tmp, bw.tr_bytes, s));
 #undef STEP
+    st = build_tiles(plan, cp, s);
+    if (st != MLBM_OK) return cleanup(st);
+    plan->c[0] = cp;
     st = check_singular(plan, s);
     if (st != MLBM_OK) return cleanup(st);
     *out = plan;
@@ -395,9 +432,12 @@ mlbm_status mlbm_import_weights(int32_t n, const double *x, const double *y,
             STEP(hipMemcpyAsync(cp.tr_val, v64.data(), sizeof(double) * nnz, hipMemcpyHostToDevice, s));
         else
             STEP(hipMemcpyAsync(cp.tr_val, v32.data(), sizeof(float) * nnz, hipMemcpyHostToDevice, s));
+        STEP(launch_ell_fill(cp, p.precision, s));
     }
     STEP(hipStreamSynchronize(s));
 #undef STEP
+    st = build_tiles(plan, cp, s);
+    if (st != MLBM_OK) return cleanup(st);
     plan->c.push_back(cp);
     *out = plan;
     return MLBM_OK;
@@ -414,6 +454,8 @@ mlbm_status mlbm_plan_get_info(const mlbm_plan *plan, mlbm_plan_info *info) {
     info->precision = plan->precision;
     info->state_bytes = (size_t)9 * plan->n_total * state_elem_bytes(plan->precision);
     info->tile_nodes = kTile;
+    info->step_lds_bytes = (int32_t)cp->lds_bytes;
+    info->fallback_tiles = cp->fallback_tiles;
     return MLBM_OK;
 }
 
@@ -423,13 +465,33 @@ mlbm_status mlbm_plan_export(const mlbm_plan *plan, int32_t cloud, int32_t what,
         return fail(MLBM_EINVAL, "bad plan, cloud or destination");
     const CloudPlan &cp = plan->c[cloud];
     const int n = cp.n, K = cp.K;
+    const size_t ntiles = (size_t)(n + kTile - 1) / kTile;
     size_t need = what == 0 ? sizeof(int32_t) * n
                 : what == 1 ? sizeof(int32_t) * (size_t)n * K
                 : what == 2 ? sizeof(int32_t) * (size_t)n * 9
-                : what == 3 ? sizeof(double) * (size_t)n * 9 * K : 0;
+                : what == 3 ? sizeof(double) * (size_t)n * 9 * K
+                : what == 4 ? sizeof(int32_t) * 2 * ntiles
+                : what == 5 ? sizeof(int32_t) * ntiles * cp.hcap
+                : what == 6 ? sizeof(uint16_t) * ntiles * cp.ocap * K
+                : what == 7 ? sizeof(uint16_t) * 8 * (size_t)n
+                : what == 8 ? sizeof(int32_t) * 2 : 0;
     if (need == 0) return fail(MLBM_EINVAL, "unknown export item");
+    if (what >= 4 && what <= 6 && !cp.tdesc) return fail(MLBM_EINVAL, "plan has no tile tables");
+    if (what == 7 && !cp.ownerL) return fail(MLBM_EINVAL, "plan has no local owners");
     if (dst_bytes != need) return fail(MLBM_ESMALLBUF, "export size mismatch");
     MLBM_HIP(hipDeviceSynchronize());
+    if (what == 8) {
+        int32_t caps[2] = {cp.ocap, cp.hcap};
+        std::memcpy(dst, caps, sizeof(caps));
+        return MLBM_OK;
+    }
+    if (what >= 4) {
+        const void *src = what == 4 ? (const void *)cp.tdesc
+                        : what == 5 ? (const void *)cp.hlist
+                        : what == 6 ? (const void *)cp.nbrL : (const void *)cp.ownerL;
+        MLBM_HIP(hipMemcpy(dst, src, need, hipMemcpyDeviceToHost));
+        return MLBM_OK;
+    }
     std::vector<int32_t> perm(n), iperm(n);
     MLBM_HIP(hipMemcpy(perm.data(), cp.perm, sizeof(int32_t) * n, hipMemcpyDeviceToHost));
     for (int p = 0; p < n; ++p) iperm[perm[p]] = p;

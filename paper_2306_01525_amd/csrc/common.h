@@ -64,11 +64,24 @@ struct CloudPlan {
     float *W32 = nullptr;     // [K][2][n][4] FP32 shape vectors, k = 1..8
     float *force32 = nullptr; // [2][n] body force (lattice units), FP32 state
     double *force64 = nullptr;// [2][n] body force, FP64 state
+    // tile-local gather tables of the LDS-staged FP32 step (tiles.hip)
+    int ocap = 0, hcap = 0;       // capacities per tile: owners, halo nodes
+    int32_t *tdesc = nullptr;     // [ntiles][2]: |O_t|, |H_t| (0: global path)
+    uint16_t *ownerL = nullptr;   // [8][n] position of owner_k(p) in O_t
+    uint16_t *nbrL = nullptr;     // [ntiles][ocap][K] position in H_t
+    int32_t *hlist = nullptr;     // [ntiles][hcap] global index of H_t entries
+    unsigned lds_bytes = 0;       // dynamic LDS of the step launch (0: no tables)
+    int fallback_tiles = -1;      // tiles stepped with global gathers (-1: unknown)
     // transposed streaming (adjoint): per direction k = 1..8, CSR over the
     // source node m of (arriving node i, weight)
-    int32_t *tr_ptr = nullptr;  // [8][n+1]
-    int32_t *tr_col = nullptr;  // [8][K*n]
-    void *tr_val = nullptr;     // [8][K*n] float (FP32 plans) or double (FP64)
+    int32_t *tr_ptr = nullptr;  // [8n+1] row offsets, row (k-1)*n + m
+    int32_t *tr_col = nullptr;  // [8Kn] arriving node, ascending within a row
+    void *tr_val = nullptr;     // [8Kn] float (FP32 plans) or double (FP64)
+    // the first tr_lw entries of every row again, slot-major ([8][lw][n]) so
+    // that the lanes of a wavefront read them with unit stride
+    int tr_lw = 0;
+    int32_t *ell_col = nullptr;
+    void *ell_val = nullptr;
 };
 
 // Bump allocator over a caller buffer (a null base computes sizes only).
@@ -147,6 +160,10 @@ hipError_t launch_force(const double *xs, const double *ys, const uint8_t *ntype
                         int kind, double mag, float *f32, double *f64, hipStream_t s);
 hipError_t launch_fill_i32(int32_t *p, int32_t v, int64_t n, hipStream_t s);
 
+// ---- tile tables (tiles.hip) ----
+// stats[0] <- max LDS bytes over tiles, stats[1] <- number of fallback tiles
+hipError_t launch_tiles(const CloudPlan &cp, int32_t *stats, hipStream_t s);
+
 // ---- sort / scan (sort.hip) ----
 size_t sort_pairs_temp_bytes(int n);
 hipError_t sort_pairs(void *tmp, size_t tmp_bytes, const uint32_t *kin, uint32_t *kout,
@@ -173,6 +190,7 @@ hipError_t launch_collide(const CloudPlan &cp, int precision, const void *f, voi
 size_t transpose_temp_bytes(int n, int K);
 hipError_t launch_transpose(const CloudPlan &cp, int precision, void *tmp, size_t tmp_bytes,
                             hipStream_t s);
+hipError_t launch_ell_fill(const CloudPlan &cp, int precision, hipStream_t s);
 hipError_t launch_loss_seed(const CloudPlan &cp, int precision, const void *fT,
                             const double *uxt, const double *uyt, void *lam, double *J,
                             double *part, hipStream_t s);

@@ -45,48 +45,15 @@ inline unsigned xcd_grid(int64_t nblocks) { return (unsigned)(((nblocks + 7) / 8
 // ------------------------------------------------------------------------
 // FP32, deviation-stored populations
 // ------------------------------------------------------------------------
-template <int MODE, bool FORCE, bool WALL, bool REC>
-__global__ __launch_bounds__(kTile) void k_step32(
-    int n, int K, int64_t nblocks, const float *__restrict__ g, float *__restrict__ go,
-    const float4 *__restrict__ W, const int32_t *__restrict__ nbr,
-    const int32_t *__restrict__ owner, const float *__restrict__ force,
-    const uint8_t *__restrict__ ntype, float rtau, float rho0, float rho_w,
-    float *__restrict__ frec) {
-    const int64_t tile = xcd_tile(nblocks);
-    if (tile >= nblocks) return;
-    const int64_t p64 = tile * kTile + threadIdx.x;
-    if (p64 >= n) return;
-    const int p = (int)p64;
 
-    float acc[8];
-#pragma unroll
-    for (int d = 0; d < 8; ++d) acc[d] = 0.0f;
-    int s[8];
-#pragma unroll
-    for (int d = 0; d < 8; ++d) s[d] = MODE == MLBM_STENCIL_OWN ? p : owner[(int64_t)d * n + p];
-
-#pragma unroll 2
-    for (int j = 0; j < K; ++j) {
-        const float4 wa = W[((int64_t)j * 2) * n + p];
-        const float4 wb = W[((int64_t)j * 2 + 1) * n + p];
-        const float w[8] = {wa.x, wa.y, wa.z, wa.w, wb.x, wb.y, wb.z, wb.w};
-        if (MODE == MLBM_STENCIL_OWN) {
-            const int q = nbr[(int64_t)j * n + p];
-#pragma unroll
-            for (int d = 0; d < 8; ++d) acc[d] += w[d] * g[(int64_t)(d + 1) * n + q];
-        } else {
-#pragma unroll
-            for (int d = 0; d < 8; ++d) {
-                const int q = nbr[(int64_t)j * n + s[d]];
-                acc[d] += w[d] * g[(int64_t)(d + 1) * n + q];
-            }
-        }
-    }
-    float f[9];
-    f[0] = g[p];
-#pragma unroll
-    for (int d = 0; d < 8; ++d) f[d + 1] = acc[d];
-
+// Moments, wall rule, BGK collision with force, and the stores of one node.
+template <bool FORCE, bool WALL, bool REC>
+__device__ __forceinline__ void collide_store32(int n, int p, float (&f)[kQ],
+                                                float *__restrict__ go,
+                                                const float *__restrict__ force,
+                                                const uint8_t *__restrict__ ntype, float rtau,
+                                                float rho0, float rho_w,
+                                                float *__restrict__ frec) {
     if (WALL && ntype[p]) {
 #pragma unroll
         for (int k = 0; k < kQ; ++k) {
@@ -120,6 +87,106 @@ __global__ __launch_bounds__(kTile) void k_step32(
         go[(int64_t)k * n + p] = v;
         if (REC) frec[(int64_t)k * n + p] = f[k];
     }
+}
+
+// One workgroup per tile of kTile nodes. Tiles with gather tables (tdesc
+// |H_t| > 0) stage the 8 moving populations of the tile's halo H_t and the
+// tile-local stencils of its owners in LDS, then every interpolation reads LDS
+// only; HBM sees the weights, the tile tables and the halo rows, all
+// contiguous. Tiles without tables gather through global memory.
+template <int MODE, bool FORCE, bool WALL, bool REC>
+__global__ __launch_bounds__(kTile) void k_step32(
+    int n, int K, int64_t nblocks, const float *__restrict__ g, float *__restrict__ go,
+    const float4 *__restrict__ W, const int32_t *__restrict__ nbr,
+    const int32_t *__restrict__ owner, const float *__restrict__ force,
+    const uint8_t *__restrict__ ntype, float rtau, float rho0, float rho_w,
+    float *__restrict__ frec, const int32_t *__restrict__ tdesc,
+    const uint16_t *__restrict__ ownerL, const uint16_t *__restrict__ nbrL,
+    const int32_t *__restrict__ hlist, int ocap, int hcap) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int64_t tile = xcd_tile(nblocks);
+    if (tile >= nblocks) return;
+    const int base = (int)(tile * kTile);
+    const int cnt = min(kTile, n - base);
+    const int tid = threadIdx.x;
+    const int nh = tdesc ? tdesc[2 * tile + 1] : 0;
+
+    float acc[8];
+#pragma unroll
+    for (int d = 0; d < 8; ++d) acc[d] = 0.0f;
+
+    if (nh > 0) {
+        const int no = tdesc[2 * tile];
+        float *gl = reinterpret_cast<float *>(smem);                 // [8][nh]
+        uint16_t *nl = reinterpret_cast<uint16_t *>(gl + 8 * nh);    // [no][K]
+        const int32_t *hl = hlist + tile * (int64_t)hcap;
+        for (int h = tid; h < nh; h += kTile) {
+            int q = hl[h];
+            q = (unsigned)q < (unsigned)n ? q : 0;   // a bad table must not fault
+#pragma unroll
+            for (int d = 0; d < 8; ++d) gl[d * nh + h] = g[(int64_t)(d + 1) * n + q];
+        }
+        const uint32_t *src =
+            reinterpret_cast<const uint32_t *>(nbrL + tile * (int64_t)ocap * K);
+        uint32_t *dst = reinterpret_cast<uint32_t *>(nl);
+        const int words = (no * K + 1) >> 1;
+        for (int w = tid; w < words; w += kTile) dst[w] = src[w];
+        __syncthreads();
+        if (tid >= cnt) return;
+        const int p = base + tid;
+        int ol[8];
+#pragma unroll
+        for (int d = 0; d < 8; ++d)
+            ol[d] = (MODE == MLBM_STENCIL_OWN ? tid : (int)ownerL[(int64_t)d * n + p]) * K;
+#pragma unroll 2
+        for (int j = 0; j < K; ++j) {
+            const float4 wa = W[((int64_t)j * 2) * n + p];
+            const float4 wb = W[((int64_t)j * 2 + 1) * n + p];
+            const float w[8] = {wa.x, wa.y, wa.z, wa.w, wb.x, wb.y, wb.z, wb.w};
+            if (MODE == MLBM_STENCIL_OWN) {
+                const int h = nl[ol[0] + j];
+#pragma unroll
+                for (int d = 0; d < 8; ++d) acc[d] += w[d] * gl[d * nh + h];
+            } else {
+#pragma unroll
+                for (int d = 0; d < 8; ++d) acc[d] += w[d] * gl[d * nh + nl[ol[d] + j]];
+            }
+        }
+        float f[kQ];
+        f[0] = g[p];
+#pragma unroll
+        for (int d = 0; d < 8; ++d) f[d + 1] = acc[d];
+        collide_store32<FORCE, WALL, REC>(n, p, f, go, force, ntype, rtau, rho0, rho_w, frec);
+        return;
+    }
+
+    if (tid >= cnt) return;
+    const int p = base + tid;
+    int s[8];
+#pragma unroll
+    for (int d = 0; d < 8; ++d) s[d] = MODE == MLBM_STENCIL_OWN ? p : owner[(int64_t)d * n + p];
+#pragma unroll 2
+    for (int j = 0; j < K; ++j) {
+        const float4 wa = W[((int64_t)j * 2) * n + p];
+        const float4 wb = W[((int64_t)j * 2 + 1) * n + p];
+        const float w[8] = {wa.x, wa.y, wa.z, wa.w, wb.x, wb.y, wb.z, wb.w};
+        if (MODE == MLBM_STENCIL_OWN) {
+            const int q = nbr[(int64_t)j * n + p];
+#pragma unroll
+            for (int d = 0; d < 8; ++d) acc[d] += w[d] * g[(int64_t)(d + 1) * n + q];
+        } else {
+#pragma unroll
+            for (int d = 0; d < 8; ++d) {
+                const int q = nbr[(int64_t)j * n + s[d]];
+                acc[d] += w[d] * g[(int64_t)(d + 1) * n + q];
+            }
+        }
+    }
+    float f[kQ];
+    f[0] = g[p];
+#pragma unroll
+    for (int d = 0; d < 8; ++d) f[d + 1] = acc[d];
+    collide_store32<FORCE, WALL, REC>(n, p, f, go, force, ntype, rtau, rho0, rho_w, frec);
 }
 
 // ------------------------------------------------------------------------
@@ -365,11 +432,13 @@ hipError_t step_variant(const CloudPlan &cp, int precision, const void *gin, voi
                            cp.owner, cp.force64, cp.ntype, 1.0 / cp.prm.tau, cp.prm.rho_wall,
                            (double *)frec);
     } else {
-        hipLaunchKernelGGL((k_step32<MODE, FORCE, WALL, REC>), grid, block, 0, s, n, cp.K,
-                           nblocks, (const float *)gin, (float *)gout,
+        hipLaunchKernelGGL((k_step32<MODE, FORCE, WALL, REC>), grid, block, cp.lds_bytes, s, n,
+                           cp.K, nblocks, (const float *)gin, (float *)gout,
                            (const float4 *)cp.W32, cp.nbr, cp.owner, cp.force32, cp.ntype,
                            (float)(1.0 / cp.prm.tau), (float)cp.prm.rho0,
-                           (float)cp.prm.rho_wall, (float *)frec);
+                           (float)cp.prm.rho_wall, (float *)frec,
+                           cp.lds_bytes ? cp.tdesc : nullptr, cp.ownerL, cp.nbrL, cp.hlist,
+                           cp.ocap, cp.hcap);
     }
     return hipGetLastError();
 }

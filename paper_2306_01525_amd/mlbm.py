@@ -239,13 +239,25 @@ class Plan:
 
     # ---- inspection --------------------------------------------------------------
     def export(self, what: str):
-        """Internal arrays in user order: 'perm', 'nbr' [n][K], 'owner' [n][9],
-        'W' [n][9][K] (FP64)."""
+        """Internal arrays: 'perm'; in user order 'nbr' [n][K], 'owner' [n][9],
+        'W' [n][9][K] (FP64); tile tables of the FP32 step in internal order
+        'tdesc' [ntiles][2], 'hlist' [ntiles][hcap], 'nbrL' [ntiles][ocap][K],
+        'ownerL' [8][n], 'caps' (ocap, hcap)."""
         import numpy as np
-        code = {"perm": 0, "nbr": 1, "owner": 2, "W": 3}[what]
         K = self.params.K
-        shape, dt = {0: ((self.n,), np.int32), 1: ((self.n, K), np.int32),
-                     2: ((self.n, 9), np.int32), 3: ((self.n, 9, K), np.float64)}[code]
+        nt = (self.n + int(self.info.tile_nodes) - 1) // int(self.info.tile_nodes)
+        codes = {"perm": 0, "nbr": 1, "owner": 2, "W": 3, "tdesc": 4, "hlist": 5, "nbrL": 6,
+                 "ownerL": 7, "caps": 8}
+        code = codes[what]
+        if code == 5:
+            shape, dt = (nt, int(self.export("caps")[1])), np.int32
+        elif code == 6:
+            shape, dt = (nt, int(self.export("caps")[0]), K), np.uint16
+        else:
+            shape, dt = {0: ((self.n,), np.int32), 1: ((self.n, K), np.int32),
+                         2: ((self.n, 9), np.int32), 3: ((self.n, 9, K), np.float64),
+                         4: ((nt, 2), np.int32), 7: ((8, self.n), np.uint16),
+                         8: ((2,), np.int32)}[code]
         out = np.empty(shape, dtype=dt)
         check(_lib.load().mlbm_plan_export(self._h, 0, code, out.ctypes.data_as(ctypes.c_void_p),
                                            out.nbytes))

@@ -72,3 +72,42 @@ def test_singular_stencil_is_reported():
     with pytest.raises(MLBMError) as ei:
         Plan.build(x, y, (0.0, 0.0), p)
     assert ei.value.status == -2
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+def test_tile_tables_are_consistent(mode):
+    """Gather tables of the FP32 step, checked on the CPU before any step
+    uses them: halo lists sorted, unique and in range; local owners and
+    local stencils map back to the global owners and stencils."""
+    c, _, _ = tgv_case(64, 30, 4, mode, seed=9)
+    plan = _build(c, c.h, 30, 4, mode)
+    perm = plan.export("perm")
+    iperm = np.empty_like(perm)
+    iperm[perm] = np.arange(c.n)
+    nbr_u = plan.export("nbr")            # user order, user indices
+    own_u = plan.export("owner")
+    # internal order, internal indices
+    nbr_i = iperm[nbr_u[perm]]
+    own_i = iperm[own_u[perm]]
+    td = plan.export("tdesc")
+    hl = plan.export("hlist")
+    nl = plan.export("nbrL")
+    ol = plan.export("ownerL") if mode == 0 else None
+    T = int(plan.info.tile_nodes)
+    say("mode", mode, "tiles", td.shape[0], "max nh", td[:, 1].max(), "max no", td[:, 0].max())
+    assert (td[:, 1] > 0).all()
+    for t in range(td.shape[0]):
+        no, nh = td[t]
+        base, cnt = t * T, min(T, c.n - t * T)
+        H = hl[t, :nh]
+        assert (H >= 0).all() and (H < c.n).all()
+        assert (np.diff(H) > 0).all()
+        if mode == 0:
+            O = np.unique(own_i[base:base + cnt, 1:])
+        else:
+            O = np.arange(base, base + cnt)
+        assert O.size == no
+        np.testing.assert_array_equal(H[nl[t, :no, :]], nbr_i[O])
+        if mode == 0:
+            np.testing.assert_array_equal(O[ol[:, base:base + cnt].T], own_i[base:base + cnt, 1:])
+    plan.close()

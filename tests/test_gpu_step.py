@@ -140,3 +140,23 @@ def test_fp32_mass_conservation():
     drift = abs(got[500][0].sum() - c.n) / c.n
     say("fp32 mass drift after 500 steps", drift)
     assert drift < 1e-6
+
+
+def test_tiles_cover_the_workload_and_fallback_path_matches():
+    """Compact clouds use LDS gather tables on every tile; a streaming
+    distance of 4 h spreads the owners of a tile beyond the table caps, so
+    those tiles gather from global memory; both paths match the oracle."""
+    from paper_2306_01525_amd import Plan
+    c, ux, uy = tgv_case(48, 20, 3, 0)
+    plan = Plan.build(c.x, c.y, c.period, _params(c.h, 20, 3, 0, 0, 0.8))
+    say("tiles: lds bytes", plan.info.step_lds_bytes, "fallback", plan.info.fallback_tiles)
+    assert plan.info.step_lds_bytes > 0 and plan.info.fallback_tiles == 0
+    plan.close()
+    dx = 4 * c.h
+    _, ref = oracle_run(c, dx, 20, 3, 0, 0.8, ux, uy, [1, 30])
+    plan = Plan.build(c.x, c.y, c.period, _params(dx, 20, 3, 0, 0, 0.8))
+    say("dx = 4h: lds bytes", plan.info.step_lds_bytes, "fallback", plan.info.fallback_tiles)
+    assert plan.info.fallback_tiles > 0
+    got = _gpu_run(plan, ux, uy, [1, 30])
+    _compare(ref, got, tol_fp32, "dx4h/fp32")
+    plan.close()
