@@ -110,6 +110,12 @@ def run_gpu(args):
     # FP32 deviation form: the headline
     log("building FP32 plan, N =", c.n)
     plan32, build_ms = build(MLBM_FP32_DEV)
+    a, b = plan32.new_state(), plan32.new_state()
+    tune_ms = plan32.autotune(plan32.init(uxt, uyt, g=a), b, 20)
+    out["tune"] = {"ms_per_step": tune_ms, "chosen": int(plan32.info.variant)}
+    log("autotune ms/step per variant:", " ".join("%.4f" % m for m in tune_ms),
+        "-> variant", plan32.info.variant)
+    del a, b
     log("build %.1f ms; timing %d FP32 steps after %d warm-up" % (build_ms, args.steps, args.warmup))
     g = plan32.init(uxt, uyt)
     torch.cuda.synchronize()
@@ -140,6 +146,7 @@ def run_gpu(args):
     if not args.skip_adjoint:
         C = 50
         planA, _ = build(MLBM_FP32_DEV, with_adjoint=1)
+        planA.set_variant(plan32.info.variant)
         with torch.cuda.stream(stream):
             ro = Rollout(planA, C, C)
             ro.forward(uxt, uyt, stream=stream)      # warm
@@ -265,6 +272,7 @@ def main():
         line["fp32_vs_fp64_rel_l2"] = r["fp32_vs_fp64"]
     if "adj_ratio" in r:
         line["adjoint_over_forward"] = r["adj_ratio"]
+    line["autotune"] = r["tune"]
     if not args.no_cpu_baseline:
         log("timing the CPU oracle (%.0f s budget)" % args.cpu_budget)
         line["cpu_baseline"] = cpu_baseline(args.cpu_budget)

@@ -99,6 +99,7 @@ typedef struct {
                                  gathers from global memory only)                  */
     int32_t fallback_tiles;   /* tiles whose gather tables exceed the LDS caps and
                                  gather from global memory (-1: not known)         */
+    int32_t variant;          /* FP32 step variant in use (mlbm_autotune)          */
 } mlbm_plan_info;
 
 /* ---- weight build (Sec. 2.2-2.3; Algorithm 1, initialisation loop) -------- */
@@ -242,6 +243,21 @@ mlbm_status mlbm_step_adjoint(const mlbm_plan *plan, const void *f_n, const void
 mlbm_status mlbm_init_adjoint(const mlbm_plan *plan, const double *u0x, const double *u0y,
                               const void *lamf_0, double *dJ_du0x, double *dJ_du0y,
                               hipStream_t stream);
+
+/* ---- tuning --------------------------------------------------------------- */
+
+/* Autotuner of the FP32 step: times every kernel variant (the unroll depth
+ * of the stencil loop and non-temporal weight loads) for n_steps steps each,
+ * after one warm-up step, on this plan's own cloud, and keeps the fastest for
+ * every later step and graph. ms_out (host, may be NULL) receives the measured
+ * milliseconds per step of each variant, *n_variants (host, may be NULL) their
+ * count. The contents of g_a and g_b are advanced (start again from
+ * mlbm_init afterwards). Synchronous. FP64 plans have a single variant. */
+mlbm_status mlbm_autotune(mlbm_plan *plan, void *g_a, void *g_b, int32_t n_steps,
+                          float *ms_out, int32_t *n_variants, hipStream_t stream);
+
+/* Select an FP32 step variant by index (0 = default); drops a created graph. */
+mlbm_status mlbm_plan_set_variant(mlbm_plan *plan, int32_t variant);
 
 /* ---- graphs ------------------------------------------------------------- */
 

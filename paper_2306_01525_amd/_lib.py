@@ -41,7 +41,8 @@ class Params(ctypes.Structure):
 class PlanInfo(ctypes.Structure):
     _fields_ = [("n_clouds", _c_i32), ("n_total", _c_i64), ("K", _c_i32), ("degree", _c_i32),
                 ("stencil_mode", _c_i32), ("precision", _c_i32), ("state_bytes", _c_sz),
-                ("tile_nodes", _c_i64), ("step_lds_bytes", _c_i32), ("fallback_tiles", _c_i32)]
+                ("tile_nodes", _c_i64), ("step_lds_bytes", _c_i32), ("fallback_tiles", _c_i32),
+                ("variant", _c_i32)]
 
 
 _P = ctypes.POINTER
@@ -67,6 +68,8 @@ SIGNATURES = {
     "mlbm_loss_seed": (_c_i32, [_c_p, _c_p, _c_p, _c_p, _c_p, _c_p, _c_p]),
     "mlbm_step_adjoint": (_c_i32, [_c_p, _c_p, _c_p, _c_p, _c_p, _c_p]),
     "mlbm_init_adjoint": (_c_i32, [_c_p, _c_p, _c_p, _c_p, _c_p, _c_p, _c_p]),
+    "mlbm_autotune": (_c_i32, [_c_p, _c_p, _c_p, _c_i32, _c_p, _P(_c_i32), _c_p]),
+    "mlbm_plan_set_variant": (_c_i32, [_c_p, _c_i32]),
     "mlbm_graph_create": (_c_i32, [_c_p, _c_p, _c_p, _c_i32, _c_p]),
     "mlbm_graph_launch": (_c_i32, [_c_p, _c_p]),
     "mlbm_last_error": (ctypes.c_char_p, []),

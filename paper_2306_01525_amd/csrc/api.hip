@@ -193,6 +193,17 @@ mlbm_status build_tiles(mlbm_plan *plan, CloudPlan &cp, hipStream_t s) {
     return MLBM_OK;
 }
 
+void drop_graph(mlbm_plan *plan) {
+    if (plan->graph_exec) {
+        (void)hipGraphExecDestroy(plan->graph_exec);
+        plan->graph_exec = nullptr;
+    }
+    if (plan->graph) {
+        (void)hipGraphDestroy(plan->graph);
+        plan->graph = nullptr;
+    }
+}
+
 const CloudPlan *single(const mlbm_plan *plan) {
     if (!plan || plan->c.empty()) {
         set_error("null plan");
@@ -456,6 +467,7 @@ mlbm_status mlbm_plan_get_info(const mlbm_plan *plan, mlbm_plan_info *info) {
     info->tile_nodes = kTile;
     info->step_lds_bytes = (int32_t)cp->lds_bytes;
     info->fallback_tiles = cp->fallback_tiles;
+    info->variant = cp->variant;
     return MLBM_OK;
 }
 
@@ -546,14 +558,7 @@ mlbm_status mlbm_plan_set_tau(mlbm_plan *plan, double tau) {
     if (!plan || plan->c.empty()) return fail(MLBM_EINVAL, "null plan");
     if (!(tau > 0.5)) return fail(MLBM_EINVAL, "tau must exceed 0.5");
     for (auto &cp : plan->c) cp.prm.tau = tau;
-    if (plan->graph_exec) {
-        (void)hipGraphExecDestroy(plan->graph_exec);
-        plan->graph_exec = nullptr;
-    }
-    if (plan->graph) {
-        (void)hipGraphDestroy(plan->graph);
-        plan->graph = nullptr;
-    }
+    drop_graph(plan);
     return MLBM_OK;
 }
 
@@ -664,6 +669,62 @@ mlbm_status mlbm_init_adjoint(const mlbm_plan *plan, const double *u0x, const do
     if (!cp || !lamf_0 || !dJ_du0x || !dJ_du0y) return fail(MLBM_EINVAL, "null argument");
     MLBM_HIP(launch_init_adjoint(*cp, plan->precision, u0x, u0y, lamf_0, dJ_du0x, dJ_du0y, s));
     return MLBM_OK;
+}
+
+mlbm_status mlbm_plan_set_variant(mlbm_plan *plan, int32_t variant) {
+    if (!plan || plan->c.empty()) return fail(MLBM_EINVAL, "null plan");
+    if (variant < 0 || variant >= kStepVariants) return fail(MLBM_EINVAL, "unknown variant");
+    for (auto &cp : plan->c) cp.variant = variant;
+    drop_graph(plan);
+    return MLBM_OK;
+}
+
+mlbm_status mlbm_autotune(mlbm_plan *plan, void *g_a, void *g_b, int32_t n_steps,
+                          float *ms_out, int32_t *n_variants, hipStream_t s) {
+    if (!plan || plan->c.empty() || !g_a || !g_b || n_steps < 1)
+        return fail(MLBM_EINVAL, "bad autotune arguments");
+    if (g_a == g_b) return fail(MLBM_EINVAL, "ping-pong buffers must differ");
+    const int nv = plan->precision == MLBM_FP64 ? 1 : kStepVariants;
+    if (n_variants) *n_variants = nv;
+    if (nv == 1) {
+        if (ms_out) ms_out[0] = 0.0f;
+        return MLBM_OK;
+    }
+    hipEvent_t e0, e1;
+    MLBM_HIP(hipEventCreate(&e0));
+    hipError_t err = hipEventCreate(&e1);
+    if (err != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return hip_fail(err, "hipEventCreate");
+    }
+    int best = 0;
+    float best_ms = 0.0f;
+    mlbm_status st = MLBM_OK;
+    for (int v = 0; v < nv && st == MLBM_OK; ++v) {
+        for (auto &cp : plan->c) cp.variant = v;
+        int32_t rb = 0;
+        st = mlbm_step(plan, g_a, g_b, 1, &rb, s);               // warm-up
+        if (st != MLBM_OK) break;
+        void *a = rb ? g_b : g_a, *b = rb ? g_a : g_b;
+        if ((err = hipEventRecord(e0, s)) != hipSuccess) { st = hip_fail(err, "hipEventRecord"); break; }
+        st = mlbm_step(plan, a, b, n_steps, &rb, s);
+        if (st != MLBM_OK) break;
+        if ((err = hipEventRecord(e1, s)) != hipSuccess) { st = hip_fail(err, "hipEventRecord"); break; }
+        if ((err = hipEventSynchronize(e1)) != hipSuccess) { st = hip_fail(err, "hipEventSynchronize"); break; }
+        float ms = 0.0f;
+        if ((err = hipEventElapsedTime(&ms, e0, e1)) != hipSuccess) { st = hip_fail(err, "hipEventElapsedTime"); break; }
+        ms /= (float)n_steps;
+        if (ms_out) ms_out[v] = ms;
+        if (v == 0 || ms < best_ms) {
+            best_ms = ms;
+            best = v;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    for (auto &cp : plan->c) cp.variant = best;
+    drop_graph(plan);
+    return st;
 }
 
 mlbm_status mlbm_graph_create(mlbm_plan *plan, void *g_a, void *g_b, int32_t n_steps,

@@ -30,6 +30,7 @@ __host__ __device__ constexpr double lat_w(int k) {
 constexpr int kQ = 9;
 constexpr int kMaxK = 48;       // largest stencil supported
 constexpr int kTile = 256;      // nodes per workgroup in the step kernels
+constexpr int kStepVariants = 6; // FP32 step tuning variants
 
 inline int poly_count(int m) { return (m + 1) * (m + 2) / 2; }
 
@@ -72,6 +73,7 @@ struct CloudPlan {
     int32_t *hlist = nullptr;     // [ntiles][hcap] global index of H_t entries
     unsigned lds_bytes = 0;       // dynamic LDS of the step launch (0: no tables)
     int fallback_tiles = -1;      // tiles stepped with global gathers (-1: unknown)
+    int variant = 0;              // FP32 step tuning variant (mlbm_autotune)
     // transposed streaming (adjoint): per direction k = 1..8, CSR over the
     // source node m of (arriving node i, weight)
     int32_t *tr_ptr = nullptr;  // [8n+1] row offsets, row (k-1)*n + m

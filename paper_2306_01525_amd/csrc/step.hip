@@ -94,7 +94,17 @@ __device__ __forceinline__ void collide_store32(int n, int p, float (&f)[kQ],
 // tile-local stencils of its owners in LDS, then every interpolation reads LDS
 // only; HBM sees the weights, the tile tables and the halo rows, all
 // contiguous. Tiles without tables gather through global memory.
-template <int MODE, bool FORCE, bool WALL, bool REC>
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+// One row of four FP32 weights; non-temporal loads do not keep the line in
+// the caches.
+__device__ __forceinline__ float4 load_w(const float4 *p, bool nt) {
+    const f32x4 *q = reinterpret_cast<const f32x4 *>(p);
+    const f32x4 v = nt ? __builtin_nontemporal_load(q) : *q;
+    return make_float4(v.x, v.y, v.z, v.w);
+}
+
+template <int MODE, bool FORCE, bool WALL, bool REC, int UNROLL, bool NT>
 __global__ __launch_bounds__(kTile) void k_step32(
     int n, int K, int64_t nblocks, const float *__restrict__ g, float *__restrict__ go,
     const float4 *__restrict__ W, const int32_t *__restrict__ nbr,
@@ -138,10 +148,10 @@ __global__ __launch_bounds__(kTile) void k_step32(
 #pragma unroll
         for (int d = 0; d < 8; ++d)
             ol[d] = (MODE == MLBM_STENCIL_OWN ? tid : (int)ownerL[(int64_t)d * n + p]) * K;
-#pragma unroll 2
+#pragma unroll UNROLL
         for (int j = 0; j < K; ++j) {
-            const float4 wa = W[((int64_t)j * 2) * n + p];
-            const float4 wb = W[((int64_t)j * 2 + 1) * n + p];
+            const float4 wa = load_w(W + ((int64_t)j * 2) * n + p, NT);
+            const float4 wb = load_w(W + ((int64_t)j * 2 + 1) * n + p, NT);
             const float w[8] = {wa.x, wa.y, wa.z, wa.w, wb.x, wb.y, wb.z, wb.w};
             if (MODE == MLBM_STENCIL_OWN) {
                 const int h = nl[ol[0] + j];
@@ -165,10 +175,10 @@ __global__ __launch_bounds__(kTile) void k_step32(
     int s[8];
 #pragma unroll
     for (int d = 0; d < 8; ++d) s[d] = MODE == MLBM_STENCIL_OWN ? p : owner[(int64_t)d * n + p];
-#pragma unroll 2
+#pragma unroll UNROLL
     for (int j = 0; j < K; ++j) {
-        const float4 wa = W[((int64_t)j * 2) * n + p];
-        const float4 wb = W[((int64_t)j * 2 + 1) * n + p];
+        const float4 wa = load_w(W + ((int64_t)j * 2) * n + p, NT);
+        const float4 wb = load_w(W + ((int64_t)j * 2 + 1) * n + p, NT);
         const float w[8] = {wa.x, wa.y, wa.z, wa.w, wb.x, wb.y, wb.z, wb.w};
         if (MODE == MLBM_STENCIL_OWN) {
             const int q = nbr[(int64_t)j * n + p];
@@ -420,25 +430,51 @@ __global__ void k_collide(int n, const T *__restrict__ f, T *__restrict__ g,
     }
 }
 
+// Tuning variants of the FP32 step: unroll depth of the stencil loop (how
+// many weight rows a lane has in flight) and non-temporal weight loads (the
+// weights are streamed once per step and need not displace the halo rows in
+// L2). Variant v: unroll {2, 4, 6}[v / 2], non-temporal v % 2.
+template <int MODE, bool FORCE, bool WALL, bool REC, int UNROLL, bool NT>
+void launch32(const CloudPlan &cp, const void *gin, void *gout, void *frec, int64_t nblocks,
+              hipStream_t s) {
+    const int n = cp.n;
+    hipLaunchKernelGGL((k_step32<MODE, FORCE, WALL, REC, UNROLL, NT>), dim3(xcd_grid(nblocks)),
+                       dim3(kTile), cp.lds_bytes, s, n, cp.K, nblocks, (const float *)gin,
+                       (float *)gout, (const float4 *)cp.W32, cp.nbr, cp.owner, cp.force32,
+                       cp.ntype, (float)(1.0 / cp.prm.tau), (float)cp.prm.rho0,
+                       (float)cp.prm.rho_wall, (float *)frec, cp.lds_bytes ? cp.tdesc : nullptr,
+                       cp.ownerL, cp.nbrL, cp.hlist, cp.ocap, cp.hcap);
+}
+
+template <int MODE, bool FORCE, bool WALL, bool REC>
+void launch32_tuned(const CloudPlan &cp, const void *gin, void *gout, void *frec,
+                    int64_t nblocks, hipStream_t s) {
+    if (FORCE || WALL) {   // walled and forced clouds use the default variant
+        launch32<MODE, FORCE, WALL, REC, 2, false>(cp, gin, gout, frec, nblocks, s);
+        return;
+    }
+    switch (cp.variant) {
+        case 1: launch32<MODE, FORCE, WALL, REC, 2, true>(cp, gin, gout, frec, nblocks, s); break;
+        case 2: launch32<MODE, FORCE, WALL, REC, 4, false>(cp, gin, gout, frec, nblocks, s); break;
+        case 3: launch32<MODE, FORCE, WALL, REC, 4, true>(cp, gin, gout, frec, nblocks, s); break;
+        case 4: launch32<MODE, FORCE, WALL, REC, 6, false>(cp, gin, gout, frec, nblocks, s); break;
+        case 5: launch32<MODE, FORCE, WALL, REC, 6, true>(cp, gin, gout, frec, nblocks, s); break;
+        default: launch32<MODE, FORCE, WALL, REC, 2, false>(cp, gin, gout, frec, nblocks, s); break;
+    }
+}
+
 template <int MODE, bool FORCE, bool WALL, bool REC>
 hipError_t step_variant(const CloudPlan &cp, int precision, const void *gin, void *gout,
                         void *frec, hipStream_t s) {
     const int n = cp.n;
     const int64_t nblocks = (n + kTile - 1) / kTile;
-    dim3 grid(xcd_grid(nblocks)), block(kTile);
     if (precision == MLBM_FP64) {
-        hipLaunchKernelGGL((k_step64<MODE, FORCE, WALL, REC>), grid, block, 0, s, n, cp.K,
-                           nblocks, (const double *)gin, (double *)gout, cp.W64, cp.nbr,
-                           cp.owner, cp.force64, cp.ntype, 1.0 / cp.prm.tau, cp.prm.rho_wall,
-                           (double *)frec);
+        hipLaunchKernelGGL((k_step64<MODE, FORCE, WALL, REC>), dim3(xcd_grid(nblocks)),
+                           dim3(kTile), 0, s, n, cp.K, nblocks, (const double *)gin,
+                           (double *)gout, cp.W64, cp.nbr, cp.owner, cp.force64, cp.ntype,
+                           1.0 / cp.prm.tau, cp.prm.rho_wall, (double *)frec);
     } else {
-        hipLaunchKernelGGL((k_step32<MODE, FORCE, WALL, REC>), grid, block, cp.lds_bytes, s, n,
-                           cp.K, nblocks, (const float *)gin, (float *)gout,
-                           (const float4 *)cp.W32, cp.nbr, cp.owner, cp.force32, cp.ntype,
-                           (float)(1.0 / cp.prm.tau), (float)cp.prm.rho0,
-                           (float)cp.prm.rho_wall, (float *)frec,
-                           cp.lds_bytes ? cp.tdesc : nullptr, cp.ownerL, cp.nbrL, cp.hlist,
-                           cp.ocap, cp.hcap);
+        launch32_tuned<MODE, FORCE, WALL, REC>(cp, gin, gout, frec, nblocks, s);
     }
     return hipGetLastError();
 }

@@ -229,6 +229,26 @@ class Plan:
                                             _ptr(gx), _ptr(gy), _stream(stream)))
         return gx, gy
 
+    # ---- tuning ----------------------------------------------------------------
+    def autotune(self, g_a, g_b, n_steps: int = 20, stream=None):
+        """Time every FP32 step variant on this cloud and keep the fastest;
+        returns the milliseconds per step of each variant. Advances g_a/g_b."""
+        ms = (ctypes.c_float * 16)()
+        nv = ctypes.c_int32()
+        check(_lib.load().mlbm_autotune(self._h, _ptr(g_a), _ptr(g_b), int(n_steps), ms,
+                                        ctypes.byref(nv), _stream(stream)))
+        self._refresh_info()
+        return [ms[i] for i in range(nv.value)]
+
+    def set_variant(self, v: int):
+        check(_lib.load().mlbm_plan_set_variant(self._h, int(v)))
+        self._refresh_info()
+
+    def _refresh_info(self):
+        info = _lib.PlanInfo()
+        check(_lib.load().mlbm_plan_get_info(self._h, ctypes.byref(info)))
+        self.info = info
+
     # ---- graphs ----------------------------------------------------------------
     def graph_create(self, g_a, g_b, n_steps: int, stream):
         check(_lib.load().mlbm_graph_create(self._h, _ptr(g_a), _ptr(g_b), int(n_steps),

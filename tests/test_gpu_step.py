@@ -160,3 +160,24 @@ def test_tiles_cover_the_workload_and_fallback_path_matches():
     got = _gpu_run(plan, ux, uy, [1, 30])
     _compare(ref, got, tol_fp32, "dx4h/fp32")
     plan.close()
+
+
+def test_step_variants_are_bitwise_identical_and_autotune_picks_one():
+    from paper_2306_01525_amd import Plan
+    c, ux, uy = tgv_case(40, 30, 4, 0)
+    plan = Plan.build(c.x, c.y, c.period, _params(c.h, 30, 4, 0, 0, 0.6))
+    ref = None
+    for v in range(6):
+        plan.set_variant(v)
+        g = plan.init(ux, uy)
+        g = plan.step(g, plan.new_state(), 25)
+        if ref is None:
+            ref = g.clone()
+        else:
+            assert torch.equal(g, ref), v
+    a, b = plan.new_state(), plan.new_state()
+    ms = plan.autotune(plan.init(ux, uy, g=a), b, 5)
+    say("variant ms/step", ["%.4f" % m for m in ms], "chosen", plan.info.variant)
+    assert len(ms) == 6 and all(m > 0 for m in ms)
+    assert ms[plan.info.variant] == min(ms)
+    plan.close()
