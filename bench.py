@@ -196,6 +196,71 @@ def cpu_baseline(budget_s: float):
                       "tau 0.6, paper stencils), %d steps in %.1f s after setup" % (steps, dt)}
 
 
+COPY_BYTES = 256 << 20
+
+
+def copy_calibration():
+    """A plain elementwise copy of known size (reads and writes COPY_BYTES)
+    for scaling the HBM byte counters."""
+    import torch
+    x = torch.ones(COPY_BYTES // 4, dtype=torch.float32, device="cuda")
+    y = torch.empty_like(x)
+    for _ in range(3):
+        torch.mul(x, 1.0, out=y)
+    torch.cuda.synchronize()
+
+
+def _read_counter_csv(path):
+    import csv
+    rows = []
+    for root, _, files in os.walk(path):
+        for f in files:
+            if f.endswith("counter_collection.csv"):
+                with open(os.path.join(root, f)) as fh:
+                    rows.extend(csv.DictReader(fh))
+    return rows
+
+
+def summarize_pmc(fetch_dir, write_dir, command):
+    """Per-dispatch FETCH_SIZE and WRITE_SIZE (KiB) of the step kernel and of
+    the copy kernel, the copy-based scale factor, and the HBM bytes per step
+    launch; writes the JSON that bench.py reads and prints a text summary."""
+    def per_kernel(rows, counter):
+        acc = {}
+        for r in rows:
+            name = r.get("Kernel_Name", "")
+            if r.get("Counter_Name", "") != counter:
+                continue
+            acc.setdefault(name, {})
+            did = r.get("Dispatch_Id", str(len(acc[name])))
+            acc[name][did] = acc[name].get(did, 0.0) + float(r["Counter_Value"])
+        return {k: sorted(v.values()) for k, v in acc.items()}
+
+    fetch = per_kernel(_read_counter_csv(fetch_dir), "FETCH_SIZE")
+    write = per_kernel(_read_counter_csv(write_dir), "WRITE_SIZE")
+    steps = [k for k in fetch if "k_step32" in k]
+    step = max(steps, key=lambda k: len(fetch[k]))
+    copy = [k for k in fetch if "elementwise" in k and "mul" in k.lower()]
+    copy = max(copy, key=lambda k: len(fetch[k]))
+
+    def median(v):
+        return v[len(v) // 2]
+
+    fk_copy, wk_copy = median(fetch[copy]), median(write[copy])
+    f_scale = (COPY_BYTES / 1024.0) / fk_copy
+    w_scale = (COPY_BYTES / 1024.0) / wk_copy
+    fk, wk = median(fetch[step]), median(write[step])
+    bytes_launch = fk * 1024.0 * f_scale + wk * 1024.0 * w_scale
+    out = {"kernel": step, "kernel_hash": step_kernel_hash(), "dispatches": len(fetch[step]),
+           "fetch_kib": fk, "write_kib": wk, "copy_kernel": copy, "copy_fetch_kib": fk_copy,
+           "copy_write_kib": wk_copy, "copy_bytes": COPY_BYTES, "fetch_scale": f_scale,
+           "write_scale": w_scale, "bytes_per_launch": bytes_launch, "command": command}
+    os.makedirs(os.path.dirname(PROFILE_PMC), exist_ok=True)
+    with open(PROFILE_PMC, "w") as fh:
+        json.dump(out, fh, indent=1)
+    print(json.dumps(out, indent=1))
+
+
 def load_traffic(nodes, steps):
     """HBM bytes per step-kernel launch from committed rocprofv3 counters,
     only when they were taken on the current kernel source."""
@@ -218,7 +283,15 @@ def main():
     ap.add_argument("--skip-adjoint", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run a copy of known size (for HBM counter scaling)")
+    ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
+                    help="summarise two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE)")
+    ap.add_argument("--pmc-command", default="", help="command recorded in the summary")
     args = ap.parse_args()
+    if args.summarize_pmc:
+        summarize_pmc(args.summarize_pmc[0], args.summarize_pmc[1], args.pmc_command)
+        return
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
               "(--gpus %d requested)" % args.gpus, file=sys.stderr)
@@ -226,6 +299,8 @@ def main():
     if int(os.environ.get("RANK", "0")) != 0:
         sys.exit(0)
 
+    if args.copy_calibration:
+        copy_calibration()
     r = run_gpu(args)
     n, K, steps = r["n"], r["K"], args.steps
     ms_step = r["ms32"] / steps
