@@ -172,6 +172,70 @@ def run_gpu(args):
     return out
 
 
+def run_batched(steps: int):
+    """64 Taylor-Green clouds of uneven size (10^4 to 2x10^5 nodes,
+    log-uniform, seed 4), each with its own tau in [0.55, 1] and degree 2-4
+    (K 12/20/30), own-node stencils (one stencil rule for the whole batch),
+    FP32. One HIP graph holds the weight build of all clouds, the initial state
+    and `steps` steps; it is launched once and timed, and the steps alone are
+    timed from a second graph."""
+    import numpy as np
+    import torch
+    from paper_2306_01525_amd import MLBM_STENCIL_OWN, Params, Plan
+    from synth import batched_tgv_specs, jittered_lattice, tgv_initial_velocity
+    specs = batched_tgv_specs(64, seed=4)
+    clouds, params, ux, uy = [], [], [], []
+    for sp in specs:
+        c = jittered_lattice(sp["n_side"], seed=sp["seed"])
+        a, b = tgv_initial_velocity(c.x, c.y, c.period[0], 0.01)
+        clouds.append((c.x, c.y, c.period, None))
+        params.append(Params(dx=c.h, K=sp["K"], degree=sp["degree"], tau=sp["tau"],
+                             stencil_mode=MLBM_STENCIL_OWN))
+        ux.append(a)
+        uy.append(b)
+    ux, uy = np.concatenate(ux), np.concatenate(uy)
+    n_total = ux.shape[0]
+    log("batched: %d clouds, %d nodes; eager build + autotune" % (len(clouds), n_total))
+    eager = Plan.build_batch(clouds, params)
+    a, b = eager.new_state(), eager.new_state()
+    tune = eager.autotune(eager.init(ux, uy, g=a), b, 10)
+    variant = int(eager.info.variant)
+    del a, b
+    stream = torch.cuda.Stream()
+    # steps only
+    with torch.cuda.stream(stream):
+        g0 = eager.init(ux, uy, stream=stream)
+        g1 = eager.new_state()
+        eager.graph_create(g0, g1, steps, stream)
+        eager.graph_launch(stream)                     # warm
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        eager.graph_launch(stream)
+        e1.record(stream)
+        torch.cuda.synchronize()
+    steps_ms = e0.elapsed_time(e1)
+    eager.close()
+    # build + init + steps in one graph
+    plan, g_a, g_b, res = Plan.build_graph(clouds, params, ux, uy, steps, stream, variant)
+    plan.graph_launch(stream)                          # warm
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    plan.graph_launch(stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    full_ms = e0.elapsed_time(e1)
+    err = plan.device_error()
+    plan.close()
+    log("batched: build+init+%d steps %.1f ms in one graph; steps alone %.1f ms" % (steps, full_ms, steps_ms))
+    return {"clouds": len(clouds), "nodes": int(n_total), "steps": steps,
+            "graph_ms_build_init_steps": full_ms, "graph_ms_steps": steps_ms,
+            "node_updates_per_s_steps": n_total * steps / (steps_ms / 1e3),
+            "node_updates_per_s_incl_build": n_total * steps / (full_ms / 1e3),
+            "variant": variant, "autotune_ms_per_step": tune, "device_error": err}
+
+
 def cpu_baseline(budget_s: float):
     """The FP64 CPU oracle on a bounded sample of the same workload: a
     128 x 128 cloud of the same kind (16,384 nodes, same jitter, K, degree,
@@ -282,6 +346,8 @@ def main():
     ap.add_argument("--skip-fp64", action="store_true")
     ap.add_argument("--skip-adjoint", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--skip-batched", action="store_true")
+    ap.add_argument("--batched-steps", type=int, default=500)
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a copy of known size (for HBM counter scaling)")
@@ -348,6 +414,8 @@ def main():
     if "adj_ratio" in r:
         line["adjoint_over_forward"] = r["adj_ratio"]
     line["autotune"] = r["tune"]
+    if not args.skip_batched:
+        line["batched_64_clouds"] = run_batched(args.batched_steps)
     if not args.no_cpu_baseline:
         log("timing the CPU oracle (%.0f s budget)" % args.cpu_budget)
         line["cpu_baseline"] = cpu_baseline(args.cpu_budget)

@@ -10,6 +10,11 @@
  * shape_vector, poly_sets). Collision is BGK (Sec. 2.1, eqs. LBM_collision,
  * feq), optionally with the body-force term of Sec. 3.
  *
+ * Several clouds (n_clouds > 1) form one plan: their nodes are concatenated
+ * in cloud order for every per-node input and output, and the state arrays
+ * hold one [9][n_c] block per cloud. Clouds with FP32 state, a common stencil
+ * rule and no walls or force are stepped by a single launch per step.
+ *
  * Conventions shared by every entry point:
  *  - Memory. The caller owns every device byte (typically torch tensors). The
  *    library never allocates device memory: sizes come from the *_query calls
@@ -255,6 +260,22 @@ mlbm_status mlbm_init_adjoint(const mlbm_plan *plan, const double *u0x, const do
  * mlbm_init afterwards). Synchronous. FP64 plans have a single variant. */
 mlbm_status mlbm_autotune(mlbm_plan *plan, void *g_a, void *g_b, int32_t n_steps,
                           float *ms_out, int32_t *n_variants, hipStream_t stream);
+
+/* The whole batched workload as one HIP graph: captures, on `stream` (not the
+ * default stream), the weight build of every cloud (mlbm_build_weights), the
+ * initial state from rho/ux/uy into g_a (mlbm_init) and n_steps steps on
+ * (g_a, g_b) (mlbm_step) with FP32 step variant `variant`. Nothing runs until
+ * mlbm_graph_launch; each launch rebuilds the weights and restarts from the
+ * initial state. Buffers as for those calls; the workspace and the inputs must
+ * stay allocated while the graph is used. The step LDS size is the capacity
+ * bound (no size read-back under capture) and a singular system is reported
+ * through mlbm_device_error after a launch. */
+mlbm_status mlbm_build_graph(const mlbm_cloud *clouds, const mlbm_params *params,
+                             int32_t n_clouds, void *plan_buf, size_t plan_bytes,
+                             void *workspace, size_t workspace_bytes, const double *rho,
+                             const double *ux, const double *uy, void *g_a, void *g_b,
+                             int32_t n_steps, int32_t variant, mlbm_plan **out,
+                             hipStream_t stream);
 
 /* Select an FP32 step variant by index (0 = default); drops a created graph. */
 mlbm_status mlbm_plan_set_variant(mlbm_plan *plan, int32_t variant);

@@ -70,6 +70,8 @@ SIGNATURES = {
     "mlbm_init_adjoint": (_c_i32, [_c_p, _c_p, _c_p, _c_p, _c_p, _c_p, _c_p]),
     "mlbm_autotune": (_c_i32, [_c_p, _c_p, _c_p, _c_i32, _c_p, _P(_c_i32), _c_p]),
     "mlbm_plan_set_variant": (_c_i32, [_c_p, _c_i32]),
+    "mlbm_build_graph": (_c_i32, [_P(Cloud), _P(Params), _c_i32, _c_p, _c_sz, _c_p, _c_sz,
+                                  _c_p, _c_p, _c_p, _c_p, _c_p, _c_i32, _c_i32, _P(_c_p), _c_p]),
     "mlbm_graph_create": (_c_i32, [_c_p, _c_p, _c_p, _c_i32, _c_p]),
     "mlbm_graph_launch": (_c_i32, [_c_p, _c_p]),
     "mlbm_last_error": (ctypes.c_char_p, []),

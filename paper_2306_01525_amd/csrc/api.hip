@@ -151,9 +151,10 @@ void layout_cloud(const mlbm_cloud &c, const mlbm_params &p, int precision, Carv
     }
 }
 
-void layout_common(Carve &pl, mlbm_plan &plan, int64_t n_total) {
+void layout_common(Carve &pl, mlbm_plan &plan, int64_t n_total, int n_clouds = 1) {
     plan.dev_err = pl.take<int32_t>(64);
-    plan.scratch64 = pl.take<double>(16 + (size_t)blocks_for(n_total, 256) * 4);
+    plan.scratch64 =
+        pl.take<double>(16 + 4 * (size_t)n_clouds + (size_t)blocks_for(n_total, 256) * 4);
 }
 
 bool capturing(hipStream_t s) {
@@ -221,21 +222,129 @@ extern "C" {
 
 const char *mlbm_last_error(void) { return g_error.c_str(); }
 
+namespace {
+
+// Layout of a whole plan (clouds back to back, then the batch tables and the
+// shared words). With null bases only the sizes are computed.
+struct PlanLayout {
+    std::vector<CloudPlan> cps;
+    std::vector<BuildWs> bws;
+    size_t plan_used = 0, ws_max = 0;
+};
+
+mlbm_status check_batch(const mlbm_cloud *clouds, const mlbm_params *params, int32_t n_clouds,
+                        bool device_cloud) {
+    if (!clouds || !params || n_clouds < 1) return fail(MLBM_EINVAL, "null argument or n_clouds < 1");
+    int64_t total = 0;
+    for (int c = 0; c < n_clouds; ++c) {
+        mlbm_status st = check_params(clouds[c], params[c], device_cloud);
+        if (st != MLBM_OK) return fail(st, "cloud " + std::to_string(c) + ": " + g_error);
+        if (params[c].precision != params[0].precision)
+            return fail(MLBM_EINVAL, "all clouds of a plan need the same precision");
+        if (n_clouds > 1 && params[c].with_adjoint)
+            return fail(MLBM_EUNSUPPORTED, "the adjoint needs a single-cloud plan");
+        if (clouds[c].period_x > 0 != clouds[c].period_y > 0)
+            return fail(MLBM_EUNSUPPORTED, "clouds periodic along one axis only");
+        total += clouds[c].n;
+    }
+    if (total > INT32_MAX / 2) return fail(MLBM_EUNSUPPORTED, "too many nodes in one plan");
+    return MLBM_OK;
+}
+
+bool batchable(const mlbm_params *params, int32_t n_clouds) {
+    if (n_clouds < 2 || params[0].precision != MLBM_FP32_DEV) return false;
+    for (int c = 0; c < n_clouds; ++c)
+        if (params[c].stencil_mode != params[0].stencil_mode || params[c].force_kind ||
+            params[c].wall_kind)
+            return false;
+    return true;
+}
+
+void layout_plan(const mlbm_cloud *clouds, const mlbm_params *params, int32_t n_clouds,
+                 void *plan_buf, void *workspace, PlanLayout &L, mlbm_plan &plan) {
+    Carve pl(plan_buf);
+    L.cps.assign(n_clouds, CloudPlan());
+    L.bws.assign(n_clouds, BuildWs());
+    int64_t off = 0, tiles = 0;
+    for (int c = 0; c < n_clouds; ++c) {
+        Carve ws(workspace);   // clouds are built one after another: shared workspace
+        layout_cloud(clouds[c], params[c], params[0].precision, pl, &ws, L.cps[c], &L.bws[c]);
+        L.cps[c].off = off;
+        off += clouds[c].n;
+        tiles += (clouds[c].n + kTile - 1) / kTile;
+        L.ws_max = std::max(L.ws_max, ws.used);
+    }
+    plan.n_total = off;
+    plan.total_tiles = tiles;
+    plan.batched = batchable(params, n_clouds);
+    plan.batch_mode = params[0].stencil_mode;
+    if (plan.batched) {
+        plan.descs = pl.take<Step32Args>(n_clouds);
+        plan.tile2cloud = pl.take<int32_t>(tiles);
+    }
+    layout_common(pl, plan, off, n_clouds);
+    L.plan_used = pl.used;
+}
+
+// Enqueue the build of one cloud (steps 1-4 of mlbm_build_weights).
+mlbm_status build_cloud(mlbm_plan *plan, CloudPlan &cp, const mlbm_cloud &c,
+                        const mlbm_params &p, BuildWs &bw, hipStream_t s) {
+    const int n = c.n;
+    if (c.period_x > 0 && c.period_y > 0)
+        MLBM_HIP(launch_geo_periodic(cp.geo, c.period_x, c.period_y, bw.gx, bw.gy, bw.hb, s));
+    else
+        MLBM_HIP(launch_geo_bbox(cp.geo, c.x, c.y, n, bw.gx, bw.gy, bw.hb, s));
+    MLBM_HIP(launch_keys(cp.geo, c.x, c.y, n, bw.keys, bw.vals, s));
+    MLBM_HIP(sort_pairs(bw.sort_tmp, bw.sort_bytes, bw.keys, bw.skeys, bw.vals, cp.perm, n,
+                        std::max(1, 2 * bw.hb), s));
+    MLBM_HIP(launch_scatter_sorted(cp.geo, c.x, c.y, c.node_type, cp.perm, bw.skeys, n, cp.xs,
+                                   cp.ys, cp.ntype, cp.iperm, bw.cstart, bw.cend, bw.gx * bw.gy, s));
+    MLBM_HIP(launch_knn(cp.geo, cp.xs, cp.ys, cp.perm, cp.iperm, bw.cstart, bw.cend, n, p.K,
+                        cp.nbr, s));
+    if (p.stencil_mode == MLBM_STENCIL_PAPER)
+        MLBM_HIP(launch_owner(cp.geo, cp.xs, cp.ys, cp.perm, cp.iperm, bw.cstart, bw.cend, n,
+                              p.dx, cp.owner, s));
+    MLBM_HIP(launch_rbf(cp.geo, cp.xs, cp.ys, cp.perm, cp.nbr, cp.owner, n, p.K, p.degree, p.dx,
+                        p.stencil_mode, cp.ntype, cp.W64, plan->dev_err, s));
+    if (cp.W32) MLBM_HIP(launch_pack_w32(cp.W64, n, p.K, cp.W32, s));
+    MLBM_HIP(launch_force(cp.xs, cp.ys, cp.ntype, n, p.force_kind, p.force_mag, cp.force32,
+                          cp.force64, s));
+    if (p.with_adjoint) MLBM_HIP(launch_transpose(cp, p.precision, bw.tr_tmp, bw.tr_bytes, s));
+    return build_tiles(plan, cp, s);
+}
+
+// Descriptor table and tile map of the batched step.
+mlbm_status build_batch(mlbm_plan *plan, hipStream_t s) {
+    if (!plan->batched) return MLBM_OK;
+    int64_t tb = 0;
+    unsigned lds = 0;
+    for (size_t c = 0; c < plan->c.size(); ++c) {
+        CloudPlan &cp = plan->c[c];
+        Step32Args a = step32_args(cp, nullptr);
+        a.soff = (int64_t)kQ * cp.off;
+        a.tile_begin = tb;
+        const int64_t nt = (cp.n + kTile - 1) / kTile;
+        MLBM_HIP(launch_set_desc(plan->descs + c, a, s));
+        MLBM_HIP(launch_fill_i32(plan->tile2cloud + tb, (int32_t)c, nt, s));
+        tb += nt;
+        lds = std::max(lds, cp.lds_bytes);
+    }
+    plan->batch_lds = lds;
+    return MLBM_OK;
+}
+
+}  // namespace
+
 mlbm_status mlbm_weights_query(const mlbm_cloud *clouds, const mlbm_params *params,
                                int32_t n_clouds, size_t *plan_bytes, size_t *workspace_bytes) {
-    if (!clouds || !params || !plan_bytes || !workspace_bytes || n_clouds < 1)
-        return fail(MLBM_EINVAL, "null argument or n_clouds < 1");
-    if (n_clouds != 1) return fail(MLBM_EUNSUPPORTED, "use mlbm_batch_* for several clouds");
-    mlbm_status st = check_params(clouds[0], params[0], false);
+    if (!plan_bytes || !workspace_bytes) return fail(MLBM_EINVAL, "null output pointer");
+    mlbm_status st = check_batch(clouds, params, n_clouds, false);
     if (st != MLBM_OK) return st;
-    Carve pl(nullptr), ws(nullptr);
-    CloudPlan cp;
-    BuildWs bw;
+    PlanLayout L;
     mlbm_plan tmp;
-    layout_cloud(clouds[0], params[0], params[0].precision, pl, &ws, cp, &bw);
-    layout_common(pl, tmp, clouds[0].n);
-    *plan_bytes = pl.used + 256;
-    *workspace_bytes = ws.used + 256;
+    layout_plan(clouds, params, n_clouds, nullptr, nullptr, L, tmp);
+    *plan_bytes = L.plan_used + 256;
+    *workspace_bytes = L.ws_max + 256;
     return MLBM_OK;
 }
 
@@ -248,58 +357,29 @@ mlbm_status mlbm_build_weights(const mlbm_cloud *clouds, const mlbm_params *para
     size_t need_p = 0, need_w = 0;
     mlbm_status st = mlbm_weights_query(clouds, params, n_clouds, &need_p, &need_w);
     if (st != MLBM_OK) return st;
-    if (!clouds[0].x || !clouds[0].y) return fail(MLBM_EINVAL, "cloud coordinates are null");
+    st = check_batch(clouds, params, n_clouds, true);
+    if (st != MLBM_OK) return st;
     if (!plan_buf || !workspace) return fail(MLBM_EINVAL, "null plan buffer or workspace");
     if (plan_bytes < need_p || workspace_bytes < need_w)
         return fail(MLBM_ESMALLBUF, "plan or workspace buffer smaller than queried");
-    const mlbm_cloud &c = clouds[0];
-    const mlbm_params &p = params[0];
     mlbm_plan *plan = new (std::nothrow) mlbm_plan();
     if (!plan) return fail(MLBM_EINVAL, "out of host memory");
-    plan->precision = p.precision;
-    plan->n_total = c.n;
-    Carve pl(plan_buf), ws(workspace);
-    CloudPlan cp;
-    BuildWs bw;
-    layout_cloud(c, p, p.precision, pl, &ws, cp, &bw);
-    layout_common(pl, *plan, c.n);
-    plan->c.push_back(cp);
-    const int n = c.n;
+    plan->precision = params[0].precision;
+    PlanLayout L;
+    layout_plan(clouds, params, n_clouds, plan_buf, workspace, L, *plan);
+    plan->c = L.cps;
     auto cleanup = [&](mlbm_status r) {
         delete plan;
         return r;
     };
-#define STEP(call)                                                      \
-    do {                                                                \
-        hipError_t e_ = (call);                                         \
-        if (e_ != hipSuccess) return cleanup(hip_fail(e_, #call));      \
-    } while (0)
-    if (c.period_x > 0 && c.period_y > 0)
-        STEP(launch_geo_periodic(cp.geo, c.period_x, c.period_y, bw.gx, bw.gy, bw.hb, s));
-    else if (c.period_x > 0 || c.period_y > 0)
-        return cleanup(fail(MLBM_EUNSUPPORTED, "clouds periodic along one axis only"));
-    else
-        STEP(launch_geo_bbox(cp.geo, c.x, c.y, n, bw.gx, bw.gy, bw.hb, s));
-    STEP(launch_keys(cp.geo, c.x, c.y, n, bw.keys, bw.vals, s));
-    STEP(sort_pairs(bw.sort_tmp, bw.sort_bytes, bw.keys, bw.skeys, bw.vals, cp.perm, n,
-                    std::max(1, 2 * bw.hb), s));
-    STEP(launch_scatter_sorted(cp.geo, c.x, c.y, c.node_type, cp.perm, bw.skeys, n, cp.xs,
-                               cp.ys, cp.ntype, cp.iperm, bw.cstart, bw.cend, bw.gx * bw.gy, s));
-    STEP(launch_knn(cp.geo, cp.xs, cp.ys, cp.perm, cp.iperm, bw.cstart, bw.cend, n, p.K, cp.nbr, s));
-    if (p.stencil_mode == MLBM_STENCIL_PAPER)
-        STEP(launch_owner(cp.geo, cp.xs, cp.ys, cp.perm, cp.iperm, bw.cstart, bw.cend, n, p.dx,
-                          cp.owner, s));
-    STEP(launch_fill_i32(plan->dev_err, INT_MAX, 1, s));
-    STEP(launch_rbf(cp.geo, cp.xs, cp.ys, cp.perm, cp.nbr, cp.owner, n, p.K, p.degree, p.dx,
-                    p.stencil_mode, cp.ntype, cp.W64, plan->dev_err, s));
-    if (cp.W32) STEP(launch_pack_w32(cp.W64, n, p.K, cp.W32, s));
-    STEP(launch_force(cp.xs, cp.ys, cp.ntype, n, p.force_kind, p.force_mag, cp.force32,
-                      cp.force64, s));
-    if (p.with_adjoint) STEP(launch_transpose(cp, p.precision, bw.tr_tmp, bw.tr_bytes, s));
-#undef STEP
-    st = build_tiles(plan, cp, s);
+    hipError_t e = launch_fill_i32(plan->dev_err, INT_MAX, 1, s);
+    if (e != hipSuccess) return cleanup(hip_fail(e, "launch_fill_i32"));
+    for (int c = 0; c < n_clouds; ++c) {
+        st = build_cloud(plan, plan->c[c], clouds[c], params[c], L.bws[c], s);
+        if (st != MLBM_OK) return cleanup(st);
+    }
+    st = build_batch(plan, s);
     if (st != MLBM_OK) return cleanup(st);
-    plan->c[0] = cp;
     st = check_singular(plan, s);
     if (st != MLBM_OK) return cleanup(st);
     *out = plan;
@@ -570,38 +650,66 @@ int32_t mlbm_device_error(const mlbm_plan *plan) {
     return v == INT_MAX ? 0 : v;
 }
 
+namespace {
+
+// Sub-array of cloud c inside a state-shaped array (cloud blocks of [9][n_c]).
+inline void *state_at(const mlbm_plan *plan, const void *base, const CloudPlan &cp) {
+    return (char *)base + (size_t)kQ * cp.off * state_elem_bytes(plan->precision);
+}
+inline const double *node_at(const double *base, const CloudPlan &cp) {
+    return base ? base + cp.off : nullptr;
+}
+inline double *out_at(double *base, const CloudPlan &cp) { return base ? base + cp.off : nullptr; }
+
+// One timestep of every cloud: the batched kernel when the plan allows it,
+// else one launch per cloud.
+hipError_t step_once(const mlbm_plan *plan, const void *gin, void *gout, void *frec,
+                     hipStream_t s) {
+    if (plan->batched && !frec) return launch_step_batch(*plan, gin, gout, s);
+    for (const CloudPlan &cp : plan->c) {
+        hipError_t e = launch_step(cp, plan->precision, state_at(plan, gin, cp),
+                                   state_at(plan, gout, cp),
+                                   frec ? state_at(plan, frec, cp) : nullptr, s);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+}  // namespace
+
 mlbm_status mlbm_init(const mlbm_plan *plan, const double *rho, const double *ux,
                       const double *uy, void *g, hipStream_t s) {
-    const CloudPlan *cp = single(plan);
-    if (!cp || !g) return fail(MLBM_EINVAL, "null plan or state");
-    MLBM_HIP(launch_init(*cp, plan->precision, rho, ux, uy, g, true, s));
+    if (!single(plan) || !g) return fail(MLBM_EINVAL, "null plan or state");
+    for (const CloudPlan &cp : plan->c)
+        MLBM_HIP(launch_init(cp, plan->precision, node_at(rho, cp), node_at(ux, cp),
+                             node_at(uy, cp), state_at(plan, g, cp), true, s));
     return MLBM_OK;
 }
 
 mlbm_status mlbm_init_f(const mlbm_plan *plan, const double *rho, const double *ux,
                         const double *uy, void *f, hipStream_t s) {
-    const CloudPlan *cp = single(plan);
-    if (!cp || !f) return fail(MLBM_EINVAL, "null plan or state");
-    MLBM_HIP(launch_init(*cp, plan->precision, rho, ux, uy, f, false, s));
+    if (!single(plan) || !f) return fail(MLBM_EINVAL, "null plan or state");
+    for (const CloudPlan &cp : plan->c)
+        MLBM_HIP(launch_init(cp, plan->precision, node_at(rho, cp), node_at(ux, cp),
+                             node_at(uy, cp), state_at(plan, f, cp), false, s));
     return MLBM_OK;
 }
 
 mlbm_status mlbm_collide(const mlbm_plan *plan, const void *f, void *g, hipStream_t s) {
-    const CloudPlan *cp = single(plan);
-    if (!cp || !f || !g) return fail(MLBM_EINVAL, "null plan or state");
+    if (!single(plan) || !f || !g) return fail(MLBM_EINVAL, "null plan or state");
     if (f == g) return fail(MLBM_EINVAL, "collide needs distinct input and output");
-    MLBM_HIP(launch_collide(*cp, plan->precision, f, g, s));
+    for (const CloudPlan &cp : plan->c)
+        MLBM_HIP(launch_collide(cp, plan->precision, state_at(plan, f, cp), state_at(plan, g, cp), s));
     return MLBM_OK;
 }
 
 mlbm_status mlbm_step(const mlbm_plan *plan, void *g_a, void *g_b, int32_t n_steps,
                       int32_t *result_in_b, hipStream_t s) {
-    const CloudPlan *cp = single(plan);
-    if (!cp || !g_a || !g_b || n_steps < 0) return fail(MLBM_EINVAL, "bad step arguments");
+    if (!single(plan) || !g_a || !g_b || n_steps < 0) return fail(MLBM_EINVAL, "bad step arguments");
     if (g_a == g_b) return fail(MLBM_EINVAL, "ping-pong buffers must differ");
     void *cur = g_a, *nxt = g_b;
     for (int t = 0; t < n_steps; ++t) {
-        MLBM_HIP(launch_step(*cp, plan->precision, cur, nxt, nullptr, s));
+        MLBM_HIP(step_once(plan, cur, nxt, nullptr, s));
         std::swap(cur, nxt);
     }
     if (result_in_b) *result_in_b = (n_steps & 1) ? 1 : 0;
@@ -610,14 +718,13 @@ mlbm_status mlbm_step(const mlbm_plan *plan, void *g_a, void *g_b, int32_t n_ste
 
 mlbm_status mlbm_step_record(const mlbm_plan *plan, void *g_a, void *g_b, int32_t n_steps,
                              void *f_rec, int32_t *result_in_b, hipStream_t s) {
-    const CloudPlan *cp = single(plan);
-    if (!cp || !g_a || !g_b || !f_rec || n_steps < 0)
+    if (!single(plan) || !g_a || !g_b || !f_rec || n_steps < 0)
         return fail(MLBM_EINVAL, "bad step arguments");
     if (g_a == g_b) return fail(MLBM_EINVAL, "ping-pong buffers must differ");
     const size_t sb = (size_t)9 * plan->n_total * state_elem_bytes(plan->precision);
     void *cur = g_a, *nxt = g_b;
     for (int t = 0; t < n_steps; ++t) {
-        MLBM_HIP(launch_step(*cp, plan->precision, cur, nxt, (char *)f_rec + sb * t, s));
+        MLBM_HIP(step_once(plan, cur, nxt, (char *)f_rec + sb * t, s));
         std::swap(cur, nxt);
     }
     if (result_in_b) *result_in_b = (n_steps & 1) ? 1 : 0;
@@ -626,23 +733,36 @@ mlbm_status mlbm_step_record(const mlbm_plan *plan, void *g_a, void *g_b, int32_
 
 mlbm_status mlbm_moments(const mlbm_plan *plan, const void *g, double *rho, double *ux,
                          double *uy, hipStream_t s) {
-    const CloudPlan *cp = single(plan);
-    if (!cp || !g) return fail(MLBM_EINVAL, "null plan or state");
-    MLBM_HIP(launch_moments(*cp, plan->precision, g, rho, ux, uy, true, s));
+    if (!single(plan) || !g) return fail(MLBM_EINVAL, "null plan or state");
+    for (const CloudPlan &cp : plan->c)
+        MLBM_HIP(launch_moments(cp, plan->precision, state_at(plan, g, cp), out_at(rho, cp),
+                                out_at(ux, cp), out_at(uy, cp), true, s));
     return MLBM_OK;
 }
 
 mlbm_status mlbm_l2_sums(const mlbm_plan *plan, const void *g, const double *ux_t,
                          const double *uy_t, double *out, hipStream_t s) {
-    const CloudPlan *cp = single(plan);
-    if (!cp || !g || !ux_t || !uy_t || !out) return fail(MLBM_EINVAL, "null argument");
-    MLBM_HIP(launch_l2(*cp, plan->precision, g, ux_t, uy_t, out, plan->scratch64, s));
+    if (!single(plan) || !g || !ux_t || !uy_t || !out) return fail(MLBM_EINVAL, "null argument");
+    if (plan->c.size() == 1) {
+        MLBM_HIP(launch_l2(plan->c[0], plan->precision, g, ux_t, uy_t, out, plan->scratch64, s));
+        return MLBM_OK;
+    }
+    // per-cloud sums into the scratch head, then one fixed-order sum of those
+    double *sums = plan->scratch64;
+    double *part = plan->scratch64 + 4 * plan->c.size();
+    for (size_t c = 0; c < plan->c.size(); ++c) {
+        const CloudPlan &cp = plan->c[c];
+        MLBM_HIP(launch_l2(cp, plan->precision, state_at(plan, g, cp), node_at(ux_t, cp),
+                           node_at(uy_t, cp), sums + 4 * c, part, s));
+    }
+    MLBM_HIP(launch_l2_final(sums, (int64_t)plan->c.size(), out, s));
     return MLBM_OK;
 }
 
 mlbm_status mlbm_loss_seed(const mlbm_plan *plan, const void *f_T, const double *ux_t,
                            const double *uy_t, void *lamf_T, double *J, hipStream_t s) {
     const CloudPlan *cp = single(plan);
+    if (cp && plan->c.size() != 1) return fail(MLBM_EUNSUPPORTED, "the adjoint needs a single-cloud plan");
     if (!cp || !f_T || !ux_t || !uy_t || !lamf_T || !J) return fail(MLBM_EINVAL, "null argument");
     if (cp->prm.force_kind || cp->has_walls)
         return fail(MLBM_EUNSUPPORTED, "adjoint without walls or force only");
@@ -654,6 +774,7 @@ mlbm_status mlbm_loss_seed(const mlbm_plan *plan, const void *f_T, const double 
 mlbm_status mlbm_step_adjoint(const mlbm_plan *plan, const void *f_n, const void *lamf_next,
                               void *lamf_n, double *dJ_dtau, hipStream_t s) {
     const CloudPlan *cp = single(plan);
+    if (cp && plan->c.size() != 1) return fail(MLBM_EUNSUPPORTED, "the adjoint needs a single-cloud plan");
     if (!cp || !f_n || !lamf_next || !lamf_n || !dJ_dtau) return fail(MLBM_EINVAL, "null argument");
     if (!cp->tr_ptr) return fail(MLBM_EINVAL, "plan was built without with_adjoint");
     if (lamf_next == lamf_n) return fail(MLBM_EINVAL, "adjoint buffers must differ");
@@ -666,6 +787,7 @@ mlbm_status mlbm_init_adjoint(const mlbm_plan *plan, const double *u0x, const do
                               const void *lamf_0, double *dJ_du0x, double *dJ_du0y,
                               hipStream_t s) {
     const CloudPlan *cp = single(plan);
+    if (cp && plan->c.size() != 1) return fail(MLBM_EUNSUPPORTED, "the adjoint needs a single-cloud plan");
     if (!cp || !lamf_0 || !dJ_du0x || !dJ_du0y) return fail(MLBM_EINVAL, "null argument");
     MLBM_HIP(launch_init_adjoint(*cp, plan->precision, u0x, u0y, lamf_0, dJ_du0x, dJ_du0y, s));
     return MLBM_OK;
@@ -729,22 +851,15 @@ mlbm_status mlbm_autotune(mlbm_plan *plan, void *g_a, void *g_b, int32_t n_steps
 
 mlbm_status mlbm_graph_create(mlbm_plan *plan, void *g_a, void *g_b, int32_t n_steps,
                               hipStream_t s) {
-    const CloudPlan *cp = single(plan);
-    if (!cp || !g_a || !g_b || n_steps < 1) return fail(MLBM_EINVAL, "bad graph arguments");
+    if (!single(plan) || !g_a || !g_b || n_steps < 1) return fail(MLBM_EINVAL, "bad graph arguments");
     if (!s) return fail(MLBM_EINVAL, "graph capture needs a non-default stream");
-    if (plan->graph_exec) {
-        (void)hipGraphExecDestroy(plan->graph_exec);
-        plan->graph_exec = nullptr;
-    }
-    if (plan->graph) {
-        (void)hipGraphDestroy(plan->graph);
-        plan->graph = nullptr;
-    }
+    if (g_a == g_b) return fail(MLBM_EINVAL, "ping-pong buffers must differ");
+    drop_graph(plan);
     MLBM_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
     void *cur = g_a, *nxt = g_b;
     hipError_t err = hipSuccess;
     for (int t = 0; t < n_steps && err == hipSuccess; ++t) {
-        err = launch_step(*cp, plan->precision, cur, nxt, nullptr, s);
+        err = step_once(plan, cur, nxt, nullptr, s);
         std::swap(cur, nxt);
     }
     hipGraph_t graph = nullptr;
@@ -756,6 +871,43 @@ mlbm_status mlbm_graph_create(mlbm_plan *plan, void *g_a, void *g_b, int32_t n_s
     if (e2 != hipSuccess) return hip_fail(e2, "hipStreamEndCapture");
     plan->graph = graph;
     MLBM_HIP(hipGraphInstantiate(&plan->graph_exec, graph, nullptr, nullptr, 0));
+    return MLBM_OK;
+}
+
+mlbm_status mlbm_build_graph(const mlbm_cloud *clouds, const mlbm_params *params,
+                             int32_t n_clouds, void *plan_buf, size_t plan_bytes,
+                             void *workspace, size_t workspace_bytes, const double *rho,
+                             const double *ux, const double *uy, void *g_a, void *g_b,
+                             int32_t n_steps, int32_t variant, mlbm_plan **out, hipStream_t s) {
+    if (!out) return fail(MLBM_EINVAL, "null output pointer");
+    *out = nullptr;
+    if (!s) return fail(MLBM_EINVAL, "graph capture needs a non-default stream");
+    if (!g_a || !g_b || g_a == g_b || n_steps < 0) return fail(MLBM_EINVAL, "bad state buffers");
+    if (variant < 0 || variant >= kStepVariants) return fail(MLBM_EINVAL, "unknown variant");
+    MLBM_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+    mlbm_plan *plan = nullptr;
+    mlbm_status st = mlbm_build_weights(clouds, params, n_clouds, plan_buf, plan_bytes, workspace,
+                                        workspace_bytes, &plan, s);
+    if (st == MLBM_OK) {
+        for (auto &cp : plan->c) cp.variant = variant;
+        st = mlbm_init(plan, rho, ux, uy, g_a, s);
+    }
+    if (st == MLBM_OK) st = mlbm_step(plan, g_a, g_b, n_steps, nullptr, s);
+    const std::string msg = g_error;
+    hipGraph_t graph = nullptr;
+    hipError_t e2 = hipStreamEndCapture(s, &graph);
+    if (st != MLBM_OK || e2 != hipSuccess) {
+        if (graph) (void)hipGraphDestroy(graph);
+        if (plan) mlbm_plan_destroy(plan);
+        return st != MLBM_OK ? fail(st, msg) : hip_fail(e2, "hipStreamEndCapture");
+    }
+    plan->graph = graph;
+    hipError_t e3 = hipGraphInstantiate(&plan->graph_exec, graph, nullptr, nullptr, 0);
+    if (e3 != hipSuccess) {
+        mlbm_plan_destroy(plan);
+        return hip_fail(e3, "hipGraphInstantiate");
+    }
+    *out = plan;
     return MLBM_OK;
 }
 

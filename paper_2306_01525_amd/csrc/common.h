@@ -86,6 +86,23 @@ struct CloudPlan {
     void *ell_val = nullptr;
 };
 
+// Arguments of the FP32 step for one cloud; also the per-cloud descriptor
+// of the batched step (soff: element offset of the cloud's state, tile_begin:
+// its first tile in the batch).
+struct Step32Args {
+    int n, K, ocap, hcap;
+    const float4 *W;
+    const int32_t *nbr, *owner;
+    const float *force;
+    const uint8_t *ntype;
+    float rtau, rho0, rho_w;
+    float *frec;
+    const int32_t *tdesc;
+    const uint16_t *ownerL, *nbrL;
+    const int32_t *hlist;
+    int64_t soff, tile_begin;
+};
+
 // Bump allocator over a caller buffer (a null base computes sizes only).
 struct Carve {
     char *base;
@@ -105,6 +122,13 @@ struct Carve {
 struct mlbm_plan {
     std::vector<mlbm::CloudPlan> c;
     int64_t n_total = 0;
+    // batched FP32 step over several clouds (one launch per step)
+    bool batched = false;           // every cloud can use the batched kernel
+    int batch_mode = 0;             // common stencil mode of the batch
+    int64_t total_tiles = 0;
+    mlbm::Step32Args *descs = nullptr;   // device [n_clouds]
+    int32_t *tile2cloud = nullptr;       // device [total_tiles]
+    unsigned batch_lds = 0;
     int precision = MLBM_FP32_DEV;
     int32_t *dev_err = nullptr;     // device word: 0 or 1 + user index
     double *scratch64 = nullptr;    // device, small reductions
@@ -180,12 +204,17 @@ hipError_t launch_init(const CloudPlan &cp, int precision, const double *rho,
                        hipStream_t s);
 hipError_t launch_step(const CloudPlan &cp, int precision, const void *gin, void *gout,
                        void *frec, hipStream_t s);
+Step32Args step32_args(const CloudPlan &cp, void *frec);
+hipError_t launch_step_batch(const mlbm_plan &plan, const void *gin, void *gout,
+                             hipStream_t s);
+hipError_t launch_set_desc(Step32Args *dst, const Step32Args &v, hipStream_t s);
 hipError_t launch_moments(const CloudPlan &cp, int precision, const void *g, double *rho,
                           double *ux, double *uy, bool post_collision, hipStream_t s);
 hipError_t launch_l2(const CloudPlan &cp, int precision, const void *g, const double *uxt,
                      const double *uyt, double *out, double *part, hipStream_t s);
 hipError_t launch_collide(const CloudPlan &cp, int precision, const void *f, void *g,
                           hipStream_t s);
+hipError_t launch_l2_final(const double *part, int64_t nparts, double *out, hipStream_t s);
 
 // ---- adjoint (adjoint.hip) ----
 // workspace of the transpose build: counts/cursors [8n] + scan temp

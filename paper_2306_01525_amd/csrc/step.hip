@@ -105,31 +105,25 @@ __device__ __forceinline__ float4 load_w(const float4 *p, bool nt) {
 }
 
 template <int MODE, bool FORCE, bool WALL, bool REC, int UNROLL, bool NT>
-__global__ __launch_bounds__(kTile) void k_step32(
-    int n, int K, int64_t nblocks, const float *__restrict__ g, float *__restrict__ go,
-    const float4 *__restrict__ W, const int32_t *__restrict__ nbr,
-    const int32_t *__restrict__ owner, const float *__restrict__ force,
-    const uint8_t *__restrict__ ntype, float rtau, float rho0, float rho_w,
-    float *__restrict__ frec, const int32_t *__restrict__ tdesc,
-    const uint16_t *__restrict__ ownerL, const uint16_t *__restrict__ nbrL,
-    const int32_t *__restrict__ hlist, int ocap, int hcap) {
-    extern __shared__ __align__(16) unsigned char smem[];
-    const int64_t tile = xcd_tile(nblocks);
-    if (tile >= nblocks) return;
+__device__ __forceinline__ void step32_tile(const Step32Args &a, const float *__restrict__ g,
+                                            float *__restrict__ go, int64_t tile,
+                                            unsigned char *smem) {
+    const int n = a.n, K = a.K;
     const int base = (int)(tile * kTile);
     const int cnt = min(kTile, n - base);
     const int tid = threadIdx.x;
-    const int nh = tdesc ? tdesc[2 * tile + 1] : 0;
+    const int nh = a.tdesc ? a.tdesc[2 * tile + 1] : 0;
+    const float4 *__restrict__ W = a.W;
 
     float acc[8];
 #pragma unroll
     for (int d = 0; d < 8; ++d) acc[d] = 0.0f;
 
     if (nh > 0) {
-        const int no = tdesc[2 * tile];
+        const int no = a.tdesc[2 * tile];
         float *gl = reinterpret_cast<float *>(smem);                 // [8][nh]
         uint16_t *nl = reinterpret_cast<uint16_t *>(gl + 8 * nh);    // [no][K]
-        const int32_t *hl = hlist + tile * (int64_t)hcap;
+        const int32_t *hl = a.hlist + tile * (int64_t)a.hcap;
         for (int h = tid; h < nh; h += kTile) {
             int q = hl[h];
             q = (unsigned)q < (unsigned)n ? q : 0;   // a bad table must not fault
@@ -137,7 +131,7 @@ __global__ __launch_bounds__(kTile) void k_step32(
             for (int d = 0; d < 8; ++d) gl[d * nh + h] = g[(int64_t)(d + 1) * n + q];
         }
         const uint32_t *src =
-            reinterpret_cast<const uint32_t *>(nbrL + tile * (int64_t)ocap * K);
+            reinterpret_cast<const uint32_t *>(a.nbrL + tile * (int64_t)a.ocap * K);
         uint32_t *dst = reinterpret_cast<uint32_t *>(nl);
         const int words = (no * K + 1) >> 1;
         for (int w = tid; w < words; w += kTile) dst[w] = src[w];
@@ -147,7 +141,7 @@ __global__ __launch_bounds__(kTile) void k_step32(
         int ol[8];
 #pragma unroll
         for (int d = 0; d < 8; ++d)
-            ol[d] = (MODE == MLBM_STENCIL_OWN ? tid : (int)ownerL[(int64_t)d * n + p]) * K;
+            ol[d] = (MODE == MLBM_STENCIL_OWN ? tid : (int)a.ownerL[(int64_t)d * n + p]) * K;
 #pragma unroll UNROLL
         for (int j = 0; j < K; ++j) {
             const float4 wa = load_w(W + ((int64_t)j * 2) * n + p, NT);
@@ -166,7 +160,8 @@ __global__ __launch_bounds__(kTile) void k_step32(
         f[0] = g[p];
 #pragma unroll
         for (int d = 0; d < 8; ++d) f[d + 1] = acc[d];
-        collide_store32<FORCE, WALL, REC>(n, p, f, go, force, ntype, rtau, rho0, rho_w, frec);
+        collide_store32<FORCE, WALL, REC>(n, p, f, go, a.force, a.ntype, a.rtau, a.rho0,
+                                          a.rho_w, a.frec);
         return;
     }
 
@@ -174,20 +169,21 @@ __global__ __launch_bounds__(kTile) void k_step32(
     const int p = base + tid;
     int s[8];
 #pragma unroll
-    for (int d = 0; d < 8; ++d) s[d] = MODE == MLBM_STENCIL_OWN ? p : owner[(int64_t)d * n + p];
+    for (int d = 0; d < 8; ++d)
+        s[d] = MODE == MLBM_STENCIL_OWN ? p : a.owner[(int64_t)d * n + p];
 #pragma unroll UNROLL
     for (int j = 0; j < K; ++j) {
         const float4 wa = load_w(W + ((int64_t)j * 2) * n + p, NT);
         const float4 wb = load_w(W + ((int64_t)j * 2 + 1) * n + p, NT);
         const float w[8] = {wa.x, wa.y, wa.z, wa.w, wb.x, wb.y, wb.z, wb.w};
         if (MODE == MLBM_STENCIL_OWN) {
-            const int q = nbr[(int64_t)j * n + p];
+            const int q = a.nbr[(int64_t)j * n + p];
 #pragma unroll
             for (int d = 0; d < 8; ++d) acc[d] += w[d] * g[(int64_t)(d + 1) * n + q];
         } else {
 #pragma unroll
             for (int d = 0; d < 8; ++d) {
-                const int q = nbr[(int64_t)j * n + s[d]];
+                const int q = a.nbr[(int64_t)j * n + s[d]];
                 acc[d] += w[d] * g[(int64_t)(d + 1) * n + q];
             }
         }
@@ -196,8 +192,38 @@ __global__ __launch_bounds__(kTile) void k_step32(
     f[0] = g[p];
 #pragma unroll
     for (int d = 0; d < 8; ++d) f[d + 1] = acc[d];
-    collide_store32<FORCE, WALL, REC>(n, p, f, go, force, ntype, rtau, rho0, rho_w, frec);
+    collide_store32<FORCE, WALL, REC>(n, p, f, go, a.force, a.ntype, a.rtau, a.rho0, a.rho_w,
+                                      a.frec);
 }
+
+template <int MODE, bool FORCE, bool WALL, bool REC, int UNROLL, bool NT>
+__global__ __launch_bounds__(kTile) void k_step32(Step32Args a, const float *__restrict__ g,
+                                                  float *__restrict__ go, int64_t nblocks) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int64_t tile = xcd_tile(nblocks);
+    if (tile >= nblocks) return;
+    step32_tile<MODE, FORCE, WALL, REC, UNROLL, NT>(a, g, go, tile, smem);
+}
+
+// All tiles of all clouds of a batched plan in one launch: the tile's cloud
+// comes from tile2cloud, its arrays and parameters from the descriptor table;
+// the state of cloud c starts soff elements into g and go.
+template <int MODE, int UNROLL, bool NT>
+__global__ __launch_bounds__(kTile) void k_step32_batch(const Step32Args *__restrict__ descs,
+                                                        const int32_t *__restrict__ tile2cloud,
+                                                        const float *__restrict__ g,
+                                                        float *__restrict__ go,
+                                                        int64_t total_tiles) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int64_t t = xcd_tile(total_tiles);
+    if (t >= total_tiles) return;
+    const Step32Args a = descs[tile2cloud[t]];
+    step32_tile<MODE, false, false, false, UNROLL, NT>(a, g + a.soff, go + a.soff,
+                                                        t - a.tile_begin, smem);
+}
+
+// Writes one batch descriptor (a kernel, so that graph capture records it).
+__global__ void k_set_desc(Step32Args *dst, Step32Args v) { *dst = v; }
 
 // ------------------------------------------------------------------------
 // FP64, plain populations
@@ -437,13 +463,29 @@ __global__ void k_collide(int n, const T *__restrict__ f, T *__restrict__ g,
 template <int MODE, bool FORCE, bool WALL, bool REC, int UNROLL, bool NT>
 void launch32(const CloudPlan &cp, const void *gin, void *gout, void *frec, int64_t nblocks,
               hipStream_t s) {
-    const int n = cp.n;
+    const Step32Args a = step32_args(cp, frec);
     hipLaunchKernelGGL((k_step32<MODE, FORCE, WALL, REC, UNROLL, NT>), dim3(xcd_grid(nblocks)),
-                       dim3(kTile), cp.lds_bytes, s, n, cp.K, nblocks, (const float *)gin,
-                       (float *)gout, (const float4 *)cp.W32, cp.nbr, cp.owner, cp.force32,
-                       cp.ntype, (float)(1.0 / cp.prm.tau), (float)cp.prm.rho0,
-                       (float)cp.prm.rho_wall, (float *)frec, cp.lds_bytes ? cp.tdesc : nullptr,
-                       cp.ownerL, cp.nbrL, cp.hlist, cp.ocap, cp.hcap);
+                       dim3(kTile), cp.lds_bytes, s, a, (const float *)gin, (float *)gout,
+                       nblocks);
+}
+
+template <int MODE, int UNROLL, bool NT>
+void launch32_batch(const mlbm_plan &plan, const void *gin, void *gout, hipStream_t s) {
+    hipLaunchKernelGGL((k_step32_batch<MODE, UNROLL, NT>), dim3(xcd_grid(plan.total_tiles)),
+                       dim3(kTile), plan.batch_lds, s, plan.descs, plan.tile2cloud,
+                       (const float *)gin, (float *)gout, plan.total_tiles);
+}
+
+template <int MODE>
+void launch32_batch_v(const mlbm_plan &plan, const void *gin, void *gout, hipStream_t s) {
+    switch (plan.c[0].variant) {
+        case 1: launch32_batch<MODE, 2, true>(plan, gin, gout, s); break;
+        case 2: launch32_batch<MODE, 4, false>(plan, gin, gout, s); break;
+        case 3: launch32_batch<MODE, 4, true>(plan, gin, gout, s); break;
+        case 4: launch32_batch<MODE, 6, false>(plan, gin, gout, s); break;
+        case 5: launch32_batch<MODE, 6, true>(plan, gin, gout, s); break;
+        default: launch32_batch<MODE, 2, false>(plan, gin, gout, s); break;
+    }
 }
 
 template <int MODE, bool FORCE, bool WALL, bool REC>
@@ -501,6 +543,44 @@ hipError_t step_force(const CloudPlan &cp, int precision, const void *gin, void 
 }
 
 }  // namespace
+
+Step32Args step32_args(const CloudPlan &cp, void *frec) {
+    Step32Args a{};
+    a.n = cp.n;
+    a.K = cp.K;
+    a.ocap = cp.ocap;
+    a.hcap = cp.hcap;
+    a.W = reinterpret_cast<const float4 *>(cp.W32);
+    a.nbr = cp.nbr;
+    a.owner = cp.owner;
+    a.force = cp.force32;
+    a.ntype = cp.ntype;
+    a.rtau = (float)(1.0 / cp.prm.tau);
+    a.rho0 = (float)cp.prm.rho0;
+    a.rho_w = (float)cp.prm.rho_wall;
+    a.frec = (float *)frec;
+    a.tdesc = cp.lds_bytes ? cp.tdesc : nullptr;
+    a.ownerL = cp.ownerL;
+    a.nbrL = cp.nbrL;
+    a.hlist = cp.hlist;
+    a.soff = 0;
+    a.tile_begin = 0;
+    return a;
+}
+
+hipError_t launch_step_batch(const mlbm_plan &plan, const void *gin, void *gout,
+                             hipStream_t s) {
+    if (plan.batch_mode == MLBM_STENCIL_OWN)
+        launch32_batch_v<MLBM_STENCIL_OWN>(plan, gin, gout, s);
+    else
+        launch32_batch_v<MLBM_STENCIL_PAPER>(plan, gin, gout, s);
+    return hipGetLastError();
+}
+
+hipError_t launch_set_desc(Step32Args *dst, const Step32Args &v, hipStream_t s) {
+    hipLaunchKernelGGL(k_set_desc, dim3(1), dim3(1), 0, s, dst, v);
+    return hipGetLastError();
+}
 
 hipError_t launch_step(const CloudPlan &cp, int precision, const void *gin, void *gout,
                        void *frec, hipStream_t s) {
@@ -572,6 +652,11 @@ hipError_t launch_collide(const CloudPlan &cp, int precision, const void *f, voi
         hipLaunchKernelGGL(k_collide<float>, dim3(blocks_for(n, 256)), dim3(256), 0, s, n,
                            (const float *)f, (float *)g, force, cp.ntype, wall,
                            1.0 / cp.prm.tau, cp.prm.rho0, cp.prm.rho_wall, 1);
+    return hipGetLastError();
+}
+
+hipError_t launch_l2_final(const double *part, int64_t nparts, double *out, hipStream_t s) {
+    hipLaunchKernelGGL(k_l2_final, dim3(1), dim3(256), 0, s, nparts, part, out);
     return hipGetLastError();
 }
 

@@ -72,16 +72,20 @@ class Params:
 class Plan:
     """A built MLBM plan: stencils, owners and shape vectors of one cloud."""
 
-    def __init__(self, handle, plan_buf, params: Params, n: int, device):
+    def __init__(self, handle, plan_buf, params, n: int, device, sizes=None, keep=()):
         self._h = handle
         self._buf = plan_buf          # keeps the caller-owned plan memory alive
-        self.params = params
+        self._keep = keep             # inputs a captured graph still reads
+        self.params = params[0] if isinstance(params, (list, tuple)) else params
+        self.params_list = list(params) if isinstance(params, (list, tuple)) else [params]
         self.n = n
+        self.sizes = list(sizes) if sizes is not None else [n]
+        self.offsets = [sum(self.sizes[:i]) for i in range(len(self.sizes))]
         self.device = device
         info = _lib.PlanInfo()
         check(_lib.load().mlbm_plan_get_info(self._h, ctypes.byref(info)))
         self.info = info
-        self.state_dtype = torch.float64 if params.precision == MLBM_FP64 else torch.float32
+        self.state_dtype = torch.float64 if self.params.precision == MLBM_FP64 else torch.float32
 
     # ---- construction ----------------------------------------------------
     @classmethod
@@ -110,6 +114,78 @@ class Plan:
         torch.cuda.current_stream().synchronize() if stream is None else stream.synchronize()
         del ws
         return cls(h, plan_buf, params, n, device)
+
+    @staticmethod
+    def _clouds(clouds, device):
+        """clouds: list of (x, y, period, node_type or None)."""
+        keep, cs = [], []
+        for x, y, period, nt in clouds:
+            xt, yt = _f64(x, device), _f64(y, device)
+            ntt = None if nt is None else torch.as_tensor(nt, dtype=torch.uint8,
+                                                          device=device).contiguous()
+            keep += [xt, yt, ntt]
+            cs.append(_lib.Cloud(int(xt.shape[0]), xt.data_ptr(), yt.data_ptr(),
+                                 ntt.data_ptr() if ntt is not None else None,
+                                 float(period[0]), float(period[1])))
+        return (_lib.Cloud * len(cs))(*cs), keep
+
+    @classmethod
+    def build_batch(cls, clouds, params_list, device="cuda", stream=None):
+        """One plan over several clouds; per-node arrays are concatenated in
+        cloud order and the state is a flat tensor of [9][n_c] blocks."""
+        L = _lib.load()
+        carr, keep = cls._clouds(clouds, device)
+        parr = (_lib.Params * len(params_list))(*[p.to_c() for p in params_list])
+        _order(stream, *keep)
+        pb, wb = ctypes.c_size_t(), ctypes.c_size_t()
+        check(L.mlbm_weights_query(carr, parr, len(params_list), ctypes.byref(pb), ctypes.byref(wb)))
+        plan_buf = torch.empty(pb.value, dtype=torch.uint8, device=device)
+        ws = torch.empty(wb.value, dtype=torch.uint8, device=device)
+        h = ctypes.c_void_p()
+        check(L.mlbm_build_weights(carr, parr, len(params_list), _ptr(plan_buf), pb.value,
+                                   _ptr(ws), wb.value, ctypes.byref(h), _stream(stream)))
+        (torch.cuda.current_stream() if stream is None else stream).synchronize()
+        sizes = [c.n for c in carr]
+        return cls(h, plan_buf, list(params_list), sum(sizes), device, sizes)
+
+    @classmethod
+    def build_graph(cls, clouds, params_list, ux, uy, n_steps, stream, variant=0, rho=None,
+                    device="cuda"):
+        """Capture build + initial state + n_steps steps of all clouds into
+        one HIP graph (nothing runs yet). Returns (plan, g_a, g_b, result):
+        plan.graph_launch(stream) runs it; `result` holds the final state."""
+        L = _lib.load()
+        carr, keep = cls._clouds(clouds, device)
+        parr = (_lib.Params * len(params_list))(*[p.to_c() for p in params_list])
+        rho, ux, uy = (_f64(a, device) for a in (rho, ux, uy))
+        keep += [rho, ux, uy]
+        torch.cuda.current_stream().synchronize()
+        pb, wb = ctypes.c_size_t(), ctypes.c_size_t()
+        check(L.mlbm_weights_query(carr, parr, len(params_list), ctypes.byref(pb), ctypes.byref(wb)))
+        plan_buf = torch.empty(pb.value, dtype=torch.uint8, device=device)
+        ws = torch.empty(wb.value, dtype=torch.uint8, device=device)
+        sizes = [c.n for c in carr]
+        dt = torch.float64 if params_list[0].precision == MLBM_FP64 else torch.float32
+        g_a = torch.empty(9 * sum(sizes), dtype=dt, device=device)
+        g_b = torch.empty_like(g_a)
+        torch.cuda.synchronize()
+        h = ctypes.c_void_p()
+        check(L.mlbm_build_graph(carr, parr, len(params_list), _ptr(plan_buf), pb.value, _ptr(ws),
+                                 wb.value, _ptr(rho), _ptr(ux), _ptr(uy), _ptr(g_a), _ptr(g_b),
+                                 int(n_steps), int(variant), ctypes.byref(h), _stream(stream)))
+        plan = cls(h, plan_buf, list(params_list), sum(sizes), device, sizes,
+                   keep=tuple(keep) + (ws,))
+        return plan, g_a, g_b, (g_b if n_steps % 2 else g_a)
+
+    def cloud_view(self, t, c):
+        """[9][n_c] view of cloud c inside a state tensor, or the [n_c] slice of
+        a per-node tensor."""
+        o, n = self.offsets[c], self.sizes[c]
+        if t.dim() == 1 and t.shape[0] == 9 * self.n:
+            return t[9 * o: 9 * (o + n)].view(9, n)
+        if t.dim() == 2 and len(self.sizes) == 1:
+            return t
+        return t[o: o + n]
 
     @classmethod
     def from_arrays(cls, x, y, nbr, owner, W, params: Params, node_type=None, device="cuda"):
@@ -148,6 +224,8 @@ class Plan:
 
     # ---- state ---------------------------------------------------------------
     def new_state(self):
+        if len(self.sizes) > 1:
+            return torch.empty(9 * self.n, dtype=self.state_dtype, device=self.device)
         return torch.empty((9, self.n), dtype=self.state_dtype, device=self.device)
 
     def init(self, ux=None, uy=None, rho=None, g=None, stream=None):
