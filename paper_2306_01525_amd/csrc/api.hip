@@ -85,6 +85,8 @@ struct BuildWs {
     size_t sort_bytes = 0;
     void *tr_tmp = nullptr;
     size_t tr_bytes = 0;
+    void *rbf_tmp = nullptr;
+    size_t rbf_bytes = 0;
     int gx = 1, gy = 1, hb = 0;
 };
 
@@ -114,7 +116,7 @@ void layout_cloud(const mlbm_cloud &c, const mlbm_params &p, int precision, Carv
         cp.force64 = pl.take<double>((size_t)2 * n);
         cp.force32 = precision == MLBM_FP32_DEV ? pl.take<float>((size_t)2 * n) : nullptr;
     }
-    if (precision == MLBM_FP32_DEV) {
+    {   // gather tables of the LDS-staged steps (both precisions)
         const int ntiles = (n + kTile - 1) / kTile;
         cp.hcap = 1024;
         cp.ocap = std::min(512, ((65536 - 8 * cp.hcap * 4) / (2 * K)) & ~1);
@@ -144,6 +146,8 @@ void layout_cloud(const mlbm_cloud &c, const mlbm_params &p, int precision, Carv
         bw->cend = ws->take<int32_t>(ncells);
         bw->sort_bytes = sort_pairs_temp_bytes(n);
         bw->sort_tmp = ws->take<char>(bw->sort_bytes);
+        bw->rbf_bytes = rbf_temp_bytes(n);
+        bw->rbf_tmp = ws->take<char>(bw->rbf_bytes);
         if (p.with_adjoint) {
             bw->tr_bytes = transpose_temp_bytes(n, K);
             bw->tr_tmp = ws->take<char>(bw->tr_bytes);
@@ -305,7 +309,7 @@ mlbm_status build_cloud(mlbm_plan *plan, CloudPlan &cp, const mlbm_cloud &c,
         MLBM_HIP(launch_owner(cp.geo, cp.xs, cp.ys, cp.perm, cp.iperm, bw.cstart, bw.cend, n,
                               p.dx, cp.owner, s));
     MLBM_HIP(launch_rbf(cp.geo, cp.xs, cp.ys, cp.perm, cp.nbr, cp.owner, n, p.K, p.degree, p.dx,
-                        p.stencil_mode, cp.ntype, cp.W64, plan->dev_err, s));
+                        p.stencil_mode, bw.rbf_tmp, bw.rbf_bytes, cp.W64, plan->dev_err, s));
     if (cp.W32) MLBM_HIP(launch_pack_w32(cp.W64, n, p.K, cp.W32, s));
     MLBM_HIP(launch_force(cp.xs, cp.ys, cp.ntype, n, p.force_kind, p.force_mag, cp.force32,
                           cp.force64, s));

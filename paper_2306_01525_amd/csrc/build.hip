@@ -354,43 +354,55 @@ __device__ __forceinline__ double cube_dist(double ax, double ay, double bx, dou
     return r * r * r;
 }
 
-// One wavefront solves one local system Phi w = phi(p) (eqs.
-// rbf_interp_set_augmented and shape_vector) for R right-hand sides by
-// Gaussian elimination with partial pivoting. Lane r holds row r of the
-// system (K RBF rows, M polynomial rows, then identity rows that pad the
-// system to NB unknowns). Rows are never moved: the pivot of column k is the
+// Departure point t of the right-hand-side list of owner s: node p and
+// direction k. Own-node stencils: the eight departure points of s itself.
+// Paper stencils: the points whose closest node is s (CSR list pts).
+struct RhsList {
+    const int32_t *ptr, *pts;   // null for own-node stencils
+};
+
+__device__ __forceinline__ void rhs_point(const RhsList &L, int s, int t, int &p, int &k) {
+    if (!L.ptr) {
+        p = s;
+        k = t + 1;
+    } else {
+        const int e = L.pts[L.ptr[s] + t];
+        p = e >> 3;
+        k = (e & 7) + 1;
+    }
+}
+
+// One wavefront solves the local system of one owner node s,
+// Phi w = phi(p) (eqs. rbf_interp_set_augmented and shape_vector), for up to R
+// departure points at a time by Gaussian elimination with partial pivoting.
+// Lane r holds row r of the system (K RBF rows, M polynomial rows, then
+// identity rows that pad the system to NB unknowns) and the R right-hand-side
+// entries of that row. Rows are never moved: the pivot of column k is the
 // not-yet-used lane with the largest |a_k| (ties: lowest lane), broadcast by
 // readlane; elimination leaves an upper-triangular system in pivot order that
-// is solved backwards. R = 8: own-node stencil, the eight departure points of
-// node p. R = 1: paper stencil, one departure point (p, k) on the stencil of
-// its owner.
+// is solved backwards, each unknown stored as soon as it is known. Owners
+// with more than R departure points repeat the (deterministic) elimination
+// for every further chunk of R points.
 template <int NB, int R>
 __global__ __launch_bounds__(256) void k_rbf(const Geo *__restrict__ geo,
                                              const double *__restrict__ xs,
                                              const double *__restrict__ ys,
                                              const int32_t *__restrict__ perm,
-                                             const int32_t *__restrict__ nbr,
-                                             const int32_t *__restrict__ owner, int n, int K,
-                                             int m, double dx, double *__restrict__ W64,
+                                             const int32_t *__restrict__ nbr, RhsList L,
+                                             int n, int K, int m, double dx,
+                                             double *__restrict__ W64,
                                              int32_t *__restrict__ dev_err) {
     const int lane = threadIdx.x & 63;
     const int64_t wave = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
-    int p, kdir;
-    if (R == 8) {
-        if (wave >= n) return;
-        p = (int)wave;
-        kdir = 1;
-    } else {
-        if (wave >= (int64_t)n * 8) return;
-        p = (int)(wave >> 3);
-        kdir = (int)(wave & 7) + 1;
-    }
+    if (wave >= n) return;
+    const int s = (int)wave;
+    const int count = L.ptr ? L.ptr[s + 1] - L.ptr[s] : 8;
+    if (count == 0) return;
     const Geo g = *geo;
     const int M = (m + 1) * (m + 2) / 2;
     const int nn = K + M;
-    const int s = (R == 8) ? p : owner[(int64_t)(kdir - 1) * n + p];
 
-    // stencil member coordinates relative to the centre s, then scaled by the
+    // stencil member coordinates relative to the centre s, scaled by the
     // stencil radius (the interpolant is invariant to this; it helps the
     // conditioning)
     double rx = 0.0, ry = 0.0;
@@ -404,112 +416,129 @@ __global__ __launch_bounds__(256) void k_rbf(const Geo *__restrict__ geo,
     for (int off = 32; off > 0; off >>= 1) rad = fmax(rad, __shfl_xor(rad, off));
     if (!(rad > 0.0)) rad = 1.0;
     const double sx = rx / rad, sy = ry / rad;
-
-    // departure points (scaled, relative to s)
-    double qx[R], qy[R];
-#pragma unroll
-    for (int t = 0; t < R; ++t) {
-        int k = (R == 8) ? t + 1 : kdir;
-        if (R == 8) {
-            qx[t] = (-lat_ex(k) * dx) / rad;
-            qy[t] = (-lat_ey(k) * dx) / rad;
-        } else {
-            qx[t] = min_image(xs[p] - lat_ex(k) * dx - xs[s], g.Lx) / rad;
-            qy[t] = min_image(ys[p] - lat_ey(k) * dx - ys[s], g.Ly) / rad;
-        }
-    }
-
-    // row `lane` of the padded system and its right-hand sides
-    double a[NB], b[R];
     const bool rbf_row = lane < K;
     const bool poly_row = lane >= K && lane < nn;
     const int qrow = lane - K;
-#pragma unroll
-    for (int c = 0; c < NB; ++c) {
-        double cxv = readlane_d(sx, c < 64 ? c : 0);
-        double cyv = readlane_d(sy, c < 64 ? c : 0);
-        double v = 0.0;
-        if (rbf_row) {
-            if (c < K) v = cube_dist(sx, sy, cxv, cyv);
-            else if (c < nn) v = monomial(c - K, sx, sy);
-        } else if (poly_row) {
-            if (c < K) v = monomial(qrow, cxv, cyv);
-        } else if (lane < NB) {
-            v = (c == lane) ? 1.0 : 0.0;
-        }
-        a[c] = v;
-    }
-#pragma unroll
-    for (int t = 0; t < R; ++t) {
-        double v = 0.0;
-        if (rbf_row) v = cube_dist(sx, sy, qx[t], qy[t]);
-        else if (poly_row) v = monomial(qrow, qx[t], qy[t]);
-        b[t] = v;
-    }
-
-    // infinity norm for the singularity threshold
-    double rs = 0.0;
-#pragma unroll
-    for (int c = 0; c < NB; ++c) rs += fabs(a[c]);
-    if (lane >= NB) rs = 0.0;
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) rs = fmax(rs, __shfl_xor(rs, off));
-    const double tiny = 1e3 * DBL_EPSILON * rs;
-
-    bool used = lane >= NB;   // lanes beyond the system never pivot
-    int pstep = NB;           // elimination step at which this lane was the pivot
-    int plane[NB];
     bool singular = false;
+
+    for (int c0 = 0; c0 < count; c0 += R) {
+        // row `lane` of the padded system and its right-hand sides
+        double a[NB], b[R];
 #pragma unroll
-    for (int k = 0; k < NB; ++k) {
-        double v = used ? -1.0 : fabs(a[k]);
-        int idx = lane;
+        for (int c = 0; c < NB; ++c) {
+            const double cxv = readlane_d(sx, c);
+            const double cyv = readlane_d(sy, c);
+            double v = 0.0;
+            if (rbf_row) {
+                if (c < K) v = cube_dist(sx, sy, cxv, cyv);
+                else if (c < nn) v = monomial(c - K, sx, sy);
+            } else if (poly_row) {
+                if (c < K) v = monomial(qrow, cxv, cyv);
+            } else if (lane < NB) {
+                v = (c == lane) ? 1.0 : 0.0;
+            }
+            a[c] = v;
+        }
 #pragma unroll
-        for (int off = 32; off > 0; off >>= 1) {
-            double ov = __shfl_xor(v, off);
-            int oi = __shfl_xor(idx, off);
-            if (ov > v || (ov == v && oi < idx)) {
-                v = ov;
-                idx = oi;
+        for (int t = 0; t < R; ++t) {
+            double v = 0.0;
+            if (c0 + t < count) {
+                int p, k;
+                rhs_point(L, s, c0 + t, p, k);
+                // departure point x_p - e_k dx relative to s, scaled
+                const double qx = (L.ptr ? min_image(xs[p] - lat_ex(k) * dx - xs[s], g.Lx)
+                                         : -lat_ex(k) * dx) / rad;
+                const double qy = (L.ptr ? min_image(ys[p] - lat_ey(k) * dx - ys[s], g.Ly)
+                                         : -lat_ey(k) * dx) / rad;
+                if (rbf_row) v = cube_dist(sx, sy, qx, qy);
+                else if (poly_row) v = monomial(qrow, qx, qy);
+            }
+            b[t] = v;
+        }
+
+        // infinity norm for the singularity threshold
+        double rs = 0.0;
+#pragma unroll
+        for (int c = 0; c < NB; ++c) rs += fabs(a[c]);
+        if (lane >= NB) rs = 0.0;
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) rs = fmax(rs, __shfl_xor(rs, off));
+        const double tiny = 1e3 * DBL_EPSILON * rs;
+
+        bool used = lane >= NB;   // lanes beyond the system never pivot
+        int pstep = NB;           // elimination step at which this lane was the pivot
+        int plane[NB];
+#pragma unroll
+        for (int k = 0; k < NB; ++k) {
+            double v = used ? -1.0 : fabs(a[k]);
+            int idx = lane;
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1) {
+                double ov = __shfl_xor(v, off);
+                int oi = __shfl_xor(idx, off);
+                if (ov > v || (ov == v && oi < idx)) {
+                    v = ov;
+                    idx = oi;
+                }
+            }
+            const int pl = __builtin_amdgcn_readfirstlane(idx);
+            plane[k] = pl;
+            if (!(v > tiny)) singular = true;
+            const double pk = readlane_d(a[k], pl);
+            const double l = (!used && lane != pl) ? a[k] / pk : 0.0;
+#pragma unroll
+            for (int c = k + 1; c < NB; ++c) a[c] = a[c] - l * readlane_d(a[c], pl);
+#pragma unroll
+            for (int t = 0; t < R; ++t) b[t] = b[t] - l * readlane_d(b[t], pl);
+            if (lane == pl) {
+                used = true;
+                pstep = k;
             }
         }
-        const int pl = __builtin_amdgcn_readfirstlane(idx);
-        plane[k] = pl;
-        if (!(v > tiny)) singular = true;
-        const double pk = readlane_d(a[k], pl);
-        const double l = (!used && lane != pl) ? a[k] / pk : 0.0;
-#pragma unroll
-        for (int c = k + 1; c < NB; ++c) a[c] = a[c] - l * readlane_d(a[c], pl);
-#pragma unroll
-        for (int t = 0; t < R; ++t) b[t] = b[t] - l * readlane_d(b[t], pl);
-        if (lane == pl) {
-            used = true;
-            pstep = k;
-        }
-    }
-    double xo[R];
-#pragma unroll
-    for (int t = 0; t < R; ++t) xo[t] = 0.0;
-#pragma unroll
-    for (int k = NB - 1; k >= 0; --k) {
-        const int pl = plane[k];
-        const double ukk = readlane_d(a[k], pl);
+        // back substitution; unknown k < K of right-hand side t is the weight
+        // of stencil member k for that departure point
+        int tp[R], tk[R];
 #pragma unroll
         for (int t = 0; t < R; ++t) {
-            const double xk = readlane_d(b[t], pl) / ukk;
-            if (pstep < k) b[t] = b[t] - a[k] * xk;
-            if (lane == k) xo[t] = xk;
+            tp[t] = -1;
+            tk[t] = 1;
+            if (c0 + t < count) rhs_point(L, s, c0 + t, tp[t], tk[t]);
         }
-    }
-    if (lane < K) {
 #pragma unroll
-        for (int t = 0; t < R; ++t) {
-            int k = (R == 8) ? t + 1 : kdir;
-            W64[((int64_t)(k - 1) * K + lane) * n + p] = xo[t];
+        for (int k = NB - 1; k >= 0; --k) {
+            const int pl = plane[k];
+            const double ukk = readlane_d(a[k], pl);
+#pragma unroll
+            for (int t = 0; t < R; ++t) {
+                const double xk = readlane_d(b[t], pl) / ukk;
+                if (pstep < k) b[t] = b[t] - a[k] * xk;
+                if (k < K && lane == k && tp[t] >= 0)
+                    W64[((int64_t)(tk[t] - 1) * K + k) * n + tp[t]] = xk;
+            }
         }
     }
-    if (singular && lane == 0) atomicMin(dev_err, perm[p] + 1);
+    if (singular && lane == 0) atomicMin(dev_err, perm[s] + 1);
 }
+
+// Owner -> departure-point lists of the paper's stencil rule (CSR): count,
+// then fill (the order inside a list does not affect the solved weights).
+__global__ void k_owned_count(int n, const int32_t *__restrict__ owner, int32_t *__restrict__ cnt) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (int64_t)8 * n) return;
+    atomicAdd(&cnt[owner[i]], 1);
+}
+
+__global__ void k_owned_fill(int n, const int32_t *__restrict__ owner,
+                             const int32_t *__restrict__ ptr, int32_t *__restrict__ cur,
+                             int32_t *__restrict__ pts) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (int64_t)8 * n) return;
+    const int k0 = (int)(i / n), p = (int)(i - (int64_t)k0 * n);   // owner is [8][n]
+    const int s = owner[i];
+    pts[ptr[s] + atomicAdd(&cur[s], 1)] = p * 8 + k0;
+}
+
+__global__ void k_set_last(int32_t *ptr, int n, int32_t v) { ptr[n] = v; }
 
 // FP32 copy of the shape vectors in the streaming layout [K][2][n][4]
 // (directions 1..4 and 5..8 as float4). After rounding, the weights of each
@@ -633,30 +662,58 @@ hipError_t launch_owner(const Geo *geo, const double *xs, const double *ys,
 
 template <int NB>
 static hipError_t launch_rbf_nb(const Geo *geo, const double *xs, const double *ys,
-                                const int32_t *perm, const int32_t *nbr, const int32_t *owner,
-                                int n, int K, int m, double dx, int mode, double *W64,
-                                int32_t *dev_err, hipStream_t s) {
-    const int64_t waves = mode == MLBM_STENCIL_OWN ? (int64_t)n : (int64_t)n * 8;
-    dim3 grid(blocks_for(waves, 4)), block(256);
-    if (mode == MLBM_STENCIL_OWN)
-        hipLaunchKernelGGL((k_rbf<NB, 8>), grid, block, 0, s, geo, xs, ys, perm, nbr, owner, n, K,
-                           m, dx, W64, dev_err);
+                                const int32_t *perm, const int32_t *nbr, RhsList L, int n, int K,
+                                int m, double dx, double *W64, int32_t *dev_err, hipStream_t s) {
+    dim3 grid(blocks_for(n, 4)), block(256);
+    if (!L.ptr)
+        hipLaunchKernelGGL((k_rbf<NB, 8>), grid, block, 0, s, geo, xs, ys, perm, nbr, L, n, K, m,
+                           dx, W64, dev_err);
     else
-        hipLaunchKernelGGL((k_rbf<NB, 1>), grid, block, 0, s, geo, xs, ys, perm, nbr, owner, n, K,
-                           m, dx, W64, dev_err);
+        hipLaunchKernelGGL((k_rbf<NB, 16>), grid, block, 0, s, geo, xs, ys, perm, nbr, L, n, K, m,
+                           dx, W64, dev_err);
     return hipGetLastError();
+}
+
+size_t rbf_temp_bytes(int n) {
+    const size_t a = ((size_t)n * 4 + 255) & ~size_t(255);
+    const size_t b = (((size_t)n + 1) * 4 + 255) & ~size_t(255);
+    const size_t c = ((size_t)8 * n * 4 + 255) & ~size_t(255);
+    return a + b + c + scan_temp_bytes(n) + 256;
 }
 
 hipError_t launch_rbf(const Geo *geo, const double *xs, const double *ys,
                       const int32_t *perm, const int32_t *nbr, const int32_t *owner,
-                      int n, int K, int m, double dx, int mode, const uint8_t *ntype,
+                      int n, int K, int m, double dx, int mode, void *tmp, size_t tmp_bytes,
                       double *W64, int32_t *dev_err, hipStream_t s) {
-    (void)ntype;
+    RhsList L{nullptr, nullptr};
+    hipError_t e;
+    if (mode == MLBM_STENCIL_PAPER) {
+        char *b = (char *)tmp;
+        int32_t *cnt = (int32_t *)b;
+        b += ((size_t)n * 4 + 255) & ~size_t(255);
+        int32_t *ptr = (int32_t *)b;
+        b += (((size_t)n + 1) * 4 + 255) & ~size_t(255);
+        int32_t *pts = (int32_t *)b;
+        b += ((size_t)8 * n * 4 + 255) & ~size_t(255);
+        const size_t scan_bytes = tmp_bytes - (size_t)(b - (char *)tmp);
+        if ((e = launch_fill_i32(cnt, 0, n, s)) != hipSuccess) return e;
+        hipLaunchKernelGGL(k_owned_count, dim3(blocks_for((int64_t)8 * n, 256)), dim3(256), 0, s, n,
+                           owner, cnt);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        if ((e = exclusive_scan(b, scan_bytes, cnt, ptr, n, s)) != hipSuccess) return e;
+        hipLaunchKernelGGL(k_set_last, dim3(1), dim3(1), 0, s, ptr, n, 8 * n);
+        if ((e = launch_fill_i32(cnt, 0, n, s)) != hipSuccess) return e;
+        hipLaunchKernelGGL(k_owned_fill, dim3(blocks_for((int64_t)8 * n, 256)), dim3(256), 0, s, n,
+                           owner, ptr, cnt, pts);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        L.ptr = ptr;
+        L.pts = pts;
+    }
     const int nn = K + poly_count(m);
-    if (nn <= 24) return launch_rbf_nb<24>(geo, xs, ys, perm, nbr, owner, n, K, m, dx, mode, W64, dev_err, s);
-    if (nn <= 32) return launch_rbf_nb<32>(geo, xs, ys, perm, nbr, owner, n, K, m, dx, mode, W64, dev_err, s);
-    if (nn <= 48) return launch_rbf_nb<48>(geo, xs, ys, perm, nbr, owner, n, K, m, dx, mode, W64, dev_err, s);
-    return launch_rbf_nb<64>(geo, xs, ys, perm, nbr, owner, n, K, m, dx, mode, W64, dev_err, s);
+    if (nn <= 24) return launch_rbf_nb<24>(geo, xs, ys, perm, nbr, L, n, K, m, dx, W64, dev_err, s);
+    if (nn <= 32) return launch_rbf_nb<32>(geo, xs, ys, perm, nbr, L, n, K, m, dx, W64, dev_err, s);
+    if (nn <= 48) return launch_rbf_nb<48>(geo, xs, ys, perm, nbr, L, n, K, m, dx, W64, dev_err, s);
+    return launch_rbf_nb<64>(geo, xs, ys, perm, nbr, L, n, K, m, dx, W64, dev_err, s);
 }
 
 hipError_t launch_pack_w32(const double *W64, int n, int K, float *W32, hipStream_t s) {

@@ -177,9 +177,12 @@ hipError_t launch_owner(const Geo *geo, const double *xs, const double *ys,
                         const int32_t *perm, const int32_t *iperm, const int32_t *cstart,
                         const int32_t *cend, int n, double dx, int32_t *owner,
                         hipStream_t s);
+// workspace of the paper-mode owner lists: counts [n], offsets [n+1],
+// points [8n], scan temp
+size_t rbf_temp_bytes(int n);
 hipError_t launch_rbf(const Geo *geo, const double *xs, const double *ys,
                       const int32_t *perm, const int32_t *nbr, const int32_t *owner,
-                      int n, int K, int m, double dx, int mode, const uint8_t *ntype,
+                      int n, int K, int m, double dx, int mode, void *tmp, size_t tmp_bytes,
                       double *W64, int32_t *dev_err, hipStream_t s);
 hipError_t launch_pack_w32(const double *W64, int n, int K, float *W32, hipStream_t s);
 hipError_t launch_force(const double *xs, const double *ys, const uint8_t *ntype, int n,

@@ -142,18 +142,49 @@ __device__ __forceinline__ void step32_tile(const Step32Args &a, const float *__
 #pragma unroll
         for (int d = 0; d < 8; ++d)
             ol[d] = (MODE == MLBM_STENCIL_OWN ? tid : (int)a.ownerL[(int64_t)d * n + p]) * K;
+        if ((K & 1) == 0) {
+            // K even: ol[d] and j are even, so two consecutive local indices
+            // are one aligned 32-bit LDS word (half the index reads)
+            constexpr int U2 = UNROLL >= 2 ? UNROLL / 2 : 1;
+#pragma unroll U2
+            for (int j = 0; j < K; j += 2) {
+                const float4 wa = load_w(W + ((int64_t)j * 2) * n + p, NT);
+                const float4 wb = load_w(W + ((int64_t)j * 2 + 1) * n + p, NT);
+                const float4 wc = load_w(W + ((int64_t)j * 2 + 2) * n + p, NT);
+                const float4 wd = load_w(W + ((int64_t)j * 2 + 3) * n + p, NT);
+                const float w0[8] = {wa.x, wa.y, wa.z, wa.w, wb.x, wb.y, wb.z, wb.w};
+                const float w1[8] = {wc.x, wc.y, wc.z, wc.w, wd.x, wd.y, wd.z, wd.w};
+                if (MODE == MLBM_STENCIL_OWN) {
+                    const uint32_t pr = *reinterpret_cast<const uint32_t *>(nl + ol[0] + j);
+                    const int h0 = (int)(pr & 0xffffu), h1 = (int)(pr >> 16);
+#pragma unroll
+                    for (int d = 0; d < 8; ++d) {
+                        acc[d] += w0[d] * gl[d * nh + h0];
+                        acc[d] += w1[d] * gl[d * nh + h1];
+                    }
+                } else {
+#pragma unroll
+                    for (int d = 0; d < 8; ++d) {
+                        const uint32_t pr = *reinterpret_cast<const uint32_t *>(nl + ol[d] + j);
+                        acc[d] += w0[d] * gl[d * nh + (int)(pr & 0xffffu)];
+                        acc[d] += w1[d] * gl[d * nh + (int)(pr >> 16)];
+                    }
+                }
+            }
+        } else {
 #pragma unroll UNROLL
-        for (int j = 0; j < K; ++j) {
-            const float4 wa = load_w(W + ((int64_t)j * 2) * n + p, NT);
-            const float4 wb = load_w(W + ((int64_t)j * 2 + 1) * n + p, NT);
-            const float w[8] = {wa.x, wa.y, wa.z, wa.w, wb.x, wb.y, wb.z, wb.w};
-            if (MODE == MLBM_STENCIL_OWN) {
-                const int h = nl[ol[0] + j];
+            for (int j = 0; j < K; ++j) {
+                const float4 wa = load_w(W + ((int64_t)j * 2) * n + p, NT);
+                const float4 wb = load_w(W + ((int64_t)j * 2 + 1) * n + p, NT);
+                const float w[8] = {wa.x, wa.y, wa.z, wa.w, wb.x, wb.y, wb.z, wb.w};
+                if (MODE == MLBM_STENCIL_OWN) {
+                    const int h = nl[ol[0] + j];
 #pragma unroll
-                for (int d = 0; d < 8; ++d) acc[d] += w[d] * gl[d * nh + h];
-            } else {
+                    for (int d = 0; d < 8; ++d) acc[d] += w[d] * gl[d * nh + h];
+                } else {
 #pragma unroll
-                for (int d = 0; d < 8; ++d) acc[d] += w[d] * gl[d * nh + nl[ol[d] + j]];
+                    for (int d = 0; d < 8; ++d) acc[d] += w[d] * gl[d * nh + nl[ol[d] + j]];
+                }
             }
         }
         float f[kQ];
@@ -228,38 +259,12 @@ __global__ void k_set_desc(Step32Args *dst, Step32Args v) { *dst = v; }
 // ------------------------------------------------------------------------
 // FP64, plain populations
 // ------------------------------------------------------------------------
-template <int MODE, bool FORCE, bool WALL, bool REC>
-__global__ __launch_bounds__(kTile) void k_step64(
-    int n, int K, int64_t nblocks, const double *__restrict__ g, double *__restrict__ go,
-    const double *__restrict__ W, const int32_t *__restrict__ nbr,
-    const int32_t *__restrict__ owner, const double *__restrict__ force,
-    const uint8_t *__restrict__ ntype, double rtau, double rho_w, double *__restrict__ frec) {
-    const int64_t tile = xcd_tile(nblocks);
-    if (tile >= nblocks) return;
-    const int64_t p64 = tile * kTile + threadIdx.x;
-    if (p64 >= n) return;
-    const int p = (int)p64;
-
-    double acc[8];
-#pragma unroll
-    for (int d = 0; d < 8; ++d) acc[d] = 0.0;
-    int s[8];
-#pragma unroll
-    for (int d = 0; d < 8; ++d) s[d] = MODE == MLBM_STENCIL_OWN ? p : owner[(int64_t)d * n + p];
-    for (int j = 0; j < K; ++j) {
-        int qo = 0;
-        if (MODE == MLBM_STENCIL_OWN) qo = nbr[(int64_t)j * n + p];
-#pragma unroll
-        for (int d = 0; d < 8; ++d) {
-            const double w = W[((int64_t)d * K + j) * n + p];
-            const int q = MODE == MLBM_STENCIL_OWN ? qo : nbr[(int64_t)j * n + s[d]];
-            acc[d] += w * g[(int64_t)(d + 1) * n + q];
-        }
-    }
-    double f[9];
-    f[0] = g[p];
-#pragma unroll
-    for (int d = 0; d < 8; ++d) f[d + 1] = acc[d];
+template <bool FORCE, bool WALL, bool REC>
+__device__ __forceinline__ void collide_store64(int n, int p, double (&f)[kQ],
+                                                double *__restrict__ go,
+                                                const double *__restrict__ force,
+                                                const uint8_t *__restrict__ ntype, double rtau,
+                                                double rho_w, double *__restrict__ frec) {
     if (WALL && ntype[p]) {
 #pragma unroll
         for (int k = 0; k < kQ; ++k) {
@@ -292,6 +297,90 @@ __global__ __launch_bounds__(kTile) void k_step64(
         go[(int64_t)k * n + p] = v;
         if (REC) frec[(int64_t)k * n + p] = f[k];
     }
+}
+
+// Same structure as the FP32 step, with the same tile tables: a tile stages
+// its halo four directions at a time (4 x |H_t| doubles take the LDS that 8 x
+// |H_t| floats take), so the directions are interpolated in two passes.
+template <int MODE, bool FORCE, bool WALL, bool REC>
+__global__ __launch_bounds__(kTile) void k_step64(
+    int n, int K, int64_t nblocks, const double *__restrict__ g, double *__restrict__ go,
+    const double *__restrict__ W, const int32_t *__restrict__ nbr,
+    const int32_t *__restrict__ owner, const double *__restrict__ force,
+    const uint8_t *__restrict__ ntype, double rtau, double rho_w, double *__restrict__ frec,
+    const int32_t *__restrict__ tdesc, const uint16_t *__restrict__ ownerL,
+    const uint16_t *__restrict__ nbrL, const int32_t *__restrict__ hlist, int ocap, int hcap) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int64_t tile = xcd_tile(nblocks);
+    if (tile >= nblocks) return;
+    const int base = (int)(tile * kTile);
+    const int cnt = min(kTile, n - base);
+    const int tid = threadIdx.x;
+    const int p = base + tid;
+    const int nh = tdesc ? tdesc[2 * tile + 1] : 0;
+
+    double acc[8];
+#pragma unroll
+    for (int d = 0; d < 8; ++d) acc[d] = 0.0;
+
+    if (nh > 0) {
+        const int no = tdesc[2 * tile];
+        double *gl = reinterpret_cast<double *>(smem);               // [4][nh]
+        uint16_t *nl = reinterpret_cast<uint16_t *>(gl + 4 * nh);    // [no][K]
+        const int32_t *hl = hlist + tile * (int64_t)hcap;
+        const uint32_t *src = reinterpret_cast<const uint32_t *>(nbrL + tile * (int64_t)ocap * K);
+        uint32_t *dst = reinterpret_cast<uint32_t *>(nl);
+        const int words = (no * K + 1) >> 1;
+        for (int w = tid; w < words; w += kTile) dst[w] = src[w];
+        int ol[8];
+#pragma unroll
+        for (int d = 0; d < 8; ++d)
+            ol[d] = tid < cnt ? (MODE == MLBM_STENCIL_OWN ? tid : (int)ownerL[(int64_t)d * n + p]) * K
+                              : 0;
+#pragma unroll
+        for (int pass = 0; pass < 2; ++pass) {
+            if (pass) __syncthreads();   // the first half is read by everyone
+            for (int h = tid; h < nh; h += kTile) {
+                int q = hl[h];
+                q = (unsigned)q < (unsigned)n ? q : 0;   // a bad table must not fault
+#pragma unroll
+                for (int dd = 0; dd < 4; ++dd)
+                    gl[dd * nh + h] = g[(int64_t)(4 * pass + dd + 1) * n + q];
+            }
+            __syncthreads();
+            if (tid < cnt) {
+                for (int j = 0; j < K; ++j) {
+#pragma unroll
+                    for (int dd = 0; dd < 4; ++dd) {
+                        const int d = 4 * pass + dd;
+                        const double w = W[((int64_t)d * K + j) * n + p];
+                        acc[d] += w * gl[dd * nh + nl[ol[MODE == MLBM_STENCIL_OWN ? 0 : d] + j]];
+                    }
+                }
+            }
+        }
+        if (tid >= cnt) return;
+    } else {
+        if (tid >= cnt) return;
+        int s[8];
+#pragma unroll
+        for (int d = 0; d < 8; ++d) s[d] = MODE == MLBM_STENCIL_OWN ? p : owner[(int64_t)d * n + p];
+        for (int j = 0; j < K; ++j) {
+            int qo = 0;
+            if (MODE == MLBM_STENCIL_OWN) qo = nbr[(int64_t)j * n + p];
+#pragma unroll
+            for (int d = 0; d < 8; ++d) {
+                const double w = W[((int64_t)d * K + j) * n + p];
+                const int q = MODE == MLBM_STENCIL_OWN ? qo : nbr[(int64_t)j * n + s[d]];
+                acc[d] += w * g[(int64_t)(d + 1) * n + q];
+            }
+        }
+    }
+    double f[kQ];
+    f[0] = g[p];
+#pragma unroll
+    for (int d = 0; d < 8; ++d) f[d + 1] = acc[d];
+    collide_store64<FORCE, WALL, REC>(n, p, f, go, force, ntype, rtau, rho_w, frec);
 }
 
 // ------------------------------------------------------------------------
@@ -512,9 +601,11 @@ hipError_t step_variant(const CloudPlan &cp, int precision, const void *gin, voi
     const int64_t nblocks = (n + kTile - 1) / kTile;
     if (precision == MLBM_FP64) {
         hipLaunchKernelGGL((k_step64<MODE, FORCE, WALL, REC>), dim3(xcd_grid(nblocks)),
-                           dim3(kTile), 0, s, n, cp.K, nblocks, (const double *)gin,
+                           dim3(kTile), cp.lds_bytes, s, n, cp.K, nblocks, (const double *)gin,
                            (double *)gout, cp.W64, cp.nbr, cp.owner, cp.force64, cp.ntype,
-                           1.0 / cp.prm.tau, cp.prm.rho_wall, (double *)frec);
+                           1.0 / cp.prm.tau, cp.prm.rho_wall, (double *)frec,
+                           cp.lds_bytes ? cp.tdesc : nullptr, cp.ownerL, cp.nbrL, cp.hlist,
+                           cp.ocap, cp.hcap);
     } else {
         launch32_tuned<MODE, FORCE, WALL, REC>(cp, gin, gout, frec, nblocks, s);
     }
