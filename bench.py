@@ -325,6 +325,37 @@ def summarize_pmc(fetch_dir, write_dir, command):
     print(json.dumps(out, indent=1))
 
 
+PROFILE_TRACE = os.path.join(ROOT, "profiles", "kernels_bench_default.txt")
+
+
+def summarize_trace(trace_dir, command):
+    """Text summary of a rocprofv3 --kernel-trace --stats run (kernel_stats.csv):
+    per kernel calls, mean and total duration, for profiles/."""
+    import csv
+    rows = []
+    for root, _, files in os.walk(trace_dir):
+        for f in files:
+            if f.endswith("kernel_stats.csv"):
+                with open(os.path.join(root, f)) as fh:
+                    rows.extend(csv.DictReader(fh))
+    rows.sort(key=lambda r: -float(r["TotalDurationNs"]))
+    lines = ["# rocprofv3 kernel trace summary (durations in microseconds)",
+             "# command: " + command,
+             "# step kernel source hash: " + step_kernel_hash(),
+             "%-8s %12s %12s %7s  %s" % ("calls", "mean_us", "total_us", "pct", "kernel")]
+    for r in rows[:25]:
+        name = r["Name"]
+        if len(name) > 110:
+            name = name[:110] + "..."
+        lines.append("%-8s %12.2f %12.1f %7s  %s" % (r["Calls"], float(r["AverageNs"]) / 1e3,
+                                                     float(r["TotalDurationNs"]) / 1e3,
+                                                     r["Percentage"][:6], name))
+    os.makedirs(os.path.dirname(PROFILE_TRACE), exist_ok=True)
+    with open(PROFILE_TRACE, "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
 def load_traffic(nodes, steps):
     """HBM bytes per step-kernel launch from committed rocprofv3 counters,
     only when they were taken on the current kernel source."""
@@ -354,7 +385,12 @@ def main():
     ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
                     help="summarise two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE)")
     ap.add_argument("--pmc-command", default="", help="command recorded in the summary")
+    ap.add_argument("--summarize-trace", metavar="TRACE_DIR",
+                    help="summarise a rocprofv3 --kernel-trace --stats run")
     args = ap.parse_args()
+    if args.summarize_trace:
+        summarize_trace(args.summarize_trace, args.pmc_command)
+        return
     if args.summarize_pmc:
         summarize_pmc(args.summarize_pmc[0], args.summarize_pmc[1], args.pmc_command)
         return
