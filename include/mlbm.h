@@ -159,7 +159,8 @@ mlbm_status mlbm_plan_get_info(const mlbm_plan *plan, mlbm_plan_info *info);
  *        3 W FP64 [n][9][K] (user order; k = 0 is the identity),
  *        4 tile descriptors int32 [ntiles][2] (|O_t|, |H_t|; 0 = global path),
  *        5 halo lists int32 [ntiles][hcap] (internal indices),
- *        6 local stencils uint16 [ntiles][ocap][K],
+ *        6 local stencils uint32 [ntiles][ocap][ceil(K/3)]: halo positions of
+ *          stencil slots 3w, 3w+1, 3w+2 in bits 0-9, 10-19, 20-29 of word w,
  *        7 local owners uint16 [8][n] (internal order; paper mode),
  *        8 capacities int32 [2] (ocap, hcap).
  * Items 4-8 describe the gather tables of the FP32 step (internal layout).

@@ -119,10 +119,10 @@ void layout_cloud(const mlbm_cloud &c, const mlbm_params &p, int precision, Carv
     {   // gather tables of the LDS-staged steps (both precisions)
         const int ntiles = (n + kTile - 1) / kTile;
         cp.hcap = 1024;
-        cp.ocap = std::min(512, ((65536 - 8 * cp.hcap * 4) / (2 * K)) & ~1);
+        cp.ocap = std::min(512, (65536 - 8 * cp.hcap * 4) / (4 * ((K + 2) / 3)));
         cp.tdesc = pl.take<int32_t>((size_t)2 * ntiles);
         if (p.stencil_mode == MLBM_STENCIL_PAPER) cp.ownerL = pl.take<uint16_t>((size_t)8 * n);
-        cp.nbrL = pl.take<uint16_t>((size_t)ntiles * cp.ocap * K);
+        cp.nbrL = pl.take<uint32_t>((size_t)ntiles * cp.ocap * ((K + 2) / 3));
         cp.hlist = pl.take<int32_t>((size_t)ntiles * cp.hcap);
     }
     if (p.with_adjoint) {
@@ -186,7 +186,7 @@ mlbm_status build_tiles(mlbm_plan *plan, CloudPlan &cp, hipStream_t s) {
     MLBM_HIP(launch_fill_i32(stats, 0, 2, s));
     MLBM_HIP(launch_tiles(cp, stats, s));
     if (capturing(s)) {
-        cp.lds_bytes = (unsigned)(8 * cp.hcap * 4 + cp.ocap * cp.K * 2);
+        cp.lds_bytes = (unsigned)(8 * cp.hcap * 4 + cp.ocap * ((cp.K + 2) / 3) * 4);
         cp.fallback_tiles = -1;
         return MLBM_OK;
     }
@@ -568,7 +568,7 @@ mlbm_status mlbm_plan_export(const mlbm_plan *plan, int32_t cloud, int32_t what,
                 : what == 3 ? sizeof(double) * (size_t)n * 9 * K
                 : what == 4 ? sizeof(int32_t) * 2 * ntiles
                 : what == 5 ? sizeof(int32_t) * ntiles * cp.hcap
-                : what == 6 ? sizeof(uint16_t) * ntiles * cp.ocap * K
+                : what == 6 ? sizeof(uint32_t) * ntiles * cp.ocap * ((K + 2) / 3)
                 : what == 7 ? sizeof(uint16_t) * 8 * (size_t)n
                 : what == 8 ? sizeof(int32_t) * 2 : 0;
     if (need == 0) return fail(MLBM_EINVAL, "unknown export item");

@@ -69,7 +69,7 @@ struct CloudPlan {
     int ocap = 0, hcap = 0;       // capacities per tile: owners, halo nodes
     int32_t *tdesc = nullptr;     // [ntiles][2]: |O_t|, |H_t| (0: global path)
     uint16_t *ownerL = nullptr;   // [8][n] position of owner_k(p) in O_t
-    uint16_t *nbrL = nullptr;     // [ntiles][ocap][K] position in H_t
+    uint32_t *nbrL = nullptr;     // [ntiles][ocap][ceil(K/3)] positions in H_t, 3 x 10 bit
     int32_t *hlist = nullptr;     // [ntiles][hcap] global index of H_t entries
     unsigned lds_bytes = 0;       // dynamic LDS of the step launch (0: no tables)
     int fallback_tiles = -1;      // tiles stepped with global gathers (-1: unknown)
@@ -98,7 +98,8 @@ struct Step32Args {
     float rtau, rho0, rho_w;
     float *frec;
     const int32_t *tdesc;
-    const uint16_t *ownerL, *nbrL;
+    const uint16_t *ownerL;
+    const uint32_t *nbrL;
     const int32_t *hlist;
     int64_t soff, tile_begin;
 };

@@ -121,8 +121,9 @@ __device__ __forceinline__ void step32_tile(const Step32Args &a, const float *__
 
     if (nh > 0) {
         const int no = a.tdesc[2 * tile];
+        const int Kw = (K + 2) / 3;                                  // index words per owner
         float *gl = reinterpret_cast<float *>(smem);                 // [8][nh]
-        uint16_t *nl = reinterpret_cast<uint16_t *>(gl + 8 * nh);    // [no][K]
+        uint32_t *nl = reinterpret_cast<uint32_t *>(gl + 8 * nh);    // [no][Kw]
         const int32_t *hl = a.hlist + tile * (int64_t)a.hcap;
         for (int h = tid; h < nh; h += kTile) {
             int q = hl[h];
@@ -130,60 +131,32 @@ __device__ __forceinline__ void step32_tile(const Step32Args &a, const float *__
 #pragma unroll
             for (int d = 0; d < 8; ++d) gl[d * nh + h] = g[(int64_t)(d + 1) * n + q];
         }
-        const uint32_t *src =
-            reinterpret_cast<const uint32_t *>(a.nbrL + tile * (int64_t)a.ocap * K);
-        uint32_t *dst = reinterpret_cast<uint32_t *>(nl);
-        const int words = (no * K + 1) >> 1;
-        for (int w = tid; w < words; w += kTile) dst[w] = src[w];
+        const uint32_t *src = a.nbrL + tile * (int64_t)a.ocap * Kw;
+        for (int w = tid; w < no * Kw; w += kTile) nl[w] = src[w];
         __syncthreads();
         if (tid >= cnt) return;
         const int p = base + tid;
         int ol[8];
 #pragma unroll
         for (int d = 0; d < 8; ++d)
-            ol[d] = (MODE == MLBM_STENCIL_OWN ? tid : (int)a.ownerL[(int64_t)d * n + p]) * K;
-        if ((K & 1) == 0) {
-            // K even: ol[d] and j are even, so two consecutive local indices
-            // are one aligned 32-bit LDS word (half the index reads)
-            constexpr int U2 = UNROLL >= 2 ? UNROLL / 2 : 1;
-#pragma unroll U2
-            for (int j = 0; j < K; j += 2) {
-                const float4 wa = load_w(W + ((int64_t)j * 2) * n + p, NT);
-                const float4 wb = load_w(W + ((int64_t)j * 2 + 1) * n + p, NT);
-                const float4 wc = load_w(W + ((int64_t)j * 2 + 2) * n + p, NT);
-                const float4 wd = load_w(W + ((int64_t)j * 2 + 3) * n + p, NT);
-                const float w0[8] = {wa.x, wa.y, wa.z, wa.w, wb.x, wb.y, wb.z, wb.w};
-                const float w1[8] = {wc.x, wc.y, wc.z, wc.w, wd.x, wd.y, wd.z, wd.w};
-                if (MODE == MLBM_STENCIL_OWN) {
-                    const uint32_t pr = *reinterpret_cast<const uint32_t *>(nl + ol[0] + j);
-                    const int h0 = (int)(pr & 0xffffu), h1 = (int)(pr >> 16);
-#pragma unroll
-                    for (int d = 0; d < 8; ++d) {
-                        acc[d] += w0[d] * gl[d * nh + h0];
-                        acc[d] += w1[d] * gl[d * nh + h1];
-                    }
-                } else {
-#pragma unroll
-                    for (int d = 0; d < 8; ++d) {
-                        const uint32_t pr = *reinterpret_cast<const uint32_t *>(nl + ol[d] + j);
-                        acc[d] += w0[d] * gl[d * nh + (int)(pr & 0xffffu)];
-                        acc[d] += w1[d] * gl[d * nh + (int)(pr >> 16)];
-                    }
-                }
-            }
-        } else {
+            ol[d] = (MODE == MLBM_STENCIL_OWN ? tid : (int)a.ownerL[(int64_t)d * n + p]) * Kw;
+        // stencil slots j = 3w, 3w+1, 3w+2 share index word w (10 bits each)
 #pragma unroll UNROLL
-            for (int j = 0; j < K; ++j) {
-                const float4 wa = load_w(W + ((int64_t)j * 2) * n + p, NT);
-                const float4 wb = load_w(W + ((int64_t)j * 2 + 1) * n + p, NT);
-                const float w[8] = {wa.x, wa.y, wa.z, wa.w, wb.x, wb.y, wb.z, wb.w};
-                if (MODE == MLBM_STENCIL_OWN) {
-                    const int h = nl[ol[0] + j];
+        for (int w = 0; w < Kw; ++w) {
+            uint32_t word[8];
 #pragma unroll
-                    for (int d = 0; d < 8; ++d) acc[d] += w[d] * gl[d * nh + h];
-                } else {
+            for (int d = 0; d < 8; ++d)
+                word[d] = (MODE == MLBM_STENCIL_OWN && d > 0) ? word[0] : nl[ol[d] + w];
 #pragma unroll
-                    for (int d = 0; d < 8; ++d) acc[d] += w[d] * gl[d * nh + nl[ol[d] + j]];
+            for (int sft = 0; sft < 3; ++sft) {
+                const int jj = 3 * w + sft;
+                if (jj < K) {
+                    const float4 wa = load_w(W + ((int64_t)jj * 2) * n + p, NT);
+                    const float4 wb = load_w(W + ((int64_t)jj * 2 + 1) * n + p, NT);
+                    const float wv[8] = {wa.x, wa.y, wa.z, wa.w, wb.x, wb.y, wb.z, wb.w};
+#pragma unroll
+                    for (int d = 0; d < 8; ++d)
+                        acc[d] += wv[d] * gl[d * nh + (int)((word[d] >> (10 * sft)) & 1023u)];
                 }
             }
         }
@@ -198,11 +171,12 @@ __device__ __forceinline__ void step32_tile(const Step32Args &a, const float *__
 
     if (tid >= cnt) return;
     const int p = base + tid;
+    constexpr int UJ = 3 * UNROLL;
     int s[8];
 #pragma unroll
     for (int d = 0; d < 8; ++d)
         s[d] = MODE == MLBM_STENCIL_OWN ? p : a.owner[(int64_t)d * n + p];
-#pragma unroll UNROLL
+#pragma unroll UJ
     for (int j = 0; j < K; ++j) {
         const float4 wa = load_w(W + ((int64_t)j * 2) * n + p, NT);
         const float4 wb = load_w(W + ((int64_t)j * 2 + 1) * n + p, NT);
@@ -309,7 +283,7 @@ __global__ __launch_bounds__(kTile) void k_step64(
     const int32_t *__restrict__ owner, const double *__restrict__ force,
     const uint8_t *__restrict__ ntype, double rtau, double rho_w, double *__restrict__ frec,
     const int32_t *__restrict__ tdesc, const uint16_t *__restrict__ ownerL,
-    const uint16_t *__restrict__ nbrL, const int32_t *__restrict__ hlist, int ocap, int hcap) {
+    const uint32_t *__restrict__ nbrL, const int32_t *__restrict__ hlist, int ocap, int hcap) {
     extern __shared__ __align__(16) unsigned char smem[];
     const int64_t tile = xcd_tile(nblocks);
     if (tile >= nblocks) return;
@@ -325,17 +299,16 @@ __global__ __launch_bounds__(kTile) void k_step64(
 
     if (nh > 0) {
         const int no = tdesc[2 * tile];
+        const int Kw = (K + 2) / 3;
         double *gl = reinterpret_cast<double *>(smem);               // [4][nh]
-        uint16_t *nl = reinterpret_cast<uint16_t *>(gl + 4 * nh);    // [no][K]
+        uint32_t *nl = reinterpret_cast<uint32_t *>(gl + 4 * nh);    // [no][Kw]
         const int32_t *hl = hlist + tile * (int64_t)hcap;
-        const uint32_t *src = reinterpret_cast<const uint32_t *>(nbrL + tile * (int64_t)ocap * K);
-        uint32_t *dst = reinterpret_cast<uint32_t *>(nl);
-        const int words = (no * K + 1) >> 1;
-        for (int w = tid; w < words; w += kTile) dst[w] = src[w];
+        const uint32_t *src = nbrL + tile * (int64_t)ocap * Kw;
+        for (int w = tid; w < no * Kw; w += kTile) nl[w] = src[w];
         int ol[8];
 #pragma unroll
         for (int d = 0; d < 8; ++d)
-            ol[d] = tid < cnt ? (MODE == MLBM_STENCIL_OWN ? tid : (int)ownerL[(int64_t)d * n + p]) * K
+            ol[d] = tid < cnt ? (MODE == MLBM_STENCIL_OWN ? tid : (int)ownerL[(int64_t)d * n + p]) * Kw
                               : 0;
 #pragma unroll
         for (int pass = 0; pass < 2; ++pass) {
@@ -349,12 +322,22 @@ __global__ __launch_bounds__(kTile) void k_step64(
             }
             __syncthreads();
             if (tid < cnt) {
-                for (int j = 0; j < K; ++j) {
+                for (int w = 0; w < Kw; ++w) {
+                    uint32_t word[4];
 #pragma unroll
-                    for (int dd = 0; dd < 4; ++dd) {
-                        const int d = 4 * pass + dd;
-                        const double w = W[((int64_t)d * K + j) * n + p];
-                        acc[d] += w * gl[dd * nh + nl[ol[MODE == MLBM_STENCIL_OWN ? 0 : d] + j]];
+                    for (int dd = 0; dd < 4; ++dd)
+                        word[dd] = nl[ol[MODE == MLBM_STENCIL_OWN ? 0 : 4 * pass + dd] + w];
+#pragma unroll
+                    for (int sft = 0; sft < 3; ++sft) {
+                        const int jj = 3 * w + sft;
+                        if (jj < K) {
+#pragma unroll
+                            for (int dd = 0; dd < 4; ++dd) {
+                                const int d = 4 * pass + dd;
+                                const double wt = W[((int64_t)d * K + jj) * n + p];
+                                acc[d] += wt * gl[dd * nh + (int)((word[dd] >> (10 * sft)) & 1023u)];
+                            }
+                        }
                     }
                 }
             }
@@ -545,10 +528,11 @@ __global__ void k_collide(int n, const T *__restrict__ f, T *__restrict__ g,
     }
 }
 
-// Tuning variants of the FP32 step: unroll depth of the stencil loop (how
-// many weight rows a lane has in flight) and non-temporal weight loads (the
-// weights are streamed once per step and need not displace the halo rows in
-// L2). Variant v: unroll {2, 4, 6}[v / 2], non-temporal v % 2.
+// Tuning variants of the FP32 step: unroll depth of the stencil loop over
+// index words (1, 2 or 3 words = 3, 6 or 9 weight rows a lane has in flight)
+// and non-temporal weight loads (the weights are streamed once per step and
+// need not displace the halo rows in L2). Variant v: unroll {1, 2, 3}[v / 2],
+// non-temporal v % 2. Tiles without tables unroll their row loop 3x that.
 template <int MODE, bool FORCE, bool WALL, bool REC, int UNROLL, bool NT>
 void launch32(const CloudPlan &cp, const void *gin, void *gout, void *frec, int64_t nblocks,
               hipStream_t s) {
@@ -568,12 +552,12 @@ void launch32_batch(const mlbm_plan &plan, const void *gin, void *gout, hipStrea
 template <int MODE>
 void launch32_batch_v(const mlbm_plan &plan, const void *gin, void *gout, hipStream_t s) {
     switch (plan.c[0].variant) {
-        case 1: launch32_batch<MODE, 2, true>(plan, gin, gout, s); break;
-        case 2: launch32_batch<MODE, 4, false>(plan, gin, gout, s); break;
-        case 3: launch32_batch<MODE, 4, true>(plan, gin, gout, s); break;
-        case 4: launch32_batch<MODE, 6, false>(plan, gin, gout, s); break;
-        case 5: launch32_batch<MODE, 6, true>(plan, gin, gout, s); break;
-        default: launch32_batch<MODE, 2, false>(plan, gin, gout, s); break;
+        case 1: launch32_batch<MODE, 1, true>(plan, gin, gout, s); break;
+        case 2: launch32_batch<MODE, 2, false>(plan, gin, gout, s); break;
+        case 3: launch32_batch<MODE, 2, true>(plan, gin, gout, s); break;
+        case 4: launch32_batch<MODE, 3, false>(plan, gin, gout, s); break;
+        case 5: launch32_batch<MODE, 3, true>(plan, gin, gout, s); break;
+        default: launch32_batch<MODE, 1, false>(plan, gin, gout, s); break;
     }
 }
 
@@ -581,16 +565,16 @@ template <int MODE, bool FORCE, bool WALL, bool REC>
 void launch32_tuned(const CloudPlan &cp, const void *gin, void *gout, void *frec,
                     int64_t nblocks, hipStream_t s) {
     if (FORCE || WALL) {   // walled and forced clouds use the default variant
-        launch32<MODE, FORCE, WALL, REC, 2, false>(cp, gin, gout, frec, nblocks, s);
+        launch32<MODE, FORCE, WALL, REC, 1, false>(cp, gin, gout, frec, nblocks, s);
         return;
     }
     switch (cp.variant) {
-        case 1: launch32<MODE, FORCE, WALL, REC, 2, true>(cp, gin, gout, frec, nblocks, s); break;
-        case 2: launch32<MODE, FORCE, WALL, REC, 4, false>(cp, gin, gout, frec, nblocks, s); break;
-        case 3: launch32<MODE, FORCE, WALL, REC, 4, true>(cp, gin, gout, frec, nblocks, s); break;
-        case 4: launch32<MODE, FORCE, WALL, REC, 6, false>(cp, gin, gout, frec, nblocks, s); break;
-        case 5: launch32<MODE, FORCE, WALL, REC, 6, true>(cp, gin, gout, frec, nblocks, s); break;
-        default: launch32<MODE, FORCE, WALL, REC, 2, false>(cp, gin, gout, frec, nblocks, s); break;
+        case 1: launch32<MODE, FORCE, WALL, REC, 1, true>(cp, gin, gout, frec, nblocks, s); break;
+        case 2: launch32<MODE, FORCE, WALL, REC, 2, false>(cp, gin, gout, frec, nblocks, s); break;
+        case 3: launch32<MODE, FORCE, WALL, REC, 2, true>(cp, gin, gout, frec, nblocks, s); break;
+        case 4: launch32<MODE, FORCE, WALL, REC, 3, false>(cp, gin, gout, frec, nblocks, s); break;
+        case 5: launch32<MODE, FORCE, WALL, REC, 3, true>(cp, gin, gout, frec, nblocks, s); break;
+        default: launch32<MODE, FORCE, WALL, REC, 1, false>(cp, gin, gout, frec, nblocks, s); break;
     }
 }
 

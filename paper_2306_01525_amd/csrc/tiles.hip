@@ -7,9 +7,10 @@
 //   O_t: the sorted set of owners {owner_k(p) : p in tile, k = 1..8}
 //        (the tile's own nodes in own-stencil mode),
 //   H_t: the sorted set of stencil members {nbr[j][o] : o in O_t, j < K},
-// and stores, with 16-bit indices local to the tile,
-//   ownerL[k][p]   = position of owner_k(p) in O_t       (paper mode),
-//   nbrL[t][o][j]  = position of nbr[j][O_t[o]] in H_t,
+// and stores, with indices local to the tile,
+//   ownerL[k][p]   = position of owner_k(p) in O_t (16 bit, paper mode),
+//   nbrL[t][o][w]  = positions of nbr[j][O_t[o]] in H_t for j = 3w, 3w+1, 3w+2,
+//                    packed as three 10-bit fields of one word (|H_t| <= 1024),
 //   hlist[t][h]    = global index of H_t[h],
 //   tdesc[t]       = (|O_t|, |H_t|), |H_t| = 0 marks a tile that does not fit
 //                    the caps and is stepped with global gathers instead.
@@ -61,7 +62,7 @@ __global__ __launch_bounds__(1024) void k_tiles(int n, int K, int mode,
                                                 const int32_t *__restrict__ owner, int ocap,
                                                 int hcap, int32_t *__restrict__ tdesc,
                                                 uint16_t *__restrict__ ownerL,
-                                                uint16_t *__restrict__ nbrL,
+                                                uint32_t *__restrict__ nbrL,
                                                 int32_t *__restrict__ hlist,
                                                 int32_t *__restrict__ stats) {
     __shared__ int ocand[kOCand];
@@ -143,11 +144,19 @@ __global__ __launch_bounds__(1024) void k_tiles(int n, int K, int mode,
         // tables
         int32_t *hl = hlist + (int64_t)t * hcap;
         for (int h = tid; h < nh; h += blockDim.x) hl[h] = hsorted[h];
-        uint16_t *nl = nbrL + (int64_t)t * ocap * K;
-        for (int e = tid; e < no * K; e += blockDim.x) {
-            const int o = e / K, j = e - o * K;
-            const int q = nbr[(int64_t)j * n + ocand[o]];
-            nl[e] = (uint16_t)lower_bound(hsorted, nh, q);
+        const int Kw = (K + 2) / 3;
+        uint32_t *nl = nbrL + (int64_t)t * ocap * Kw;
+        for (int e = tid; e < no * Kw; e += blockDim.x) {
+            const int o = e / Kw, w = e - o * Kw;
+            uint32_t word = 0;
+            for (int sft = 0; sft < 3; ++sft) {
+                const int j = 3 * w + sft;
+                if (j < K) {
+                    const int q = nbr[(int64_t)j * n + ocand[o]];
+                    word |= (uint32_t)lower_bound(hsorted, nh, q) << (10 * sft);
+                }
+            }
+            nl[e] = word;
         }
         if (mode != MLBM_STENCIL_OWN) {
             for (int i = tid; i < 8 * cnt; i += blockDim.x) {
@@ -162,8 +171,8 @@ __global__ __launch_bounds__(1024) void k_tiles(int n, int K, int mode,
         tdesc[2 * t + 1] = fits ? nh : 0;
         if (fits) {
             // LDS bytes of this tile in the step kernel: 8 directions x nh
-            // populations (float) + no x K local indices (uint16)
-            atomicMax(&stats[0], 8 * nh * 4 + ((no * K * 2 + 3) & ~3));
+            // populations (float) + no x ceil(K/3) index words
+            atomicMax(&stats[0], 8 * nh * 4 + no * ((K + 2) / 3) * 4);
         } else {
             atomicAdd(&stats[1], 1);
         }

@@ -339,7 +339,8 @@ class Plan:
     def export(self, what: str):
         """Internal arrays: 'perm'; in user order 'nbr' [n][K], 'owner' [n][9],
         'W' [n][9][K] (FP64); tile tables of the FP32 step in internal order
-        'tdesc' [ntiles][2], 'hlist' [ntiles][hcap], 'nbrL' [ntiles][ocap][K],
+        'tdesc' [ntiles][2], 'hlist' [ntiles][hcap], 'nbrL' [ntiles][ocap][ceil(K/3)]
+        (three 10-bit halo positions per word),
         'ownerL' [8][n], 'caps' (ocap, hcap)."""
         import numpy as np
         K = self.params.K
@@ -350,7 +351,7 @@ class Plan:
         if code == 5:
             shape, dt = (nt, int(self.export("caps")[1])), np.int32
         elif code == 6:
-            shape, dt = (nt, int(self.export("caps")[0]), K), np.uint16
+            shape, dt = (nt, int(self.export("caps")[0]), (K + 2) // 3), np.uint32
         else:
             shape, dt = {0: ((self.n,), np.int32), 1: ((self.n, K), np.int32),
                          2: ((self.n, 9), np.int32), 3: ((self.n, 9, K), np.float64),

@@ -91,7 +91,10 @@ def test_tile_tables_are_consistent(mode):
     own_i = iperm[own_u[perm]]
     td = plan.export("tdesc")
     hl = plan.export("hlist")
-    nl = plan.export("nbrL")
+    words = plan.export("nbrL")
+    # three 10-bit halo positions per word -> [ntiles][ocap][K]
+    nl = np.stack([(words >> (10 * s_)) & 1023 for s_ in range(3)], axis=-1)
+    nl = nl.reshape(words.shape[0], words.shape[1], -1)[:, :, :30]
     ol = plan.export("ownerL") if mode == 0 else None
     T = int(plan.info.tile_nodes)
     say("mode", mode, "tiles", td.shape[0], "max nh", td[:, 1].max(), "max no", td[:, 0].max())
