@@ -162,8 +162,15 @@ mlbm_status mlbm_plan_get_info(const mlbm_plan *plan, mlbm_plan_info *info);
  *        6 local stencils uint32 [ntiles][ocap][ceil(K/3)]: halo positions of
  *          stencil slots 3w, 3w+1, 3w+2 in bits 0-9, 10-19, 20-29 of word w,
  *        7 local owners uint16 [8][n] (internal order; paper mode),
- *        8 capacities int32 [2] (ocap, hcap).
- * Items 4-8 describe the gather tables of the FP32 step (internal layout).
+ *        8 capacities int32 [2] (ocap, hcap),
+ *        9 adjoint tile descriptors int32 [ntiles] (|I_t|; 0 = global path),
+ *       10 inverse halo lists int32 [ntiles][hcap] (internal indices),
+ *       11 adjoint local columns uint32 [8][ceil((K+4)/3)][n]: positions in I_t
+ *          of transposed-row entries 3w, 3w+1, 3w+2 (bits as in item 6),
+ *       12 transposed row pointers int32 [8n+1] (row (k-1)n + m),
+ *       13 transposed row heads int32 [8][K+4][n] (internal indices).
+ * Items 4-8 describe the gather tables of the LDS-staged steps and items 9-13
+ * those of the adjoint step (internal layout; 9-13 need with_adjoint).
  * Cloud `cloud`; dst_bytes must match exactly. */
 mlbm_status mlbm_plan_export(const mlbm_plan *plan, int32_t cloud, int32_t what, void *dst,
                              size_t dst_bytes);

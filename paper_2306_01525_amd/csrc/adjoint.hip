@@ -9,6 +9,8 @@
 // row in that fixed order, so the adjoint needs no atomics and is
 // deterministic. The weights are the ones the forward step uses (FP32 after
 // the partition-of-unity correction, or FP64).
+#include <climits>
+
 #include "common.h"
 
 namespace mlbm {
@@ -146,28 +148,184 @@ __device__ __forceinline__ void moments_of(const T *f, int n, int p, int dev, do
 //   lam_b = (1 - 1/tau) lg_b + (1/tau) (A + B . e_b),
 //   A = sum_a lg_a d feq_a / d rho, B = sum_a lg_a d feq_a / d j,
 //   d C_a / d tau = (f_a - feq_a) / tau^2.
+// Inverse halo of a tile of source nodes: every arriving node that the head
+// (first lw entries) of the transposed rows of the tile's nodes reads, sorted
+// (LDS hash set, then a bitonic network), capped at hcap. The slot-major
+// columns of those rows are rewritten as positions in that set, three 10-bit
+// fields per word: elocal[k-1][w][m] holds slots 3w, 3w+1, 3w+2.
+constexpr int kAHash = 4096;
+
+__device__ void bitonic_sort_a(int *a, int npow2) {
+    for (int k = 2; k <= npow2; k <<= 1) {
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            for (int i = threadIdx.x; i < npow2; i += blockDim.x) {
+                const int ixj = i ^ j;
+                if (ixj > i) {
+                    const bool up = (i & k) == 0;
+                    const int ai = a[i], aj = a[ixj];
+                    if ((ai > aj) == up) {
+                        a[i] = aj;
+                        a[ixj] = ai;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    }
+}
+
+__device__ __forceinline__ int lower_bound_a(const int *a, int len, int v) {
+    int lo = 0, hi = len;
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (a[mid] < v) lo = mid + 1;
+        else hi = mid;
+    }
+    return lo;
+}
+
+__global__ __launch_bounds__(1024) void k_adj_tiles(int n, int lw, int hcap, int cap,
+                                                    const int32_t *__restrict__ ptr,
+                                                    const int32_t *__restrict__ ecol,
+                                                    int32_t *__restrict__ tdescT,
+                                                    int32_t *__restrict__ ilist,
+                                                    uint32_t *__restrict__ elocal,
+                                                    int32_t *__restrict__ stats) {
+    __shared__ int hset[kAHash];
+    __shared__ int hsorted[kAHash];
+    __shared__ int s_n, s_over, s_fill;
+    const int t = blockIdx.x, tid = threadIdx.x;
+    const int base = t * kTile, cnt = min(kTile, n - base);
+    const int lw3 = (lw + 2) / 3;
+    for (int i = tid; i < kAHash; i += blockDim.x) hset[i] = -1;
+    if (tid == 0) {
+        s_n = 0;
+        s_over = 0;
+        s_fill = 0;
+    }
+    __syncthreads();
+    for (int e = tid; e < 8 * cnt * lw; e += blockDim.x) {
+        const int k0 = e / (cnt * lw), r = e - k0 * cnt * lw;
+        const int l = r / lw, sl = r - l * lw;
+        const int m = base + l;
+        const int64_t row = (int64_t)k0 * n + m;
+        if (sl >= ptr[row + 1] - ptr[row]) continue;
+        const int q = ecol[((int64_t)k0 * lw + sl) * n + m];
+        uint32_t h = ((uint32_t)q * 2654435761u) >> 20;
+        for (int probe = 0; probe < kAHash; ++probe) {
+            const int old = atomicCAS(&hset[h], -1, q);
+            if (old == -1) {
+                atomicAdd(&s_n, 1);
+                break;
+            }
+            if (old == q) break;
+            h = (h + 1) & (kAHash - 1);
+            if (probe == kAHash - 1) atomicOr(&s_over, 1);
+        }
+    }
+    __syncthreads();
+    const int ni = s_n;
+    const bool fits = !s_over && ni <= cap && cap <= hcap && cap <= 1024;
+    if (fits) {
+        for (int i = tid; i < kAHash; i += blockDim.x) hsorted[i] = INT_MAX;
+        __syncthreads();
+        for (int i = tid; i < kAHash; i += blockDim.x) {
+            const int v = hset[i];
+            if (v != -1) hsorted[atomicAdd(&s_fill, 1)] = v;
+        }
+        __syncthreads();
+        int np2 = 1;
+        while (np2 < ni) np2 <<= 1;
+        bitonic_sort_a(hsorted, np2);
+        for (int h = tid; h < ni; h += blockDim.x) ilist[(int64_t)t * hcap + h] = hsorted[h];
+        for (int e = tid; e < 8 * cnt * lw3; e += blockDim.x) {
+            const int k0 = e / (cnt * lw3), r = e - k0 * cnt * lw3;
+            const int l = r / lw3, w = r - l * lw3;
+            const int m = base + l;
+            const int64_t row = (int64_t)k0 * n + m;
+            const int len = ptr[row + 1] - ptr[row];
+            uint32_t word = 0;
+            for (int sft = 0; sft < 3; ++sft) {
+                const int sl = 3 * w + sft;
+                if (sl < lw && sl < len) {
+                    const int q = ecol[((int64_t)k0 * lw + sl) * n + m];
+                    word |= (uint32_t)lower_bound_a(hsorted, ni, q) << (10 * sft);
+                }
+            }
+            elocal[((int64_t)k0 * lw3 + w) * n + m] = word;
+        }
+    }
+    if (tid == 0) {
+        tdescT[t] = fits ? ni : 0;
+        if (fits) atomicMax(&stats[0], ni);
+        else atomicAdd(&stats[1], 1);
+    }
+}
+
+// lam_n = C'(f^n)^T (S^T lam_next); part[block] = sum of (S^T lam).(dC/dtau).
+//   d feq_a / d rho = w_a [1 - 4.5 (e_a.u)^2 + 1.5 u^2]
+//   d feq_a / d j   = w_a [3 e_a + 9 (e_a.u) e_a - 3 u]
+//   C_a = f_a - (f_a - feq_a)/tau, so
+//   lam_b = (1 - 1/tau) lg_b + (1/tau) (A + B . e_b),
+//   A = sum_a lg_a d feq_a / d rho, B = sum_a lg_a d feq_a / d j,
+//   d C_a / d tau = (f_a - feq_a) / tau^2.
+// One workgroup per tile of source nodes. Tiles with an inverse halo stage
+// lam_next of that halo in LDS and read the row heads through local indices;
+// other tiles (and the rare row tails beyond lw entries) read global memory.
+// Every row is summed in its sorted order, so both paths give identical sums.
 template <class T>
 __global__ __launch_bounds__(256) void k_adj_step(
     int n, const T *__restrict__ fn, const T *__restrict__ lam_next, T *__restrict__ lam_n,
     const int32_t *__restrict__ ptr, const int32_t *__restrict__ col, const T *__restrict__ val,
-    int lw, const int32_t *__restrict__ ecol, const T *__restrict__ eval, double rtau,
-    double rho0, int dev, double *__restrict__ part) {
-    const int m = blockIdx.x * blockDim.x + threadIdx.x;
+    int lw, const int32_t *__restrict__ ecol, const T *__restrict__ eval,
+    const int32_t *__restrict__ tdescT, const int32_t *__restrict__ ilist,
+    const uint32_t *__restrict__ elocal, int hcap, double rtau, double rho0, int dev,
+    double *__restrict__ part) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int t = blockIdx.x, tid = threadIdx.x;
+    const int m = t * kTile + tid;
+    const int ni = tdescT ? tdescT[t] : 0;
+    T *L = reinterpret_cast<T *>(smem);   // [8][ni]
+    if (ni > 0) {
+        const int32_t *il = ilist + (int64_t)t * hcap;
+        for (int h = tid; h < ni; h += kTile) {
+            int q = il[h];
+            q = (unsigned)q < (unsigned)n ? q : 0;   // a bad table must not fault
+#pragma unroll
+            for (int k = 1; k < kQ; ++k) L[(k - 1) * ni + h] = lam_next[(int64_t)k * n + q];
+        }
+        __syncthreads();
+    }
     double dt = 0.0;
     if (m < n) {
         T lg[kQ];
         lg[0] = lam_next[m];
+        const int lw3 = (lw + 2) / 3;
 #pragma unroll
         for (int k = 1; k < kQ; ++k) {
             const int64_t row = (int64_t)(k - 1) * n + m;
             const int b = ptr[row], len = ptr[row + 1] - b;
             const T *lk = lam_next + (int64_t)k * n;
-            const int32_t *ec = ecol + (int64_t)(k - 1) * lw * n + m;
             const T *ev = eval + (int64_t)(k - 1) * lw * n + m;
             const int head = len < lw ? len : lw;
             T acc = 0;
             // the row in its sorted order: slot-major head, then the CSR tail
-            for (int e = 0; e < head; ++e) acc += ev[(int64_t)e * n] * lk[ec[(int64_t)e * n]];
+            if (ni > 0) {
+                const uint32_t *el = elocal + (int64_t)(k - 1) * lw3 * n + m;
+                const T *Lk = L + (k - 1) * ni;
+                for (int w = 0; 3 * w < head; ++w) {
+                    const uint32_t word = el[(int64_t)w * n];
+#pragma unroll
+                    for (int sft = 0; sft < 3; ++sft) {
+                        const int e = 3 * w + sft;
+                        if (e < head)
+                            acc += ev[(int64_t)e * n] * Lk[(word >> (10 * sft)) & 1023u];
+                    }
+                }
+            } else {
+                const int32_t *ec = ecol + (int64_t)(k - 1) * lw * n + m;
+                for (int e = 0; e < head; ++e) acc += ev[(int64_t)e * n] * lk[ec[(int64_t)e * n]];
+            }
             for (int e = lw; e < len; ++e) acc += val[b + e] * lk[col[b + e]];
             lg[k] = acc;
         }
@@ -326,16 +484,21 @@ hipError_t launch_step_adjoint(const CloudPlan &cp, int precision, const void *f
     const int n = cp.n;
     const int64_t nb = blocks_for(n, 256);
     const double rtau = 1.0 / cp.prm.tau;
+    const size_t esz = precision == MLBM_FP64 ? sizeof(double) : sizeof(float);
+    const unsigned lds = cp.adj_ni ? (unsigned)(8 * cp.adj_ni * esz) : 0;
+    const int32_t *td = cp.adj_ni ? cp.tdescT : nullptr;
     if (precision == MLBM_FP64)
-        hipLaunchKernelGGL(k_adj_step<double>, dim3(nb), dim3(256), 0, s, n, (const double *)fn,
+        hipLaunchKernelGGL(k_adj_step<double>, dim3(nb), dim3(256), lds, s, n, (const double *)fn,
                            (const double *)lam_next, (double *)lam_n, cp.tr_ptr, cp.tr_col,
                            (const double *)cp.tr_val, cp.tr_lw, cp.ell_col,
-                           (const double *)cp.ell_val, rtau, cp.prm.rho0, 0, part);
+                           (const double *)cp.ell_val, td, cp.ilist, cp.elocal, cp.hcap, rtau,
+                           cp.prm.rho0, 0, part);
     else
-        hipLaunchKernelGGL(k_adj_step<float>, dim3(nb), dim3(256), 0, s, n, (const float *)fn,
+        hipLaunchKernelGGL(k_adj_step<float>, dim3(nb), dim3(256), lds, s, n, (const float *)fn,
                            (const float *)lam_next, (float *)lam_n, cp.tr_ptr, cp.tr_col,
                            (const float *)cp.tr_val, cp.tr_lw, cp.ell_col,
-                           (const float *)cp.ell_val, rtau, cp.prm.rho0, 1, part);
+                           (const float *)cp.ell_val, td, cp.ilist, cp.elocal, cp.hcap, rtau,
+                           cp.prm.rho0, 1, part);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_sum_final, dim3(1), dim3(256), 0, s, nb, (const double *)part, dtau, 1);
@@ -352,6 +515,13 @@ hipError_t launch_init_adjoint(const CloudPlan &cp, int precision, const double 
     else
         hipLaunchKernelGGL(k_init_adjoint<float>, dim3(blocks_for(n, 256)), dim3(256), 0, s, n,
                            cp.perm, u0x, u0y, (const float *)lam0, cp.prm.rho0, gx, gy);
+    return hipGetLastError();
+}
+
+hipError_t launch_adj_tiles(const CloudPlan &cp, int32_t *stats, hipStream_t s) {
+    const int ntiles = (cp.n + kTile - 1) / kTile;
+    hipLaunchKernelGGL(k_adj_tiles, dim3(ntiles), dim3(1024), 0, s, cp.n, cp.tr_lw, cp.hcap,
+                       cp.adj_cap, cp.tr_ptr, cp.ell_col, cp.tdescT, cp.ilist, cp.elocal, stats);
     return hipGetLastError();
 }
 

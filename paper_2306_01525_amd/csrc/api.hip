@@ -135,6 +135,12 @@ void layout_cloud(const mlbm_cloud &c, const mlbm_params &p, int precision, Carv
         cp.ell_val = precision == MLBM_FP64
                          ? (void *)pl.take<double>((size_t)8 * cp.tr_lw * n)
                          : (void *)pl.take<float>((size_t)8 * cp.tr_lw * n);
+        const int ntiles = (n + kTile - 1) / kTile;
+        cp.tdescT = pl.take<int32_t>((size_t)ntiles);
+        cp.ilist = pl.take<int32_t>((size_t)ntiles * cp.hcap);
+        cp.elocal = pl.take<uint32_t>((size_t)8 * ((cp.tr_lw + 2) / 3) * n);
+        // 8 values of lam per inverse-halo node plus the 2 KiB reduction buffer
+        cp.adj_cap = precision == MLBM_FP64 ? 960 : cp.hcap;
     }
     if (ws && bw) {
         choose_grid(n, c.period_x, c.period_y, bw->gx, bw->gy, bw->hb);
@@ -207,6 +213,24 @@ void drop_graph(mlbm_plan *plan) {
         (void)hipGraphDestroy(plan->graph);
         plan->graph = nullptr;
     }
+}
+
+// Inverse-halo tables of the adjoint; the launch LDS is 8 values per node of
+// the largest inverse halo (the cap when the stream is captured).
+mlbm_status build_adj_tiles(mlbm_plan *plan, CloudPlan &cp, hipStream_t s) {
+    if (!cp.tdescT) return MLBM_OK;
+    int32_t *stats = plan->dev_err + 1;
+    MLBM_HIP(launch_fill_i32(stats, 0, 2, s));
+    MLBM_HIP(launch_adj_tiles(cp, stats, s));
+    if (capturing(s)) {
+        cp.adj_ni = cp.adj_cap;
+        return MLBM_OK;
+    }
+    int32_t h[2] = {0, 0};
+    MLBM_HIP(hipStreamSynchronize(s));
+    MLBM_HIP(hipMemcpy(h, stats, sizeof(h), hipMemcpyDeviceToHost));
+    cp.adj_ni = h[0];
+    return MLBM_OK;
 }
 
 const CloudPlan *single(const mlbm_plan *plan) {
@@ -314,6 +338,8 @@ mlbm_status build_cloud(mlbm_plan *plan, CloudPlan &cp, const mlbm_cloud &c,
     MLBM_HIP(launch_force(cp.xs, cp.ys, cp.ntype, n, p.force_kind, p.force_mag, cp.force32,
                           cp.force64, s));
     if (p.with_adjoint) MLBM_HIP(launch_transpose(cp, p.precision, bw.tr_tmp, bw.tr_bytes, s));
+    mlbm_status st = build_adj_tiles(plan, cp, s);
+    if (st != MLBM_OK) return st;
     return build_tiles(plan, cp, s);
 }
 
@@ -528,6 +554,9 @@ mlbm_status mlbm_import_weights(int32_t n, const double *x, const double *y,
         else
             STEP(hipMemcpyAsync(cp.tr_val, v32.data(), sizeof(float) * nnz, hipMemcpyHostToDevice, s));
         STEP(launch_ell_fill(cp, p.precision, s));
+        STEP(hipStreamSynchronize(s));
+        st = build_adj_tiles(plan, cp, s);
+        if (st != MLBM_OK) return cleanup(st);
     }
     STEP(hipStreamSynchronize(s));
 #undef STEP
@@ -570,8 +599,14 @@ mlbm_status mlbm_plan_export(const mlbm_plan *plan, int32_t cloud, int32_t what,
                 : what == 5 ? sizeof(int32_t) * ntiles * cp.hcap
                 : what == 6 ? sizeof(uint32_t) * ntiles * cp.ocap * ((K + 2) / 3)
                 : what == 7 ? sizeof(uint16_t) * 8 * (size_t)n
-                : what == 8 ? sizeof(int32_t) * 2 : 0;
+                : what == 8 ? sizeof(int32_t) * 2
+                : what == 9 ? sizeof(int32_t) * ntiles
+                : what == 10 ? sizeof(int32_t) * ntiles * cp.hcap
+                : what == 11 ? sizeof(uint32_t) * 8 * (size_t)((cp.tr_lw + 2) / 3) * n
+                : what == 12 ? sizeof(int32_t) * ((size_t)8 * n + 1)
+                : what == 13 ? sizeof(int32_t) * 8 * (size_t)cp.tr_lw * n : 0;
     if (need == 0) return fail(MLBM_EINVAL, "unknown export item");
+    if (what >= 9 && !cp.tdescT) return fail(MLBM_EINVAL, "plan was built without with_adjoint");
     if (what >= 4 && what <= 6 && !cp.tdesc) return fail(MLBM_EINVAL, "plan has no tile tables");
     if (what == 7 && !cp.ownerL) return fail(MLBM_EINVAL, "plan has no local owners");
     if (dst_bytes != need) return fail(MLBM_ESMALLBUF, "export size mismatch");
@@ -579,6 +614,14 @@ mlbm_status mlbm_plan_export(const mlbm_plan *plan, int32_t cloud, int32_t what,
     if (what == 8) {
         int32_t caps[2] = {cp.ocap, cp.hcap};
         std::memcpy(dst, caps, sizeof(caps));
+        return MLBM_OK;
+    }
+    if (what >= 9) {
+        const void *src = what == 9 ? (const void *)cp.tdescT
+                        : what == 10 ? (const void *)cp.ilist
+                        : what == 11 ? (const void *)cp.elocal
+                        : what == 12 ? (const void *)cp.tr_ptr : (const void *)cp.ell_col;
+        MLBM_HIP(hipMemcpy(dst, src, need, hipMemcpyDeviceToHost));
         return MLBM_OK;
     }
     if (what >= 4) {

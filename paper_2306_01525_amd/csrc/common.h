@@ -84,6 +84,12 @@ struct CloudPlan {
     int tr_lw = 0;
     int32_t *ell_col = nullptr;
     void *ell_val = nullptr;
+    // inverse halos of source tiles for the LDS-staged adjoint gather
+    int32_t *tdescT = nullptr;    // [ntiles] |I_t| (0: global gathers)
+    int32_t *ilist = nullptr;     // [ntiles][hcap] arriving nodes, sorted
+    uint32_t *elocal = nullptr;   // [8][ceil(lw/3)][n] row heads as 3 x 10-bit positions in I_t
+    int adj_cap = 0;              // largest |I_t| kept; the launch's LDS stays within 64 KiB
+    int adj_ni = 0;               // largest |I_t| (LDS of the adjoint launch: 8 |I_t| values)
 };
 
 // Arguments of the FP32 step for one cloud; also the per-cloud descriptor
@@ -226,6 +232,8 @@ size_t transpose_temp_bytes(int n, int K);
 hipError_t launch_transpose(const CloudPlan &cp, int precision, void *tmp, size_t tmp_bytes,
                             hipStream_t s);
 hipError_t launch_ell_fill(const CloudPlan &cp, int precision, hipStream_t s);
+// stats[0] <- largest inverse halo, stats[1] <- tiles without one
+hipError_t launch_adj_tiles(const CloudPlan &cp, int32_t *stats, hipStream_t s);
 hipError_t launch_loss_seed(const CloudPlan &cp, int precision, const void *fT,
                             const double *uxt, const double *uyt, void *lam, double *J,
                             double *part, hipStream_t s);

@@ -341,14 +341,18 @@ class Plan:
         'W' [n][9][K] (FP64); tile tables of the FP32 step in internal order
         'tdesc' [ntiles][2], 'hlist' [ntiles][hcap], 'nbrL' [ntiles][ocap][ceil(K/3)]
         (three 10-bit halo positions per word),
-        'ownerL' [8][n], 'caps' (ocap, hcap)."""
+        'ownerL' [8][n], 'caps' (ocap, hcap); adjoint tables (with_adjoint) 'tdescT'
+        [ntiles], 'ilist' [ntiles][hcap], 'elocal' [8][ceil((K+4)/3)][n], 'tr_ptr'
+        [8n+1], 'ell_col' [8][K+4][n]."""
         import numpy as np
         K = self.params.K
         nt = (self.n + int(self.info.tile_nodes) - 1) // int(self.info.tile_nodes)
         codes = {"perm": 0, "nbr": 1, "owner": 2, "W": 3, "tdesc": 4, "hlist": 5, "nbrL": 6,
-                 "ownerL": 7, "caps": 8}
+                 "ownerL": 7, "caps": 8, "tdescT": 9, "ilist": 10, "elocal": 11, "tr_ptr": 12,
+                 "ell_col": 13}
         code = codes[what]
-        if code == 5:
+        lw = K + 4
+        if code in (5, 10):
             shape, dt = (nt, int(self.export("caps")[1])), np.int32
         elif code == 6:
             shape, dt = (nt, int(self.export("caps")[0]), (K + 2) // 3), np.uint32
@@ -356,7 +360,10 @@ class Plan:
             shape, dt = {0: ((self.n,), np.int32), 1: ((self.n, K), np.int32),
                          2: ((self.n, 9), np.int32), 3: ((self.n, 9, K), np.float64),
                          4: ((nt, 2), np.int32), 7: ((8, self.n), np.uint16),
-                         8: ((2,), np.int32)}[code]
+                         8: ((2,), np.int32), 9: ((nt,), np.int32),
+                         11: ((8, (lw + 2) // 3, self.n), np.uint32),
+                         12: ((8 * self.n + 1,), np.int32),
+                         13: ((8, lw, self.n), np.int32)}[code]
         out = np.empty(shape, dtype=dt)
         check(_lib.load().mlbm_plan_export(self._h, 0, code, out.ctypes.data_as(ctypes.c_void_p),
                                            out.nbytes))

@@ -114,3 +114,60 @@ def test_tile_tables_are_consistent(mode):
         if mode == 0:
             np.testing.assert_array_equal(O[ol[:, base:base + cnt].T], own_i[base:base + cnt, 1:])
     plan.close()
+
+
+@pytest.mark.parametrize("mode,precision", [(0, 0), (1, 1)])
+def test_adjoint_tables_are_consistent(mode, precision):
+    """Transposed stencil operator and the gather tables of the adjoint step,
+    checked on the CPU before any adjoint step uses them: row lengths and row
+    heads match the transpose of the forward stencils (rows sorted by arriving
+    node), inverse halo lists are sorted, unique and in range, and the local
+    columns map back to the row heads."""
+    from paper_2306_01525_amd import Params, Plan
+    K, m = 30, 4
+    c, _, _ = tgv_case(64, K, m, mode, seed=9)
+    p = Params(dx=c.h, K=K, degree=m, tau=0.8, stencil_mode=mode, precision=precision,
+               with_adjoint=1)
+    plan = Plan.build(c.x, c.y, c.period, p)
+    n = c.n
+    perm = plan.export("perm")
+    iperm = np.empty_like(perm)
+    iperm[perm] = np.arange(n)
+    nbr_i = iperm[plan.export("nbr")[perm]]
+    own_i = iperm[plan.export("owner")[perm]]
+    ptr = plan.export("tr_ptr")
+    ecol = plan.export("ell_col")
+    td = plan.export("tdescT")
+    il = plan.export("ilist")
+    words = plan.export("elocal")
+    lw = K + 4
+    el = np.stack([(words >> (10 * s_)) & 1023 for s_ in range(3)], axis=2)
+    el = el.reshape(8, -1, n)[:, :lw, :]              # [8][lw][n] (slot-major)
+    assert ptr[0] == 0 and ptr[-1] == 8 * K * n and (np.diff(ptr) >= 0).all()
+    lens = np.diff(ptr).reshape(8, n)
+    arrive = np.repeat(np.arange(n), K)
+    for k in range(1, 9):
+        S = nbr_i[own_i[:, k]] if mode == 0 else nbr_i
+        src = S.ravel()
+        np.testing.assert_array_equal(lens[k - 1], np.bincount(src, minlength=n))
+        order = np.lexsort((arrive, src))
+        rows_src, rows_arr = src[order], arrive[order]
+        start = np.concatenate([[0], np.cumsum(lens[k - 1])[:-1]])
+        slot = np.arange(src.size) - start[rows_src]
+        head = slot < lw
+        np.testing.assert_array_equal(ecol[k - 1][slot[head], rows_src[head]], rows_arr[head])
+    T = int(plan.info.tile_nodes)
+    say("mode", mode, "precision", precision, "tiles", td.size, "max |I_t|", td.max(),
+        "global tiles", int((td == 0).sum()))
+    assert (td > 0).all()
+    assert td.max() <= (960 if precision == 1 else 1024)
+    for t in range(td.size):
+        ni = td[t]
+        I = il[t, :ni]
+        assert (I >= 0).all() and (I < n).all() and (np.diff(I) > 0).all()
+        ms = np.arange(t * T, min(n, (t + 1) * T))
+        for k in range(8):
+            hl = np.minimum(lens[k, ms], lw)
+            mask = np.arange(lw)[:, None] < hl[None, :]
+            np.testing.assert_array_equal(I[el[k][:, ms][mask]], ecol[k][:, ms][mask])
+    plan.close()
