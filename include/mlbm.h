@@ -165,10 +165,12 @@ mlbm_status mlbm_plan_get_info(const mlbm_plan *plan, mlbm_plan_info *info);
  *        8 capacities int32 [2] (ocap, hcap),
  *        9 adjoint tile descriptors int32 [ntiles] (|I_t|; 0 = global path),
  *       10 inverse halo lists int32 [ntiles][hcap] (internal indices),
- *       11 adjoint local columns uint32 [8][ceil((K+4)/3)][n]: positions in I_t
- *          of transposed-row entries 3w, 3w+1, 3w+2 (bits as in item 6),
+ *       11 adjoint local columns uint32 [ceil((K+4)/3)][2][n][4]: positions
+ *          in I_t of entries 3w, 3w+1, 3w+2 of transposed row k-1 = 4h + q
+ *          at [w][h][m][q] (bits as in item 6),
  *       12 transposed row pointers int32 [8n+1] (row (k-1)n + m),
- *       13 transposed row heads int32 [8][K+4][n] (internal indices).
+ *       13 transposed row heads int32 [K+4][2][n][4] (internal indices,
+ *          entry e of row k-1 = 4h + q at [e][h][m][q]; m past the row end).
  * Items 4-8 describe the gather tables of the LDS-staged steps and items 9-13
  * those of the adjoint step (internal layout; 9-13 need with_adjoint).
  * Cloud `cloud`; dst_bytes must match exactly. */

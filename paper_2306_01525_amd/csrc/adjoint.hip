@@ -59,14 +59,35 @@ __global__ void k_tr_fill(int n, int K, int mode, const int32_t *__restrict__ nb
     }
 }
 
-// Sort each CSR row by arriving node (rows hold about K entries).
+// Sort each CSR row by arriving node. One wavefront per row: an arriving node
+// appears at most once in a row, so the rank of an entry (how many entries of
+// the row have a smaller column) is its sorted position. Rows longer than a
+// wavefront (not met with K <= 48 on clouds of even spacing) take an insertion
+// sort by one lane.
 template <class T>
-__global__ void k_tr_sort(int64_t rows, const int32_t *__restrict__ ptr,
-                          int32_t *__restrict__ col, T *__restrict__ val) {
-    int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (r >= rows) return;
-    const int b = ptr[r], e = ptr[r + 1];
-    for (int a = b + 1; a < e; ++a) {
+__global__ __launch_bounds__(256) void k_tr_sort(int64_t rows, const int32_t *__restrict__ ptr,
+                                                 int32_t *__restrict__ col, T *__restrict__ val) {
+    const int lane = threadIdx.x & 63;
+    const int64_t r = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (r >= rows) return;   // uniform across the wavefront
+    const int b = ptr[r], len = ptr[r + 1] - b;
+    if (len <= 64) {
+        int c = INT_MAX;
+        T v = 0;
+        if (lane < len) {
+            c = col[b + lane];
+            v = val[b + lane];
+        }
+        int rank = 0;
+        for (int j = 0; j < 64; ++j) rank += __shfl(c, j, 64) < c;
+        if (lane < len) {
+            col[b + rank] = c;
+            val[b + rank] = v;
+        }
+        return;
+    }
+    if (lane != 0) return;
+    for (int a = b + 1; a < b + len; ++a) {
         const int c = col[a];
         const T v = val[a];
         int q = a - 1;
@@ -82,17 +103,25 @@ __global__ void k_tr_sort(int64_t rows, const int32_t *__restrict__ ptr,
 
 __global__ void k_set_i32(int32_t *p, int32_t v) { *p = v; }
 
-// Slot-major copy of the first lw entries of every sorted CSR row.
+// Index of slot e of transposed row k (0..7) of node m in the slot-major,
+// direction-interleaved arrays [slot][2][n][4]: one lane reads the four
+// directions of a half as one 16-byte (FP32) vector, as the forward weights.
+__device__ __forceinline__ int64_t ell_at(int64_t e, int k, int n, int m) {
+    return ((e * 2 + (k >> 2)) * n + m) * 4 + (k & 3);
+}
+
+// Slot-major copy of the first lw entries of every sorted CSR row. Slots past
+// the end of a row hold weight 0 and column m (local position 0).
 template <class T>
 __global__ void k_ell_fill(int n, int lw, const int32_t *__restrict__ ptr,
                            const int32_t *__restrict__ col, const T *__restrict__ val,
                            int32_t *__restrict__ ecol, T *__restrict__ eval) {
     const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (r >= (int64_t)8 * n) return;
-    const int64_t k = r / n, m = r - k * n;
+    const int m = (int)(r % n), k = (int)(r / n);
     const int b = ptr[r], len = ptr[r + 1] - b;
     for (int e = 0; e < lw; ++e) {
-        const int64_t dst = (k * lw + e) * n + m;
+        const int64_t dst = ell_at(e, k, n, m);
         ecol[dst] = e < len ? col[b + e] : (int32_t)m;
         eval[dst] = e < len ? val[b + e] : (T)0;
     }
@@ -150,9 +179,10 @@ __device__ __forceinline__ void moments_of(const T *f, int n, int p, int dev, do
 //   d C_a / d tau = (f_a - feq_a) / tau^2.
 // Inverse halo of a tile of source nodes: every arriving node that the head
 // (first lw entries) of the transposed rows of the tile's nodes reads, sorted
-// (LDS hash set, then a bitonic network), capped at hcap. The slot-major
+// (LDS hash set, then a bitonic network), capped at cap. The slot-major
 // columns of those rows are rewritten as positions in that set, three 10-bit
-// fields per word: elocal[k-1][w][m] holds slots 3w, 3w+1, 3w+2.
+// fields per word: word w of row k of node m (layout as ell_at) holds slots
+// 3w, 3w+1, 3w+2; fields past the end of the row are 0.
 constexpr int kAHash = 4096;
 
 __device__ void bitonic_sort_a(int *a, int npow2) {
@@ -210,7 +240,7 @@ __global__ __launch_bounds__(1024) void k_adj_tiles(int n, int lw, int hcap, int
         const int m = base + l;
         const int64_t row = (int64_t)k0 * n + m;
         if (sl >= ptr[row + 1] - ptr[row]) continue;
-        const int q = ecol[((int64_t)k0 * lw + sl) * n + m];
+        const int q = ecol[ell_at(sl, k0, n, m)];
         uint32_t h = ((uint32_t)q * 2654435761u) >> 20;
         for (int probe = 0; probe < kAHash; ++probe) {
             const int old = atomicCAS(&hset[h], -1, q);
@@ -248,11 +278,11 @@ __global__ __launch_bounds__(1024) void k_adj_tiles(int n, int lw, int hcap, int
             for (int sft = 0; sft < 3; ++sft) {
                 const int sl = 3 * w + sft;
                 if (sl < lw && sl < len) {
-                    const int q = ecol[((int64_t)k0 * lw + sl) * n + m];
+                    const int q = ecol[ell_at(sl, k0, n, m)];
                     word |= (uint32_t)lower_bound_a(hsorted, ni, q) << (10 * sft);
                 }
             }
-            elocal[((int64_t)k0 * lw3 + w) * n + m] = word;
+            elocal[ell_at(w, k0, n, m)] = word;
         }
     }
     if (tid == 0) {
@@ -298,36 +328,69 @@ __global__ __launch_bounds__(256) void k_adj_step(
     }
     double dt = 0.0;
     if (m < n) {
+        // The eight transposed rows of node m are walked together (eight
+        // independent sums keep many loads in flight); each row is summed in
+        // its sorted order: slot-major head (zero-weight padding adds nothing),
+        // then the CSR tail of rows longer than lw.
         T lg[kQ];
         lg[0] = lam_next[m];
-        const int lw3 = (lw + 2) / 3;
+        int bk[8], ln[8], hmax = 0;
 #pragma unroll
-        for (int k = 1; k < kQ; ++k) {
-            const int64_t row = (int64_t)(k - 1) * n + m;
-            const int b = ptr[row], len = ptr[row + 1] - b;
-            const T *lk = lam_next + (int64_t)k * n;
-            const T *ev = eval + (int64_t)(k - 1) * lw * n + m;
-            const int head = len < lw ? len : lw;
-            T acc = 0;
-            // the row in its sorted order: slot-major head, then the CSR tail
-            if (ni > 0) {
-                const uint32_t *el = elocal + (int64_t)(k - 1) * lw3 * n + m;
-                const T *Lk = L + (k - 1) * ni;
-                for (int w = 0; 3 * w < head; ++w) {
-                    const uint32_t word = el[(int64_t)w * n];
+        for (int k = 0; k < 8; ++k) {
+            const int64_t row = (int64_t)k * n + m;
+            bk[k] = ptr[row];
+            ln[k] = ptr[row + 1] - bk[k];
+            const int hd = ln[k] < lw ? ln[k] : lw;
+            hmax = hd > hmax ? hd : hmax;
+            lg[k + 1] = 0;
+        }
+        // slots past a row's end hold weight 0: every lane walks its longest row
+        typedef T T4 __attribute__((ext_vector_type(4)));
+        typedef uint32_t U4 __attribute__((ext_vector_type(4)));
+        typedef int32_t I4 __attribute__((ext_vector_type(4)));
+        const int64_t hs = (int64_t)n * 4;   // stride of one half of a slot
+        if (ni > 0) {
+            const U4 *elw = reinterpret_cast<const U4 *>(elocal) + m;
+            for (int w = 0; 3 * w < hmax; ++w) {
+                const U4 wa = elw[(int64_t)(2 * w) * n], wb = elw[(int64_t)(2 * w + 1) * n];
 #pragma unroll
-                    for (int sft = 0; sft < 3; ++sft) {
-                        const int e = 3 * w + sft;
-                        if (e < head)
-                            acc += ev[(int64_t)e * n] * Lk[(word >> (10 * sft)) & 1023u];
+                for (int sft = 0; sft < 3; ++sft) {
+                    const int e = 3 * w + sft;
+                    if (e < hmax) {
+                        const T4 va = *reinterpret_cast<const T4 *>(eval + 2 * e * hs + m * 4);
+                        const T4 vb = *reinterpret_cast<const T4 *>(eval + (2 * e + 1) * hs + m * 4);
+                        const int sh = 10 * sft;
+                        lg[1] += va.x * L[0 * ni + ((wa.x >> sh) & 1023u)];
+                        lg[2] += va.y * L[1 * ni + ((wa.y >> sh) & 1023u)];
+                        lg[3] += va.z * L[2 * ni + ((wa.z >> sh) & 1023u)];
+                        lg[4] += va.w * L[3 * ni + ((wa.w >> sh) & 1023u)];
+                        lg[5] += vb.x * L[4 * ni + ((wb.x >> sh) & 1023u)];
+                        lg[6] += vb.y * L[5 * ni + ((wb.y >> sh) & 1023u)];
+                        lg[7] += vb.z * L[6 * ni + ((wb.z >> sh) & 1023u)];
+                        lg[8] += vb.w * L[7 * ni + ((wb.w >> sh) & 1023u)];
                     }
                 }
-            } else {
-                const int32_t *ec = ecol + (int64_t)(k - 1) * lw * n + m;
-                for (int e = 0; e < head; ++e) acc += ev[(int64_t)e * n] * lk[ec[(int64_t)e * n]];
             }
-            for (int e = lw; e < len; ++e) acc += val[b + e] * lk[col[b + e]];
-            lg[k] = acc;
+        } else {
+            for (int e = 0; e < hmax; ++e) {
+                const T4 va = *reinterpret_cast<const T4 *>(eval + 2 * e * hs + m * 4);
+                const T4 vb = *reinterpret_cast<const T4 *>(eval + (2 * e + 1) * hs + m * 4);
+                const I4 ca = *reinterpret_cast<const I4 *>(ecol + 2 * e * hs + m * 4);
+                const I4 cb = *reinterpret_cast<const I4 *>(ecol + (2 * e + 1) * hs + m * 4);
+                lg[1] += va.x * lam_next[1 * (int64_t)n + ca.x];
+                lg[2] += va.y * lam_next[2 * (int64_t)n + ca.y];
+                lg[3] += va.z * lam_next[3 * (int64_t)n + ca.z];
+                lg[4] += va.w * lam_next[4 * (int64_t)n + ca.w];
+                lg[5] += vb.x * lam_next[5 * (int64_t)n + cb.x];
+                lg[6] += vb.y * lam_next[6 * (int64_t)n + cb.y];
+                lg[7] += vb.z * lam_next[7 * (int64_t)n + cb.z];
+                lg[8] += vb.w * lam_next[8 * (int64_t)n + cb.w];
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            const T *lk = lam_next + (int64_t)(k + 1) * n;
+            for (int e = bk[k] + lw; e < bk[k] + ln[k]; ++e) lg[k + 1] += val[e] * lk[col[e]];
         }
         T fk[kQ], rho, ux, uy, drho;
         moments_of<T>(fn, n, m, dev, rho0, fk, rho, ux, uy, drho);
@@ -434,14 +497,14 @@ hipError_t launch_transpose(const CloudPlan &cp, int precision, void *tmp, size_
                            mode, cp.nbr, cp.owner, (const float *)nullptr, cp.W64, cp.tr_ptr, cnt,
                            cp.tr_col, (double *)cp.tr_val);
         if ((e = hipGetLastError()) != hipSuccess) return e;
-        hipLaunchKernelGGL(k_tr_sort<double>, dim3(blocks_for(rows, 256)), dim3(256), 0, s, rows,
+        hipLaunchKernelGGL(k_tr_sort<double>, dim3(blocks_for(rows, 4)), dim3(256), 0, s, rows,
                            cp.tr_ptr, cp.tr_col, (double *)cp.tr_val);
     } else {
         hipLaunchKernelGGL(k_tr_fill<float>, dim3(blocks_for(n, 256)), dim3(256), 0, s, n, K,
                            mode, cp.nbr, cp.owner, cp.W32, (const double *)nullptr, cp.tr_ptr,
                            cnt, cp.tr_col, (float *)cp.tr_val);
         if ((e = hipGetLastError()) != hipSuccess) return e;
-        hipLaunchKernelGGL(k_tr_sort<float>, dim3(blocks_for(rows, 256)), dim3(256), 0, s, rows,
+        hipLaunchKernelGGL(k_tr_sort<float>, dim3(blocks_for(rows, 4)), dim3(256), 0, s, rows,
                            cp.tr_ptr, cp.tr_col, (float *)cp.tr_val);
     }
     if ((e = hipGetLastError()) != hipSuccess) return e;

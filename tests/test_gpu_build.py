@@ -136,13 +136,15 @@ def test_adjoint_tables_are_consistent(mode, precision):
     nbr_i = iperm[plan.export("nbr")[perm]]
     own_i = iperm[plan.export("owner")[perm]]
     ptr = plan.export("tr_ptr")
-    ecol = plan.export("ell_col")
+    # [slot][half][n][quad] -> [8][slot][n]
+    ecol = plan.export("ell_col").transpose(1, 3, 0, 2).reshape(8, K + 4, -1)
     td = plan.export("tdescT")
     il = plan.export("ilist")
-    words = plan.export("elocal")
+    words = plan.export("elocal").transpose(1, 3, 0, 2).reshape(8, -1, n)
     lw = K + 4
     el = np.stack([(words >> (10 * s_)) & 1023 for s_ in range(3)], axis=2)
     el = el.reshape(8, -1, n)[:, :lw, :]              # [8][lw][n] (slot-major)
+    assert (el[:, :, :][np.arange(lw)[None, :, None] >= np.diff(ptr).reshape(8, 1, n)] == 0).all()
     assert ptr[0] == 0 and ptr[-1] == 8 * K * n and (np.diff(ptr) >= 0).all()
     lens = np.diff(ptr).reshape(8, n)
     arrive = np.repeat(np.arange(n), K)
