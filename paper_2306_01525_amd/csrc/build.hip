@@ -325,27 +325,21 @@ __device__ __forceinline__ double readlane_d(double v, int l) {
     return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
 }
 
-// Monomial q of eq. poly_sets (order 1, x, y, x^2, xy, y^2, x^3, x^2y, xy^2,
-// y^3, x^4, x^3y, x^2y^2, xy^3, y^4) at (x, y).
+// Monomial q of eq. poly_sets (graded order 1, x, y, x^2, xy, y^2, x^3, x^2y,
+// xy^2, y^3, x^4, x^3y, x^2y^2, xy^3, y^4; q < 15): q lies in degree d, at
+// offset j within it, and is x^(d-j) y^j. Written without branches on q, so
+// that a lane-dependent q costs no divergent code.
+__device__ __forceinline__ double pow_upto4(double x, int e) {
+    double p = 1.0;
+#pragma unroll
+    for (int t = 0; t < 4; ++t) p = t < e ? p * x : p;
+    return p;
+}
+
 __device__ __forceinline__ double monomial(int q, double x, double y) {
-    switch (q) {
-        case 0: return 1.0;
-        case 1: return x;
-        case 2: return y;
-        case 3: return x * x;
-        case 4: return x * y;
-        case 5: return y * y;
-        case 6: return x * x * x;
-        case 7: return x * x * y;
-        case 8: return x * y * y;
-        case 9: return y * y * y;
-        case 10: return x * x * x * x;
-        case 11: return x * x * x * y;
-        case 12: return x * x * y * y;
-        case 13: return x * y * y * y;
-        case 14: return y * y * y * y;
-        default: return 0.0;
-    }
+    const int d = (q >= 1) + (q >= 3) + (q >= 6) + (q >= 10);
+    const int j = q - d * (d + 1) / 2;
+    return pow_upto4(x, d - j) * pow_upto4(y, j);
 }
 
 __device__ __forceinline__ double cube_dist(double ax, double ay, double bx, double by) {
@@ -372,17 +366,28 @@ __device__ __forceinline__ void rhs_point(const RhsList &L, int s, int t, int &p
     }
 }
 
+// Orders the LDS accesses of one wavefront: LDS operations of a wavefront
+// complete in issue order, so only the compiler has to be kept from moving
+// accesses across this point.
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // One wavefront solves the local system of one owner node s,
-// Phi w = phi(p) (eqs. rbf_interp_set_augmented and shape_vector), for up to R
-// departure points at a time by Gaussian elimination with partial pivoting.
-// Lane r holds row r of the system (K RBF rows, M polynomial rows, then
-// identity rows that pad the system to NB unknowns) and the R right-hand-side
-// entries of that row. Rows are never moved: the pivot of column k is the
-// not-yet-used lane with the largest |a_k| (ties: lowest lane), broadcast by
-// readlane; elimination leaves an upper-triangular system in pivot order that
-// is solved backwards, each unknown stored as soon as it is known. Owners
-// with more than R departure points repeat the (deterministic) elimination
-// for every further chunk of R points.
+// Phi w = phi(p) (eqs. rbf_interp_set_augmented and shape_vector), for every
+// departure point that uses the stencil of s, by Gauss-Jordan elimination with
+// partial pivoting. Lane r holds row r of the system (K RBF rows, M polynomial
+// rows, then identity rows that pad the system to NB unknowns) in registers.
+// Rows are never moved: the pivot of column k is the not-yet-used lane with the
+// largest |a_k| (ties: lowest lane); it copies its row to LDS and every other
+// lane, pivot rows of earlier steps included, subtracts its multiple of that
+// row and keeps the multiplier in a_k. At the end the pivot row of step j
+// holds a_j x_j = b, so unknown j (the weight of stencil member j, j < K) is
+// one division away, with no back substitution. The right-hand sides
+// (departure points) are taken R at a time: the first group is eliminated
+// along with the matrix, later groups by replaying the stored multipliers.
 template <int NB, int R>
 __global__ __launch_bounds__(256) void k_rbf(const Geo *__restrict__ geo,
                                              const double *__restrict__ xs,
@@ -392,15 +397,18 @@ __global__ __launch_bounds__(256) void k_rbf(const Geo *__restrict__ geo,
                                              int n, int K, int m, double dx,
                                              double *__restrict__ W64,
                                              int32_t *__restrict__ dev_err) {
-    const int lane = threadIdx.x & 63;
-    const int64_t wave = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
-    if (wave >= n) return;
+    __shared__ double s_row[4][NB + R];
+    __shared__ double s_cx[4][64], s_cy[4][64];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int64_t wave = (int64_t)blockIdx.x * 4 + wv;
+    if (wave >= n) return;   // uniform across the wavefront
     const int s = (int)wave;
     const int count = L.ptr ? L.ptr[s + 1] - L.ptr[s] : 8;
     if (count == 0) return;
     const Geo g = *geo;
     const int M = (m + 1) * (m + 2) / 2;
     const int nn = K + M;
+    double *row = s_row[wv];
 
     // stencil member coordinates relative to the centre s, scaled by the
     // stencil radius (the interpolant is invariant to this; it helps the
@@ -416,29 +424,42 @@ __global__ __launch_bounds__(256) void k_rbf(const Geo *__restrict__ geo,
     for (int off = 32; off > 0; off >>= 1) rad = fmax(rad, __shfl_xor(rad, off));
     if (!(rad > 0.0)) rad = 1.0;
     const double sx = rx / rad, sy = ry / rad;
+    s_cx[wv][lane] = sx;
+    s_cy[wv][lane] = sy;
+    wave_lds_sync();
     const bool rbf_row = lane < K;
     const bool poly_row = lane >= K && lane < nn;
     const int qrow = lane - K;
-    bool singular = false;
 
-    for (int c0 = 0; c0 < count; c0 += R) {
-        // row `lane` of the padded system and its right-hand sides
-        double a[NB], b[R];
+    // row `lane` of the padded system (selected without divergent branches)
+    double a[NB];
 #pragma unroll
-        for (int c = 0; c < NB; ++c) {
-            const double cxv = readlane_d(sx, c);
-            const double cyv = readlane_d(sy, c);
-            double v = 0.0;
-            if (rbf_row) {
-                if (c < K) v = cube_dist(sx, sy, cxv, cyv);
-                else if (c < nn) v = monomial(c - K, sx, sy);
-            } else if (poly_row) {
-                if (c < K) v = monomial(qrow, cxv, cyv);
-            } else if (lane < NB) {
-                v = (c == lane) ? 1.0 : 0.0;
-            }
-            a[c] = v;
-        }
+    for (int c = 0; c < NB; ++c) {
+        const double cxv = s_cx[wv][c], cyv = s_cy[wv][c];
+        const double r3 = cube_dist(sx, sy, cxv, cyv);
+        const double pr = monomial(c < nn ? c - K : 0, sx, sy);   // row lane, column c >= K
+        const double pc = monomial(poly_row ? qrow : 0, cxv, cyv);   // row qrow, column c < K
+        const double id = c == lane ? 1.0 : 0.0;
+        a[c] = rbf_row ? (c < K ? r3 : (c < nn ? pr : 0.0))
+             : poly_row ? (c < K ? pc : 0.0)
+             : lane < NB ? id : 0.0;
+    }
+    // infinity norm for the singularity threshold
+    double rs = 0.0;
+#pragma unroll
+    for (int c = 0; c < NB; ++c) rs += fabs(a[c]);
+    if (lane >= NB) rs = 0.0;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) rs = fmax(rs, __shfl_xor(rs, off));
+    const double tiny = 1e3 * DBL_EPSILON * rs;
+    bool singular = false;
+    // elimination step at which this lane was the pivot (-1: padding lane)
+    // and its pivot value
+    int pstep = lane < NB ? NB : -1;
+    double piv = 1.0;
+
+    // right-hand sides c0 .. c0+R-1 (row `lane` of each)
+    auto load_rhs = [&](int c0, double(&b)[R]) {
 #pragma unroll
         for (int t = 0; t < R; ++t) {
             double v = 0.0;
@@ -450,72 +471,80 @@ __global__ __launch_bounds__(256) void k_rbf(const Geo *__restrict__ geo,
                                          : -lat_ex(k) * dx) / rad;
                 const double qy = (L.ptr ? min_image(ys[p] - lat_ey(k) * dx - ys[s], g.Ly)
                                          : -lat_ey(k) * dx) / rad;
-                if (rbf_row) v = cube_dist(sx, sy, qx, qy);
-                else if (poly_row) v = monomial(qrow, qx, qy);
+                const double r3 = cube_dist(sx, sy, qx, qy);
+                const double pq = monomial(poly_row ? qrow : 0, qx, qy);
+                v = rbf_row ? r3 : (poly_row ? pq : 0.0);
             }
             b[t] = v;
         }
-
-        // infinity norm for the singularity threshold
-        double rs = 0.0;
-#pragma unroll
-        for (int c = 0; c < NB; ++c) rs += fabs(a[c]);
-        if (lane >= NB) rs = 0.0;
-#pragma unroll
-        for (int off = 32; off > 0; off >>= 1) rs = fmax(rs, __shfl_xor(rs, off));
-        const double tiny = 1e3 * DBL_EPSILON * rs;
-
-        bool used = lane >= NB;   // lanes beyond the system never pivot
-        int pstep = NB;           // elimination step at which this lane was the pivot
-        int plane[NB];
-#pragma unroll
-        for (int k = 0; k < NB; ++k) {
-            double v = used ? -1.0 : fabs(a[k]);
-            int idx = lane;
-#pragma unroll
-            for (int off = 32; off > 0; off >>= 1) {
-                double ov = __shfl_xor(v, off);
-                int oi = __shfl_xor(idx, off);
-                if (ov > v || (ov == v && oi < idx)) {
-                    v = ov;
-                    idx = oi;
-                }
-            }
-            const int pl = __builtin_amdgcn_readfirstlane(idx);
-            plane[k] = pl;
-            if (!(v > tiny)) singular = true;
-            const double pk = readlane_d(a[k], pl);
-            const double l = (!used && lane != pl) ? a[k] / pk : 0.0;
-#pragma unroll
-            for (int c = k + 1; c < NB; ++c) a[c] = a[c] - l * readlane_d(a[c], pl);
-#pragma unroll
-            for (int t = 0; t < R; ++t) b[t] = b[t] - l * readlane_d(b[t], pl);
-            if (lane == pl) {
-                used = true;
-                pstep = k;
-            }
-        }
-        // back substitution; unknown k < K of right-hand side t is the weight
-        // of stencil member k for that departure point
-        int tp[R], tk[R];
-#pragma unroll
-        for (int t = 0; t < R; ++t) {
-            tp[t] = -1;
-            tk[t] = 1;
-            if (c0 + t < count) rhs_point(L, s, c0 + t, tp[t], tk[t]);
-        }
-#pragma unroll
-        for (int k = NB - 1; k >= 0; --k) {
-            const int pl = plane[k];
-            const double ukk = readlane_d(a[k], pl);
+    };
+    // the pivot row of step j < K holds a_j x_j = b: x_j is the weight of
+    // stencil member j for each departure point
+    auto store = [&](int c0, const double(&b)[R]) {
+        if (pstep >= 0 && pstep < K) {
 #pragma unroll
             for (int t = 0; t < R; ++t) {
-                const double xk = readlane_d(b[t], pl) / ukk;
-                if (pstep < k) b[t] = b[t] - a[k] * xk;
-                if (k < K && lane == k && tp[t] >= 0)
-                    W64[((int64_t)(tk[t] - 1) * K + k) * n + tp[t]] = xk;
+                if (c0 + t < count) {
+                    int p, k;
+                    rhs_point(L, s, c0 + t, p, k);
+                    W64[((int64_t)(k - 1) * K + pstep) * n + p] = b[t] / piv;
+                }
             }
         }
+    };
+
+    double b[R];
+    load_rhs(0, b);
+    // elimination, carrying the first group of right-hand sides
+#pragma unroll
+    for (int k = 0; k < NB; ++k) {
+        // pivot: the lowest open lane holding the largest |a_k|
+        const double v = pstep > k ? fabs(a[k]) : -1.0;
+        double vm = v;
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) vm = fmax(vm, __shfl_xor(vm, off));
+        const int pl = __builtin_amdgcn_readfirstlane(__builtin_ctzll(__ballot(v == vm)));
+        if (!(vm > tiny)) singular = true;
+        if (lane == pl) {
+#pragma unroll
+            for (int c = k; c < NB; ++c) row[c] = a[c];
+#pragma unroll
+            for (int t = 0; t < R; ++t) row[NB + t] = b[t];
+            pstep = k;
+            piv = a[k];
+        }
+        wave_lds_sync();
+        const double l = lane != pl ? a[k] / row[k] : 0.0;
+        // (the LDS reads are issued 16 at a time, which bounds the registers
+        // they hold)
+#pragma unroll
+        for (int c = k + 1; c < NB; ++c) {
+            a[c] = a[c] - l * row[c];
+            if ((c - k) % 16 == 0) __builtin_amdgcn_sched_barrier(0);
+        }
+#pragma unroll
+        for (int t = 0; t < R; ++t) b[t] = b[t] - l * row[NB + t];
+        if (lane != pl) a[k] = l;
+        wave_lds_sync();
+    }
+    store(0, b);
+    // further groups: replay the stored multipliers
+    for (int c0 = R; c0 < count; c0 += R) {
+        load_rhs(c0, b);
+#pragma unroll
+        for (int k = 0; k < NB; ++k) {
+            if (pstep == k) {
+#pragma unroll
+                for (int t = 0; t < R; ++t) row[NB + t] = b[t];
+            }
+            wave_lds_sync();
+            if (pstep != k) {
+#pragma unroll
+                for (int t = 0; t < R; ++t) b[t] = b[t] - a[k] * row[NB + t];
+            }
+            wave_lds_sync();
+        }
+        store(c0, b);
     }
     if (singular && lane == 0) atomicMin(dev_err, perm[s] + 1);
 }
@@ -665,12 +694,8 @@ static hipError_t launch_rbf_nb(const Geo *geo, const double *xs, const double *
                                 const int32_t *perm, const int32_t *nbr, RhsList L, int n, int K,
                                 int m, double dx, double *W64, int32_t *dev_err, hipStream_t s) {
     dim3 grid(blocks_for(n, 4)), block(256);
-    if (!L.ptr)
-        hipLaunchKernelGGL((k_rbf<NB, 8>), grid, block, 0, s, geo, xs, ys, perm, nbr, L, n, K, m,
-                           dx, W64, dev_err);
-    else
-        hipLaunchKernelGGL((k_rbf<NB, 16>), grid, block, 0, s, geo, xs, ys, perm, nbr, L, n, K, m,
-                           dx, W64, dev_err);
+    hipLaunchKernelGGL((k_rbf<NB, 8>), grid, block, 0, s, geo, xs, ys, perm, nbr, L, n, K, m, dx,
+                       W64, dev_err);
     return hipGetLastError();
 }
 
