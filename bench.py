@@ -48,6 +48,13 @@ def bytes_per_update(K: int, precision: str, paper_mode: bool) -> int:
     return b + (32 if paper_mode else 0)
 
 
+def adjoint_bytes_per_update(K: int) -> float:
+    """What one reversed FP32 step must move per node with the tile-local
+    transposed operator: 8K entries of (4-byte weight + 10-bit position),
+    8 row pointers, f^n (36 B), lambda^{n+1} once (36 B), lambda^n (36 B)."""
+    return 8 * K * (4 + 4 / 3) + 8 * 4 + 3 * 36
+
+
 def step_kernel_hash() -> str:
     h = hashlib.sha256()
     for f in ("step.hip", "common.h"):
@@ -154,6 +161,7 @@ def run_gpu(args):
             ro.backward(stream=stream)
             torch.cuda.synchronize()
             e = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+            e0, e1 = e[0], e[2]
             e[0].record(stream)
             ro.forward(uxt, uyt, stream=stream)
             ro.loss(tx_t, ty_t, stream=stream)
@@ -165,6 +173,23 @@ def run_gpu(args):
         bwd = e[1].elapsed_time(e[2])
         out.update(adj_ratio=bwd / fwd, adj_fwd_ms=fwd, adj_bwd_ms=bwd)
         log("adjoint: forward %.2f ms, recompute+reverse %.2f ms, ratio %.2f" % (fwd, bwd, bwd / fwd))
+        # one reversed step on its own (gather + collision VJP + d/dtau partials)
+        with torch.cuda.stream(stream):
+            fn = planA.init(uxt, uyt)
+            lam_a = torch.randn_like(fn)
+            lam_b = torch.empty_like(fn)
+            dtau = torch.zeros(1, dtype=torch.float64, device=dev)
+            reps = 50
+            for _ in range(5):
+                planA.step_adjoint(fn, lam_a, lam_b, dtau, stream=stream)
+            torch.cuda.synchronize()
+            e0.record(stream)
+            for _ in range(reps):
+                planA.step_adjoint(fn, lam_a, lam_b, dtau, stream=stream)
+            e1.record(stream)
+            torch.cuda.synchronize()
+        out["adj_step_ms"] = e0.elapsed_time(e1) / reps
+        log("adjoint step alone: %.4f ms" % out["adj_step_ms"])
         planA.close()
     out["n"] = c.n
     out["K"] = K
@@ -449,6 +474,16 @@ def main():
         line["fp32_vs_fp64_rel_l2"] = r["fp32_vs_fp64"]
     if "adj_ratio" in r:
         line["adjoint_over_forward"] = r["adj_ratio"]
+        abpu = adjoint_bytes_per_update(K)
+        ach = abpu * n / (r["adj_step_ms"] / 1e3) / 1e9
+        line["adjoint_step"] = {"ms": r["adj_step_ms"], "bytes_per_update": abpu,
+                                "achieved": ach, "unit": "GB/s", "frac": ach / HBM_PEAK_GBS}
+    # local solves: n = K + M unknowns (M = 15 monomials of degree <= 4), LU-class
+    # elimination 2n^3/3 plus 8 right-hand sides at 2n^2 each, per node
+    nn = K + 15
+    flop = n * (2.0 * nn ** 3 / 3.0 + 16.0 * nn ** 2)
+    line["build"] = {"ms": r["build_ms"], "fp64_flop_algorithmic": flop,
+                     "tflops": flop / (r["build_ms"] / 1e3) / 1e12}
     line["autotune"] = r["tune"]
     if not args.skip_batched:
         line["batched_64_clouds"] = run_batched(args.batched_steps)
