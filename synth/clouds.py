@@ -90,10 +90,12 @@ def annulus_poisson(r_in: float, r_out: float, h: float, seed: int = 0,
     cell = h / math.sqrt(2.0)
     lo = -r_out - 2 * cell
     g = int(math.ceil((2 * r_out + 4 * cell) / cell)) + 1
-    grid = -np.ones((g, g), dtype=np.int64)
     cap = bx.shape[0] + int(1.2 * math.pi * (r_out ** 2 - r_in ** 2) / (cell * cell))
-    px = np.empty(cap)
-    py = np.empty(cap)
+    # point store with a far-away sentinel at index `cap`; the background grid
+    # (flattened, g x g) holds a point index per cell or the sentinel
+    px = np.full(cap + 1, 1e18)
+    py = np.full(cap + 1, 1e18)
+    grid = np.full(g * g, cap, dtype=np.int64)
     count = 0
 
     def insert(xs, ys):
@@ -103,15 +105,12 @@ def annulus_poisson(r_in: float, r_out: float, h: float, seed: int = 0,
         k = xs.shape[0]
         px[count:count + k] = xs
         py[count:count + k] = ys
-        # boundary nodes may share a cell: keep a list by storing the first and
-        # checking boundary nodes separately below
-        grid[cx, cy] = np.arange(count, count + k)
+        # wall nodes may share a cell: the grid keeps the last, and interior
+        # candidates are checked against the wall nodes separately below
+        grid[cx * g + cy] = np.arange(count, count + k)
         count += k
 
     insert(bx, by)
-    # Wall nodes are few and can share a background cell, so interior
-    # candidates are also checked against the wall nodes near their radius.
-    wall_r = np.hypot(bx, by)
 
     ci = np.arange(g)
     cxx, cyy = np.meshgrid(ci, ci, indexing="ij")
@@ -119,51 +118,49 @@ def annulus_poisson(r_in: float, r_out: float, h: float, seed: int = 0,
     ccy = lo + (cyy + 0.5) * cell
     rc = np.hypot(ccx, ccy)
     in_band = (rc > r_in - cell) & (rc < r_out + cell)
-    offs = [(a, b) for a in range(-2, 3) for b in range(-2, 3)]
+    offs = [a * g + b for a in range(-2, 3) for b in range(-2, 3)]
     wall_sorted = np.argsort(np.arctan2(by, bx))
     wall_ang = np.arctan2(by, bx)[wall_sorted]
 
+    inner = np.zeros_like(in_band)
+    inner[2:-2, 2:-2] = True
+    phase_cells = [np.nonzero(in_band & inner & (cxx % 3 == phx) & (cyy % 3 == phy))
+                   for phx in range(3) for phy in range(3)]
     for _ in range(rounds):
-        for phx in range(3):
-            for phy in range(3):
-                sel = in_band & (grid < 0) & (cxx % 3 == phx) & (cyy % 3 == phy)
-                sel[:2, :] = False
-                sel[-2:, :] = False
-                sel[:, :2] = False
-                sel[:, -2:] = False
-                kx, ky = np.nonzero(sel)
-                if kx.size == 0:
-                    continue
-                cand_x = lo + (kx + rng.random(kx.size)) * cell
-                cand_y = lo + (ky + rng.random(ky.size)) * cell
-                rr = np.hypot(cand_x, cand_y)
-                ok = (rr >= r_in) & (rr <= r_out)
-                for a, b in offs:
-                    nb_idx = grid[kx + a, ky + b]
-                    has = nb_idx >= 0
-                    d2 = np.full(kx.size, np.inf)
-                    d2[has] = (px[nb_idx[has]] - cand_x[has]) ** 2 + \
-                              (py[nb_idx[has]] - cand_y[has]) ** 2
-                    ok &= d2 >= h * h
-                near_wall = ok & ((rr < r_in + h) | (rr > r_out - h))
-                if near_wall.any():
-                    idx = np.nonzero(near_wall)[0]
-                    ang = np.arctan2(cand_y[idx], cand_x[idx])
-                    pos = np.searchsorted(wall_ang, ang)
-                    nw = wall_sorted.shape[0]
-                    bad = np.zeros(idx.size, dtype=bool)
-                    for off in range(-4, 5):
-                        w = wall_sorted[(pos + off) % nw]
-                        d2 = (bx[w] - cand_x[idx]) ** 2 + (by[w] - cand_y[idx]) ** 2
-                        bad |= d2 < h * h
-                    ok[idx[bad]] = False
-                if ok.any():
-                    insert(cand_x[ok], cand_y[ok])
+        for ph in range(9):
+            kx, ky = phase_cells[ph]
+            lin = kx * g + ky
+            empty = grid[lin] == cap
+            kx, ky, lin = kx[empty], ky[empty], lin[empty]
+            phase_cells[ph] = (kx, ky)
+            if kx.size == 0:
+                continue
+            cand_x = lo + (kx + rng.random(kx.size)) * cell
+            cand_y = lo + (ky + rng.random(ky.size)) * cell
+            rr = np.hypot(cand_x, cand_y)
+            ok = (rr >= r_in) & (rr <= r_out)
+            for o in offs:
+                nb_idx = grid[lin + o]
+                d2 = (px[nb_idx] - cand_x) ** 2 + (py[nb_idx] - cand_y) ** 2
+                ok &= d2 >= h * h
+            near_wall = ok & ((rr < r_in + h) | (rr > r_out - h))
+            if near_wall.any():
+                idx = np.nonzero(near_wall)[0]
+                ang = np.arctan2(cand_y[idx], cand_x[idx])
+                pos = np.searchsorted(wall_ang, ang)
+                nw = wall_sorted.shape[0]
+                bad = np.zeros(idx.size, dtype=bool)
+                for off in range(-4, 5):
+                    w = wall_sorted[(pos + off) % nw]
+                    d2 = (bx[w] - cand_x[idx]) ** 2 + (by[w] - cand_y[idx]) ** 2
+                    bad |= d2 < h * h
+                ok[idx[bad]] = False
+            if ok.any():
+                insert(cand_x[ok], cand_y[ok])
     x = px[:count].copy()
     y = py[:count].copy()
     node_type = np.zeros(count, dtype=np.uint8)
     node_type[:bx.shape[0]] = 1
-    del wall_r
     return Cloud(x, y, node_type, (0.0, 0.0), float(h))
 
 
