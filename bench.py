@@ -9,9 +9,11 @@ populations. A timed step is one fused stream+collide pass over all nodes;
 the weight build is timed separately.
 
 Also reported: the same step in plain FP64, the adjoint/forward cost of a
-checkpointed reverse sweep, L2 errors against the analytic decay, the
-roofline position of the step kernel, and the FP64 CPU oracle timed on the
-host cores on a bounded sample of the same workload.
+checkpointed reverse sweep and of one reversed step, L2 errors against the
+analytic decay, the roofline position of the step kernel, the weight-build
+rate, the annular channel (about 490,000 Poisson-disk nodes with walls and
+body force), 64 uneven clouds in one graph, and the FP64 CPU oracle timed on
+the host cores on a bounded sample of the same workload.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
 """
@@ -194,6 +196,45 @@ def run_gpu(args):
     out["n"] = c.n
     out["K"] = K
     plan32.close()
+    return out
+
+
+def run_annulus(steps: int, warmup: int):
+    """The annular channel at about 490,000 Poisson-disk nodes (R1 = 1, R2 = 2,
+    seed 3): K = 20, degree 3, paper stencils, dx = h, tau = 0.7, equilibrium
+    walls, azimuthal force 1e-6. FP32 steps timed as for the headline."""
+    import numpy as np
+    import torch
+    from paper_2306_01525_amd import Params, Plan
+    from synth.clouds import annulus_h_for_count, annulus_poisson
+    c = annulus_poisson(1.0, 2.0, annulus_h_for_count(1.0, 2.0, 500_000), seed=3)
+    K = 20
+    p = Params(dx=c.h, K=K, degree=3, tau=0.7, stencil_mode=0, force_kind=1, force_mag=1e-6,
+               wall_kind=1, rho_wall=1.0)
+    log("annulus: n = %d, h = %.3e; building" % (c.n, c.h))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    plan = Plan.build(c.x, c.y, c.period, p, node_type=c.node_type)
+    torch.cuda.synchronize()
+    build_ms = (time.perf_counter() - t0) * 1e3
+    stream = torch.cuda.Stream()
+    zeros = np.zeros(c.n)
+    tune = plan.autotune(plan.init(zeros, zeros), plan.new_state(), 20)
+    log("annulus: autotune ms/step per variant:", " ".join("%.4f" % t for t in tune),
+        "-> variant", plan.info.variant)
+    ms, g = time_steps(plan, plan.init(zeros, zeros), steps, warmup, stream)
+    _, u, v = plan.moments(g)
+    bpu = bytes_per_update(K, "f32", True)
+    per = ms / steps
+    out = {"nodes": c.n, "K": K, "degree": 3, "steps": steps, "ms_per_step": per,
+           "value": c.n / (per / 1e3), "bytes_per_update": bpu,
+           "roofline_frac": bpu * c.n / (per / 1e3) / 1e9 / HBM_PEAK_GBS,
+           "build_ms": build_ms, "fallback_tiles": int(plan.info.fallback_tiles),
+           "autotune_ms_per_step": tune, "variant": int(plan.info.variant),
+           "max_speed": float(torch.sqrt(u * u + v * v).max()),
+           "device_error": plan.device_error()}
+    log("annulus: %.4f ms/step, %.2e node-updates/s" % (per, out["value"]))
+    plan.close()
     return out
 
 
@@ -403,6 +444,7 @@ def main():
     ap.add_argument("--skip-adjoint", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--skip-batched", action="store_true")
+    ap.add_argument("--skip-annulus", action="store_true")
     ap.add_argument("--batched-steps", type=int, default=500)
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--copy-calibration", action="store_true",
@@ -485,6 +527,8 @@ def main():
     line["build"] = {"ms": r["build_ms"], "fp64_flop_algorithmic": flop,
                      "tflops": flop / (r["build_ms"] / 1e3) / 1e12}
     line["autotune"] = r["tune"]
+    if not args.skip_annulus:
+        line["annulus_490k"] = run_annulus(args.steps, args.warmup)
     if not args.skip_batched:
         line["batched_64_clouds"] = run_batched(args.batched_steps)
     if not args.no_cpu_baseline:

@@ -564,7 +564,7 @@ void launch32_batch_v(const mlbm_plan &plan, const void *gin, void *gout, hipStr
 template <int MODE, bool FORCE, bool WALL, bool REC>
 void launch32_tuned(const CloudPlan &cp, const void *gin, void *gout, void *frec,
                     int64_t nblocks, hipStream_t s) {
-    if (FORCE || WALL) {   // walled and forced clouds use the default variant
+    if (FORCE != WALL) {   // clouds with only one of force and walls: default variant
         launch32<MODE, FORCE, WALL, REC, 1, false>(cp, gin, gout, frec, nblocks, s);
         return;
     }

@@ -164,17 +164,24 @@ def test_tiles_cover_the_workload_and_fallback_path_matches():
 
 def test_step_variants_are_bitwise_identical_and_autotune_picks_one():
     from paper_2306_01525_amd import Plan
+    ca = annulus_case(0.05)
+    walled = Plan.build(ca.x, ca.y, ca.period,
+                        _params(0.05, 20, 3, 0, 0, 0.7, force_kind=1, force_mag=1e-5,
+                                wall_kind=1, rho_wall=1.0), node_type=ca.node_type)
+    za = np.zeros(ca.n)
     c, ux, uy = tgv_case(40, 30, 4, 0)
     plan = Plan.build(c.x, c.y, c.period, _params(c.h, 30, 4, 0, 0, 0.6))
-    ref = None
-    for v in range(6):
-        plan.set_variant(v)
-        g = plan.init(ux, uy)
-        g = plan.step(g, plan.new_state(), 25)
-        if ref is None:
-            ref = g.clone()
-        else:
-            assert torch.equal(g, ref), v
+    for pl, vx, vy in ((walled, za, za), (plan, ux, uy)):
+        ref = None
+        for v in range(6):
+            pl.set_variant(v)
+            g = pl.init(vx, vy)
+            g = pl.step(g, pl.new_state(), 25)
+            if ref is None:
+                ref = g.clone()
+            else:
+                assert torch.equal(g, ref), v
+    walled.close()
     a, b = plan.new_state(), plan.new_state()
     ms = plan.autotune(plan.init(ux, uy, g=a), b, 5)
     say("variant ms/step", ["%.4f" % m for m in ms], "chosen", plan.info.variant)
