@@ -216,6 +216,15 @@ mlbm_status mlbm_moments(const mlbm_plan *plan, const void *g, double *rho, doub
 mlbm_status mlbm_l2_sums(const mlbm_plan *plan, const void *g, const double *ux_t,
                          const double *uy_t, double *out, hipStream_t stream);
 
+/* Steady-state residual (Sec. 3, annular channel: runs stop when the relative
+ * change of the velocity field falls below a threshold): with U = |u| of
+ * state g at every node and speed (device FP64 [n_total], user order) holding
+ * U of the previous check, out[0] = sum (U - U_prev)^2, out[1] = sum U^2
+ * (out[2], out[3] = 0), so the residual is sqrt(out[0] / out[1]). speed is
+ * overwritten with the current U (zero it before the first check). */
+mlbm_status mlbm_residual(const mlbm_plan *plan, const void *g, double *speed, double *out,
+                          hipStream_t stream);
+
 /* ---- differentiation (no walls, no force) ----------------------------------- */
 
 /* Forward steps that also record the pre-collision populations f^n of every

@@ -65,6 +65,7 @@ SIGNATURES = {
     "mlbm_step_record": (_c_i32, [_c_p, _c_p, _c_p, _c_i32, _c_p, _P(_c_i32), _c_p]),
     "mlbm_moments": (_c_i32, [_c_p, _c_p, _c_p, _c_p, _c_p, _c_p]),
     "mlbm_l2_sums": (_c_i32, [_c_p, _c_p, _c_p, _c_p, _c_p, _c_p]),
+    "mlbm_residual": (_c_i32, [_c_p, _c_p, _c_p, _c_p, _c_p]),
     "mlbm_loss_seed": (_c_i32, [_c_p, _c_p, _c_p, _c_p, _c_p, _c_p, _c_p]),
     "mlbm_step_adjoint": (_c_i32, [_c_p, _c_p, _c_p, _c_p, _c_p, _c_p]),
     "mlbm_init_adjoint": (_c_i32, [_c_p, _c_p, _c_p, _c_p, _c_p, _c_p, _c_p]),

@@ -806,6 +806,24 @@ mlbm_status mlbm_l2_sums(const mlbm_plan *plan, const void *g, const double *ux_
     return MLBM_OK;
 }
 
+mlbm_status mlbm_residual(const mlbm_plan *plan, const void *g, double *speed, double *out,
+                          hipStream_t s) {
+    if (!single(plan) || !g || !speed || !out) return fail(MLBM_EINVAL, "null argument");
+    if (plan->c.size() == 1) {
+        MLBM_HIP(launch_residual(plan->c[0], plan->precision, g, speed, out, plan->scratch64, s));
+        return MLBM_OK;
+    }
+    double *sums = plan->scratch64;
+    double *part = plan->scratch64 + 4 * plan->c.size();
+    for (size_t c = 0; c < plan->c.size(); ++c) {
+        const CloudPlan &cp = plan->c[c];
+        MLBM_HIP(launch_residual(cp, plan->precision, state_at(plan, g, cp),
+                                 speed + cp.off, sums + 4 * c, part, s));
+    }
+    MLBM_HIP(launch_l2_final(sums, (int64_t)plan->c.size(), out, s));
+    return MLBM_OK;
+}
+
 mlbm_status mlbm_loss_seed(const mlbm_plan *plan, const void *f_T, const double *ux_t,
                            const double *uy_t, void *lamf_T, double *J, hipStream_t s) {
     const CloudPlan *cp = single(plan);

@@ -222,6 +222,9 @@ hipError_t launch_moments(const CloudPlan &cp, int precision, const void *g, dou
                           double *ux, double *uy, bool post_collision, hipStream_t s);
 hipError_t launch_l2(const CloudPlan &cp, int precision, const void *g, const double *uxt,
                      const double *uyt, double *out, double *part, hipStream_t s);
+// speed: device FP64 [n] user order, in/out; out[0..3] as launch_l2
+hipError_t launch_residual(const CloudPlan &cp, int precision, const void *g, double *speed,
+                           double *out, double *part, hipStream_t s);
 hipError_t launch_collide(const CloudPlan &cp, int precision, const void *f, void *g,
                           hipStream_t s);
 hipError_t launch_l2_final(const double *part, int64_t nparts, double *out, hipStream_t s);

@@ -477,6 +477,62 @@ __global__ __launch_bounds__(256) void k_l2_partial(
     if (threadIdx.x < 4) part[(int64_t)blockIdx.x * 4 + threadIdx.x] = sh[threadIdx.x][0];
 }
 
+// Speed |u| of every node against the speed of an earlier check (user order,
+// overwritten with the current speed): part[block] = (sum (|u| - |u_prev|)^2,
+// sum |u|^2, 0, 0). The relative residual of the steady-state runs is
+// sqrt(out[0] / out[1]).
+template <class T>
+__global__ __launch_bounds__(256) void k_residual_partial(
+    int n, const int32_t *__restrict__ perm, const T *__restrict__ g,
+    const float *__restrict__ f32, const double *__restrict__ f64,
+    const uint8_t *__restrict__ ntype, double rho0, int dev, double *__restrict__ speed,
+    double *__restrict__ part) {
+    __shared__ double sh[2][256];
+    int p = blockIdx.x * blockDim.x + threadIdx.x;
+    double a0 = 0, a1 = 0;
+    if (p < n) {
+        double r = 0.0, jx = 0.0, jy = 0.0;
+        for (int k = 0; k < kQ; ++k) {
+            const double v = (double)g[(int64_t)k * n + p];
+            r += v;
+            jx += v * lat_ex(k);
+            jy += v * lat_ey(k);
+        }
+        if (dev) r += rho0;
+        if (!(ntype && ntype[p])) {
+            if (f32) {
+                jx -= (double)f32[p];
+                jy -= (double)f32[n + p];
+            } else if (f64) {
+                jx -= f64[p];
+                jy -= f64[n + p];
+            }
+        }
+        const int u = perm[p];
+        const double U = sqrt(jx * jx + jy * jy) / r;
+        const double d = U - speed[u];
+        a0 = d * d;
+        a1 = U * U;
+        speed[u] = U;
+    }
+    sh[0][threadIdx.x] = a0;
+    sh[1][threadIdx.x] = a1;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) {
+            sh[0][threadIdx.x] += sh[0][threadIdx.x + w];
+            sh[1][threadIdx.x] += sh[1][threadIdx.x + w];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        part[blockIdx.x * 4 + 0] = sh[0][0];
+        part[blockIdx.x * 4 + 1] = sh[1][0];
+        part[blockIdx.x * 4 + 2] = 0.0;
+        part[blockIdx.x * 4 + 3] = 0.0;
+    }
+}
+
 __global__ __launch_bounds__(256) void k_l2_final(int64_t nparts, const double *__restrict__ part,
                                                   double *__restrict__ out) {
     __shared__ double sh[4][256];
@@ -708,6 +764,24 @@ hipError_t launch_l2(const CloudPlan &cp, int precision, const void *g, const do
     else
         hipLaunchKernelGGL(k_l2_partial<float>, dim3(nb), dim3(256), 0, s, n, cp.perm,
                            (const float *)g, f32, f64, cp.ntype, cp.prm.rho0, 1, uxt, uyt, part);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_l2_final, dim3(1), dim3(256), 0, s, nb, (const double *)part, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_residual(const CloudPlan &cp, int precision, const void *g, double *speed,
+                           double *out, double *part, hipStream_t s) {
+    const int n = cp.n;
+    const int64_t nb = blocks_for(n, 256);
+    const float *f32 = precision != MLBM_FP64 ? cp.force32 : nullptr;
+    const double *f64 = precision == MLBM_FP64 ? cp.force64 : nullptr;
+    if (precision == MLBM_FP64)
+        hipLaunchKernelGGL(k_residual_partial<double>, dim3(nb), dim3(256), 0, s, n, cp.perm,
+                           (const double *)g, f32, f64, cp.ntype, cp.prm.rho0, 0, speed, part);
+    else
+        hipLaunchKernelGGL(k_residual_partial<float>, dim3(nb), dim3(256), 0, s, n, cp.perm,
+                           (const float *)g, f32, f64, cp.ntype, cp.prm.rho0, 1, speed, part);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_l2_final, dim3(1), dim3(256), 0, s, nb, (const double *)part, out);

@@ -278,6 +278,45 @@ class Plan:
                                        _stream(stream)))
         return out
 
+    def residual(self, g, speed, stream=None):
+        """Relative change of the speed field since the check that filled
+        `speed` (device FP64 [n], overwritten with the current speed)."""
+        out = torch.empty(4, dtype=torch.float64, device=self.device)
+        _order(stream, out)
+        check(_lib.load().mlbm_residual(self._h, _ptr(g), _ptr(speed), _ptr(out), _stream(stream)))
+        if stream is not None:
+            torch.cuda.current_stream().wait_stream(stream)
+        s = out.cpu().tolist()
+        return (s[0] / s[1]) ** 0.5 if s[1] > 0 else float("inf")
+
+    def run_to_steady(self, g, tol=1e-8, check_every=100, max_steps=500_000, plateau=10,
+                      stream=None):
+        """Step until the residual between checks `check_every` steps apart
+        falls below `tol`, stops decreasing for `plateau` checks in a row
+        (FP32 can level off above tol), or `max_steps` is reached. Returns
+        (state, steps, residual, reason) with reason 'tol', 'plateau' or
+        'max_steps'."""
+        other = self.new_state()
+        speed = torch.zeros(self.n, dtype=torch.float64, device=self.device)
+        _order(stream, speed)
+        self.residual(g, speed, stream)
+        steps, best, stall, r = 0, float("inf"), 0, float("inf")
+        while steps < max_steps:
+            res = self.step(g, other, check_every, stream=stream)
+            if res is other:
+                g, other = other, g
+            steps += check_every
+            r = self.residual(g, speed, stream)
+            if r < tol:
+                return g, steps, r, "tol"
+            if r < best:
+                best, stall = r, 0
+            else:
+                stall += 1
+                if stall >= plateau:
+                    return g, steps, r, "plateau"
+        return g, steps, r, "max_steps"
+
     def l2(self, g, ux_t, uy_t):
         """(L2 of the u-component, L2 of the velocity vector), eq. L2norm."""
         s = self.l2_sums(g, ux_t, uy_t).cpu().tolist()

@@ -181,3 +181,46 @@ def test_steady_state_matches_oracle_and_analytic(precision):
     e1 = analytic.l2_error(ut, analytic.annulus_profile(r / 0.05, R1 / 0.05, R2 / 0.05, G, 0.5 / 3))
     say("tau 1.0 h 0.050: L2(u_phi) %.3e" % e1)
     assert e1 < 1e-2
+
+
+@pytest.mark.parametrize("precision", [1, 0])
+def test_residual_and_run_to_steady(precision):
+    """The steady-state residual ||U^n - U^m|| / ||U^n|| (U = |u|) equals its
+    definition evaluated on the moments; the residual-driven run stops on the
+    threshold (FP64) or on it or a plateau (FP32), at the same steady field."""
+    h = 0.05
+    c = annulus_poisson(R1, R2, h, seed=3)
+    plan = _plan(c, h, precision)
+    zeros = np.zeros(c.n)
+    g = plan.init(zeros, zeros)
+    other = plan.new_state()
+    speed = torch.zeros(c.n, dtype=torch.float64, device="cuda")
+    r0 = None
+    U = []
+    for _ in range(2):
+        res = plan.step(g, other, 100)
+        if res is other:
+            g, other = other, g
+        r0 = plan.residual(g, speed)
+        _, u, v = (a.cpu().numpy() for a in plan.moments(g))
+        U.append(np.hypot(u, v))
+    np.testing.assert_allclose(speed.cpu().numpy(), U[1], rtol=1e-5 if precision == 0 else 1e-12,
+                               atol=1e-12)
+    want = np.linalg.norm(U[1] - U[0]) / np.linalg.norm(U[1])
+    say("residual after 200 steps: GPU %.6e, from the moments %.6e" % (r0, want))
+    assert abs(r0 - want) <= (1e-10 if precision == 1 else 1e-4) * want
+
+    g = plan.init(zeros, zeros)
+    tol = 1e-8 if precision == 1 else 1e-7
+    gs, steps, r, why = plan.run_to_steady(g, tol=tol, check_every=100, max_steps=60_000)
+    _, u, v = (a.cpu().numpy() for a in plan.moments(gs))
+    plan.close()
+    say("run to steady: %d steps, residual %.2e, stopped on %s" % (steps, r, why))
+    if precision == 1:
+        assert why == "tol"
+    else:
+        assert why in ("tol", "plateau")
+    _, u2, v2 = _steady(c, h, precision, TAU)
+    d = rel_l2(np.stack([u, v]), np.stack([u2, v2]))
+    say("against the 30-relaxation-time field: %.2e" % d)
+    assert d < 1e-4
