@@ -225,6 +225,26 @@ mlbm_status mlbm_l2_sums(const mlbm_plan *plan, const void *g, const double *ux_
 mlbm_status mlbm_residual(const mlbm_plan *plan, const void *g, double *speed, double *out,
                           hipStream_t stream);
 
+/* ---- standard lattice Boltzmann (the paper's reference method) ----------------
+ * D2Q9 BGK on a periodic nx x ny lattice of unit spacing and time step, with
+ * streaming by an index shift (eq. LBM_streaming) and the collision of the
+ * MLBM step (eqs. LBM_collision, feq). Node (ix, iy) is index iy * nx + ix;
+ * the state is [9][ny][nx] post-collision populations, FP32 deviations from
+ * w_k rho0 (MLBM_FP32_DEV) or plain FP64 (MLBM_FP64), caller-owned device
+ * memory of 9 * nx * ny elements. Inputs and outputs are device FP64 [ny][nx]
+ * (rho may be NULL for rho0, u for rest). nx * ny * 9 must fit in int32. */
+mlbm_status mlbm_lbm_init(int32_t nx, int32_t ny, int32_t precision, double rho0,
+                          const double *rho, const double *ux, const double *uy, void *g,
+                          hipStream_t stream);
+/* n_steps steps, ping-pong between g_a and g_b (distinct); *result_in_b = 1
+ * when the result is in g_b. */
+mlbm_status mlbm_lbm_step(int32_t nx, int32_t ny, int32_t precision, double tau, double rho0,
+                          void *g_a, void *g_b, int32_t n_steps, int32_t *result_in_b,
+                          hipStream_t stream);
+mlbm_status mlbm_lbm_moments(int32_t nx, int32_t ny, int32_t precision, double rho0,
+                             const void *g, double *rho, double *ux, double *uy,
+                             hipStream_t stream);
+
 /* ---- differentiation (no walls, no force) ----------------------------------- */
 
 /* Forward steps that also record the pre-collision populations f^n of every

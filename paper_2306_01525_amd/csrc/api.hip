@@ -7,6 +7,7 @@
 #include <cstring>
 #include <new>
 #include <string>
+#include <utility>
 #include <vector>
 
 #include "common.h"
@@ -821,6 +822,52 @@ mlbm_status mlbm_residual(const mlbm_plan *plan, const void *g, double *speed, d
                                  speed + cp.off, sums + 4 * c, part, s));
     }
     MLBM_HIP(launch_l2_final(sums, (int64_t)plan->c.size(), out, s));
+    return MLBM_OK;
+}
+
+namespace {
+mlbm_status check_lattice(int32_t nx, int32_t ny, int32_t precision) {
+    if (nx < 1 || ny < 1 || (int64_t)nx * ny > INT32_MAX / kQ)
+        return fail(MLBM_EINVAL, "lattice size out of range");
+    if (precision != MLBM_FP32_DEV && precision != MLBM_FP64)
+        return fail(MLBM_EINVAL, "unknown precision");
+    return MLBM_OK;
+}
+}  // namespace
+
+mlbm_status mlbm_lbm_init(int32_t nx, int32_t ny, int32_t precision, double rho0,
+                          const double *rho, const double *ux, const double *uy, void *g,
+                          hipStream_t s) {
+    mlbm_status st = check_lattice(nx, ny, precision);
+    if (st != MLBM_OK) return st;
+    if (!g) return fail(MLBM_EINVAL, "null state");
+    MLBM_HIP(launch_lbm_init(nx * ny, precision, rho0, rho, ux, uy, g, s));
+    return MLBM_OK;
+}
+
+mlbm_status mlbm_lbm_step(int32_t nx, int32_t ny, int32_t precision, double tau, double rho0,
+                          void *g_a, void *g_b, int32_t n_steps, int32_t *result_in_b,
+                          hipStream_t s) {
+    mlbm_status st = check_lattice(nx, ny, precision);
+    if (st != MLBM_OK) return st;
+    if (!g_a || !g_b || g_a == g_b) return fail(MLBM_EINVAL, "two distinct state buffers needed");
+    if (!(tau > 0.5)) return fail(MLBM_EINVAL, "tau must exceed 1/2");
+    if (n_steps < 0) return fail(MLBM_EINVAL, "negative step count");
+    void *a = g_a, *b = g_b;
+    for (int32_t t = 0; t < n_steps; ++t) {
+        MLBM_HIP(launch_lbm_step(nx, ny, precision, tau, rho0, a, b, s));
+        std::swap(a, b);
+    }
+    if (result_in_b) *result_in_b = (n_steps & 1) ? 1 : 0;
+    return MLBM_OK;
+}
+
+mlbm_status mlbm_lbm_moments(int32_t nx, int32_t ny, int32_t precision, double rho0,
+                             const void *g, double *rho, double *ux, double *uy, hipStream_t s) {
+    mlbm_status st = check_lattice(nx, ny, precision);
+    if (st != MLBM_OK) return st;
+    if (!g) return fail(MLBM_EINVAL, "null state");
+    MLBM_HIP(launch_lbm_moments(nx * ny, precision, rho0, g, rho, ux, uy, s));
     return MLBM_OK;
 }
 

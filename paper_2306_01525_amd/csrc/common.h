@@ -225,6 +225,13 @@ hipError_t launch_l2(const CloudPlan &cp, int precision, const void *g, const do
 // speed: device FP64 [n] user order, in/out; out[0..3] as launch_l2
 hipError_t launch_residual(const CloudPlan &cp, int precision, const void *g, double *speed,
                            double *out, double *part, hipStream_t s);
+// standard lattice Boltzmann on a periodic nx x ny lattice, state [9][ny][nx]
+hipError_t launch_lbm_step(int nx, int ny, int precision, double tau, double rho0,
+                           const void *g, void *go, hipStream_t s);
+hipError_t launch_lbm_init(int n, int precision, double rho0, const double *rho, const double *ux,
+                           const double *uy, void *g, hipStream_t s);
+hipError_t launch_lbm_moments(int n, int precision, double rho0, const void *g, double *rho,
+                              double *ux, double *uy, hipStream_t s);
 hipError_t launch_collide(const CloudPlan &cp, int precision, const void *f, void *g,
                           hipStream_t s);
 hipError_t launch_l2_final(const double *part, int64_t nparts, double *out, hipStream_t s);

@@ -377,7 +377,7 @@ __global__ void k_init(int n, const int32_t *__restrict__ perm, const double *__
                        T *__restrict__ g) {
     int p = blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= n) return;
-    const int u = perm[p];
+    const int u = perm ? perm[p] : p;
     double r = rho ? rho[u] : rho0;
     double vx = ux ? ux[u] : 0.0, vy = uy ? uy[u] : 0.0;
     const bool is_wall = wall && ntype && ntype[p];
@@ -422,7 +422,7 @@ __global__ void k_moments(int n, const int32_t *__restrict__ perm, const T *__re
             jy -= f64[n + p];
         }
     }
-    const int u = perm[p];
+    const int u = perm ? perm[p] : p;
     if (rho) rho[u] = r;
     if (ux) ux[u] = jx / r;
     if (uy) uy[u] = jy / r;
@@ -673,6 +673,42 @@ hipError_t step_force(const CloudPlan &cp, int precision, const void *gin, void 
                              : step_wall<MODE, false>(cp, precision, gin, gout, frec, s);
 }
 
+// ------------------------------------------------------------------------
+// Standard lattice Boltzmann (eq. LBM_streaming): the reference method of the
+// paper on a periodic nx x ny lattice, state [9][ny][nx] with x fastest.
+// Streaming is a pull by the index shift x - e_k (wrapped), followed by the
+// same moments and BGK collision as the fused MLBM step. Workgroups cover 256
+// consecutive nodes of a row; the XCD map keeps neighbouring rows, which read
+// each other's populations, in one L2.
+// ------------------------------------------------------------------------
+template <class T>
+__global__ __launch_bounds__(256) void k_lbm_step(int nx, int ny, int64_t nblocks,
+                                                  const T *__restrict__ g, T *__restrict__ go,
+                                                  double rtau, double rho0) {
+    const int64_t b = xcd_tile(nblocks);
+    if (b >= nblocks) return;
+    const int bx = (nx + 255) / 256;
+    const int y = (int)(b / bx);
+    const int x = (int)(b - (int64_t)y * bx) * 256 + threadIdx.x;
+    if (x >= nx) return;
+    const int64_t n = (int64_t)nx * ny;
+    const int p = y * nx + x;
+    T f[kQ];
+#pragma unroll
+    for (int k = 0; k < kQ; ++k) {
+        int sx = x - (int)lat_ex(k), sy = y - (int)lat_ey(k);
+        sx = sx < 0 ? sx + nx : (sx >= nx ? sx - nx : sx);
+        sy = sy < 0 ? sy + ny : (sy >= ny ? sy - ny : sy);
+        f[k] = g[(int64_t)k * n + (int64_t)sy * nx + sx];
+    }
+    if constexpr (sizeof(T) == 4)
+        collide_store32<false, false, false>((int)n, p, f, go, nullptr, nullptr, (float)rtau,
+                                             (float)rho0, 0.0f, nullptr);
+    else
+        collide_store64<false, false, false>((int)n, p, f, go, nullptr, nullptr, rtau, 0.0,
+                                             nullptr);
+}
+
 }  // namespace
 
 Step32Args step32_args(const CloudPlan &cp, void *frec) {
@@ -806,6 +842,46 @@ hipError_t launch_collide(const CloudPlan &cp, int precision, const void *f, voi
 
 hipError_t launch_l2_final(const double *part, int64_t nparts, double *out, hipStream_t s) {
     hipLaunchKernelGGL(k_l2_final, dim3(1), dim3(256), 0, s, nparts, part, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_lbm_step(int nx, int ny, int precision, double tau, double rho0,
+                           const void *g, void *go, hipStream_t s) {
+    const int64_t nblocks = (int64_t)ny * ((nx + 255) / 256);
+    if (precision == MLBM_FP64)
+        hipLaunchKernelGGL(k_lbm_step<double>, dim3(xcd_grid(nblocks)), dim3(256), 0, s, nx, ny,
+                           nblocks, (const double *)g, (double *)go, 1.0 / tau, rho0);
+    else
+        hipLaunchKernelGGL(k_lbm_step<float>, dim3(xcd_grid(nblocks)), dim3(256), 0, s, nx, ny,
+                           nblocks, (const float *)g, (float *)go, 1.0 / tau, rho0);
+    return hipGetLastError();
+}
+
+hipError_t launch_lbm_init(int n, int precision, double rho0, const double *rho, const double *ux,
+                           const double *uy, void *g, hipStream_t s) {
+    if (precision == MLBM_FP64)
+        hipLaunchKernelGGL(k_init<double>, dim3(blocks_for(n, 256)), dim3(256), 0, s, n,
+                           (const int32_t *)nullptr, rho, ux, uy, (const uint8_t *)nullptr,
+                           (const double *)nullptr, rho0, rho0, 0, 0, 0, (double *)g);
+    else
+        hipLaunchKernelGGL(k_init<float>, dim3(blocks_for(n, 256)), dim3(256), 0, s, n,
+                           (const int32_t *)nullptr, rho, ux, uy, (const uint8_t *)nullptr,
+                           (const double *)nullptr, rho0, rho0, 0, 1, 0, (float *)g);
+    return hipGetLastError();
+}
+
+hipError_t launch_lbm_moments(int n, int precision, double rho0, const void *g, double *rho,
+                              double *ux, double *uy, hipStream_t s) {
+    if (precision == MLBM_FP64)
+        hipLaunchKernelGGL(k_moments<double>, dim3(blocks_for(n, 256)), dim3(256), 0, s, n,
+                           (const int32_t *)nullptr, (const double *)g, (const float *)nullptr,
+                           (const double *)nullptr, (const uint8_t *)nullptr, rho0, 0, rho, ux,
+                           uy);
+    else
+        hipLaunchKernelGGL(k_moments<float>, dim3(blocks_for(n, 256)), dim3(256), 0, s, n,
+                           (const int32_t *)nullptr, (const float *)g, (const float *)nullptr,
+                           (const double *)nullptr, (const uint8_t *)nullptr, rho0, 1, rho, ux,
+                           uy);
     return hipGetLastError();
 }
 
