@@ -216,6 +216,15 @@ mlbm_status mlbm_moments(const mlbm_plan *plan, const void *g, double *rho, doub
 mlbm_status mlbm_l2_sums(const mlbm_plan *plan, const void *g, const double *ux_t,
                          const double *uy_t, double *out, hipStream_t stream);
 
+/* Interpolation alone (Sec. 4, Fig. interp_test): the plan's streaming
+ * operator applied to a scalar field, in FP64 with the FP64 shape vectors:
+ * out[k-1][i] = sum_j w_{i,k,j} field[stencil member j of the stencil that
+ * serves departure point x_i - e_k dx], k = 1..8. field: device FP64
+ * [n_total], user order; out: device FP64 [8][n_total], user order (clouds of
+ * a multi-cloud plan at their offsets). */
+mlbm_status mlbm_interpolate(const mlbm_plan *plan, const double *field, double *out,
+                             hipStream_t stream);
+
 /* Steady-state residual (Sec. 3, annular channel: runs stop when the relative
  * change of the velocity field falls below a threshold): with U = |u| of
  * state g at every node and speed (device FP64 [n_total], user order) holding

@@ -66,6 +66,7 @@ SIGNATURES = {
     "mlbm_moments": (_c_i32, [_c_p, _c_p, _c_p, _c_p, _c_p, _c_p]),
     "mlbm_l2_sums": (_c_i32, [_c_p, _c_p, _c_p, _c_p, _c_p, _c_p]),
     "mlbm_residual": (_c_i32, [_c_p, _c_p, _c_p, _c_p, _c_p]),
+    "mlbm_interpolate": (_c_i32, [_c_p, _c_p, _c_p, _c_p]),
     "mlbm_lbm_init": (_c_i32, [_c_i32, _c_i32, _c_i32, _c_d, _c_p, _c_p, _c_p, _c_p, _c_p]),
     "mlbm_lbm_step": (_c_i32, [_c_i32, _c_i32, _c_i32, _c_d, _c_d, _c_p, _c_p, _c_i32, _c_p,
                                _c_p]),

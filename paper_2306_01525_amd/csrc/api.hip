@@ -788,6 +788,14 @@ mlbm_status mlbm_moments(const mlbm_plan *plan, const void *g, double *rho, doub
     return MLBM_OK;
 }
 
+mlbm_status mlbm_interpolate(const mlbm_plan *plan, const double *field, double *out,
+                             hipStream_t s) {
+    if (!single(plan) || !field || !out) return fail(MLBM_EINVAL, "null argument");
+    for (const CloudPlan &cp : plan->c)
+        MLBM_HIP(launch_interpolate(cp, node_at(field, cp), plan->n_total, out_at(out, cp), s));
+    return MLBM_OK;
+}
+
 mlbm_status mlbm_l2_sums(const mlbm_plan *plan, const void *g, const double *ux_t,
                          const double *uy_t, double *out, hipStream_t s) {
     if (!single(plan) || !g || !ux_t || !uy_t || !out) return fail(MLBM_EINVAL, "null argument");

@@ -225,6 +225,9 @@ hipError_t launch_l2(const CloudPlan &cp, int precision, const void *g, const do
 // speed: device FP64 [n] user order, in/out; out[0..3] as launch_l2
 hipError_t launch_residual(const CloudPlan &cp, int precision, const void *g, double *speed,
                            double *out, double *part, hipStream_t s);
+// field: device FP64 [n] of this cloud (user order); out[k-1][u] at out + (k-1)*out_stride
+hipError_t launch_interpolate(const CloudPlan &cp, const double *field, int64_t out_stride,
+                              double *out, hipStream_t s);
 // standard lattice Boltzmann on a periodic nx x ny lattice, state [9][ny][nx]
 hipError_t launch_lbm_step(int nx, int ny, int precision, double tau, double rho0,
                            const void *g, void *go, hipStream_t s);

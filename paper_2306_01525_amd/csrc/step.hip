@@ -709,7 +709,37 @@ __global__ __launch_bounds__(256) void k_lbm_step(int nx, int ny, int64_t nblock
                                              nullptr);
 }
 
+// Interpolation alone (Sec. 4, Fig. interp_test): the streaming operator of
+// the plan applied to a scalar field, in FP64 with the FP64 shape vectors.
+// out[k-1][u] = sum_j W_k[j](p) field[user(nbr[j][owner_k(p)])], u = user(p).
+__global__ __launch_bounds__(256) void k_interpolate(int n, int K, int mode,
+                                                     const double *__restrict__ W64,
+                                                     const int32_t *__restrict__ nbr,
+                                                     const int32_t *__restrict__ owner,
+                                                     const int32_t *__restrict__ perm,
+                                                     const double *__restrict__ field,
+                                                     int64_t out_stride, double *__restrict__ out) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= n) return;
+    const int u = perm[p];
+    for (int k = 1; k < kQ; ++k) {
+        const int s = mode == MLBM_STENCIL_OWN ? p : owner[(int64_t)(k - 1) * n + p];
+        double acc = 0.0;
+        for (int j = 0; j < K; ++j)
+            acc += W64[((int64_t)(k - 1) * K + j) * n + p] * field[perm[nbr[(int64_t)j * n + s]]];
+        out[(int64_t)(k - 1) * out_stride + u] = acc;
+    }
+}
+
 }  // namespace
+
+hipError_t launch_interpolate(const CloudPlan &cp, const double *field, int64_t out_stride,
+                              double *out, hipStream_t s) {
+    hipLaunchKernelGGL(k_interpolate, dim3(blocks_for(cp.n, 256)), dim3(256), 0, s, cp.n, cp.K,
+                       cp.prm.stencil_mode, cp.W64, cp.nbr, cp.owner, cp.perm, field, out_stride,
+                       out);
+    return hipGetLastError();
+}
 
 Step32Args step32_args(const CloudPlan &cp, void *frec) {
     Step32Args a{};

@@ -278,6 +278,15 @@ class Plan:
                                        _stream(stream)))
         return out
 
+    def interpolate(self, field, stream=None):
+        """The streaming operator applied to a scalar field (user order):
+        returns FP64 [8][n], row k-1 = the field interpolated at x_i - e_k dx."""
+        field = _f64(field, self.device)
+        out = torch.empty((8, self.n), dtype=torch.float64, device=self.device)
+        _order(stream, field, out)
+        check(_lib.load().mlbm_interpolate(self._h, _ptr(field), _ptr(out), _stream(stream)))
+        return out
+
     def residual(self, g, speed, stream=None):
         """Relative change of the speed field since the check that filled
         `speed` (device FP64 [n], overwritten with the current speed)."""

@@ -1,0 +1,142 @@
+"""The paper's convergence studies, run on the GPU.
+
+* `tgv_error_map`: the Taylor-Green study of Sec. 3 (Fig. h_dx_explained and
+  Fig. tgv_conv_P): the L2 error of the u-component at t_end over a grid of
+  streaming distances dx_ML and node spacings h, for P2 and P4 augmentation.
+* `lbm_errors`: the standard LBM on the same flow at dx = h (the black curve
+  of Fig. tgv_conv_P).
+* `interpolation_convergence`: interpolation alone (Sec. 4, Fig.
+  interp_test), one build and one application of the streaming operator per
+  cloud.
+
+Flow and scaling follow Sec. 3: the unit periodic square, u = U0 cos 2 pi x
+sin 2 pi y, v = -U0 sin 2 pi x cos 2 pi y decaying as exp(-2 nu k^2 t) with
+k = 2 pi, U0 = 1, nu = 1, tau = 0.8, dt = 1e-3 at dx = 1/10 and dt
+proportional to dx^2 (diffusive scaling), t_end = ln 10 / (2 nu k^2), and the
+number of steps is round(t_end / dt). The paper's Poisson-disk clouds are
+replaced by lattices of side 1/h jittered by U[-0.3 h, 0.3 h] (seeded).
+
+Run as `python -m paper_2306_01525_amd.studies` for the full maps (JSON on
+stdout).
+"""
+from __future__ import annotations
+
+import json
+import math
+
+import numpy as np
+
+TWO_PI = 2.0 * math.pi
+NU, U0, TAU = 1.0, 1.0, 0.8
+T_END = math.log(10.0) / (2.0 * NU * TWO_PI ** 2)
+
+
+def _dt(dx: float) -> float:
+    """Diffusive scaling from dt = 1e-3 at dx = 1/10."""
+    return 1e-3 * (dx / 0.1) ** 2
+
+
+def _tgv_lattice_units(x, y, dx: float):
+    """Initial velocity in lattice units (U0 dt / dx)."""
+    s = U0 * _dt(dx) / dx
+    return (s * np.cos(TWO_PI * x) * np.sin(TWO_PI * y),
+            -s * np.sin(TWO_PI * x) * np.cos(TWO_PI * y))
+
+
+def _steps(dx: float) -> int:
+    return int(round(T_END / _dt(dx)))
+
+
+def _decay(steps: int, dx: float) -> float:
+    return math.exp(-2.0 * NU * TWO_PI ** 2 * steps * _dt(dx))
+
+
+def tgv_error_map(dx_ml=(1 / 10, 1 / 40, 1 / 160),
+                  hs=(1 / 10, 1 / 20, 1 / 40, 1 / 80, 1 / 160, 1 / 320),
+                  degrees=(2, 4), K: int = 25, precision: int = 1, seed: int = 5,
+                  stencil_mode: int = 0, device="cuda"):
+    """One record per (dx_ML, h, degree): nodes, steps and the L2 error of the
+    u-component at t_end (NaN when the run diverged)."""
+    from .mlbm import Params, Plan
+    from synth import jittered_lattice
+    out = []
+    for h in hs:
+        n_side = int(round(1.0 / h))
+        c = jittered_lattice(n_side, length=1.0, seed=seed + n_side)
+        for dx in dx_ml:
+            steps = _steps(dx)
+            ux, uy = _tgv_lattice_units(c.x, c.y, dx)
+            a = _decay(steps, dx)
+            for m in degrees:
+                p = Params(dx=dx, K=K, degree=m, tau=TAU, stencil_mode=stencil_mode,
+                           precision=precision)
+                plan = Plan.build(c.x, c.y, c.period, p, device=device)
+                g = plan.step(plan.init(ux, uy), plan.new_state(), steps)
+                l2 = plan.l2(g, a * ux, a * uy)[0]
+                plan.close()
+                out.append({"dx_ml": dx, "h": h, "degree": m, "nodes": c.n, "steps": steps,
+                            "l2_u": l2 if math.isfinite(l2) else float("nan")})
+    return out
+
+
+def lbm_errors(dxs=(1 / 10, 1 / 20, 1 / 40, 1 / 80, 1 / 160), precision: int = 1,
+               device="cuda"):
+    """The standard LBM on the regular lattice of spacing dx, same flow."""
+    from .lbm import Lattice
+    out = []
+    for dx in dxs:
+        n = int(round(1.0 / dx))
+        ix, iy = np.meshgrid(np.arange(n), np.arange(n))
+        x, y = ix.ravel() * dx, iy.ravel() * dx
+        steps = _steps(dx)
+        ux, uy = _tgv_lattice_units(x, y, dx)
+        lat = Lattice(n, n, TAU, precision, device=device)
+        g = lat.step(lat.init(ux, uy), lat.new_state(), steps)
+        _, u, _ = lat.moments(g)
+        u = u.cpu().numpy()
+        t = _decay(steps, dx) * ux
+        out.append({"dx": dx, "nodes": n * n, "steps": steps,
+                    "l2_u": float(np.linalg.norm(u - t) / np.linalg.norm(t))})
+    return out
+
+
+def interpolation_convergence(n_sides=(20, 40, 80, 160), degrees=(2, 4), K: int = 25,
+                              dx: float = 0.1, seed: int = 11, stencil_mode: int = 0,
+                              device="cuda"):
+    """f = 0.01 sin 2 pi x cos 2 pi y on the unit periodic square, interpolated
+    at every departure point x_i - e_k dx (k = 1..8); L2 error over all of them
+    per cloud, and the least-squares slope of log L2 against log h."""
+    from .mlbm import Params, Plan
+    from synth import jittered_lattice
+    ex = np.array([0, 1, 0, -1, 0, 1, -1, -1, 1], dtype=float)
+    ey = np.array([0, 0, 1, 0, -1, 1, 1, -1, -1], dtype=float)
+    records, slopes = [], {}
+    for m in degrees:
+        hs, errs = [], []
+        for n in n_sides:
+            c = jittered_lattice(n, length=1.0, seed=seed + n)
+            p = Params(dx=dx, K=K, degree=m, tau=TAU, stencil_mode=stencil_mode, precision=1)
+            plan = Plan.build(c.x, c.y, c.period, p, device=device)
+            f = 0.01 * np.sin(TWO_PI * c.x) * np.cos(TWO_PI * c.y)
+            got = plan.interpolate(f).cpu().numpy()
+            plan.close()
+            px = c.x[None, :] - ex[1:, None] * dx
+            py = c.y[None, :] - ey[1:, None] * dx
+            exact = 0.01 * np.sin(TWO_PI * px) * np.cos(TWO_PI * py)
+            e = float(np.linalg.norm(got - exact) / np.linalg.norm(exact))
+            records.append({"degree": m, "n_side": n, "h": 1.0 / n, "l2": e})
+            hs.append(1.0 / n)
+            errs.append(e)
+        slopes[m] = float(np.polyfit(np.log(hs), np.log(errs), 1)[0])
+    return records, slopes
+
+
+def main():
+    res = {"tgv_error_map": tgv_error_map(), "lbm": lbm_errors()}
+    rec, slopes = interpolation_convergence()
+    res["interpolation"] = {"records": rec, "slopes": {str(k): v for k, v in slopes.items()}}
+    print(json.dumps(res))
+
+
+if __name__ == "__main__":
+    main()
