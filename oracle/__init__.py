@@ -65,6 +65,8 @@ _SIGS = {
     "orc_walls": (None, [_I, _P, _D, _P]),
     "orc_azimuthal_force": (None, [_I, _P, _P, _D, _P, _P, _P]),
     "orc_run": (None, [_I, _I, _P, _P, _P, _D, _P, _P, _P, _D, _I, _P]),
+    "orc_run_links": (None, [_I, _I, _P, _P, _P, _D, _P, _P, _P, _I, _P]),
+    "orc_bounce": (None, [_I, _P, _P]),
     "orc_lbm_run": (None, [_I, _I, _D, _I, _P]),
     "orc_loss_cs": (None, [_I, _I, _P, _P, _P, _D, _D, _I, _D, _P, _P, _P, _P, _P, _P,
                            _P, _P]),
@@ -268,12 +270,37 @@ def azimuthal_force(x, y, g, node_type=None):
     return ax, ay
 
 
-def run(f, nbr, own, W, tau, steps, ax=None, ay=None, node_type=None, rho_w=1.0):
-    """Advance f ([n][9], copied) by `steps` MLBM timesteps."""
+def bounce_links(nx, ny, node_type):
+    """Populations that enter the fluid from outside at wall nodes: bit k-1 of
+    the result is set where node_type != 0 and e_k . n < 0, n = the outward
+    normal of the fluid domain (Sec. 3, bounce-back walls)."""
+    ex, ey, _, _ = tables()
+    nx, ny = _f64(nx), _f64(ny)
+    nt = np.asarray(node_type)
+    bits = (ex[None, 1:] * nx[:, None] + ey[None, 1:] * ny[:, None] < 0.0) & (nt[:, None] != 0)
+    return (bits.astype(np.int64) << np.arange(8)).sum(axis=1).astype(np.uint8)
+
+
+def bounce(f, links):
+    f = _f64(f).copy()
+    lk = np.ascontiguousarray(links, dtype=np.uint8)
+    lib().orc_bounce(f.shape[0], _p(lk), _p(f))
+    return f
+
+
+def run(f, nbr, own, W, tau, steps, ax=None, ay=None, node_type=None, rho_w=1.0, links=None):
+    """Advance f ([n][9], copied) by `steps` MLBM timesteps. With `links`
+    (from bounce_links) the walls are the bounce-back rule and the force acts
+    at every node; otherwise wall nodes (node_type) hold feq(rho_w, 0)."""
     f = _f64(f).copy()
     nbr, own, W = _i32(nbr), _i32(own), _f64(W)
     ax = None if ax is None else _f64(ax)
     ay = None if ay is None else _f64(ay)
+    if links is not None:
+        lk = np.ascontiguousarray(links, dtype=np.uint8)
+        lib().orc_run_links(f.shape[0], nbr.shape[1], _p(nbr), _p(own), _p(W), float(tau),
+                            _p(ax), _p(ay), _p(lk), int(steps), _p(f))
+        return f
     nt = None if node_type is None else np.ascontiguousarray(node_type, dtype=np.uint8)
     lib().orc_run(f.shape[0], nbr.shape[1], _p(nbr), _p(own), _p(W), float(tau), _p(ax),
                   _p(ay), _p(nt), float(rho_w), int(steps), _p(f))

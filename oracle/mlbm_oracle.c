@@ -363,6 +363,24 @@ void orc_run(int n, int K, const int *nbr, const int *owner, const double *W, do
     free(tmp);
 }
 
+/* Bounce-back walls (Sec. 3, annular channel): per step COLLIDE with the
+ * body force at every node, STREAM, then the reflection of the flagged
+ * populations at wall nodes (links: [n], bit k-1 = direction k enters from
+ * outside). f: [n][9], updated in place. */
+void orc_run_links(int n, int K, const int *nbr, const int *owner, const double *W, double tau,
+                   const double *ax, const double *ay, const unsigned char *links, int steps,
+                   double *f) {
+    double *tmp = malloc(sizeof(double) * (size_t)n * Q);
+    for (int t = 0; t < steps; ++t) {
+        collide_all_r(n, f, tau, ax, ay, NULL, tmp);
+        stream_all_r(n, K, nbr, owner, W, tmp, f);
+        bounce_r(n, links, f);
+    }
+    free(tmp);
+}
+
+void orc_bounce(int n, const unsigned char *links, double *f) { bounce_r(n, links, f); }
+
 /* Standard LBM on a periodic nx x ny lattice (node index iy*nx + ix): BGK
  * collision then index-shift streaming f_k(x) = f_k^post(x - e_k)
  * (eq. LBM_streaming). f: [nx*ny][9], updated in place. */
