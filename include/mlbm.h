@@ -63,6 +63,10 @@ typedef struct {
     const uint8_t *node_type;   /* device, [n]: 0 fluid, 1 wall; NULL = all fluid */
     double period_x, period_y;  /* > 0: periodic with that period, coordinates in
                                    [0, period); 0: open along that axis          */
+    const double *normal_x, *normal_y;   /* device, [n], user order: the outward
+                                   normal of the fluid domain at wall nodes (read
+                                   there only); needed by bounce-back walls,
+                                   otherwise may be NULL                          */
 } mlbm_cloud;
 
 /* Simulation parameters of one cloud (Algorithm 1: "simulation parameters"). */
@@ -84,7 +88,13 @@ typedef struct {
                                origin (Sec. 3), magnitude force_mag (lattice units) */
     double force_mag;
     int32_t wall_kind;      /* 0 none; 1 wall nodes (node_type 1) hold the rest
-                               equilibrium feq(rho_wall, 0) after every stream     */
+                               equilibrium feq(rho_wall, 0) after every stream and
+                               receive no force; 2 bounce-back (Sec. 3): at wall
+                               nodes each population entering from outside
+                               (e_k . n < 0) takes the streamed value of the
+                               opposite direction; wall nodes collide and are
+                               forced like the others. 2 needs the normals and is
+                               not available through mlbm_import_weights       */
     double rho_wall;
     int32_t with_adjoint;   /* 1: also build the transposed streaming operator
                                used by mlbm_step_adjoint (8K entries per node)     */

@@ -28,7 +28,7 @@ _c_sz = ctypes.c_size_t
 
 class Cloud(ctypes.Structure):
     _fields_ = [("n", _c_i32), ("x", _c_p), ("y", _c_p), ("node_type", _c_p),
-                ("period_x", _c_d), ("period_y", _c_d)]
+                ("period_x", _c_d), ("period_y", _c_d), ("normal_x", _c_p), ("normal_y", _c_p)]
 
 
 class Params(ctypes.Structure):

@@ -70,7 +70,9 @@ mlbm_status check_params(const mlbm_cloud &c, const mlbm_params &p, bool device_
     if (p.stencil_mode != MLBM_STENCIL_PAPER && p.stencil_mode != MLBM_STENCIL_OWN)
         return fail(MLBM_EINVAL, "unknown stencil mode");
     if (p.force_kind != 0 && p.force_kind != 1) return fail(MLBM_EINVAL, "unknown force kind");
-    if (p.wall_kind != 0 && p.wall_kind != 1) return fail(MLBM_EINVAL, "unknown wall kind");
+    if (p.wall_kind < 0 || p.wall_kind > 2) return fail(MLBM_EINVAL, "unknown wall kind");
+    if (p.wall_kind == 2 && (!c.node_type || !c.normal_x || !c.normal_y))
+        return fail(MLBM_EINVAL, "bounce-back walls need node types and wall normals");
     if (!(p.rho0 > 0.0)) return fail(MLBM_EINVAL, "rho0 must be positive");
     if (p.wall_kind == 1 && !(p.rho_wall > 0.0)) return fail(MLBM_EINVAL, "rho_wall must be positive");
     if (p.with_adjoint && (p.force_kind != 0 || p.wall_kind != 0))
@@ -109,6 +111,7 @@ void layout_cloud(const mlbm_cloud &c, const mlbm_params &p, int precision, Carv
     cp.perm = pl.take<int32_t>(n);
     cp.iperm = pl.take<int32_t>(n);
     cp.ntype = pl.take<uint8_t>(n);
+    cp.links = p.wall_kind == 2 ? pl.take<uint8_t>(n) : nullptr;
     cp.nbr = pl.take<int32_t>((size_t)K * n);
     cp.owner = p.stencil_mode == MLBM_STENCIL_PAPER ? pl.take<int32_t>((size_t)8 * n) : nullptr;
     cp.W64 = pl.take<double>((size_t)8 * K * n);
@@ -336,8 +339,11 @@ mlbm_status build_cloud(mlbm_plan *plan, CloudPlan &cp, const mlbm_cloud &c,
     MLBM_HIP(launch_rbf(cp.geo, cp.xs, cp.ys, cp.perm, cp.nbr, cp.owner, n, p.K, p.degree, p.dx,
                         p.stencil_mode, bw.rbf_tmp, bw.rbf_bytes, cp.W64, plan->dev_err, s));
     if (cp.W32) MLBM_HIP(launch_pack_w32(cp.W64, n, p.K, cp.W32, s));
-    MLBM_HIP(launch_force(cp.xs, cp.ys, cp.ntype, n, p.force_kind, p.force_mag, cp.force32,
-                          cp.force64, s));
+    // equilibrium wall nodes receive no force; with bounce-back every node does
+    MLBM_HIP(launch_force(cp.xs, cp.ys, p.wall_kind == 1 ? cp.ntype : nullptr, n, p.force_kind,
+                          p.force_mag, cp.force32, cp.force64, s));
+    if (cp.links)
+        MLBM_HIP(launch_links(cp.ntype, cp.perm, c.normal_x, c.normal_y, n, cp.links, s));
     if (p.with_adjoint) MLBM_HIP(launch_transpose(cp, p.precision, bw.tr_tmp, bw.tr_bytes, s));
     mlbm_status st = build_adj_tiles(plan, cp, s);
     if (st != MLBM_OK) return st;

@@ -626,7 +626,32 @@ __global__ void k_force(const double *__restrict__ xs, const double *__restrict_
     }
 }
 
+// Bounce-back link masks (Sec. 3): at wall node p (internal order), bit k-1
+// is set when e_k . n < 0 for the outward normal n of the fluid domain, i.e.
+// population k enters the fluid from outside the wall.
+__global__ void k_links(const uint8_t *__restrict__ ntype, const int32_t *__restrict__ perm,
+                        const double *__restrict__ nx, const double *__restrict__ ny, int n,
+                        uint8_t *__restrict__ links) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= n) return;
+    unsigned m = 0;
+    if (ntype[p]) {
+        const int u = perm[p];
+        const double a = nx[u], b = ny[u];
+        for (int k = 1; k < kQ; ++k)
+            if (lat_ex(k) * a + lat_ey(k) * b < 0.0) m |= 1u << (k - 1);
+    }
+    links[p] = (uint8_t)m;
+}
+
 }  // namespace
+
+hipError_t launch_links(const uint8_t *ntype, const int32_t *perm, const double *nx,
+                        const double *ny, int n, uint8_t *links, hipStream_t s) {
+    hipLaunchKernelGGL(k_links, dim3(blocks_for(n, 256)), dim3(256), 0, s, ntype, perm, nx, ny,
+                       n, links);
+    return hipGetLastError();
+}
 
 hipError_t launch_geo_periodic(Geo *geo, double Lx, double Ly, int gx, int gy, int hb,
                                hipStream_t s) {

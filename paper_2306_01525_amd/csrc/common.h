@@ -26,6 +26,13 @@ __host__ __device__ constexpr int lat_ey(int k) {
 __host__ __device__ constexpr double lat_w(int k) {
     return k == 0 ? 4.0 / 9.0 : (k <= 4 ? 1.0 / 9.0 : 1.0 / 36.0);
 }
+// opposite direction: 1<->3, 2<->4, 5<->7, 6<->8
+__host__ __device__ constexpr int lat_opp(int k) {
+    return k == 0 ? 0 : (k <= 4 ? ((k + 1) & 3) + 1 : ((k - 3) & 3) + 5);
+}
+static_assert(lat_opp(1) == 3 && lat_opp(2) == 4 && lat_opp(3) == 1 && lat_opp(4) == 2 &&
+              lat_opp(5) == 7 && lat_opp(6) == 8 && lat_opp(7) == 5 && lat_opp(8) == 6,
+              "opposite directions");
 
 constexpr int kQ = 9;
 constexpr int kMaxK = 48;       // largest stencil supported
@@ -52,7 +59,8 @@ struct CloudPlan {
     mlbm_params prm{};
     int K = 0, m = 0, M = 0;
     double Lx = 0, Ly = 0;
-    bool has_walls = false;
+    bool has_walls = false;      // equilibrium wall nodes (wall_kind 1)
+    uint8_t *links = nullptr;    // [n] bounce-back link masks (wall_kind 2)
     bool imported = false;
     Geo *geo = nullptr;       // device
     double *xs = nullptr, *ys = nullptr;     // [n]
@@ -194,6 +202,10 @@ hipError_t launch_rbf(const Geo *geo, const double *xs, const double *ys,
 hipError_t launch_pack_w32(const double *W64, int n, int K, float *W32, hipStream_t s);
 hipError_t launch_force(const double *xs, const double *ys, const uint8_t *ntype, int n,
                         int kind, double mag, float *f32, double *f64, hipStream_t s);
+// bounce-back links of wall nodes: links[p] bit k-1 set where ntype[p] and
+// e_k . n(user(p)) < 0
+hipError_t launch_links(const uint8_t *ntype, const int32_t *perm, const double *nx,
+                        const double *ny, int n, uint8_t *links, hipStream_t s);
 hipError_t launch_fill_i32(int32_t *p, int32_t v, int64_t n, hipStream_t s);
 
 // ---- tile tables (tiles.hip) ----

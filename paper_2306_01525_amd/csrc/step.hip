@@ -46,15 +46,32 @@ inline unsigned xcd_grid(int64_t nblocks) { return (unsigned)(((nblocks + 7) / 8
 // FP32, deviation-stored populations
 // ------------------------------------------------------------------------
 
+// Bounce-back wall rule (Sec. 3): each population flagged in the node's link
+// mask (bit k-1: it enters the fluid from outside the wall) takes the
+// streamed value of the opposite direction. Flagged directions point into the
+// fluid, so their opposites are never flagged.
+template <class T>
+__device__ __forceinline__ void bounce_back(unsigned links, T (&f)[kQ]) {
+    if (!links) return;
+    T g[kQ];
+#pragma unroll
+    for (int k = 0; k < kQ; ++k) g[k] = f[k];
+#pragma unroll
+    for (int k = 1; k < kQ; ++k)
+        if ((links >> (k - 1)) & 1u) f[k] = g[lat_opp(k)];
+}
+
 // Moments, wall rule, BGK collision with force, and the stores of one node.
-template <bool FORCE, bool WALL, bool REC>
+// WALL: 0 none; 1 equilibrium wall nodes (ntype = node types); 2 bounce-back
+// (ntype = the nodes' link masks).
+template <bool FORCE, int WALL, bool REC>
 __device__ __forceinline__ void collide_store32(int n, int p, float (&f)[kQ],
                                                 float *__restrict__ go,
                                                 const float *__restrict__ force,
                                                 const uint8_t *__restrict__ ntype, float rtau,
                                                 float rho0, float rho_w,
                                                 float *__restrict__ frec) {
-    if (WALL && ntype[p]) {
+    if (WALL == 1 && ntype[p]) {
 #pragma unroll
         for (int k = 0; k < kQ; ++k) {
             const float v = wk32(k) * (rho_w - rho0);
@@ -63,6 +80,7 @@ __device__ __forceinline__ void collide_store32(int n, int p, float (&f)[kQ],
         }
         return;
     }
+    if (WALL == 2) bounce_back(ntype[p], f);
     float drho = 0.0f, jx = 0.0f, jy = 0.0f;
 #pragma unroll
     for (int k = 0; k < kQ; ++k) {
@@ -104,7 +122,7 @@ __device__ __forceinline__ float4 load_w(const float4 *p, bool nt) {
     return make_float4(v.x, v.y, v.z, v.w);
 }
 
-template <int MODE, bool FORCE, bool WALL, bool REC, int UNROLL, bool NT>
+template <int MODE, bool FORCE, int WALL, bool REC, int UNROLL, bool NT>
 __device__ __forceinline__ void step32_tile(const Step32Args &a, const float *__restrict__ g,
                                             float *__restrict__ go, int64_t tile,
                                             unsigned char *smem) {
@@ -201,7 +219,7 @@ __device__ __forceinline__ void step32_tile(const Step32Args &a, const float *__
                                       a.frec);
 }
 
-template <int MODE, bool FORCE, bool WALL, bool REC, int UNROLL, bool NT>
+template <int MODE, bool FORCE, int WALL, bool REC, int UNROLL, bool NT>
 __global__ __launch_bounds__(kTile) void k_step32(Step32Args a, const float *__restrict__ g,
                                                   float *__restrict__ go, int64_t nblocks) {
     extern __shared__ __align__(16) unsigned char smem[];
@@ -233,13 +251,13 @@ __global__ void k_set_desc(Step32Args *dst, Step32Args v) { *dst = v; }
 // ------------------------------------------------------------------------
 // FP64, plain populations
 // ------------------------------------------------------------------------
-template <bool FORCE, bool WALL, bool REC>
+template <bool FORCE, int WALL, bool REC>
 __device__ __forceinline__ void collide_store64(int n, int p, double (&f)[kQ],
                                                 double *__restrict__ go,
                                                 const double *__restrict__ force,
                                                 const uint8_t *__restrict__ ntype, double rtau,
                                                 double rho_w, double *__restrict__ frec) {
-    if (WALL && ntype[p]) {
+    if (WALL == 1 && ntype[p]) {
 #pragma unroll
         for (int k = 0; k < kQ; ++k) {
             const double v = lat_w(k) * rho_w;
@@ -248,6 +266,7 @@ __device__ __forceinline__ void collide_store64(int n, int p, double (&f)[kQ],
         }
         return;
     }
+    if (WALL == 2) bounce_back(ntype[p], f);
     double rho = 0.0, jx = 0.0, jy = 0.0;
 #pragma unroll
     for (int k = 0; k < kQ; ++k) {
@@ -276,7 +295,7 @@ __device__ __forceinline__ void collide_store64(int n, int p, double (&f)[kQ],
 // Same structure as the FP32 step, with the same tile tables: a tile stages
 // its halo four directions at a time (4 x |H_t| doubles take the LDS that 8 x
 // |H_t| floats take), so the directions are interpolated in two passes.
-template <int MODE, bool FORCE, bool WALL, bool REC>
+template <int MODE, bool FORCE, int WALL, bool REC>
 __global__ __launch_bounds__(kTile) void k_step64(
     int n, int K, int64_t nblocks, const double *__restrict__ g, double *__restrict__ go,
     const double *__restrict__ W, const int32_t *__restrict__ nbr,
@@ -589,7 +608,7 @@ __global__ void k_collide(int n, const T *__restrict__ f, T *__restrict__ g,
 // and non-temporal weight loads (the weights are streamed once per step and
 // need not displace the halo rows in L2). Variant v: unroll {1, 2, 3}[v / 2],
 // non-temporal v % 2. Tiles without tables unroll their row loop 3x that.
-template <int MODE, bool FORCE, bool WALL, bool REC, int UNROLL, bool NT>
+template <int MODE, bool FORCE, int WALL, bool REC, int UNROLL, bool NT>
 void launch32(const CloudPlan &cp, const void *gin, void *gout, void *frec, int64_t nblocks,
               hipStream_t s) {
     const Step32Args a = step32_args(cp, frec);
@@ -617,10 +636,10 @@ void launch32_batch_v(const mlbm_plan &plan, const void *gin, void *gout, hipStr
     }
 }
 
-template <int MODE, bool FORCE, bool WALL, bool REC>
+template <int MODE, bool FORCE, int WALL, bool REC>
 void launch32_tuned(const CloudPlan &cp, const void *gin, void *gout, void *frec,
                     int64_t nblocks, hipStream_t s) {
-    if (FORCE != WALL) {   // clouds with only one of force and walls: default variant
+    if (WALL == 2 || FORCE != (WALL == 1)) {   // other wall/force mixes: default variant
         launch32<MODE, FORCE, WALL, REC, 1, false>(cp, gin, gout, frec, nblocks, s);
         return;
     }
@@ -634,7 +653,7 @@ void launch32_tuned(const CloudPlan &cp, const void *gin, void *gout, void *frec
     }
 }
 
-template <int MODE, bool FORCE, bool WALL, bool REC>
+template <int MODE, bool FORCE, int WALL, bool REC>
 hipError_t step_variant(const CloudPlan &cp, int precision, const void *gin, void *gout,
                         void *frec, hipStream_t s) {
     const int n = cp.n;
@@ -642,7 +661,8 @@ hipError_t step_variant(const CloudPlan &cp, int precision, const void *gin, voi
     if (precision == MLBM_FP64) {
         hipLaunchKernelGGL((k_step64<MODE, FORCE, WALL, REC>), dim3(xcd_grid(nblocks)),
                            dim3(kTile), cp.lds_bytes, s, n, cp.K, nblocks, (const double *)gin,
-                           (double *)gout, cp.W64, cp.nbr, cp.owner, cp.force64, cp.ntype,
+                           (double *)gout, cp.W64, cp.nbr, cp.owner, cp.force64,
+                           cp.prm.wall_kind == 2 ? cp.links : cp.ntype,
                            1.0 / cp.prm.tau, cp.prm.rho_wall, (double *)frec,
                            cp.lds_bytes ? cp.tdesc : nullptr, cp.ownerL, cp.nbrL, cp.hlist,
                            cp.ocap, cp.hcap);
@@ -652,7 +672,7 @@ hipError_t step_variant(const CloudPlan &cp, int precision, const void *gin, voi
     return hipGetLastError();
 }
 
-template <int MODE, bool FORCE, bool WALL>
+template <int MODE, bool FORCE, int WALL>
 hipError_t step_rec(const CloudPlan &cp, int precision, const void *gin, void *gout,
                     void *frec, hipStream_t s) {
     return frec ? step_variant<MODE, FORCE, WALL, true>(cp, precision, gin, gout, frec, s)
@@ -662,8 +682,11 @@ hipError_t step_rec(const CloudPlan &cp, int precision, const void *gin, void *g
 template <int MODE, bool FORCE>
 hipError_t step_wall(const CloudPlan &cp, int precision, const void *gin, void *gout,
                      void *frec, hipStream_t s) {
-    return cp.has_walls ? step_rec<MODE, FORCE, true>(cp, precision, gin, gout, frec, s)
-                        : step_rec<MODE, FORCE, false>(cp, precision, gin, gout, frec, s);
+    switch (cp.prm.wall_kind) {
+        case 1: return step_rec<MODE, FORCE, 1>(cp, precision, gin, gout, frec, s);
+        case 2: return step_rec<MODE, FORCE, 2>(cp, precision, gin, gout, frec, s);
+        default: return step_rec<MODE, FORCE, 0>(cp, precision, gin, gout, frec, s);
+    }
 }
 
 template <int MODE>
@@ -741,6 +764,10 @@ hipError_t launch_interpolate(const CloudPlan &cp, const double *field, int64_t 
     return hipGetLastError();
 }
 
+// Nodes whose populations carry no body force (so the moments need no
+// correction there): the equilibrium wall nodes; with bounce-back, none.
+inline const uint8_t *fmask(const CloudPlan &cp) { return cp.has_walls ? cp.ntype : nullptr; }
+
 Step32Args step32_args(const CloudPlan &cp, void *frec) {
     Step32Args a{};
     a.n = cp.n;
@@ -751,7 +778,7 @@ Step32Args step32_args(const CloudPlan &cp, void *frec) {
     a.nbr = cp.nbr;
     a.owner = cp.owner;
     a.force = cp.force32;
-    a.ntype = cp.ntype;
+    a.ntype = cp.prm.wall_kind == 2 ? cp.links : cp.ntype;   // link masks for bounce-back
     a.rtau = (float)(1.0 / cp.prm.tau);
     a.rho0 = (float)cp.prm.rho0;
     a.rho_w = (float)cp.prm.rho_wall;
@@ -809,11 +836,11 @@ hipError_t launch_moments(const CloudPlan &cp, int precision, const void *g, dou
     const double *f64 = post_collision && precision == MLBM_FP64 ? cp.force64 : nullptr;
     if (precision == MLBM_FP64)
         hipLaunchKernelGGL(k_moments<double>, dim3(blocks_for(n, 256)), dim3(256), 0, s, n,
-                           cp.perm, (const double *)g, f32, f64, cp.ntype, cp.prm.rho0, 0, rho,
+                           cp.perm, (const double *)g, f32, f64, fmask(cp), cp.prm.rho0, 0, rho,
                            ux, uy);
     else
         hipLaunchKernelGGL(k_moments<float>, dim3(blocks_for(n, 256)), dim3(256), 0, s, n,
-                           cp.perm, (const float *)g, f32, f64, cp.ntype, cp.prm.rho0, 1, rho,
+                           cp.perm, (const float *)g, f32, f64, fmask(cp), cp.prm.rho0, 1, rho,
                            ux, uy);
     return hipGetLastError();
 }
@@ -826,10 +853,10 @@ hipError_t launch_l2(const CloudPlan &cp, int precision, const void *g, const do
     const double *f64 = precision == MLBM_FP64 ? cp.force64 : nullptr;
     if (precision == MLBM_FP64)
         hipLaunchKernelGGL(k_l2_partial<double>, dim3(nb), dim3(256), 0, s, n, cp.perm,
-                           (const double *)g, f32, f64, cp.ntype, cp.prm.rho0, 0, uxt, uyt, part);
+                           (const double *)g, f32, f64, fmask(cp), cp.prm.rho0, 0, uxt, uyt, part);
     else
         hipLaunchKernelGGL(k_l2_partial<float>, dim3(nb), dim3(256), 0, s, n, cp.perm,
-                           (const float *)g, f32, f64, cp.ntype, cp.prm.rho0, 1, uxt, uyt, part);
+                           (const float *)g, f32, f64, fmask(cp), cp.prm.rho0, 1, uxt, uyt, part);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_l2_final, dim3(1), dim3(256), 0, s, nb, (const double *)part, out);
@@ -844,10 +871,10 @@ hipError_t launch_residual(const CloudPlan &cp, int precision, const void *g, do
     const double *f64 = precision == MLBM_FP64 ? cp.force64 : nullptr;
     if (precision == MLBM_FP64)
         hipLaunchKernelGGL(k_residual_partial<double>, dim3(nb), dim3(256), 0, s, n, cp.perm,
-                           (const double *)g, f32, f64, cp.ntype, cp.prm.rho0, 0, speed, part);
+                           (const double *)g, f32, f64, fmask(cp), cp.prm.rho0, 0, speed, part);
     else
         hipLaunchKernelGGL(k_residual_partial<float>, dim3(nb), dim3(256), 0, s, n, cp.perm,
-                           (const float *)g, f32, f64, cp.ntype, cp.prm.rho0, 1, speed, part);
+                           (const float *)g, f32, f64, fmask(cp), cp.prm.rho0, 1, speed, part);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_l2_final, dim3(1), dim3(256), 0, s, nb, (const double *)part, out);

@@ -23,6 +23,10 @@ def _ptr(t):
     return None if t is None else ctypes.c_void_p(t.data_ptr())
 
 
+def _addr(t):
+    return None if t is None else t.data_ptr()
+
+
 def _stream(stream=None):
     s = torch.cuda.current_stream() if stream is None else stream
     return ctypes.c_void_p(s.cuda_stream)
@@ -90,17 +94,22 @@ class Plan:
     # ---- construction ----------------------------------------------------
     @classmethod
     def build(cls, x, y, period, params: Params, node_type=None, device="cuda",
-              stream=None):
+              stream=None, normals=None):
+        """normals: (nx, ny), the outward normal of the fluid domain at wall
+        nodes (user order); needed by bounce-back walls (wall_kind 2)."""
         L = _lib.load()
         x = _f64(x, device)
         y = _f64(y, device)
         nt = None
         if node_type is not None:
             nt = torch.as_tensor(node_type, dtype=torch.uint8, device=device).contiguous()
+        nx = ny = None
+        if normals is not None:
+            nx, ny = _f64(normals[0], device), _f64(normals[1], device)
         n = int(x.shape[0])
-        _order(stream, x, y, nt)
+        _order(stream, x, y, nt, nx, ny)
         cloud = _lib.Cloud(n, x.data_ptr(), y.data_ptr(), nt.data_ptr() if nt is not None else None,
-                           float(period[0]), float(period[1]))
+                           float(period[0]), float(period[1]), _addr(nx), _addr(ny))
         cp = params.to_c()
         pb, wb = ctypes.c_size_t(), ctypes.c_size_t()
         check(L.mlbm_weights_query(ctypes.byref(cloud), ctypes.byref(cp), 1, ctypes.byref(pb),
@@ -117,16 +126,20 @@ class Plan:
 
     @staticmethod
     def _clouds(clouds, device):
-        """clouds: list of (x, y, period, node_type or None)."""
+        """clouds: list of (x, y, period, node_type or None[, (nx, ny) normals])."""
         keep, cs = [], []
-        for x, y, period, nt in clouds:
+        for cl in clouds:
+            x, y, period, nt = cl[:4]
             xt, yt = _f64(x, device), _f64(y, device)
             ntt = None if nt is None else torch.as_tensor(nt, dtype=torch.uint8,
                                                           device=device).contiguous()
-            keep += [xt, yt, ntt]
+            nx = ny = None
+            if len(cl) > 4 and cl[4] is not None:
+                nx, ny = _f64(cl[4][0], device), _f64(cl[4][1], device)
+            keep += [xt, yt, ntt, nx, ny]
             cs.append(_lib.Cloud(int(xt.shape[0]), xt.data_ptr(), yt.data_ptr(),
                                  ntt.data_ptr() if ntt is not None else None,
-                                 float(period[0]), float(period[1])))
+                                 float(period[0]), float(period[1]), _addr(nx), _addr(ny)))
         return (_lib.Cloud * len(cs))(*cs), keep
 
     @classmethod
@@ -302,9 +315,9 @@ class Plan:
                       stream=None):
         """Step until the residual between checks `check_every` steps apart
         falls below `tol`, stops decreasing for `plateau` checks in a row
-        (FP32 can level off above tol), or `max_steps` is reached. Returns
-        (state, steps, residual, reason) with reason 'tol', 'plateau' or
-        'max_steps'."""
+        (FP32 can level off above tol; plateau=None never stops on this), or
+        `max_steps` is reached. Returns (state, steps, residual, reason) with
+        reason 'tol', 'plateau' or 'max_steps'."""
         other = self.new_state()
         speed = torch.zeros(self.n, dtype=torch.float64, device=self.device)
         _order(stream, speed)
@@ -322,7 +335,7 @@ class Plan:
                 best, stall = r, 0
             else:
                 stall += 1
-                if stall >= plateau:
+                if plateau is not None and stall >= plateau:
                     return g, steps, r, "plateau"
         return g, steps, r, "max_steps"
 

@@ -8,6 +8,8 @@
 * `interpolation_convergence`: interpolation alone (Sec. 4, Fig.
   interp_test), one build and one application of the streaming operator per
   cloud.
+* `annulus_convergence`: the annular channel of Sec. 3 (Fig. bch_conv) with
+  the paper's bounce-back walls and settings, run to the steady state.
 
 Flow and scaling follow Sec. 3: the unit periodic square, u = U0 cos 2 pi x
 sin 2 pi y, v = -U0 sin 2 pi x cos 2 pi y decaying as exp(-2 nu k^2 t) with
@@ -131,8 +133,56 @@ def interpolation_convergence(n_sides=(20, 40, 80, 160), degrees=(2, 4), K: int 
     return records, slopes
 
 
+def annulus_speed(r, dx: float, g: float, tau: float, r1: float = 1.0, r2: float = 2.0):
+    """|u_phi| of eq. bch_solution in lattice units (r in cloud units)."""
+    nu = (tau - 0.5) / 3.0
+    rl, a, b = r / dx, r1 / dx, r2 / dx
+    alpha = (a * a + a * b + b * b) / (a + b)
+    beta = (a * a * b * b) / (a + b)
+    return np.abs((g / (3.0 * nu)) * (rl * rl - alpha * rl + beta / rl))
+
+
+def annulus_convergence(hs=(1 / 10, 1 / 20, 1 / 40, 1 / 55, 1 / 80, 1 / 110), dx: float = 1 / 160,
+                        K: int = 15, degree: int = 2, tau: float = 1.0, g: float = 1e-6,
+                        tol: float = 1e-10, max_steps: int = 500_000, precision: int = 1,
+                        seed: int = 3, device="cuda"):
+    """The annular channel of Sec. 3 with the paper's settings: R1 = 1, R2 = 2,
+    azimuthal acceleration g (lattice units) at every node, bounce-back walls
+    on boundary nodes placed on the circles, dx_ML = 1/160, tau = 1, N_L = 15
+    with P2, from rest until the residual between checks 100 steps apart
+    falls below `tol` (or a plateau, or max_steps). One record per h: nodes,
+    steps, why the run stopped, the L2 error of the speed against eq.
+    bch_solution and the largest speed at a wall node."""
+    from .mlbm import Params, Plan
+    from synth.clouds import annulus_poisson
+    out = []
+    for h in hs:
+        c = annulus_poisson(1.0, 2.0, h, seed=seed)
+        r = np.hypot(c.x, c.y)
+        sgn = np.where(r < 1.5, -1.0, 1.0)          # outward normal of the fluid domain
+        p = Params(dx=dx, K=K, degree=degree, tau=tau, stencil_mode=0, precision=precision,
+                   force_kind=1, force_mag=g, wall_kind=2)
+        plan = Plan.build(c.x, c.y, c.period, p, node_type=c.node_type, device=device,
+                          normals=(sgn * c.x / r, sgn * c.y / r))
+        zeros = np.zeros(c.n)
+        # the start from rest rings with sound waves that make the residual
+        # wander for a while: FP64 runs stop on the threshold or the limit only
+        gs, steps, res, why = plan.run_to_steady(plan.init(zeros, zeros), tol=tol,
+                                                 check_every=100, max_steps=max_steps,
+                                                 plateau=None if precision == 1 else 50)
+        _, u, v = (a.cpu().numpy() for a in plan.moments(gs))
+        plan.close()
+        U = np.hypot(u, v)
+        exact = annulus_speed(r, dx, g, tau)
+        out.append({"h": h, "nodes": c.n, "steps": steps, "residual": res, "stop": why,
+                    "l2_speed": float(np.linalg.norm(U - exact) / np.linalg.norm(exact)),
+                    "wall_speed_max": float(U[c.node_type == 1].max() / exact.max())})
+    return out
+
+
 def main():
-    res = {"tgv_error_map": tgv_error_map(), "lbm": lbm_errors()}
+    res = {"tgv_error_map": tgv_error_map(), "lbm": lbm_errors(),
+           "annulus": annulus_convergence()}
     rec, slopes = interpolation_convergence()
     res["interpolation"] = {"records": rec, "slopes": {str(k): v for k, v in slopes.items()}}
     print(json.dumps(res))

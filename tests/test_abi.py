@@ -33,7 +33,7 @@ def _query(n=100, **kw):
              force_kind=0, force_mag=0.0, wall_kind=0, rho_wall=1.0, with_adjoint=0)
     p.update(kw)
     cp = _lib.Params(**p)
-    cl = _lib.Cloud(n, None, None, None, 1.0, 1.0)
+    cl = _lib.Cloud(n, None, None, None, 1.0, 1.0, None, None)
     pb, wb = ctypes.c_size_t(), ctypes.c_size_t()
     st = L.mlbm_weights_query(ctypes.byref(cl), ctypes.byref(cp), 1, ctypes.byref(pb),
                               ctypes.byref(wb))

@@ -4,6 +4,8 @@ paper stencils, the launch configuration the benchmark times): sampled
 outputs against the oracle computed one node at a time, and FP32 against FP64.
 At reduced size: the steady state against the oracle and against the
 analytic profile of eq. bch_solution, improving under refinement."""
+import math
+
 import numpy as np
 import pytest
 
@@ -224,3 +226,82 @@ def test_residual_and_run_to_steady(precision):
     d = rel_l2(np.stack([u, v]), np.stack([u2, v2]))
     say("against the 30-relaxation-time field: %.2e" % d)
     assert d < 1e-4
+
+
+def _normals(c):
+    r = np.hypot(c.x, c.y)
+    s = np.where(r < 0.5 * (R1 + R2), -1.0, 1.0)
+    return s * c.x / r, s * c.y / r
+
+
+@pytest.mark.parametrize("tau", [1.0, 0.8])
+def test_bounce_back_walls_match_oracle(tau):
+    """The paper's wall rule (bounce-back on boundary nodes, force at every
+    node): GPU against the oracle after 1, 50 and 400 steps, both precisions,
+    with the paper's N_L = 15 and P2 at dx = 1/40."""
+    from paper_2306_01525_amd import Params, Plan
+    c = annulus_poisson(R1, R2, 0.1, seed=3)
+    dx, K, m, g = 1.0 / 40, 15, 2, 1e-5
+    nx, ny = _normals(c)
+    links = oracle.bounce_links(nx, ny, c.node_type)
+    nbr, own, W = oracle.build_plan(c, dx, K, m, mode=0)
+    ax, ay = oracle.azimuthal_force(c.x, c.y, g, None)
+    ux, uy = _swirl(c, 1e-3)
+    f = oracle.equilibrium(np.ones(c.n), ux, uy)
+    ref, done = {}, 0
+    for s_ in (1, 50, 400):
+        f = oracle.run(f, nbr, own, W, tau, s_ - done, ax, ay, links=links)
+        done = s_
+        ref[s_] = oracle.moments(f)
+    for prec, tol in ((1, lambda s: 1e-11), (0, lambda s: 4 * tol_fp32(s))):
+        p = Params(dx=dx, K=K, degree=m, tau=tau, stencil_mode=0, precision=prec,
+                   force_kind=1, force_mag=g, wall_kind=2)
+        plan = Plan.build(c.x, c.y, c.period, p, node_type=c.node_type, normals=(nx, ny))
+        gst = plan.init(ux, uy)
+        other = plan.new_state()
+        done = 0
+        for s_ in (1, 50, 400):
+            res = plan.step(gst, other, s_ - done)
+            if res is other:
+                gst, other = other, gst
+            done = s_
+            r_g, u_g, v_g = (a.cpu().numpy() for a in plan.moments(gst))
+            r_o, u_o, v_o = ref[s_]
+            e = rel_l2(np.stack([u_g, v_g]), np.stack([u_o, v_o]))
+            er = float(np.abs(r_g - r_o).max())
+            say("tau %.1f precision %d step %d: rel L2 velocity %.2e, max |drho| %.2e"
+                % (tau, prec, s_, e, er))
+            assert e < tol(s_) and er < tol(s_)
+        assert plan.device_error() == 0
+        plan.close()
+
+
+def test_bounce_back_needs_normals():
+    from paper_2306_01525_amd import MLBMError, Params, Plan
+    c = annulus_poisson(R1, R2, 0.1, seed=3)
+    p = Params(dx=0.05, K=15, degree=2, tau=1.0, wall_kind=2)
+    with pytest.raises(MLBMError):
+        Plan.build(c.x, c.y, c.period, p, node_type=c.node_type)
+
+
+def test_annulus_study_with_the_papers_settings():
+    """Sec. 3, Fig. bch_conv: dx_ML = 1/160, tau = 1, N_L = 15 with P2,
+    bounce-back walls, from rest. The wall nodes stay at rest and the error of
+    the speed against eq. bch_solution falls with h (about second order from
+    h = 1/20 to 1/80 on these clouds). The runs end on the step limit: a slow
+    drift of the total mass (the interpolation does not conserve it) keeps the
+    residual near 1e-7 per 100 steps on the coarser clouds."""
+    from paper_2306_01525_amd.studies import annulus_convergence
+    res = annulus_convergence(hs=(1 / 20, 1 / 40, 1 / 80), max_steps=300_000)
+    for r in res:
+        say("h 1/%d n %d: %d steps (%s, residual %.1e), L2(speed) %.3e, wall speed %.1e"
+            % (round(1 / r["h"]), r["nodes"], r["steps"], r["stop"], r["residual"],
+               r["l2_speed"], r["wall_speed_max"]))
+        assert r["wall_speed_max"] < 1e-12
+        assert r["residual"] < 1e-6
+    e = [r["l2_speed"] for r in res]
+    order = math.log(e[0] / e[2]) / math.log(4.0)
+    say("order from h = 1/20 to 1/80: %.2f" % order)
+    assert e[0] > e[1] > e[2]
+    assert order > 1.5
+    assert e[2] < 5e-4
