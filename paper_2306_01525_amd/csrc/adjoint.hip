@@ -51,7 +51,7 @@ __global__ void k_tr_fill(int n, int K, int mode, const int32_t *__restrict__ nb
             col[pos] = i;
             T w;
             if (W64)
-                w = (T)W64[((int64_t)(k - 1) * K + j) * n + i];
+                w = (T)W64[w64_at(k, j, n, i)];
             else
                 w = (T)W32[(((int64_t)j * 2 + ((k - 1) >> 2)) * n + i) * 4 + ((k - 1) & 3)];
             val[pos] = w;

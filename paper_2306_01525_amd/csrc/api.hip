@@ -143,8 +143,8 @@ void layout_cloud(const mlbm_cloud &c, const mlbm_params &p, int precision, Carv
         cp.tdescT = pl.take<int32_t>((size_t)ntiles);
         cp.ilist = pl.take<int32_t>((size_t)ntiles * cp.hcap);
         cp.elocal = pl.take<uint32_t>((size_t)8 * ((cp.tr_lw + 2) / 3) * n);
-        // 8 values of lam per inverse-halo node plus the 2 KiB reduction buffer
-        cp.adj_cap = precision == MLBM_FP64 ? 960 : cp.hcap;
+        // 8 values of lam per inverse-halo node (64 KiB in FP64 at the cap)
+        cp.adj_cap = cp.hcap;
     }
     if (ws && bw) {
         choose_grid(n, c.period_x, c.period_y, bw->gx, bw->gy, bw->hb);
@@ -484,7 +484,7 @@ mlbm_status mlbm_import_weights(int32_t n, const double *x, const double *y,
     for (int i = 0; i < n; ++i)
         for (int k = 1; k < 9; ++k)
             for (int j = 0; j < K; ++j)
-                hw[((size_t)(k - 1) * K + j) * n + i] = W[((size_t)i * 9 + k) * K + j];
+                hw[w64_at(k, j, n, i)] = W[((size_t)i * 9 + k) * K + j];
     if (node_type)
         for (int i = 0; i < n; ++i) {
             nt[i] = node_type[i];
@@ -549,7 +549,7 @@ mlbm_status mlbm_import_weights(int32_t n, const double *x, const double *y,
                     int pos = cur[r]++;
                     col[pos] = i;
                     if (p.precision == MLBM_FP64)
-                        v64[pos] = hw[((size_t)(k - 1) * K + j) * n + i];
+                        v64[pos] = hw[w64_at(k, j, n, i)];
                     else
                         v32[pos] = w32[(((size_t)j * 2 + ((k - 1) >> 2)) * n + i) * 4 + ((k - 1) & 3)];
                 }
@@ -675,7 +675,7 @@ mlbm_status mlbm_plan_export(const mlbm_plan *plan, int32_t cloud, int32_t what,
         for (int j = 0; j < K; ++j) o[((size_t)u * 9) * K + j] = j == 0 ? 1.0 : 0.0;
         for (int k = 1; k < 9; ++k)
             for (int j = 0; j < K; ++j)
-                o[((size_t)u * 9 + k) * K + j] = w[((size_t)(k - 1) * K + j) * n + p];
+                o[((size_t)u * 9 + k) * K + j] = w[w64_at(k, j, n, p)];
     }
     return MLBM_OK;
 }

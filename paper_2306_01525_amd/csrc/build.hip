@@ -487,7 +487,7 @@ __global__ __launch_bounds__(256) void k_rbf(const Geo *__restrict__ geo,
                 if (c0 + t < count) {
                     int p, k;
                     rhs_point(L, s, c0 + t, p, k);
-                    W64[((int64_t)(k - 1) * K + pstep) * n + p] = b[t] / piv;
+                    W64[w64_at(k, pstep, n, p)] = b[t] / piv;
                 }
             }
         }
@@ -579,14 +579,13 @@ __global__ void k_pack_w32(const double *__restrict__ W64, int n, int K, float *
     int p = blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= n) return;
     for (int k = 1; k < kQ; ++k) {
-        const double *w = W64 + (int64_t)(k - 1) * K * n + p;
         double sum = 0.0;
-        for (int j = 0; j < K; ++j) sum += (double)(float)w[(int64_t)j * n];
+        for (int j = 0; j < K; ++j) sum += (double)(float)W64[w64_at(k, j, n, p)];
         const double defect = 1.0 - sum;
         int jstar = -1;
         double best = DBL_MAX;
         for (int j = 0; j < K; ++j) {
-            double a = fabs(w[(int64_t)j * n]);
+            double a = fabs(W64[w64_at(k, j, n, p)]);
             if (a >= 64.0 * fabs(defect) && a < best) {
                 best = a;
                 jstar = j;
@@ -594,7 +593,7 @@ __global__ void k_pack_w32(const double *__restrict__ W64, int n, int K, float *
         }
         const int h = (k - 1) >> 2, c = (k - 1) & 3;
         for (int j = 0; j < K; ++j) {
-            double v = w[(int64_t)j * n];
+            double v = W64[w64_at(k, j, n, p)];
             float f = (float)v;
             if (j == jstar) f = (float)((double)f + defect);
             W32[(((int64_t)j * 2 + h) * n + p) * 4 + c] = f;

@@ -35,6 +35,13 @@ static_assert(lat_opp(1) == 3 && lat_opp(2) == 4 && lat_opp(3) == 1 && lat_opp(4
               "opposite directions");
 
 constexpr int kQ = 9;
+
+// FP64 shape vectors, layout [K][4][n][2]: slot j of directions (1,2), (3,4),
+// (5,6), (7,8) of node p form one 16-byte pair, so a lane reads two directions
+// per load and a wavefront reads 1 KiB of consecutive memory.
+__host__ __device__ inline int64_t w64_at(int k, int j, int64_t n, int64_t p) {
+    return (((int64_t)j * 4 + ((k - 1) >> 1)) * n + p) * 2 + ((k - 1) & 1);
+}
 constexpr int kMaxK = 48;       // largest stencil supported
 constexpr int kTile = 256;      // nodes per workgroup in the step kernels
 constexpr int kStepVariants = 6; // FP32 step tuning variants
@@ -96,7 +103,7 @@ struct CloudPlan {
     int32_t *tdescT = nullptr;    // [ntiles] |I_t| (0: global gathers)
     int32_t *ilist = nullptr;     // [ntiles][hcap] arriving nodes, sorted
     uint32_t *elocal = nullptr;   // [8][ceil(lw/3)][n] row heads as 3 x 10-bit positions in I_t
-    int adj_cap = 0;              // largest |I_t| kept; the launch's LDS stays within 64 KiB
+    int adj_cap = 0;              // largest |I_t| kept (10-bit positions: at most 1024)
     int adj_ni = 0;               // largest |I_t| (LDS of the adjoint launch: 8 |I_t| values)
 };
 

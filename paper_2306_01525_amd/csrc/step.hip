@@ -294,7 +294,9 @@ __device__ __forceinline__ void collide_store64(int n, int p, double (&f)[kQ],
 
 // Same structure as the FP32 step, with the same tile tables: a tile stages
 // its halo four directions at a time (4 x |H_t| doubles take the LDS that 8 x
-// |H_t| floats take), so the directions are interpolated in two passes.
+// |H_t| floats take), so the directions are interpolated in two passes. (One
+// pass over 8 x |H_t| doubles fits the LDS too, but the larger footprint
+// lowers the workgroups per CU and measured slower.)
 template <int MODE, bool FORCE, int WALL, bool REC>
 __global__ __launch_bounds__(kTile) void k_step64(
     int n, int K, int64_t nblocks, const double *__restrict__ g, double *__restrict__ go,
@@ -315,6 +317,7 @@ __global__ __launch_bounds__(kTile) void k_step64(
     double acc[8];
 #pragma unroll
     for (int d = 0; d < 8; ++d) acc[d] = 0.0;
+    const double2 *W2 = reinterpret_cast<const double2 *>(W);   // [K][4][n] pairs
 
     if (nh > 0) {
         const int no = tdesc[2 * tile];
@@ -350,12 +353,14 @@ __global__ __launch_bounds__(kTile) void k_step64(
                     for (int sft = 0; sft < 3; ++sft) {
                         const int jj = 3 * w + sft;
                         if (jj < K) {
+                            // directions 4 pass + 1 .. 4 pass + 4 as two pairs
+                            const double2 wa = W2[((int64_t)jj * 4 + 2 * pass) * n + p];
+                            const double2 wb = W2[((int64_t)jj * 4 + 2 * pass + 1) * n + p];
+                            const double wt[4] = {wa.x, wa.y, wb.x, wb.y};
 #pragma unroll
-                            for (int dd = 0; dd < 4; ++dd) {
-                                const int d = 4 * pass + dd;
-                                const double wt = W[((int64_t)d * K + jj) * n + p];
-                                acc[d] += wt * gl[dd * nh + (int)((word[dd] >> (10 * sft)) & 1023u)];
-                            }
+                            for (int dd = 0; dd < 4; ++dd)
+                                acc[4 * pass + dd] +=
+                                    wt[dd] * gl[dd * nh + (int)((word[dd] >> (10 * sft)) & 1023u)];
                         }
                     }
                 }
@@ -372,7 +377,7 @@ __global__ __launch_bounds__(kTile) void k_step64(
             if (MODE == MLBM_STENCIL_OWN) qo = nbr[(int64_t)j * n + p];
 #pragma unroll
             for (int d = 0; d < 8; ++d) {
-                const double w = W[((int64_t)d * K + j) * n + p];
+                const double w = W[w64_at(d + 1, j, n, p)];
                 const int q = MODE == MLBM_STENCIL_OWN ? qo : nbr[(int64_t)j * n + s[d]];
                 acc[d] += w * g[(int64_t)(d + 1) * n + q];
             }
@@ -749,7 +754,7 @@ __global__ __launch_bounds__(256) void k_interpolate(int n, int K, int mode,
         const int s = mode == MLBM_STENCIL_OWN ? p : owner[(int64_t)(k - 1) * n + p];
         double acc = 0.0;
         for (int j = 0; j < K; ++j)
-            acc += W64[((int64_t)(k - 1) * K + j) * n + p] * field[perm[nbr[(int64_t)j * n + s]]];
+            acc += W64[w64_at(k, j, n, p)] * field[perm[nbr[(int64_t)j * n + s]]];
         out[(int64_t)(k - 1) * out_stride + u] = acc;
     }
 }

@@ -162,7 +162,7 @@ def test_adjoint_tables_are_consistent(mode, precision):
     say("mode", mode, "precision", precision, "tiles", td.size, "max |I_t|", td.max(),
         "global tiles", int((td == 0).sum()))
     assert (td > 0).all()
-    assert td.max() <= (960 if precision == 1 else 1024)
+    assert td.max() <= 1024
     for t in range(td.size):
         ni = td[t]
         I = il[t, :ni]
