@@ -389,14 +389,13 @@ __device__ __forceinline__ void wave_lds_sync() {
 // (departure points) are taken R at a time: the first group is eliminated
 // along with the matrix, later groups by replaying the stored multipliers.
 template <int NB, int R>
-__global__ __launch_bounds__(256) void k_rbf(const Geo *__restrict__ geo,
-                                             const double *__restrict__ xs,
-                                             const double *__restrict__ ys,
-                                             const int32_t *__restrict__ perm,
-                                             const int32_t *__restrict__ nbr, RhsList L,
-                                             int n, int K, int m, double dx,
-                                             double *__restrict__ W64,
-                                             int32_t *__restrict__ dev_err) {
+__device__ __forceinline__ void rbf_solve(const Geo *__restrict__ geo,
+                                          const double *__restrict__ xs,
+                                          const double *__restrict__ ys,
+                                          const int32_t *__restrict__ perm,
+                                          const int32_t *__restrict__ nbr, RhsList L, int n,
+                                          int K, int m, double dx, double *__restrict__ W64,
+                                          int32_t *__restrict__ dev_err) {
     __shared__ double s_row[4][NB + R];
     __shared__ double s_cx[4][64], s_cy[4][64];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -547,6 +546,25 @@ __global__ __launch_bounds__(256) void k_rbf(const Geo *__restrict__ geo,
         store(c0, b);
     }
     if (singular && lane == 0) atomicMin(dev_err, perm[s] + 1);
+}
+
+// Systems up to 48 unknowns keep two wavefronts per SIMD (a few registers
+// spill at 48, which costs less than the latency a lone wavefront leaves
+// exposed); 64 unknowns need the whole register file of one wavefront.
+template <int NB, int R>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_rbf(
+    const Geo *__restrict__ geo, const double *__restrict__ xs, const double *__restrict__ ys,
+    const int32_t *__restrict__ perm, const int32_t *__restrict__ nbr, RhsList L, int n, int K,
+    int m, double dx, double *__restrict__ W64, int32_t *__restrict__ dev_err) {
+    rbf_solve<NB, R>(geo, xs, ys, perm, nbr, L, n, K, m, dx, W64, dev_err);
+}
+
+template <int NB, int R>
+__global__ __launch_bounds__(256) void k_rbf_wide(
+    const Geo *__restrict__ geo, const double *__restrict__ xs, const double *__restrict__ ys,
+    const int32_t *__restrict__ perm, const int32_t *__restrict__ nbr, RhsList L, int n, int K,
+    int m, double dx, double *__restrict__ W64, int32_t *__restrict__ dev_err) {
+    rbf_solve<NB, R>(geo, xs, ys, perm, nbr, L, n, K, m, dx, W64, dev_err);
 }
 
 // Owner -> departure-point lists of the paper's stencil rule (CSR): count,
@@ -718,8 +736,12 @@ static hipError_t launch_rbf_nb(const Geo *geo, const double *xs, const double *
                                 const int32_t *perm, const int32_t *nbr, RhsList L, int n, int K,
                                 int m, double dx, double *W64, int32_t *dev_err, hipStream_t s) {
     dim3 grid(blocks_for(n, 4)), block(256);
-    hipLaunchKernelGGL((k_rbf<NB, 8>), grid, block, 0, s, geo, xs, ys, perm, nbr, L, n, K, m, dx,
-                       W64, dev_err);
+    if constexpr (NB <= 48)
+        hipLaunchKernelGGL((k_rbf<NB, 8>), grid, block, 0, s, geo, xs, ys, perm, nbr, L, n, K, m,
+                           dx, W64, dev_err);
+    else
+        hipLaunchKernelGGL((k_rbf_wide<NB, 8>), grid, block, 0, s, geo, xs, ys, perm, nbr, L, n,
+                           K, m, dx, W64, dev_err);
     return hipGetLastError();
 }
 
