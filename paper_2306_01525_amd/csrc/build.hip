@@ -366,6 +366,28 @@ __device__ __forceinline__ void rhs_point(const RhsList &L, int s, int t, int &p
     }
 }
 
+// Move a double between lanes by a DPP pattern (all lanes active).
+template <int CTRL>
+__device__ __forceinline__ double dpp_move(double v) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, false);
+    return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+
+// Largest value over the 64 lanes of a wavefront (all lanes active), the same
+// in every lane: DPP exchanges inside each row of 16 lanes (swap neighbours,
+// swap pairs, mirror the half-rows, mirror the row) leave the row's largest
+// value in all its lanes; the four rows are then combined from scalar reads.
+__device__ __forceinline__ double wave_max(double v) {
+    v = fmax(v, dpp_move<0xB1>(v));    // quad_perm [1,0,3,2]
+    v = fmax(v, dpp_move<0x4E>(v));    // quad_perm [2,3,0,1]
+    v = fmax(v, dpp_move<0x141>(v));   // row_half_mirror
+    v = fmax(v, dpp_move<0x140>(v));   // row_mirror
+    return fmax(fmax(readlane_d(v, 0), readlane_d(v, 16)),
+                fmax(readlane_d(v, 32), readlane_d(v, 48)));
+}
+
 // Orders the LDS accesses of one wavefront: LDS operations of a wavefront
 // complete in issue order, so only the compiler has to be kept from moving
 // accesses across this point.
@@ -499,9 +521,7 @@ __device__ __forceinline__ void rbf_solve(const Geo *__restrict__ geo,
     for (int k = 0; k < NB; ++k) {
         // pivot: the lowest open lane holding the largest |a_k|
         const double v = pstep > k ? fabs(a[k]) : -1.0;
-        double vm = v;
-#pragma unroll
-        for (int off = 32; off > 0; off >>= 1) vm = fmax(vm, __shfl_xor(vm, off));
+        const double vm = wave_max(v);
         const int pl = __builtin_amdgcn_readfirstlane(__builtin_ctzll(__ballot(v == vm)));
         if (!(vm > tiny)) singular = true;
         if (lane == pl) {
