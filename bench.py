@@ -523,7 +523,8 @@ def main():
         summarize_pmc(args.summarize_pmc[0], args.summarize_pmc[1], args.pmc_command)
         return
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
+        print("bench.py measures one GPU only: the library has no multi-GPU path; a cloud "
+              "would shard by Hilbert-ordered tile ranges with a halo exchange per step "
               "(--gpus %d requested)" % args.gpus, file=sys.stderr)
         sys.exit(2)
     if int(os.environ.get("RANK", "0")) != 0:

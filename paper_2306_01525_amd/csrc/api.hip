@@ -469,7 +469,6 @@ mlbm_status mlbm_import_weights(int32_t n, const double *x, const double *y,
     layout_cloud(c, p, p.precision, pl, nullptr, cp, nullptr);
     layout_common(pl, *plan, n);
     cp.imported = true;
-    bool any_wall = false;
     std::vector<int32_t> ident(n), hn((size_t)K * n), ho;
     std::vector<uint8_t> nt(n, 0);
     std::vector<double> hw((size_t)8 * K * n);
@@ -486,10 +485,7 @@ mlbm_status mlbm_import_weights(int32_t n, const double *x, const double *y,
             for (int j = 0; j < K; ++j)
                 hw[w64_at(k, j, n, i)] = W[((size_t)i * 9 + k) * K + j];
     if (node_type)
-        for (int i = 0; i < n; ++i) {
-            nt[i] = node_type[i];
-            any_wall |= nt[i] != 0;
-        }
+        for (int i = 0; i < n; ++i) nt[i] = node_type[i];
     cp.has_walls = p.wall_kind == 1;
     auto cleanup = [&](mlbm_status r) {
         delete plan;
@@ -514,7 +510,6 @@ mlbm_status mlbm_import_weights(int32_t n, const double *x, const double *y,
     STEP(launch_force(cp.xs, cp.ys, cp.ntype, n, p.force_kind, p.force_mag, cp.force32,
                       cp.force64, s));
     STEP(launch_fill_i32(plan->dev_err, INT_MAX, 1, s));
-    (void)any_wall;
     if (p.with_adjoint) {
         // This path has no workspace argument, so the transposed operator is
         // assembled on the host (rows filled in ascending arriving node, which

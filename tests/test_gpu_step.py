@@ -188,3 +188,32 @@ def test_step_variants_are_bitwise_identical_and_autotune_picks_one():
     assert len(ms) == 6 and all(m > 0 for m in ms)
     assert ms[plan.info.variant] == min(ms)
     plan.close()
+
+
+EXTREME_CASES = [
+    # (label, K, degree, mode): the largest stencil (K + M = 63 and 54 unknowns,
+    # the widest local solve and kNN paths, 16 index words per stencil) and the
+    # smallest (K = M = 6, the polynomial block alone fixes the system)
+    ("K48-m4-paper", 48, 4, 0),
+    ("K48-m2-own", 48, 2, 1),
+    ("K6-m2-own", 6, 2, 1),
+]
+
+
+@pytest.mark.parametrize("label,K,m,mode", EXTREME_CASES, ids=[c[0] for c in EXTREME_CASES])
+def test_extreme_stencil_sizes_match_oracle(label, K, m, mode):
+    from paper_2306_01525_amd import Plan
+    c, ux, uy = tgv_case(30, K, m, mode, seed=17)
+    tau, steps = 0.8, 40
+    say("case", label, "n", c.n)
+    (nbr, own, W), ref = oracle_run(c, c.h, K, m, mode, tau, ux, uy, [1, steps])
+    for prec, tol in ((1, lambda s: TOL_FP64), (0, tol_fp32)):
+        plan = Plan.build(c.x, c.y, c.period, _params(c.h, K, m, mode, prec, tau))
+        if prec == 1:
+            np.testing.assert_array_equal(plan.export("nbr"), nbr)
+            err = np.abs(plan.export("W")[:, 1:, :] - W[:, 1:, :]).max()
+            say("  max |W_gpu - W_oracle| = %.2e" % err)
+            assert err < 1e-9
+        got = _gpu_run(plan, ux, uy, [1, steps])
+        _compare(ref, got, tol, "%s/%s" % (label, "fp64" if prec else "fp32"))
+        plan.close()
