@@ -5,6 +5,9 @@
 #include <climits>
 #include <cmath>
 #include <cstring>
+#include <map>
+#include <memory>
+#include <mutex>
 #include <new>
 #include <string>
 #include <utility>
@@ -167,6 +170,7 @@ void layout_cloud(const mlbm_cloud &c, const mlbm_params &p, int precision, Carv
 
 void layout_common(Carve &pl, mlbm_plan &plan, int64_t n_total, int n_clouds = 1) {
     plan.dev_err = pl.take<int32_t>(64);
+    plan.stats = pl.take<int32_t>((size_t)kStats * n_clouds);
     plan.scratch64 =
         pl.take<double>(16 + 4 * (size_t)n_clouds + (size_t)blocks_for(n_total, 256) * 4);
 }
@@ -188,23 +192,42 @@ mlbm_status check_singular(mlbm_plan *plan, hipStream_t s) {
     return MLBM_OK;
 }
 
-// Tile tables of the LDS-staged step; when the stream is not captured, the
-// launch LDS size is the largest tile's need, else the capacity bound.
-mlbm_status build_tiles(mlbm_plan *plan, CloudPlan &cp, hipStream_t s) {
-    if (!cp.tdesc) return MLBM_OK;
-    int32_t *stats = plan->dev_err + 1;
-    MLBM_HIP(launch_fill_i32(stats, 0, 2, s));
-    MLBM_HIP(launch_tiles(cp, stats, s));
+// Gather tables of the LDS-staged step and of the adjoint. Their kernels
+// record per cloud (stats + kStats * cloud): [0] the largest LDS need of a
+// step tile, [1] step tiles without tables, [2] the largest inverse halo,
+// [3] adjoint tiles without one. The tables are enqueued for every cloud
+// first; finish_tables then reads all the records at once (one
+// synchronisation), or, while the stream is being captured, takes the
+// capacity bounds instead.
+mlbm_status enqueue_tables(CloudPlan &cp, int32_t *stats, hipStream_t s) {
+    if (cp.tdescT) MLBM_HIP(launch_adj_tiles(cp, stats + 2, s));
+    if (cp.tdesc) MLBM_HIP(launch_tiles(cp, stats, s));
+    return MLBM_OK;
+}
+
+mlbm_status finish_tables(mlbm_plan *plan, hipStream_t s) {
+    const size_t nc = plan->c.size();
     if (capturing(s)) {
-        cp.lds_bytes = (unsigned)(8 * cp.hcap * 4 + cp.ocap * ((cp.K + 2) / 3) * 4);
-        cp.fallback_tiles = -1;
+        for (CloudPlan &cp : plan->c) {
+            if (cp.tdesc) {
+                cp.lds_bytes = (unsigned)(8 * cp.hcap * 4 + cp.ocap * ((cp.K + 2) / 3) * 4);
+                cp.fallback_tiles = -1;
+            }
+            if (cp.tdescT) cp.adj_ni = cp.adj_cap;
+        }
         return MLBM_OK;
     }
-    int32_t h[2] = {0, 0};
+    std::vector<int32_t> h(kStats * nc);
     MLBM_HIP(hipStreamSynchronize(s));
-    MLBM_HIP(hipMemcpy(h, stats, sizeof(h), hipMemcpyDeviceToHost));
-    cp.lds_bytes = (unsigned)h[0];
-    cp.fallback_tiles = h[1];
+    MLBM_HIP(hipMemcpy(h.data(), plan->stats, sizeof(int32_t) * h.size(), hipMemcpyDeviceToHost));
+    for (size_t c = 0; c < nc; ++c) {
+        CloudPlan &cp = plan->c[c];
+        if (cp.tdesc) {
+            cp.lds_bytes = (unsigned)h[kStats * c];
+            cp.fallback_tiles = h[kStats * c + 1];
+        }
+        if (cp.tdescT) cp.adj_ni = h[kStats * c + 2];
+    }
     return MLBM_OK;
 }
 
@@ -217,24 +240,6 @@ void drop_graph(mlbm_plan *plan) {
         (void)hipGraphDestroy(plan->graph);
         plan->graph = nullptr;
     }
-}
-
-// Inverse-halo tables of the adjoint; the launch LDS is 8 values per node of
-// the largest inverse halo (the cap when the stream is captured).
-mlbm_status build_adj_tiles(mlbm_plan *plan, CloudPlan &cp, hipStream_t s) {
-    if (!cp.tdescT) return MLBM_OK;
-    int32_t *stats = plan->dev_err + 1;
-    MLBM_HIP(launch_fill_i32(stats, 0, 2, s));
-    MLBM_HIP(launch_adj_tiles(cp, stats, s));
-    if (capturing(s)) {
-        cp.adj_ni = cp.adj_cap;
-        return MLBM_OK;
-    }
-    int32_t h[2] = {0, 0};
-    MLBM_HIP(hipStreamSynchronize(s));
-    MLBM_HIP(hipMemcpy(h, stats, sizeof(h), hipMemcpyDeviceToHost));
-    cp.adj_ni = h[0];
-    return MLBM_OK;
 }
 
 const CloudPlan *single(const mlbm_plan *plan) {
@@ -261,7 +266,8 @@ namespace {
 struct PlanLayout {
     std::vector<CloudPlan> cps;
     std::vector<BuildWs> bws;
-    size_t plan_used = 0, ws_max = 0;
+    size_t plan_used = 0, ws_max = 0;   // ws_max: the whole workspace (all lanes)
+    int lanes = 1;                      // clouds built concurrently (c on lane c % lanes)
 };
 
 mlbm_status check_batch(const mlbm_cloud *clouds, const mlbm_params *params, int32_t n_clouds,
@@ -297,15 +303,26 @@ void layout_plan(const mlbm_cloud *clouds, const mlbm_params *params, int32_t n_
     Carve pl(plan_buf);
     L.cps.assign(n_clouds, CloudPlan());
     L.bws.assign(n_clouds, BuildWs());
+    // Clouds are built on up to kBuildLanes streams at once; each lane has a
+    // workspace region of the largest cloud's need, reused cloud after cloud.
+    size_t stride = 0;
+    for (int c = 0; c < n_clouds; ++c) {
+        Carve p0(nullptr), w0(nullptr);
+        CloudPlan cp0;
+        BuildWs bw0;
+        layout_cloud(clouds[c], params[c], params[0].precision, p0, &w0, cp0, &bw0);
+        stride = std::max(stride, (w0.used + 255) & ~size_t(255));
+    }
+    L.lanes = std::min(n_clouds, kBuildLanes);
     int64_t off = 0, tiles = 0;
     for (int c = 0; c < n_clouds; ++c) {
-        Carve ws(workspace);   // clouds are built one after another: shared workspace
+        Carve ws(workspace ? (char *)workspace + (size_t)(c % L.lanes) * stride : nullptr);
         layout_cloud(clouds[c], params[c], params[0].precision, pl, &ws, L.cps[c], &L.bws[c]);
         L.cps[c].off = off;
         off += clouds[c].n;
         tiles += (clouds[c].n + kTile - 1) / kTile;
-        L.ws_max = std::max(L.ws_max, ws.used);
     }
+    L.ws_max = stride * L.lanes;
     plan.n_total = off;
     plan.total_tiles = tiles;
     plan.batched = batchable(params, n_clouds);
@@ -320,7 +337,7 @@ void layout_plan(const mlbm_cloud *clouds, const mlbm_params *params, int32_t n_
 
 // Enqueue the build of one cloud (steps 1-4 of mlbm_build_weights).
 mlbm_status build_cloud(mlbm_plan *plan, CloudPlan &cp, const mlbm_cloud &c,
-                        const mlbm_params &p, BuildWs &bw, hipStream_t s) {
+                        const mlbm_params &p, BuildWs &bw, int32_t *stats, hipStream_t s) {
     const int n = c.n;
     if (c.period_x > 0 && c.period_y > 0)
         MLBM_HIP(launch_geo_periodic(cp.geo, c.period_x, c.period_y, bw.gx, bw.gy, bw.hb, s));
@@ -345,12 +362,72 @@ mlbm_status build_cloud(mlbm_plan *plan, CloudPlan &cp, const mlbm_cloud &c,
     if (cp.links)
         MLBM_HIP(launch_links(cp.ntype, cp.perm, c.normal_x, c.normal_y, n, cp.links, s));
     if (p.with_adjoint) MLBM_HIP(launch_transpose(cp, p.precision, bw.tr_tmp, bw.tr_bytes, s));
-    mlbm_status st = build_adj_tiles(plan, cp, s);
-    if (st != MLBM_OK) return st;
-    return build_tiles(plan, cp, s);
+    return enqueue_tables(cp, stats, s);
 }
 
 // Descriptor table and tile map of the batched step.
+// Streams and events that let the clouds of one plan build concurrently: per
+// device, created once (outside any graph capture) and kept for the process.
+struct LanePool {
+    hipStream_t st[kBuildLanes - 1] = {};
+    hipEvent_t ev[kBuildLanes] = {};
+    std::mutex mu;
+};
+
+LanePool *lane_pool() {
+    static std::mutex m;
+    static std::map<int, std::unique_ptr<LanePool>> pools;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return nullptr;
+    std::lock_guard<std::mutex> lock(m);
+    std::unique_ptr<LanePool> &p = pools[dev];
+    if (!p) {
+        auto q = std::make_unique<LanePool>();
+        for (int i = 0; i < kBuildLanes - 1; ++i)
+            if (hipStreamCreateWithFlags(&q->st[i], hipStreamNonBlocking) != hipSuccess)
+                return nullptr;
+        for (int i = 0; i < kBuildLanes; ++i)
+            if (hipEventCreateWithFlags(&q->ev[i], hipEventDisableTiming) != hipSuccess)
+                return nullptr;
+        p = std::move(q);
+    }
+    return p.get();
+}
+
+// Enqueue the builds of all clouds: cloud c on lane c % lanes, lane 0 being
+// the caller's stream and the others forked from it and joined back to it (in
+// a captured stream the lanes become parallel branches of the graph).
+mlbm_status build_clouds(mlbm_plan *plan, const mlbm_cloud *clouds, const mlbm_params *params,
+                         PlanLayout &L, hipStream_t s) {
+    const int nc = (int)plan->c.size();
+    LanePool *pool = L.lanes > 1 ? lane_pool() : nullptr;
+    if (!pool) {
+        if (L.lanes > 1) return fail(MLBM_EHIP, "could not create the build streams");
+        for (int c = 0; c < nc; ++c) {
+            mlbm_status st = build_cloud(plan, plan->c[c], clouds[c], params[c], L.bws[c],
+                                         plan->stats + kStats * c, s);
+            if (st != MLBM_OK) return st;
+        }
+        return MLBM_OK;
+    }
+    std::lock_guard<std::mutex> lock(pool->mu);
+    MLBM_HIP(hipEventRecord(pool->ev[0], s));
+    for (int l = 1; l < L.lanes; ++l) MLBM_HIP(hipStreamWaitEvent(pool->st[l - 1], pool->ev[0], 0));
+    mlbm_status st = MLBM_OK;
+    for (int c = 0; c < nc && st == MLBM_OK; ++c) {
+        const int l = c % L.lanes;
+        st = build_cloud(plan, plan->c[c], clouds[c], params[c], L.bws[c],
+                         plan->stats + kStats * c, l ? pool->st[l - 1] : s);
+    }
+    // join every lane, also after an error, so no capture is left forked
+    for (int l = 1; l < L.lanes; ++l) {
+        hipError_t e = hipEventRecord(pool->ev[l], pool->st[l - 1]);
+        if (e == hipSuccess) e = hipStreamWaitEvent(s, pool->ev[l], 0);
+        if (e != hipSuccess && st == MLBM_OK) st = hip_fail(e, "joining the build streams");
+    }
+    return st;
+}
+
 mlbm_status build_batch(mlbm_plan *plan, hipStream_t s) {
     if (!plan->batched) return MLBM_OK;
     int64_t tb = 0;
@@ -410,11 +487,12 @@ mlbm_status mlbm_build_weights(const mlbm_cloud *clouds, const mlbm_params *para
         return r;
     };
     hipError_t e = launch_fill_i32(plan->dev_err, INT_MAX, 1, s);
+    if (e == hipSuccess) e = launch_fill_i32(plan->stats, 0, (int64_t)kStats * n_clouds, s);
     if (e != hipSuccess) return cleanup(hip_fail(e, "launch_fill_i32"));
-    for (int c = 0; c < n_clouds; ++c) {
-        st = build_cloud(plan, plan->c[c], clouds[c], params[c], L.bws[c], s);
-        if (st != MLBM_OK) return cleanup(st);
-    }
+    st = build_clouds(plan, clouds, params, L, s);
+    if (st != MLBM_OK) return cleanup(st);
+    st = finish_tables(plan, s);
+    if (st != MLBM_OK) return cleanup(st);
     st = build_batch(plan, s);
     if (st != MLBM_OK) return cleanup(st);
     st = check_singular(plan, s);
@@ -556,15 +634,14 @@ mlbm_status mlbm_import_weights(int32_t n, const double *x, const double *y,
         else
             STEP(hipMemcpyAsync(cp.tr_val, v32.data(), sizeof(float) * nnz, hipMemcpyHostToDevice, s));
         STEP(launch_ell_fill(cp, p.precision, s));
-        STEP(hipStreamSynchronize(s));
-        st = build_adj_tiles(plan, cp, s);
-        if (st != MLBM_OK) return cleanup(st);
     }
-    STEP(hipStreamSynchronize(s));
+    STEP(launch_fill_i32(plan->stats, 0, kStats, s));
 #undef STEP
-    st = build_tiles(plan, cp, s);
+    st = enqueue_tables(cp, plan->stats, s);
     if (st != MLBM_OK) return cleanup(st);
     plan->c.push_back(cp);
+    st = finish_tables(plan, s);
+    if (st != MLBM_OK) return cleanup(st);
     *out = plan;
     return MLBM_OK;
 }
@@ -1005,6 +1082,7 @@ mlbm_status mlbm_build_graph(const mlbm_cloud *clouds, const mlbm_params *params
     if (!s) return fail(MLBM_EINVAL, "graph capture needs a non-default stream");
     if (!g_a || !g_b || g_a == g_b || n_steps < 0) return fail(MLBM_EINVAL, "bad state buffers");
     if (variant < 0 || variant >= kStepVariants) return fail(MLBM_EINVAL, "unknown variant");
+    if (n_clouds > 1 && !lane_pool()) return fail(MLBM_EHIP, "could not create the build streams");
     MLBM_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
     mlbm_plan *plan = nullptr;
     mlbm_status st = mlbm_build_weights(clouds, params, n_clouds, plan_buf, plan_bytes, workspace,

