@@ -119,8 +119,12 @@ def run_gpu(args):
         torch.cuda.synchronize()
         return plan, (time.perf_counter() - t0) * 1e3
 
-    # FP32 deviation form: the headline
+    # FP32 deviation form: the headline. The first build of the process also
+    # pays one-time costs (code objects, library set-up): a second build is
+    # the build time reported.
     log("building FP32 plan, N =", c.n)
+    plan32, build_cold_ms = build(MLBM_FP32_DEV)
+    plan32.close()
     plan32, build_ms = build(MLBM_FP32_DEV)
     a, b = plan32.new_state(), plan32.new_state()
     tune_ms = plan32.autotune(plan32.init(uxt, uyt, g=a), b, 20)
@@ -140,7 +144,8 @@ def run_gpu(args):
     tx_t, ty_t = torch.tensor(tx, device=dev), torch.tensor(ty, device=dev)
     l2u32, l2v32 = plan32.l2(g32, tx_t, ty_t)
     _, u32, v32 = plan32.moments(g32)
-    out.update(ms32=ms32, build_ms=build_ms, l2_32=(l2u32, l2v32), l2_steps=total)
+    out.update(ms32=ms32, build_ms=build_ms, build_cold_ms=build_cold_ms, l2_32=(l2u32, l2v32),
+               l2_steps=total)
     log("FP32: %.3f ms/step, L2(u) vs analytic %.3e" % (ms32 / args.steps, l2u32))
 
     # FP64 plain form, same number of steps
@@ -587,7 +592,8 @@ def main():
     # elimination 2n^3/3 plus 8 right-hand sides at 2n^2 each, per node
     nn = K + 15
     flop = n * (2.0 * nn ** 3 / 3.0 + 16.0 * nn ** 2)
-    line["build"] = {"ms": r["build_ms"], "fp64_flop_algorithmic": flop,
+    line["build"] = {"ms": r["build_ms"], "first_build_ms": r["build_cold_ms"],
+                     "fp64_flop_algorithmic": flop,
                      "tflops": flop / (r["build_ms"] / 1e3) / 1e12}
     line["autotune"] = r["tune"]
     if not args.skip_lbm:
