@@ -535,14 +535,15 @@ __device__ __forceinline__ void rbf_solve(const Geo *__restrict__ geo,
         wave_lds_sync();
         const double l = lane != pl ? a[k] / row[k] : 0.0;
         // (the LDS reads are issued 16 at a time, which bounds the registers
-        // they hold)
+        // they hold; the updates are explicit fused multiply-adds, since only
+        // the distances that decide stencil ties must round like the oracle)
 #pragma unroll
         for (int c = k + 1; c < NB; ++c) {
-            a[c] = a[c] - l * row[c];
+            a[c] = __builtin_fma(-l, row[c], a[c]);
             if ((c - k) % 16 == 0) __builtin_amdgcn_sched_barrier(0);
         }
 #pragma unroll
-        for (int t = 0; t < R; ++t) b[t] = b[t] - l * row[NB + t];
+        for (int t = 0; t < R; ++t) b[t] = __builtin_fma(-l, row[NB + t], b[t]);
         if (lane != pl) a[k] = l;
         wave_lds_sync();
     }
@@ -559,7 +560,7 @@ __device__ __forceinline__ void rbf_solve(const Geo *__restrict__ geo,
             wave_lds_sync();
             if (pstep != k) {
 #pragma unroll
-                for (int t = 0; t < R; ++t) b[t] = b[t] - a[k] * row[NB + t];
+                for (int t = 0; t < R; ++t) b[t] = __builtin_fma(-a[k], row[NB + t], b[t]);
             }
             wave_lds_sync();
         }
