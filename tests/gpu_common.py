@@ -24,6 +24,50 @@ TOL_FP64 = 1e-11
 TOL_W = 1e-9
 
 
+def weight_bounds(c, nbr, own, W, K, m):
+    """Bound on the difference of two backward-stable solutions of the same
+    local systems, per (node, direction): (K + M) eps kappa_inf(A_s)
+    max(1, max_j |w_j|), with A_s the scaled local system of the owner s whose
+    stencil carries that departure point (Sec. 2, eq. Phi_L). The matrix does
+    not depend on the departure point, so one per owner."""
+    L = c.period
+    nn = K + oracle.poly_count(m)
+    kappa = np.empty(c.n)
+    for s in range(c.n):
+        st = nbr[s]
+        rx = (c.x[st] - c.x[s] + L[0] / 2) % L[0] - L[0] / 2
+        ry = (c.y[st] - c.y[s] + L[1] / 2) % L[1] - L[1] / 2
+        A, _ = oracle.local_system(rx, ry, 0.0, 0.0, m)
+        kappa[s] = np.linalg.cond(A, np.inf)
+    return nn * 2.0 ** -52 * kappa[own] * np.maximum(1.0, np.abs(W).max(axis=2))
+
+
+def first_step_bounds(nbr, own, wb, f0):
+    """Per-node bound on the moments after one step from the populations f0
+    [n][9] when every weight of (node, direction) may be off by wb [n][9]: the
+    streamed population k of node i moves by at most wb[i, k] sum_j |f0_jk|
+    over the owner's stencil, and |e_k| <= 1 carries that to the momentum."""
+    n = f0.shape[0]
+    b = np.zeros(n)
+    for k in range(1, 9):
+        b += wb[:, k] * np.abs(f0[nbr[own[:, k]], k]).sum(axis=1)
+    return b
+
+
+def first_step_rounding_bounds(nbr, own, W, f0, eps):
+    """Per-node bound on the rounding of one step from f0 in a format of unit
+    roundoff eps: each streamed population sums K products of rounded weights
+    and populations (the FP32 partition-of-unity repair moves one weight by at
+    most the rounding defect of the sum), so it is off by a few units of
+    eps sum_j |w_j| |f0_j|; 8 of those plus 8 eps for the collision and the
+    moment sums."""
+    n = f0.shape[0]
+    b = np.ones(n)
+    for k in range(1, 9):
+        b += (np.abs(W[:, k, :]) * np.abs(f0[nbr[own[:, k]], k])).sum(axis=1)
+    return 8.0 * eps * b
+
+
 def tol_fp32(steps: int) -> float:
     """Relative L2 bound on the velocity of the FP32 deviation path against
     the FP64 oracle. Each step adds rounding of the stored deviations and of

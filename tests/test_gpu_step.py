@@ -4,8 +4,9 @@ import numpy as np
 import pytest
 
 import oracle
-from gpu_common import (TOL_FP64, TOL_W, annulus_case, oracle_run, rel_l2, say, tgv_case,
-                        tol_fp32)
+from gpu_common import (EPS32, TOL_FP64, annulus_case, first_step_bounds,
+                        first_step_rounding_bounds, oracle_run, rel_l2, say, tgv_case,
+                        tol_fp32, weight_bounds)
 from synth import tgv_initial_velocity
 
 pytestmark = pytest.mark.gpu
@@ -196,13 +197,14 @@ EXTREME_CASES = [
     # stencil (K + M = 63 and 54 unknowns, the widest local solve and kNN paths,
     # 16 index words per stencil) and the smallest (K = M = 6: the polynomial
     # block alone fixes the weights). Six-point quadratic interpolation is
-    # poorly conditioned on near-regular points: the two solvers' weights agree
-    # to ~1e-10 rather than ~1e-13 (populations to K times that), and the run
-    # diverges within a few tens of steps in the oracle and on the GPU alike,
-    # so that case is compared after the first step only.
+    # poorly conditioned on near-regular points (condition numbers up to ~2e7,
+    # weights up to ~2e3): the two solvers' weights there agree only to the
+    # conditioning bound, and the run diverges within a few tens of steps in
+    # the oracle and on the GPU alike, so that case is compared after the first
+    # step only, node by node, against the bound the weights imply (None).
     ("K48-m4-paper", 48, 4, 0, [1, 40], lambda s: TOL_FP64),
     ("K48-m2-own", 48, 2, 1, [1, 40], lambda s: TOL_FP64),
-    ("K6-m2-own", 6, 2, 1, [1], lambda s: 6 * TOL_W * s),
+    ("K6-m2-own", 6, 2, 1, [1], None),
 ]
 
 
@@ -214,13 +216,30 @@ def test_extreme_stencil_sizes_match_oracle(label, K, m, mode, steps, tol64):
     tau = 0.8
     say("case", label, "n", c.n)
     (nbr, own, W), ref = oracle_run(c, c.h, K, m, mode, tau, ux, uy, steps)
-    for prec, tol in ((1, tol64), (0, lambda s: max(tol_fp32(s), tol64(s)))):
+    wb = weight_bounds(c, nbr, own, W, K, m)
+    for prec in (1, 0):
         plan = Plan.build(c.x, c.y, c.period, _params(c.h, K, m, mode, prec, tau))
         if prec == 1:
             np.testing.assert_array_equal(plan.export("nbr"), nbr)
-            err = np.abs(plan.export("W")[:, 1:, :] - W[:, 1:, :]).max()
-            say("  max |W_gpu - W_oracle| = %.2e" % err)
-            assert err < TOL_W
+            dW = np.abs(plan.export("W")[:, 1:, :] - W[:, 1:, :]).max(axis=2)
+            say("  max |W_gpu - W_oracle| = %.2e, largest fraction of its bound %.2e"
+                % (dW.max(), (dW / wb[:, 1:]).max()))
+            assert (dW <= wb[:, 1:]).all()
         got = _gpu_run(plan, ux, uy, steps)
-        _compare(ref, got, tol, "%s/%s" % (label, "fp64" if prec else "fp32"))
+        if tol64 is None:
+            # one step from equilibrium: per-node bound from the weight bounds
+            # plus the rounding of the step in the state's precision
+            f0 = oracle.equilibrium(np.ones(c.n), ux, uy)
+            b = first_step_bounds(nbr, own, wb, f0) + first_step_rounding_bounds(
+                nbr, own, W, f0, 2.0 ** -53 if prec else EPS32)
+            r_o, u_o, v_o = ref[1]
+            r_g, u_g, v_g = got[1]
+            worst = max(float((np.abs(a - o) / b).max())
+                        for a, o in ((r_g, r_o), (r_g * u_g, r_o * u_o), (r_g * v_g, r_o * v_o)))
+            say("  %s step 1: largest |moment difference| / bound %.2e"
+                % ("fp64" if prec else "fp32", worst))
+            assert worst <= 1.0
+        else:
+            tol = tol64 if prec == 1 else (lambda s: max(tol_fp32(s), tol64(s)))
+            _compare(ref, got, tol, "%s/%s" % (label, "fp64" if prec else "fp32"))
         plan.close()
