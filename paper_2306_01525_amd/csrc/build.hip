@@ -318,28 +318,13 @@ __global__ __launch_bounds__(256) void k_owner(const Geo *__restrict__ geo,
     }
 }
 
-__device__ __forceinline__ double readlane_d(double v, int l) {
-    long long b = __double_as_longlong(v);
-    int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), l);
-    int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
-    return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
-}
-
-// Monomial q of eq. poly_sets (graded order 1, x, y, x^2, xy, y^2, x^3, x^2y,
-// xy^2, y^3, x^4, x^3y, x^2y^2, xy^3, y^4; q < 15): q lies in degree d, at
-// offset j within it, and is x^(d-j) y^j. Written without branches on q, so
-// that a lane-dependent q costs no divergent code.
+// x^e for 0 <= e <= 4, without branches on e, so that a lane-dependent
+// exponent costs no divergent code.
 __device__ __forceinline__ double pow_upto4(double x, int e) {
     double p = 1.0;
 #pragma unroll
     for (int t = 0; t < 4; ++t) p = t < e ? p * x : p;
     return p;
-}
-
-__device__ __forceinline__ double monomial(int q, double x, double y) {
-    const int d = (q >= 1) + (q >= 3) + (q >= 6) + (q >= 10);
-    const int j = q - d * (d + 1) / 2;
-    return pow_upto4(x, d - j) * pow_upto4(y, j);
 }
 
 __device__ __forceinline__ double cube_dist(double ax, double ay, double bx, double by) {
@@ -366,26 +351,30 @@ __device__ __forceinline__ void rhs_point(const RhsList &L, int s, int t, int &p
     }
 }
 
-// Move a double between lanes by a DPP pattern (all lanes active).
-template <int CTRL>
-__device__ __forceinline__ double dpp_move(double v) {
-    const long long b = __double_as_longlong(v);
-    const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, 0xF, 0xF, false);
-    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, false);
-    return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+// Largest 32-bit key over the 64 lanes of a wavefront (all lanes active), the
+// same in every lane: DPP exchanges inside each row of 16 lanes (swap
+// neighbours, swap pairs, mirror the half-rows, mirror the row) leave the
+// row's largest key in all its lanes; the four rows are then combined from
+// scalar reads.
+__device__ __forceinline__ uint32_t wave_max_u32(uint32_t v) {
+    v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0xB1, 0xF, 0xF, false));
+    v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x4E, 0xF, 0xF, false));
+    v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x141, 0xF, 0xF, false));
+    v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x140, 0xF, 0xF, false));
+    const uint32_t r0 = __builtin_amdgcn_readlane(v, 0), r1 = __builtin_amdgcn_readlane(v, 16);
+    const uint32_t r2 = __builtin_amdgcn_readlane(v, 32), r3 = __builtin_amdgcn_readlane(v, 48);
+    return max(max(r0, r1), max(r2, r3));
 }
 
-// Largest value over the 64 lanes of a wavefront (all lanes active), the same
-// in every lane: DPP exchanges inside each row of 16 lanes (swap neighbours,
-// swap pairs, mirror the half-rows, mirror the row) leave the row's largest
-// value in all its lanes; the four rows are then combined from scalar reads.
-__device__ __forceinline__ double wave_max(double v) {
-    v = fmax(v, dpp_move<0xB1>(v));    // quad_perm [1,0,3,2]
-    v = fmax(v, dpp_move<0x4E>(v));    // quad_perm [2,3,0,1]
-    v = fmax(v, dpp_move<0x141>(v));   // row_half_mirror
-    v = fmax(v, dpp_move<0x140>(v));   // row_mirror
-    return fmax(fmax(readlane_d(v, 0), readlane_d(v, 16)),
-                fmax(readlane_d(v, 32), readlane_d(v, 48)));
+// 1/x to within about an ulp: the hardware estimate (about 2^-23 relative
+// error for the magnitudes met here) refined by two Newton steps r += r(1 - xr),
+// each of which squares the relative error. Zero gives NaN, which the
+// singularity test catches where it matters (a zero pivot).
+__device__ __forceinline__ double recip(double x) {
+    double r = __builtin_amdgcn_rcp(x);
+    r = __builtin_fma(r, __builtin_fma(-x, r, 1.0), r);
+    r = __builtin_fma(r, __builtin_fma(-x, r, 1.0), r);
+    return r;
 }
 
 // Orders the LDS accesses of one wavefront: LDS operations of a wavefront
@@ -402,14 +391,18 @@ __device__ __forceinline__ void wave_lds_sync() {
 // departure point that uses the stencil of s, by Gauss-Jordan elimination with
 // partial pivoting. Lane r holds row r of the system (K RBF rows, M polynomial
 // rows, then identity rows that pad the system to NB unknowns) in registers.
-// Rows are never moved: the pivot of column k is the not-yet-used lane with the
-// largest |a_k| (ties: lowest lane); it copies its row to LDS and every other
-// lane, pivot rows of earlier steps included, subtracts its multiple of that
-// row and keeps the multiplier in a_k. At the end the pivot row of step j
-// holds a_j x_j = b, so unknown j (the weight of stencil member j, j < K) is
-// one division away, with no back substitution. The right-hand sides
-// (departure points) are taken R at a time: the first group is eliminated
-// along with the matrix, later groups by replaying the stored multipliers.
+// Rows are never moved: the pivot of column k is a not-yet-used lane with the
+// largest |a_k|, compared on the upper 32 bits of its binary64 encoding
+// (exponent and 20 mantissa bits, so within a factor 1 + 2^-20 of the largest,
+// which keeps the growth bound of partial pivoting; ties: lowest lane). It
+// copies its row and its reciprocal 1/a_k to LDS, and every other lane, pivot
+// rows of earlier steps included, subtracts its multiple of that row and
+// keeps the multiplier in a_k. At the end the pivot row of step j holds
+// a_j x_j = b, so unknown j (the weight of stencil member j, j < K) is one
+// product with the kept reciprocal away, with no back substitution. The
+// right-hand sides (departure points) are taken R at a time: the first group
+// is eliminated along with the matrix, later groups by replaying the stored
+// multipliers.
 template <int NB, int R>
 __device__ __forceinline__ void rbf_solve(const Geo *__restrict__ geo,
                                           const double *__restrict__ xs,
@@ -418,9 +411,14 @@ __device__ __forceinline__ void rbf_solve(const Geo *__restrict__ geo,
                                           const int32_t *__restrict__ nbr, RhsList L, int n,
                                           int K, int m, double dx, double *__restrict__ W64,
                                           int32_t *__restrict__ dev_err) {
-    __shared__ double s_row[4][NB + R];
-    __shared__ double s_cx[4][64], s_cy[4][64];
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    constexpr int MP = 15;   // monomials of degree <= 4 (table row stride, odd)
+    __shared__ double s_row[4][NB + R + 1];
+    __shared__ double2 s_c[4][64];
+    __shared__ double s_P[4][kMaxK * MP];
+    __shared__ double2 s_q[4][R];
+    __shared__ int2 s_pk[4][R];
+    const int lane = threadIdx.x & 63;
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int64_t wave = (int64_t)blockIdx.x * 4 + wv;
     if (wave >= n) return;   // uniform across the wavefront
     const int s = (int)wave;
@@ -430,6 +428,7 @@ __device__ __forceinline__ void rbf_solve(const Geo *__restrict__ geo,
     const int M = (m + 1) * (m + 2) / 2;
     const int nn = K + M;
     double *row = s_row[wv];
+    double *P = s_P[wv];
 
     // stencil member coordinates relative to the centre s, scaled by the
     // stencil radius (the interpolant is invariant to this; it helps the
@@ -445,25 +444,48 @@ __device__ __forceinline__ void rbf_solve(const Geo *__restrict__ geo,
     for (int off = 32; off > 0; off >>= 1) rad = fmax(rad, __shfl_xor(rad, off));
     if (!(rad > 0.0)) rad = 1.0;
     const double sx = rx / rad, sy = ry / rad;
-    s_cx[wv][lane] = sx;
-    s_cy[wv][lane] = sy;
+    s_c[wv][lane] = make_double2(sx, sy);
+    // monomials of each member (eq. poly_sets, graded order 1, x, y, x^2, xy,
+    // y^2, x^3, ..., y^4: monomial q of degree d at offset j is x^(d-j) y^j),
+    // row `lane` of the table
+    if (lane < K) {
+        double xp[5], yp[5];
+        xp[0] = yp[0] = 1.0;
+#pragma unroll
+        for (int e = 1; e < 5; ++e) {
+            xp[e] = xp[e - 1] * sx;
+            yp[e] = yp[e - 1] * sy;
+        }
+        int q = 0;
+#pragma unroll
+        for (int d = 0; d <= 4; ++d)
+#pragma unroll
+            for (int j = 0; j <= d; ++j) P[lane * MP + q++] = xp[d - j] * yp[j];
+    }
     wave_lds_sync();
     const bool rbf_row = lane < K;
     const bool poly_row = lane >= K && lane < nn;
     const int qrow = lane - K;
+    // table entries this lane reads: polynomial q of every member (polynomial
+    // rows), every polynomial of its own member (RBF rows)
+    const int pcol = poly_row ? qrow : 0;
+    const int prow = (rbf_row ? lane : 0) * MP - K;
 
-    // row `lane` of the padded system (selected without divergent branches)
+    // row `lane` of the padded system; the branches on the column are uniform
     double a[NB];
 #pragma unroll
     for (int c = 0; c < NB; ++c) {
-        const double cxv = s_cx[wv][c], cyv = s_cy[wv][c];
-        const double r3 = cube_dist(sx, sy, cxv, cyv);
-        const double pr = monomial(c < nn ? c - K : 0, sx, sy);   // row lane, column c >= K
-        const double pc = monomial(poly_row ? qrow : 0, cxv, cyv);   // row qrow, column c < K
-        const double id = c == lane ? 1.0 : 0.0;
-        a[c] = rbf_row ? (c < K ? r3 : (c < nn ? pr : 0.0))
-             : poly_row ? (c < K ? pc : 0.0)
-             : lane < NB ? id : 0.0;
+        if (c < K) {
+            const double2 cc = s_c[wv][c];
+            const double r3 = cube_dist(sx, sy, cc.x, cc.y);
+            const double pc = P[c * MP + pcol];
+            a[c] = rbf_row ? r3 : (poly_row ? pc : 0.0);
+        } else if (c < nn) {
+            const double pr = P[prow + c];
+            a[c] = rbf_row ? pr : 0.0;
+        } else {
+            a[c] = c == lane ? 1.0 : 0.0;
+        }
     }
     // infinity norm for the singularity threshold
     double rs = 0.0;
@@ -475,28 +497,39 @@ __device__ __forceinline__ void rbf_solve(const Geo *__restrict__ geo,
     const double tiny = 1e3 * DBL_EPSILON * rs;
     bool singular = false;
     // elimination step at which this lane was the pivot (-1: padding lane)
-    // and its pivot value
+    // and the reciprocal of its pivot value
     int pstep = lane < NB ? NB : -1;
-    double piv = 1.0;
+    double pinv = 1.0;
 
-    // right-hand sides c0 .. c0+R-1 (row `lane` of each)
+    // right-hand sides c0 .. c0+R-1 (row `lane` of each). Lane t < R first
+    // locates departure point c0 + t (node p, direction k) and its position
+    // x_p - e_k dx relative to s, scaled, for the whole wavefront.
+    const double irad = 1.0 / rad;
+    // exponents of monomial qrow (degree qd, offset qey within it)
+    const int qd = (qrow >= 1) + (qrow >= 3) + (qrow >= 6) + (qrow >= 10);
+    const int qey = poly_row ? qrow - qd * (qd + 1) / 2 : 0;
+    const int qex = poly_row ? qd - qey : 0;
     auto load_rhs = [&](int c0, double(&b)[R]) {
+        if (lane < R) {
+            double qx = 0.0, qy = 0.0;
+            int p = 0, k = 1;
+            if (c0 + lane < count) {
+                rhs_point(L, s, c0 + lane, p, k);
+                qx = (L.ptr ? min_image(xs[p] - lat_ex(k) * dx - xs[s], g.Lx)
+                            : -lat_ex(k) * dx) * irad;
+                qy = (L.ptr ? min_image(ys[p] - lat_ey(k) * dx - ys[s], g.Ly)
+                            : -lat_ey(k) * dx) * irad;
+            }
+            s_q[wv][lane] = make_double2(qx, qy);
+            s_pk[wv][lane] = make_int2(p, k);
+        }
+        wave_lds_sync();
 #pragma unroll
         for (int t = 0; t < R; ++t) {
-            double v = 0.0;
-            if (c0 + t < count) {
-                int p, k;
-                rhs_point(L, s, c0 + t, p, k);
-                // departure point x_p - e_k dx relative to s, scaled
-                const double qx = (L.ptr ? min_image(xs[p] - lat_ex(k) * dx - xs[s], g.Lx)
-                                         : -lat_ex(k) * dx) / rad;
-                const double qy = (L.ptr ? min_image(ys[p] - lat_ey(k) * dx - ys[s], g.Ly)
-                                         : -lat_ey(k) * dx) / rad;
-                const double r3 = cube_dist(sx, sy, qx, qy);
-                const double pq = monomial(poly_row ? qrow : 0, qx, qy);
-                v = rbf_row ? r3 : (poly_row ? pq : 0.0);
-            }
-            b[t] = v;
+            const double2 q = s_q[wv][t];
+            const double r3 = cube_dist(sx, sy, q.x, q.y);
+            const double pq = pow_upto4(q.x, qex) * pow_upto4(q.y, qey);
+            b[t] = c0 + t < count ? (rbf_row ? r3 : (poly_row ? pq : 0.0)) : 0.0;
         }
     };
     // the pivot row of step j < K holds a_j x_j = b: x_j is the weight of
@@ -506,9 +539,8 @@ __device__ __forceinline__ void rbf_solve(const Geo *__restrict__ geo,
 #pragma unroll
             for (int t = 0; t < R; ++t) {
                 if (c0 + t < count) {
-                    int p, k;
-                    rhs_point(L, s, c0 + t, p, k);
-                    W64[w64_at(k, pstep, n, p)] = b[t] / piv;
+                    const int2 pk = s_pk[wv][t];
+                    W64[w64_at(pk.y, pstep, n, pk.x)] = b[t] * pinv;
                 }
             }
         }
@@ -519,21 +551,23 @@ __device__ __forceinline__ void rbf_solve(const Geo *__restrict__ geo,
     // elimination, carrying the first group of right-hand sides
 #pragma unroll
     for (int k = 0; k < NB; ++k) {
-        // pivot: the lowest open lane holding the largest |a_k|
-        const double v = pstep > k ? fabs(a[k]) : -1.0;
-        const double vm = wave_max(v);
-        const int pl = __builtin_amdgcn_readfirstlane(__builtin_ctzll(__ballot(v == vm)));
-        if (!(vm > tiny)) singular = true;
+        const uint32_t key =
+            pstep > k ? ((uint32_t)(__double_as_longlong(a[k]) >> 32) & 0x7FFFFFFFu) | 1u : 0u;
+        const double rk = recip(a[k]);
+        const uint32_t km = wave_max_u32(key);
+        const int pl = __builtin_amdgcn_readfirstlane(__builtin_ctzll(__ballot(key == km)));
         if (lane == pl) {
 #pragma unroll
             for (int c = k; c < NB; ++c) row[c] = a[c];
 #pragma unroll
             for (int t = 0; t < R; ++t) row[NB + t] = b[t];
+            row[NB + R] = rk;
             pstep = k;
-            piv = a[k];
+            pinv = rk;
         }
         wave_lds_sync();
-        const double l = lane != pl ? a[k] / row[k] : 0.0;
+        if (!(fabs(row[k]) > tiny)) singular = true;
+        const double l = lane != pl ? a[k] * row[NB + R] : 0.0;
         // (the LDS reads are issued 16 at a time, which bounds the registers
         // they hold; the updates are explicit fused multiply-adds, since only
         // the distances that decide stencil ties must round like the oracle)
@@ -569,11 +603,13 @@ __device__ __forceinline__ void rbf_solve(const Geo *__restrict__ geo,
     if (singular && lane == 0) atomicMin(dev_err, perm[s] + 1);
 }
 
-// Systems up to 48 unknowns keep two wavefronts per SIMD (a few registers
-// spill at 48, which costs less than the latency a lone wavefront leaves
-// exposed); 64 unknowns need the whole register file of one wavefront.
-template <int NB, int R>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_rbf(
+// Occupancy against registers: 24 unknowns fit four wavefronts per SIMD and
+// 32 three (a few registers spill, which costs less than the latency fewer
+// wavefronts leave exposed); 48 unknowns keep two, since the spills a third
+// would need cost what it gains; 64 unknowns need the whole register file of
+// one wavefront.
+template <int NB, int R, int WPE>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) void k_rbf(
     const Geo *__restrict__ geo, const double *__restrict__ xs, const double *__restrict__ ys,
     const int32_t *__restrict__ perm, const int32_t *__restrict__ nbr, RhsList L, int n, int K,
     int m, double dx, double *__restrict__ W64, int32_t *__restrict__ dev_err) {
@@ -757,9 +793,10 @@ static hipError_t launch_rbf_nb(const Geo *geo, const double *xs, const double *
                                 const int32_t *perm, const int32_t *nbr, RhsList L, int n, int K,
                                 int m, double dx, double *W64, int32_t *dev_err, hipStream_t s) {
     dim3 grid(blocks_for(n, 4)), block(256);
+    constexpr int wpe = NB == 24 ? 4 : NB == 32 ? 3 : 2;
     if constexpr (NB <= 48)
-        hipLaunchKernelGGL((k_rbf<NB, 8>), grid, block, 0, s, geo, xs, ys, perm, nbr, L, n, K, m,
-                           dx, W64, dev_err);
+        hipLaunchKernelGGL((k_rbf<NB, 8, wpe>), grid, block, 0, s, geo, xs, ys, perm, nbr, L, n, K,
+                           m, dx, W64, dev_err);
     else
         hipLaunchKernelGGL((k_rbf_wide<NB, 8>), grid, block, 0, s, geo, xs, ys, perm, nbr, L, n,
                            K, m, dx, W64, dev_err);
