@@ -351,19 +351,33 @@ __device__ __forceinline__ void rhs_point(const RhsList &L, int s, int t, int &p
     }
 }
 
-// Largest 32-bit key over the 64 lanes of a wavefront (all lanes active), the
-// same in every lane: DPP exchanges inside each row of 16 lanes (swap
-// neighbours, swap pairs, mirror the half-rows, mirror the row) leave the
-// row's largest key in all its lanes; the four rows are then combined from
-// scalar reads.
-__device__ __forceinline__ uint32_t wave_max_u32(uint32_t v) {
+// Largest 32-bit key over each group of 64/SYS lanes of a wavefront (all
+// lanes active; SYS = 1 or 2), the same in every lane of the group: DPP
+// exchanges inside each row of 16 lanes (swap neighbours, swap pairs, mirror
+// the half-rows, mirror the row) leave the row's largest key in all its lanes;
+// the rows of a group are then combined from scalar reads.
+template <int SYS>
+__device__ __forceinline__ uint32_t group_max_u32(uint32_t v, int half) {
     v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0xB1, 0xF, 0xF, false));
     v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x4E, 0xF, 0xF, false));
     v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x141, 0xF, 0xF, false));
     v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x140, 0xF, 0xF, false));
     const uint32_t r0 = __builtin_amdgcn_readlane(v, 0), r1 = __builtin_amdgcn_readlane(v, 16);
     const uint32_t r2 = __builtin_amdgcn_readlane(v, 32), r3 = __builtin_amdgcn_readlane(v, 48);
-    return max(max(r0, r1), max(r2, r3));
+    if constexpr (SYS == 1)
+        return max(max(r0, r1), max(r2, r3));
+    else
+        return half ? max(r2, r3) : max(r0, r1);
+}
+
+// Row stride (doubles) of the pivot-row buffers: NB + R + 1 values, padded
+// so that the two buffers of a paired wavefront start at least four LDS
+// banks apart and their same-index reads do not collide.
+constexpr int row_stride(int NB, int R, int SYS) {
+    int rs = NB + R + 1;
+    if (SYS == 2)
+        while ((2 * rs) % 64 < 8 || (2 * rs) % 64 > 56) ++rs;
+    return rs;
 }
 
 // 1/x to within about an ulp: the hardware estimate (about 2^-23 relative
@@ -386,24 +400,26 @@ __device__ __forceinline__ void wave_lds_sync() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// One wavefront solves the local system of one owner node s,
-// Phi w = phi(p) (eqs. rbf_interp_set_augmented and shape_vector), for every
-// departure point that uses the stencil of s, by Gauss-Jordan elimination with
-// partial pivoting. Lane r holds row r of the system (K RBF rows, M polynomial
-// rows, then identity rows that pad the system to NB unknowns) in registers.
-// Rows are never moved: the pivot of column k is a not-yet-used lane with the
-// largest |a_k|, compared on the upper 32 bits of its binary64 encoding
-// (exponent and 20 mantissa bits, so within a factor 1 + 2^-20 of the largest,
-// which keeps the growth bound of partial pivoting; ties: lowest lane). It
-// copies its row and its reciprocal 1/a_k to LDS, and every other lane, pivot
-// rows of earlier steps included, subtracts its multiple of that row and
-// keeps the multiplier in a_k. At the end the pivot row of step j holds
-// a_j x_j = b, so unknown j (the weight of stencil member j, j < K) is one
-// product with the kept reciprocal away, with no back substitution. The
+// One wavefront solves the local systems of SYS owner nodes (SYS = 2 when a
+// system has at most 32 unknowns: lanes 0-31 and 32-63 then hold one system
+// each), Phi w = phi(p) (eqs. rbf_interp_set_augmented and shape_vector) of
+// owner s for every departure point that uses the stencil of s, by
+// Gauss-Jordan elimination with partial pivoting. Lane r of a system's group
+// holds row r of the system (K RBF rows, M polynomial rows, then identity
+// rows that pad the system to NB unknowns) in registers. Rows are never
+// moved: the pivot of column k is a not-yet-used lane with the largest |a_k|,
+// compared on the upper 32 bits of its binary64 encoding (exponent and 20
+// mantissa bits, so within a factor 1 + 2^-20 of the largest, which keeps the
+// growth bound of partial pivoting; ties: lowest lane). It copies its row and
+// its reciprocal 1/a_k to its group's LDS buffer, and every other lane of the
+// group, pivot rows of earlier steps included, subtracts its multiple of that
+// row and keeps the multiplier in a_k. At the end the pivot row of step j
+// holds a_j x_j = b, so unknown j (the weight of stencil member j, j < K) is
+// one product with the kept reciprocal away, with no back substitution. The
 // right-hand sides (departure points) are taken R at a time: the first group
 // is eliminated along with the matrix, later groups by replaying the stored
 // multipliers.
-template <int NB, int R>
+template <int NB, int R, int SYS>
 __device__ __forceinline__ void rbf_solve(const Geo *__restrict__ geo,
                                           const double *__restrict__ xs,
                                           const double *__restrict__ ys,
@@ -411,44 +427,58 @@ __device__ __forceinline__ void rbf_solve(const Geo *__restrict__ geo,
                                           const int32_t *__restrict__ nbr, RhsList L, int n,
                                           int K, int m, double dx, double *__restrict__ W64,
                                           int32_t *__restrict__ dev_err) {
+    static_assert(SYS == 1 || (SYS == 2 && NB <= 32), "two systems need 32 lanes each");
+    constexpr int LW = 64 / SYS;                   // lanes per system
+    constexpr int KT = SYS == 2 ? 32 : kMaxK;      // table rows per system
     constexpr int MP = 15;   // monomials of degree <= 4 (table row stride, odd)
-    __shared__ double s_row[4][NB + R + 1];
+    constexpr int RS = row_stride(NB, R, SYS);
+    __shared__ double s_row[4][SYS * RS];
     __shared__ double2 s_c[4][64];
-    __shared__ double s_P[4][kMaxK * MP];
-    __shared__ double2 s_q[4][R];
-    __shared__ int2 s_pk[4][R];
+    __shared__ double s_P[4][SYS * KT * MP];
+    __shared__ double2 s_q[4][SYS * R];
+    __shared__ int2 s_pk[4][SYS * R];
     const int lane = threadIdx.x & 63;
+    const int half = SYS == 2 ? lane >> 5 : 0;     // this lane's system
+    const int ll = lane & (LW - 1);                // row within it
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int64_t wave = (int64_t)blockIdx.x * 4 + wv;
-    if (wave >= n) return;   // uniform across the wavefront
-    const int s = (int)wave;
-    const int count = L.ptr ? L.ptr[s + 1] - L.ptr[s] : 8;
-    if (count == 0) return;
+    const int64_t s0 = ((int64_t)blockIdx.x * 4 + wv) * SYS;
+    if (s0 >= n) return;   // uniform across the wavefront
+    // a group past the last node solves its neighbour's system again and
+    // stores nothing
+    const bool live = s0 + half < n;
+    const int s = (int)(live ? s0 + half : s0);
+    const int count = live ? (L.ptr ? L.ptr[s + 1] - L.ptr[s] : 8) : 0;
+    int cmax = __builtin_amdgcn_readlane(count, 0);
+    if constexpr (SYS == 2) cmax = max(cmax, __builtin_amdgcn_readlane(count, 32));
+    if (cmax == 0) return;
     const Geo g = *geo;
     const int M = (m + 1) * (m + 2) / 2;
     const int nn = K + M;
-    double *row = s_row[wv];
-    double *P = s_P[wv];
+    double *row = s_row[wv] + half * RS;
+    double *P = s_P[wv] + half * KT * MP;
+    const double2 *cw = s_c[wv] + half * LW;
+    double2 *qw = s_q[wv] + half * R;
+    int2 *pkw = s_pk[wv] + half * R;
 
     // stencil member coordinates relative to the centre s, scaled by the
     // stencil radius (the interpolant is invariant to this; it helps the
     // conditioning)
     double rx = 0.0, ry = 0.0;
-    if (lane < K) {
-        int q = nbr[(int64_t)lane * n + s];
+    if (ll < K) {
+        int q = nbr[(int64_t)ll * n + s];
         rx = min_image(xs[q] - xs[s], g.Lx);
         ry = min_image(ys[q] - ys[s], g.Ly);
     }
     double rad = sqrt(rx * rx + ry * ry);
 #pragma unroll
-    for (int off = 32; off > 0; off >>= 1) rad = fmax(rad, __shfl_xor(rad, off));
+    for (int off = LW / 2; off > 0; off >>= 1) rad = fmax(rad, __shfl_xor(rad, off));
     if (!(rad > 0.0)) rad = 1.0;
     const double sx = rx / rad, sy = ry / rad;
     s_c[wv][lane] = make_double2(sx, sy);
     // monomials of each member (eq. poly_sets, graded order 1, x, y, x^2, xy,
     // y^2, x^3, ..., y^4: monomial q of degree d at offset j is x^(d-j) y^j),
-    // row `lane` of the table
-    if (lane < K) {
+    // row `ll` of the table
+    if (ll < K) {
         double xp[5], yp[5];
         xp[0] = yp[0] = 1.0;
 #pragma unroll
@@ -460,23 +490,23 @@ __device__ __forceinline__ void rbf_solve(const Geo *__restrict__ geo,
 #pragma unroll
         for (int d = 0; d <= 4; ++d)
 #pragma unroll
-            for (int j = 0; j <= d; ++j) P[lane * MP + q++] = xp[d - j] * yp[j];
+            for (int j = 0; j <= d; ++j) P[ll * MP + q++] = xp[d - j] * yp[j];
     }
     wave_lds_sync();
-    const bool rbf_row = lane < K;
-    const bool poly_row = lane >= K && lane < nn;
-    const int qrow = lane - K;
+    const bool rbf_row = ll < K;
+    const bool poly_row = ll >= K && ll < nn;
+    const int qrow = ll - K;
     // table entries this lane reads: polynomial q of every member (polynomial
     // rows), every polynomial of its own member (RBF rows)
     const int pcol = poly_row ? qrow : 0;
-    const int prow = (rbf_row ? lane : 0) * MP - K;
+    const int prow = (rbf_row ? ll : 0) * MP - K;
 
-    // row `lane` of the padded system; the branches on the column are uniform
+    // row `ll` of the padded system; the branches on the column are uniform
     double a[NB];
 #pragma unroll
     for (int c = 0; c < NB; ++c) {
         if (c < K) {
-            const double2 cc = s_c[wv][c];
+            const double2 cc = cw[c];
             const double r3 = cube_dist(sx, sy, cc.x, cc.y);
             const double pc = P[c * MP + pcol];
             a[c] = rbf_row ? r3 : (poly_row ? pc : 0.0);
@@ -484,49 +514,49 @@ __device__ __forceinline__ void rbf_solve(const Geo *__restrict__ geo,
             const double pr = P[prow + c];
             a[c] = rbf_row ? pr : 0.0;
         } else {
-            a[c] = c == lane ? 1.0 : 0.0;
+            a[c] = c == ll ? 1.0 : 0.0;
         }
     }
     // infinity norm for the singularity threshold
     double rs = 0.0;
 #pragma unroll
     for (int c = 0; c < NB; ++c) rs += fabs(a[c]);
-    if (lane >= NB) rs = 0.0;
+    if (ll >= NB) rs = 0.0;
 #pragma unroll
-    for (int off = 32; off > 0; off >>= 1) rs = fmax(rs, __shfl_xor(rs, off));
+    for (int off = LW / 2; off > 0; off >>= 1) rs = fmax(rs, __shfl_xor(rs, off));
     const double tiny = 1e3 * DBL_EPSILON * rs;
     bool singular = false;
     // elimination step at which this lane was the pivot (-1: padding lane)
     // and the reciprocal of its pivot value
-    int pstep = lane < NB ? NB : -1;
+    int pstep = ll < NB ? NB : -1;
     double pinv = 1.0;
 
-    // right-hand sides c0 .. c0+R-1 (row `lane` of each). Lane t < R first
-    // locates departure point c0 + t (node p, direction k) and its position
-    // x_p - e_k dx relative to s, scaled, for the whole wavefront.
+    // right-hand sides c0 .. c0+R-1 (row `ll` of each). Lane t < R of each
+    // group first locates departure point c0 + t (node p, direction k) and its
+    // position x_p - e_k dx relative to s, scaled, for the whole group.
     const double irad = 1.0 / rad;
     // exponents of monomial qrow (degree qd, offset qey within it)
     const int qd = (qrow >= 1) + (qrow >= 3) + (qrow >= 6) + (qrow >= 10);
     const int qey = poly_row ? qrow - qd * (qd + 1) / 2 : 0;
     const int qex = poly_row ? qd - qey : 0;
     auto load_rhs = [&](int c0, double(&b)[R]) {
-        if (lane < R) {
+        if (ll < R) {
             double qx = 0.0, qy = 0.0;
             int p = 0, k = 1;
-            if (c0 + lane < count) {
-                rhs_point(L, s, c0 + lane, p, k);
+            if (c0 + ll < count) {
+                rhs_point(L, s, c0 + ll, p, k);
                 qx = (L.ptr ? min_image(xs[p] - lat_ex(k) * dx - xs[s], g.Lx)
                             : -lat_ex(k) * dx) * irad;
                 qy = (L.ptr ? min_image(ys[p] - lat_ey(k) * dx - ys[s], g.Ly)
                             : -lat_ey(k) * dx) * irad;
             }
-            s_q[wv][lane] = make_double2(qx, qy);
-            s_pk[wv][lane] = make_int2(p, k);
+            qw[ll] = make_double2(qx, qy);
+            pkw[ll] = make_int2(p, k);
         }
         wave_lds_sync();
 #pragma unroll
         for (int t = 0; t < R; ++t) {
-            const double2 q = s_q[wv][t];
+            const double2 q = qw[t];
             const double r3 = cube_dist(sx, sy, q.x, q.y);
             const double pq = pow_upto4(q.x, qex) * pow_upto4(q.y, qey);
             b[t] = c0 + t < count ? (rbf_row ? r3 : (poly_row ? pq : 0.0)) : 0.0;
@@ -539,7 +569,7 @@ __device__ __forceinline__ void rbf_solve(const Geo *__restrict__ geo,
 #pragma unroll
             for (int t = 0; t < R; ++t) {
                 if (c0 + t < count) {
-                    const int2 pk = s_pk[wv][t];
+                    const int2 pk = pkw[t];
                     W64[w64_at(pk.y, pstep, n, pk.x)] = b[t] * pinv;
                 }
             }
@@ -554,8 +584,17 @@ __device__ __forceinline__ void rbf_solve(const Geo *__restrict__ geo,
         const uint32_t key =
             pstep > k ? ((uint32_t)(__double_as_longlong(a[k]) >> 32) & 0x7FFFFFFFu) | 1u : 0u;
         const double rk = recip(a[k]);
-        const uint32_t km = wave_max_u32(key);
-        const int pl = __builtin_amdgcn_readfirstlane(__builtin_ctzll(__ballot(key == km)));
+        const uint32_t km = group_max_u32<SYS>(key, half);
+        // every group has an open lane (NB - k of them), so its mask is not empty
+        const uint64_t hit = __ballot(key == km);
+        int pl;
+        if constexpr (SYS == 1) {
+            pl = __builtin_amdgcn_readfirstlane(__builtin_ctzll(hit));
+        } else {
+            const int pa = __builtin_amdgcn_readfirstlane(__builtin_ctz((uint32_t)hit));
+            const int pb = __builtin_amdgcn_readfirstlane(32 + __builtin_ctz((uint32_t)(hit >> 32)));
+            pl = half ? pb : pa;
+        }
         if (lane == pl) {
 #pragma unroll
             for (int c = k; c < NB; ++c) row[c] = a[c];
@@ -583,7 +622,7 @@ __device__ __forceinline__ void rbf_solve(const Geo *__restrict__ geo,
     }
     store(0, b);
     // further groups: replay the stored multipliers
-    for (int c0 = R; c0 < count; c0 += R) {
+    for (int c0 = R; c0 < cmax; c0 += R) {
         load_rhs(c0, b);
 #pragma unroll
         for (int k = 0; k < NB; ++k) {
@@ -600,20 +639,20 @@ __device__ __forceinline__ void rbf_solve(const Geo *__restrict__ geo,
         }
         store(c0, b);
     }
-    if (singular && lane == 0) atomicMin(dev_err, perm[s] + 1);
+    if (singular && live && ll == 0) atomicMin(dev_err, perm[s] + 1);
 }
 
 // Occupancy against registers: 24 unknowns fit four wavefronts per SIMD and
 // 32 three (a few registers spill, which costs less than the latency fewer
-// wavefronts leave exposed); 48 unknowns keep two, since the spills a third
-// would need cost what it gains; 64 unknowns need the whole register file of
-// one wavefront.
-template <int NB, int R, int WPE>
+// wavefronts leave exposed); both pair two systems per wavefront. 48 unknowns
+// keep two wavefronts, since the spills a third would need cost what it
+// gains; 64 unknowns need the whole register file of one wavefront.
+template <int NB, int R, int WPE, int SYS>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) void k_rbf(
     const Geo *__restrict__ geo, const double *__restrict__ xs, const double *__restrict__ ys,
     const int32_t *__restrict__ perm, const int32_t *__restrict__ nbr, RhsList L, int n, int K,
     int m, double dx, double *__restrict__ W64, int32_t *__restrict__ dev_err) {
-    rbf_solve<NB, R>(geo, xs, ys, perm, nbr, L, n, K, m, dx, W64, dev_err);
+    rbf_solve<NB, R, SYS>(geo, xs, ys, perm, nbr, L, n, K, m, dx, W64, dev_err);
 }
 
 template <int NB, int R>
@@ -621,7 +660,7 @@ __global__ __launch_bounds__(256) void k_rbf_wide(
     const Geo *__restrict__ geo, const double *__restrict__ xs, const double *__restrict__ ys,
     const int32_t *__restrict__ perm, const int32_t *__restrict__ nbr, RhsList L, int n, int K,
     int m, double dx, double *__restrict__ W64, int32_t *__restrict__ dev_err) {
-    rbf_solve<NB, R>(geo, xs, ys, perm, nbr, L, n, K, m, dx, W64, dev_err);
+    rbf_solve<NB, R, 1>(geo, xs, ys, perm, nbr, L, n, K, m, dx, W64, dev_err);
 }
 
 // Owner -> departure-point lists of the paper's stencil rule (CSR): count,
@@ -792,11 +831,12 @@ template <int NB>
 static hipError_t launch_rbf_nb(const Geo *geo, const double *xs, const double *ys,
                                 const int32_t *perm, const int32_t *nbr, RhsList L, int n, int K,
                                 int m, double dx, double *W64, int32_t *dev_err, hipStream_t s) {
-    dim3 grid(blocks_for(n, 4)), block(256);
     constexpr int wpe = NB == 24 ? 4 : NB == 32 ? 3 : 2;
+    constexpr int sys = NB <= 32 ? 2 : 1;   // systems per wavefront
+    dim3 grid(blocks_for(n, 4 * sys)), block(256);
     if constexpr (NB <= 48)
-        hipLaunchKernelGGL((k_rbf<NB, 8, wpe>), grid, block, 0, s, geo, xs, ys, perm, nbr, L, n, K,
-                           m, dx, W64, dev_err);
+        hipLaunchKernelGGL((k_rbf<NB, 8, wpe, sys>), grid, block, 0, s, geo, xs, ys, perm, nbr, L,
+                           n, K, m, dx, W64, dev_err);
     else
         hipLaunchKernelGGL((k_rbf_wide<NB, 8>), grid, block, 0, s, geo, xs, ys, perm, nbr, L, n,
                            K, m, dx, W64, dev_err);
