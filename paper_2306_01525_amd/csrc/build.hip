@@ -688,29 +688,47 @@ __global__ void k_set_last(int32_t *ptr, int n, int32_t v) { ptr[n] = v; }
 // (node, direction) no longer sum to one; the defect 1 - sum (evaluated in
 // FP64) is added to one weight, the smallest in magnitude among those at least
 // 64 times larger than the defect, so the rounded weights keep the partition
-// of unity that the deviation-stored populations rely on.
-__global__ void k_pack_w32(const double *__restrict__ W64, int n, int K, float *__restrict__ W32) {
-    int p = blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= n) return;
-    for (int k = 1; k < kQ; ++k) {
-        double sum = 0.0;
-        for (int j = 0; j < K; ++j) sum += (double)(float)W64[w64_at(k, j, n, p)];
-        const double defect = 1.0 - sum;
-        int jstar = -1;
-        double best = DBL_MAX;
-        for (int j = 0; j < K; ++j) {
-            double a = fabs(W64[w64_at(k, j, n, p)]);
-            if (a >= 64.0 * fabs(defect) && a < best) {
-                best = a;
-                jstar = j;
-            }
+// of unity that the deviation-stored populations rely on. One thread per
+// (node, direction), numbered like the inner [4][n][2] part of the FP64
+// layout so that each of its K loads is coalesced; the weights stay in
+// registers between the three passes.
+template <int KB>
+__global__ __launch_bounds__(256) void k_pack_w32(const double *__restrict__ W64, int n, int K,
+                                                  float *__restrict__ W32) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (int64_t)8 * n) return;
+    const int64_t plane = (int64_t)8 * n;   // distance between members j and j+1
+    const int h = (int)(t & 1);
+    const int64_t pk = t >> 1;
+    const int kk = (int)(pk / n);
+    const int p = (int)(pk - (int64_t)kk * n);
+    const int k = 2 * kk + h + 1;
+    double w[KB];
+    double sum = 0.0;
+#pragma unroll
+    for (int j = 0; j < KB; ++j) {
+        w[j] = j < K ? W64[j * plane + t] : 0.0;
+        sum += (double)(float)w[j];
+    }
+    const double defect = 1.0 - sum;
+    int jstar = -1;
+    double best = DBL_MAX;
+#pragma unroll
+    for (int j = 0; j < KB; ++j) {
+        const double a = fabs(w[j]);
+        if (j < K && a >= 64.0 * fabs(defect) && a < best) {
+            best = a;
+            jstar = j;
         }
-        const int h = (k - 1) >> 2, c = (k - 1) & 3;
-        for (int j = 0; j < K; ++j) {
-            double v = W64[w64_at(k, j, n, p)];
-            float f = (float)v;
+    }
+    const int hh = (k - 1) >> 2, c = (k - 1) & 3;
+    float *out = W32 + ((int64_t)hh * n + p) * 4 + c;
+#pragma unroll
+    for (int j = 0; j < KB; ++j) {
+        if (j < K) {
+            float f = (float)w[j];
             if (j == jstar) f = (float)((double)f + defect);
-            W32[(((int64_t)j * 2 + h) * n + p) * 4 + c] = f;
+            out[(int64_t)j * 8 * n] = f;
         }
     }
 }
@@ -886,7 +904,13 @@ hipError_t launch_rbf(const Geo *geo, const double *xs, const double *ys,
 }
 
 hipError_t launch_pack_w32(const double *W64, int n, int K, float *W32, hipStream_t s) {
-    hipLaunchKernelGGL(k_pack_w32, dim3(blocks_for(n, 256)), dim3(256), 0, s, W64, n, K, W32);
+    const dim3 grid(blocks_for((int64_t)8 * n, 256)), block(256);
+    if (K <= 16)
+        hipLaunchKernelGGL(k_pack_w32<16>, grid, block, 0, s, W64, n, K, W32);
+    else if (K <= 32)
+        hipLaunchKernelGGL(k_pack_w32<32>, grid, block, 0, s, W64, n, K, W32);
+    else
+        hipLaunchKernelGGL(k_pack_w32<kMaxK>, grid, block, 0, s, W64, n, K, W32);
     return hipGetLastError();
 }
 

@@ -46,6 +46,29 @@ __device__ void bitonic_sort(int *a, int npow2) {
     }
 }
 
+// Exclusive prefix sum of v over the workgroup (at most 16 wavefronts), and
+// the sum of all v in `total`. Every thread of the workgroup must call it.
+__device__ int block_scan_excl(int v, int *s_wsum, int &total) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    int x = v;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const int y = __shfl_up(x, off);
+        if (lane >= off) x += y;
+    }
+    if (lane == 63) s_wsum[w] = x;
+    __syncthreads();
+    int before = 0, all = 0;
+    for (int i = 0; i < nw; ++i) {
+        const int c = s_wsum[i];
+        before += i < w ? c : 0;
+        all += c;
+    }
+    __syncthreads();
+    total = all;
+    return before + x - v;
+}
+
 // Position of v in the sorted array a[0..len) (v is present).
 __device__ __forceinline__ int lower_bound(const int *a, int len, int v) {
     int lo = 0, hi = len;
@@ -69,6 +92,8 @@ __global__ __launch_bounds__(1024) void k_tiles(int n, int K, int mode,
     __shared__ int hset[kHashSize];
     __shared__ int hsorted[kHashSize];
     __shared__ int s_no, s_nh, s_over, s_fill;
+    __shared__ int s_wsum[16];
+    static_assert(2 * 1024 == kOCand, "two owner candidates per thread");
     const int t = blockIdx.x;
     const int base = t * kTile;
     const int cnt = min(kTile, n - base);
@@ -92,18 +117,22 @@ __global__ __launch_bounds__(1024) void k_tiles(int n, int K, int mode,
     }
     __syncthreads();
     if (mode != MLBM_STENCIL_OWN) bitonic_sort(ocand, kOCand);
-    // unique, in place at the front (serial over a sorted list of 2048 is
-    // cheap next to the rest; done by one wavefront-uniform thread)
-    if (tid == 0) {
-        int w = 0;
-        for (int i = 0; i < kOCand; ++i) {
-            const int v = ocand[i];
-            if (v == INT_MAX) break;
-            if (w == 0 || ocand[w - 1] != v) ocand[w++] = v;
-        }
-        s_no = w;
+    // unique: thread tid keeps entries 2 tid and 2 tid + 1 where they differ
+    // from their predecessor, and a block scan of the kept counts gives their
+    // positions (compacted through hsorted, unused until H_t is sorted)
+    {
+        const int e0 = 2 * tid, v0 = ocand[e0], v1 = ocand[e0 + 1];
+        const int k0 = v0 != INT_MAX && (e0 == 0 || ocand[e0 - 1] != v0);
+        const int k1 = v1 != INT_MAX && v1 != v0;
+        int total;
+        const int pos = block_scan_excl(k0 + k1, s_wsum, total);
+        if (k0) hsorted[pos] = v0;
+        if (k1) hsorted[pos + k0] = v1;
+        __syncthreads();
+        for (int i = tid; i < total; i += blockDim.x) ocand[i] = hsorted[i];
+        if (tid == 0) s_no = total;
+        __syncthreads();
     }
-    __syncthreads();
     const int no = s_no;
     bool fits = no <= ocap;
 
