@@ -175,12 +175,17 @@ mlbm_status mlbm_plan_get_info(const mlbm_plan *plan, mlbm_plan_info *info);
  *        8 capacities int32 [2] (ocap, hcap),
  *        9 adjoint tile descriptors int32 [ntiles] (|I_t|; 0 = global path),
  *       10 inverse halo lists int32 [ntiles][hcap] (internal indices),
- *       11 adjoint local columns uint32 [ceil((K+4)/3)][2][n][4]: positions
- *          in I_t of entries 3w, 3w+1, 3w+2 of transposed row k-1 = 4h + q
- *          at [w][h][m][q] (bits as in item 6),
+ *       11 adjoint local columns uint32 [ceil((K+4)/3) * n64][8]: positions
+ *          in I_t of entries 3w, 3w+1, 3w+2 of transposed row k-1 of node m
+ *          (bits as in item 6), compacted like item 13 over triples w (node
+ *          m takes part in triple w when 3w < hd(m)),
  *       12 transposed row pointers int32 [8n+1] (row (k-1)n + m),
- *       13 transposed row heads int32 [K+4][2][n][4] (internal indices,
- *          entry e of row k-1 = 4h + q at [e][h][m][q]; m past the row end).
+ *       13 transposed row heads int32 [(K+4) * n64][8], n64 = n rounded up
+ *          to a multiple of 64 (internal indices). Nodes are grouped by 64;
+ *          hd(m) = max over the 8 rows of node m of min(length, K+4). Group g
+ *          starts at unit g*64*(K+4), and its slot e = 0, 1, ... holds one
+ *          unit for each node of the group with hd > e, in node order; unit
+ *          entry k-1 is entry e of row k-1 of that node (m past the row end).
  * Items 4-8 describe the gather tables of the LDS-staged steps and items 9-13
  * those of the adjoint step (internal layout; 9-13 need with_adjoint).
  * Cloud `cloud`; dst_bytes must match exactly. */

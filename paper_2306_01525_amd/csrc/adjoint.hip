@@ -103,27 +103,59 @@ __global__ __launch_bounds__(256) void k_tr_sort(int64_t rows, const int32_t *__
 
 __global__ void k_set_i32(int32_t *p, int32_t v) { *p = v; }
 
-// Index of slot e of transposed row k (0..7) of node m in the slot-major,
-// direction-interleaved arrays [slot][2][n][4]: one lane reads the four
-// directions of a half as one 16-byte (FP32) vector, as the forward weights.
-__device__ __forceinline__ int64_t ell_at(int64_t e, int k, int n, int m) {
-    return ((e * 2 + (k >> 2)) * n + m) * 4 + (k & 3);
+// Row heads of the transposed operator, compacted per group of 64 nodes (one
+// wavefront, consecutive internal indices). Node m's head length is
+//   hd(m) = max over its eight rows of min(row length, lw),
+// and slot e of a group holds, in node order, one unit for each node of the
+// group with hd > e: the eight rows' entry e (directions 1-4 and 5-8 as two
+// 16-byte FP32 vectors, as the forward weights; zero weight and column m past
+// a row's end). The group's slots follow one another from unit g * 64 * lw.
+// A wavefront walking slots in order finds its units with a ballot: the
+// active lanes of slot e are consecutive units, so every load is coalesced,
+// and the lines fetched hold only nodes that use them. The 10-bit local
+// columns of the inverse halo are compacted the same way over triples of
+// slots (a node takes part in triple w when 3w < hd), from unit g * 64 * lw3.
+// Number of lanes below this one whose bit is set in the wavefront mask.
+__device__ __forceinline__ int lanes_below(uint64_t mask) {
+    return (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
+                                          __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
 }
 
-// Slot-major copy of the first lw entries of every sorted CSR row. Slots past
-// the end of a row hold weight 0 and column m (local position 0).
+// Compacted copy of the first lw entries of every sorted CSR row: one lane
+// per node, whole wavefronts per group (lanes past the last node take part
+// in the ballots with hd = 0).
 template <class T>
-__global__ void k_ell_fill(int n, int lw, const int32_t *__restrict__ ptr,
-                           const int32_t *__restrict__ col, const T *__restrict__ val,
-                           int32_t *__restrict__ ecol, T *__restrict__ eval) {
-    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (r >= (int64_t)8 * n) return;
-    const int m = (int)(r % n), k = (int)(r / n);
-    const int b = ptr[r], len = ptr[r + 1] - b;
+__global__ __launch_bounds__(256) void k_ell_fill(int n, int lw, const int32_t *__restrict__ ptr,
+                                                  const int32_t *__restrict__ col,
+                                                  const T *__restrict__ val,
+                                                  int32_t *__restrict__ ecol, T *__restrict__ eval) {
+    const int m = blockIdx.x * blockDim.x + threadIdx.x;
+    int b[8], len[8], hd = 0;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        b[k] = len[k] = 0;
+        if (m < n) {
+            const int64_t row = (int64_t)k * n + m;
+            b[k] = ptr[row];
+            len[k] = ptr[row + 1] - b[k];
+            hd = max(hd, min(len[k], lw));
+        }
+    }
+    const int64_t g0 = (int64_t)(m >> 6) * 64 * lw;
+    int64_t off = 0;
     for (int e = 0; e < lw; ++e) {
-        const int64_t dst = ell_at(e, k, n, m);
-        ecol[dst] = e < len ? col[b + e] : (int32_t)m;
-        eval[dst] = e < len ? val[b + e] : (T)0;
+        const bool on = e < hd;
+        const uint64_t mask = __ballot(on);
+        if (mask == 0) break;
+        if (on) {
+            const int64_t u = (g0 + off + lanes_below(mask)) * 8;
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                ecol[u + k] = e < len[k] ? col[b[k] + e] : (int32_t)m;
+                eval[u + k] = e < len[k] ? val[b[k] + e] : (T)0;
+            }
+        }
+        off += __popcll(mask);
     }
 }
 
@@ -216,7 +248,7 @@ __device__ __forceinline__ int lower_bound_a(const int *a, int len, int v) {
 
 __global__ __launch_bounds__(1024) void k_adj_tiles(int n, int lw, int hcap, int cap,
                                                     const int32_t *__restrict__ ptr,
-                                                    const int32_t *__restrict__ ecol,
+                                                    const int32_t *__restrict__ col,
                                                     int32_t *__restrict__ tdescT,
                                                     int32_t *__restrict__ ilist,
                                                     uint32_t *__restrict__ elocal,
@@ -240,7 +272,7 @@ __global__ __launch_bounds__(1024) void k_adj_tiles(int n, int lw, int hcap, int
         const int m = base + l;
         const int64_t row = (int64_t)k0 * n + m;
         if (sl >= ptr[row + 1] - ptr[row]) continue;
-        const int q = ecol[ell_at(sl, k0, n, m)];
+        const int q = col[ptr[row] + sl];
         uint32_t h = ((uint32_t)q * 2654435761u) >> 20;
         for (int probe = 0; probe < kAHash; ++probe) {
             const int old = atomicCAS(&hset[h], -1, q);
@@ -268,21 +300,42 @@ __global__ __launch_bounds__(1024) void k_adj_tiles(int n, int lw, int hcap, int
         while (np2 < ni) np2 <<= 1;
         bitonic_sort_a(hsorted, np2);
         for (int h = tid; h < ni; h += blockDim.x) ilist[(int64_t)t * hcap + h] = hsorted[h];
-        for (int e = tid; e < 8 * cnt * lw3; e += blockDim.x) {
-            const int k0 = e / (cnt * lw3), r = e - k0 * cnt * lw3;
-            const int l = r / lw3, w = r - l * lw3;
-            const int m = base + l;
-            const int64_t row = (int64_t)k0 * n + m;
-            const int len = ptr[row + 1] - ptr[row];
-            uint32_t word = 0;
-            for (int sft = 0; sft < 3; ++sft) {
-                const int sl = 3 * w + sft;
-                if (sl < lw && sl < len) {
-                    const int q = ecol[ell_at(sl, k0, n, m)];
-                    word |= (uint32_t)lower_bound_a(hsorted, ni, q) << (10 * sft);
+        // local columns, one lane per node of the tile (the first four
+        // wavefronts, one per group of 64 nodes)
+        if (tid < kTile) {
+            const int m = base + tid;
+            int rb[8], len[8], hd = 0;
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                rb[k] = len[k] = 0;
+                if (m < n) {
+                    const int64_t row = (int64_t)k * n + m;
+                    rb[k] = ptr[row];
+                    len[k] = ptr[row + 1] - rb[k];
+                    hd = max(hd, min(len[k], lw));
                 }
             }
-            elocal[ell_at(w, k0, n, m)] = word;
+            const int64_t g0 = (int64_t)(m >> 6) * 64 * lw3;
+            int64_t off = 0;
+            for (int w = 0; w < lw3; ++w) {
+                const bool on = 3 * w < hd;
+                const uint64_t mask = __ballot(on);
+                if (mask == 0) break;
+                if (on) {
+                    const int64_t u = (g0 + off + lanes_below(mask)) * 8;
+                    for (int k = 0; k < 8; ++k) {
+                        uint32_t word = 0;
+                        for (int sft = 0; sft < 3; ++sft) {
+                            const int sl = 3 * w + sft;
+                            if (sl < lw && sl < len[k])
+                                word |= (uint32_t)lower_bound_a(hsorted, ni, col[rb[k] + sl])
+                                        << (10 * sft);
+                        }
+                        elocal[u + k] = word;
+                    }
+                }
+                off += __popcll(mask);
+            }
         }
     }
     if (tid == 0) {
@@ -312,10 +365,73 @@ __global__ __launch_bounds__(256) void k_adj_step(
     const uint32_t *__restrict__ elocal, int hcap, double rtau, double rho0, int dev,
     double *__restrict__ part) {
     extern __shared__ __align__(16) unsigned char smem[];
+    typedef T T4 __attribute__((ext_vector_type(4)));
+    typedef uint32_t U4 __attribute__((ext_vector_type(4)));
+    typedef int32_t I4 __attribute__((ext_vector_type(4)));
     const int t = blockIdx.x, tid = threadIdx.x;
     const int m = t * kTile + tid;
     const int ni = tdescT ? tdescT[t] : 0;
     T *L = reinterpret_cast<T *>(smem);   // [8][ni]
+
+    // The eight transposed rows of node m are walked together (eight
+    // independent sums keep many loads in flight); each row is summed in its
+    // sorted order: head (zero-weight padding adds nothing), then the CSR
+    // tail of rows longer than lw. Lanes past the last node walk nothing.
+    T lg[kQ];
+    int bk[8], ln[8], hmax = 0;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        bk[k] = ln[k] = 0;
+        if (m < n) {
+            const int64_t row = (int64_t)k * n + m;
+            bk[k] = ptr[row];
+            ln[k] = ptr[row + 1] - bk[k];
+            hmax = max(hmax, min(ln[k], lw));
+        }
+        lg[k + 1] = 0;
+    }
+    // The heads are compacted per wavefront (64 nodes): slot e holds one unit
+    // for each lane with hmax > e, and a ballot gives this lane's unit; slots
+    // past a row's end hold weight 0. The loads of a triple of slots are
+    // issued together (fetching one triple ahead, or the first one before the
+    // inverse halo is staged, measured slower: it costs a wavefront per SIMD).
+    // A lane past its head (or past the last node) reads its group's first
+    // unit instead (a line the group fetches anyway; one shared address for
+    // every such lane of the grid would be a hot spot) and adds nothing: its
+    // weights are zeroed and its local columns point at position 0.
+    const T4 *ev = reinterpret_cast<const T4 *>(eval);
+    const U4 *elw = reinterpret_cast<const U4 *>(elocal);
+    const int lw3 = (lw + 2) / 3;
+    const int64_t grp = min(m, n - 1) >> 6;   // lanes past the last node: its group
+    const int64_t gv = grp * 64 * lw, gw = grp * 64 * lw3;
+    int64_t voff = 0, woff = 0;
+    int wmax = hmax;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) wmax = max(wmax, __shfl_xor(wmax, off));
+    const int ntrip = (wmax + 2) / 3;
+    struct Triple {
+        U4 wa, wb;
+        T4 va[3], vb[3];
+    };
+    auto fetch = [&](int w, Triple &tr) {
+        const bool onw = 3 * w < hmax;
+        const uint64_t mw = __ballot(onw);
+        const int64_t uw = gw + (onw ? woff + lanes_below(mw) : 0);
+        const U4 wa = elw[2 * uw], wb = elw[2 * uw + 1];
+        tr.wa = onw ? wa : (U4)0;
+        tr.wb = onw ? wb : (U4)0;
+        woff += __popcll(mw);
+#pragma unroll
+        for (int sft = 0; sft < 3; ++sft) {
+            const bool on = 3 * w + sft < hmax;
+            const uint64_t me = __ballot(on);
+            const int64_t u = gv + (on ? voff + lanes_below(me) : 0);
+            const T4 va = ev[2 * u], vb = ev[2 * u + 1];
+            tr.va[sft] = on ? va : (T4)0;
+            tr.vb[sft] = on ? vb : (T4)0;
+            voff += __popcll(me);
+        }
+    };
     if (ni > 0) {
         const int32_t *il = ilist + (int64_t)t * hcap;
         for (int h = tid; h < ni; h += kTile) {
@@ -325,58 +441,37 @@ __global__ __launch_bounds__(256) void k_adj_step(
             for (int k = 1; k < kQ; ++k) L[(k - 1) * ni + h] = lam_next[(int64_t)k * n + q];
         }
         __syncthreads();
+        for (int w = 0; w < ntrip; ++w) {
+            Triple cur;
+            fetch(w, cur);
+#pragma unroll
+            for (int sft = 0; sft < 3; ++sft) {
+                const T4 a4 = cur.va[sft], b4 = cur.vb[sft];
+                const U4 wa = cur.wa, wb = cur.wb;
+                const int sh = 10 * sft;
+                lg[1] += a4.x * L[0 * ni + ((wa.x >> sh) & 1023u)];
+                lg[2] += a4.y * L[1 * ni + ((wa.y >> sh) & 1023u)];
+                lg[3] += a4.z * L[2 * ni + ((wa.z >> sh) & 1023u)];
+                lg[4] += a4.w * L[3 * ni + ((wa.w >> sh) & 1023u)];
+                lg[5] += b4.x * L[4 * ni + ((wb.x >> sh) & 1023u)];
+                lg[6] += b4.y * L[5 * ni + ((wb.y >> sh) & 1023u)];
+                lg[7] += b4.z * L[6 * ni + ((wb.z >> sh) & 1023u)];
+                lg[8] += b4.w * L[7 * ni + ((wb.w >> sh) & 1023u)];
+            }
+        }
     }
     double dt = 0.0;
     if (m < n) {
-        // The eight transposed rows of node m are walked together (eight
-        // independent sums keep many loads in flight); each row is summed in
-        // its sorted order: slot-major head (zero-weight padding adds nothing),
-        // then the CSR tail of rows longer than lw.
-        T lg[kQ];
         lg[0] = lam_next[m];
-        int bk[8], ln[8], hmax = 0;
-#pragma unroll
-        for (int k = 0; k < 8; ++k) {
-            const int64_t row = (int64_t)k * n + m;
-            bk[k] = ptr[row];
-            ln[k] = ptr[row + 1] - bk[k];
-            const int hd = ln[k] < lw ? ln[k] : lw;
-            hmax = hd > hmax ? hd : hmax;
-            lg[k + 1] = 0;
-        }
-        // slots past a row's end hold weight 0: every lane walks its longest row
-        typedef T T4 __attribute__((ext_vector_type(4)));
-        typedef uint32_t U4 __attribute__((ext_vector_type(4)));
-        typedef int32_t I4 __attribute__((ext_vector_type(4)));
-        const int64_t hs = (int64_t)n * 4;   // stride of one half of a slot
-        if (ni > 0) {
-            const U4 *elw = reinterpret_cast<const U4 *>(elocal) + m;
-            for (int w = 0; 3 * w < hmax; ++w) {
-                const U4 wa = elw[(int64_t)(2 * w) * n], wb = elw[(int64_t)(2 * w + 1) * n];
-#pragma unroll
-                for (int sft = 0; sft < 3; ++sft) {
-                    const int e = 3 * w + sft;
-                    if (e < hmax) {
-                        const T4 va = *reinterpret_cast<const T4 *>(eval + 2 * e * hs + m * 4);
-                        const T4 vb = *reinterpret_cast<const T4 *>(eval + (2 * e + 1) * hs + m * 4);
-                        const int sh = 10 * sft;
-                        lg[1] += va.x * L[0 * ni + ((wa.x >> sh) & 1023u)];
-                        lg[2] += va.y * L[1 * ni + ((wa.y >> sh) & 1023u)];
-                        lg[3] += va.z * L[2 * ni + ((wa.z >> sh) & 1023u)];
-                        lg[4] += va.w * L[3 * ni + ((wa.w >> sh) & 1023u)];
-                        lg[5] += vb.x * L[4 * ni + ((wb.x >> sh) & 1023u)];
-                        lg[6] += vb.y * L[5 * ni + ((wb.y >> sh) & 1023u)];
-                        lg[7] += vb.z * L[6 * ni + ((wb.z >> sh) & 1023u)];
-                        lg[8] += vb.w * L[7 * ni + ((wb.w >> sh) & 1023u)];
-                    }
-                }
-            }
-        } else {
-            for (int e = 0; e < hmax; ++e) {
-                const T4 va = *reinterpret_cast<const T4 *>(eval + 2 * e * hs + m * 4);
-                const T4 vb = *reinterpret_cast<const T4 *>(eval + (2 * e + 1) * hs + m * 4);
-                const I4 ca = *reinterpret_cast<const I4 *>(ecol + 2 * e * hs + m * 4);
-                const I4 cb = *reinterpret_cast<const I4 *>(ecol + (2 * e + 1) * hs + m * 4);
+        if (ni == 0) {
+            const I4 *ec = reinterpret_cast<const I4 *>(ecol);
+            for (int e = 0; e < lw; ++e) {
+                const bool on = e < hmax;
+                const uint64_t me = __ballot(on);
+                if (me == 0) break;
+                const int64_t u = on ? gv + voff + lanes_below(me) : gv;
+                const T4 va = on ? ev[2 * u] : (T4)0, vb = on ? ev[2 * u + 1] : (T4)0;
+                const I4 ca = ec[2 * u], cb = ec[2 * u + 1];
                 lg[1] += va.x * lam_next[1 * (int64_t)n + ca.x];
                 lg[2] += va.y * lam_next[2 * (int64_t)n + ca.y];
                 lg[3] += va.z * lam_next[3 * (int64_t)n + ca.z];
@@ -385,6 +480,7 @@ __global__ __launch_bounds__(256) void k_adj_step(
                 lg[6] += vb.y * lam_next[6 * (int64_t)n + cb.y];
                 lg[7] += vb.z * lam_next[7 * (int64_t)n + cb.z];
                 lg[8] += vb.w * lam_next[8 * (int64_t)n + cb.w];
+                voff += __popcll(me);
             }
         }
 #pragma unroll
@@ -512,13 +608,13 @@ hipError_t launch_transpose(const CloudPlan &cp, int precision, void *tmp, size_
 }
 
 hipError_t launch_ell_fill(const CloudPlan &cp, int precision, hipStream_t s) {
-    const int64_t rows = (int64_t)8 * cp.n;
+    const dim3 grid(blocks_for(cp.n, 256)), block(256);
     if (precision == MLBM_FP64)
-        hipLaunchKernelGGL(k_ell_fill<double>, dim3(blocks_for(rows, 256)), dim3(256), 0, s, cp.n,
+        hipLaunchKernelGGL(k_ell_fill<double>, grid, block, 0, s, cp.n,
                            cp.tr_lw, cp.tr_ptr, cp.tr_col, (const double *)cp.tr_val, cp.ell_col,
                            (double *)cp.ell_val);
     else
-        hipLaunchKernelGGL(k_ell_fill<float>, dim3(blocks_for(rows, 256)), dim3(256), 0, s, cp.n,
+        hipLaunchKernelGGL(k_ell_fill<float>, grid, block, 0, s, cp.n,
                            cp.tr_lw, cp.tr_ptr, cp.tr_col, (const float *)cp.tr_val, cp.ell_col,
                            (float *)cp.ell_val);
     return hipGetLastError();
@@ -584,7 +680,7 @@ hipError_t launch_init_adjoint(const CloudPlan &cp, int precision, const double 
 hipError_t launch_adj_tiles(const CloudPlan &cp, int32_t *stats, hipStream_t s) {
     const int ntiles = (cp.n + kTile - 1) / kTile;
     hipLaunchKernelGGL(k_adj_tiles, dim3(ntiles), dim3(1024), 0, s, cp.n, cp.tr_lw, cp.hcap,
-                       cp.adj_cap, cp.tr_ptr, cp.ell_col, cp.tdescT, cp.ilist, cp.elocal, stats);
+                       cp.adj_cap, cp.tr_ptr, cp.tr_col, cp.tdescT, cp.ilist, cp.elocal, stats);
     return hipGetLastError();
 }
 

@@ -138,14 +138,15 @@ void layout_cloud(const mlbm_cloud &c, const mlbm_params &p, int precision, Carv
         cp.tr_val = precision == MLBM_FP64 ? (void *)pl.take<double>((size_t)8 * K * n)
                                            : (void *)pl.take<float>((size_t)8 * K * n);
         cp.tr_lw = K + 4;
-        cp.ell_col = pl.take<int32_t>((size_t)8 * cp.tr_lw * n);
+        const size_t hn = (size_t)head_nodes(n);
+        cp.ell_col = pl.take<int32_t>((size_t)8 * cp.tr_lw * hn);
         cp.ell_val = precision == MLBM_FP64
-                         ? (void *)pl.take<double>((size_t)8 * cp.tr_lw * n)
-                         : (void *)pl.take<float>((size_t)8 * cp.tr_lw * n);
+                         ? (void *)pl.take<double>((size_t)8 * cp.tr_lw * hn)
+                         : (void *)pl.take<float>((size_t)8 * cp.tr_lw * hn);
         const int ntiles = (n + kTile - 1) / kTile;
         cp.tdescT = pl.take<int32_t>((size_t)ntiles);
         cp.ilist = pl.take<int32_t>((size_t)ntiles * cp.hcap);
-        cp.elocal = pl.take<uint32_t>((size_t)8 * ((cp.tr_lw + 2) / 3) * n);
+        cp.elocal = pl.take<uint32_t>((size_t)8 * ((cp.tr_lw + 2) / 3) * hn);
         // 8 values of lam per inverse-halo node (64 KiB in FP64 at the cap)
         cp.adj_cap = cp.hcap;
     }
@@ -681,9 +682,9 @@ mlbm_status mlbm_plan_export(const mlbm_plan *plan, int32_t cloud, int32_t what,
                 : what == 8 ? sizeof(int32_t) * 2
                 : what == 9 ? sizeof(int32_t) * ntiles
                 : what == 10 ? sizeof(int32_t) * ntiles * cp.hcap
-                : what == 11 ? sizeof(uint32_t) * 8 * (size_t)((cp.tr_lw + 2) / 3) * n
+                : what == 11 ? sizeof(uint32_t) * 8 * (size_t)((cp.tr_lw + 2) / 3) * head_nodes(n)
                 : what == 12 ? sizeof(int32_t) * ((size_t)8 * n + 1)
-                : what == 13 ? sizeof(int32_t) * 8 * (size_t)cp.tr_lw * n : 0;
+                : what == 13 ? sizeof(int32_t) * 8 * (size_t)cp.tr_lw * head_nodes(n) : 0;
     if (need == 0) return fail(MLBM_EINVAL, "unknown export item");
     if (what >= 9 && !cp.tdescT) return fail(MLBM_EINVAL, "plan was built without with_adjoint");
     if (what >= 4 && what <= 6 && !cp.tdesc) return fail(MLBM_EINVAL, "plan has no tile tables");

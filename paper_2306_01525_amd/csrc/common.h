@@ -43,6 +43,10 @@ __host__ __device__ inline int64_t w64_at(int k, int j, int64_t n, int64_t p) {
     return (((int64_t)j * 4 + ((k - 1) >> 1)) * n + p) * 2 + ((k - 1) & 1);
 }
 constexpr int kMaxK = 48;       // largest stencil supported
+// Nodes rounded up to whole wavefronts: the row heads of the transposed
+// operator are compacted per group of 64 nodes, and each slot of a group has
+// room for all 64.
+inline int64_t head_nodes(int n) { return ((int64_t)n + 63) / 64 * 64; }
 constexpr int kTile = 256;      // nodes per workgroup in the step kernels
 constexpr int kStepVariants = 6; // FP32 step tuning variants
 constexpr int kBuildLanes = 4;   // clouds of one plan built concurrently

@@ -403,8 +403,9 @@ class Plan:
         'tdesc' [ntiles][2], 'hlist' [ntiles][hcap], 'nbrL' [ntiles][ocap][ceil(K/3)]
         (three 10-bit halo positions per word),
         'ownerL' [8][n], 'caps' (ocap, hcap); adjoint tables (with_adjoint) 'tdescT'
-        [ntiles], 'ilist' [ntiles][hcap], 'elocal' [ceil((K+4)/3)][2][n][4], 'tr_ptr'
-        [8n+1], 'ell_col' [K+4][2][n][4] (row k-1 = 4 * half + lane of the quad)."""
+        [ntiles], 'ilist' [ntiles][hcap], 'tr_ptr' [8n+1], and the row heads compacted
+        per group of 64 nodes (see mlbm_plan_export): 'ell_col' [(K+4) n64][8],
+        'elocal' [ceil((K+4)/3) n64][8], n64 = n rounded up to a multiple of 64."""
         import numpy as np
         K = self.params.K
         nt = (self.n + int(self.info.tile_nodes) - 1) // int(self.info.tile_nodes)
@@ -413,6 +414,7 @@ class Plan:
                  "ell_col": 13}
         code = codes[what]
         lw = K + 4
+        n64 = (self.n + 63) // 64 * 64
         if code in (5, 10):
             shape, dt = (nt, int(self.export("caps")[1])), np.int32
         elif code == 6:
@@ -422,9 +424,9 @@ class Plan:
                          2: ((self.n, 9), np.int32), 3: ((self.n, 9, K), np.float64),
                          4: ((nt, 2), np.int32), 7: ((8, self.n), np.uint16),
                          8: ((2,), np.int32), 9: ((nt,), np.int32),
-                         11: (((lw + 2) // 3, 2, self.n, 4), np.uint32),
+                         11: (((lw + 2) // 3 * n64, 8), np.uint32),
                          12: ((8 * self.n + 1,), np.int32),
-                         13: ((lw, 2, self.n, 4), np.int32)}[code]
+                         13: ((lw * n64, 8), np.int32)}[code]
         out = np.empty(shape, dtype=dt)
         check(_lib.load().mlbm_plan_export(self._h, 0, code, out.ctypes.data_as(ctypes.c_void_p),
                                            out.nbytes))
