@@ -380,6 +380,14 @@ constexpr int row_stride(int NB, int R, int SYS) {
     return rs;
 }
 
+// The double in lane l of a wavefront (l uniform), in scalar registers.
+__device__ __forceinline__ double readlane_d(double v, int l) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), l);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+    return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+
 // 1/x to within about an ulp: the hardware estimate (about 2^-23 relative
 // error for the magnitudes met here) refined by two Newton steps r += r(1 - xr),
 // each of which squares the relative error. Zero gives NaN, which the
@@ -578,6 +586,50 @@ __device__ __forceinline__ void rbf_solve(const Geo *__restrict__ geo,
 
     double b[R];
     load_rhs(0, b);
+    if constexpr (SYS == 1) {
+        // One system per wavefront: the pivot row is broadcast through scalar
+        // registers (two lane reads per value, used directly as the scalar
+        // operand of the updates) instead of LDS, which the four SIMDs of a
+        // compute unit share and which every lane would otherwise read the
+        // whole row from. Lane k keeps the pivot lane of step k for the
+        // replay of further groups.
+        int plog = 0;
+#pragma unroll
+        for (int k = 0; k < NB; ++k) {
+            const uint32_t key =
+                pstep > k ? ((uint32_t)(__double_as_longlong(a[k]) >> 32) & 0x7FFFFFFFu) | 1u : 0u;
+            const double rk = recip(a[k]);
+            const uint32_t km = group_max_u32<1>(key, 0);
+            const int pl = __builtin_amdgcn_readfirstlane(__builtin_ctzll(__ballot(key == km)));
+            const double pv = readlane_d(a[k], pl), pi = readlane_d(rk, pl);
+            if (!(fabs(pv) > tiny)) singular = true;
+            if (lane == pl) {
+                pstep = k;
+                pinv = pi;
+            }
+            if (lane == k) plog = pl;
+            const double l = lane != pl ? a[k] * pi : 0.0;
+#pragma unroll
+            for (int c = k + 1; c < NB; ++c) a[c] = __builtin_fma(-l, readlane_d(a[c], pl), a[c]);
+#pragma unroll
+            for (int t = 0; t < R; ++t) b[t] = __builtin_fma(-l, readlane_d(b[t], pl), b[t]);
+            if (lane != pl) a[k] = l;
+        }
+        store(0, b);
+        for (int c0 = R; c0 < cmax; c0 += R) {
+            load_rhs(c0, b);
+#pragma unroll
+            for (int k = 0; k < NB; ++k) {
+                const int pk = __builtin_amdgcn_readlane(plog, k);
+                const double l = lane != pk ? a[k] : 0.0;
+#pragma unroll
+                for (int t = 0; t < R; ++t) b[t] = __builtin_fma(-l, readlane_d(b[t], pk), b[t]);
+            }
+            store(c0, b);
+        }
+        if (singular && live && ll == 0) atomicMin(dev_err, perm[s] + 1);
+        return;
+    }
     // elimination, carrying the first group of right-hand sides
 #pragma unroll
     for (int k = 0; k < NB; ++k) {
