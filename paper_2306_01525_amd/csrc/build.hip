@@ -694,25 +694,16 @@ __device__ __forceinline__ void rbf_solve(const Geo *__restrict__ geo,
     if (singular && live && ll == 0) atomicMin(dev_err, perm[s] + 1);
 }
 
-// Occupancy against registers: 24 unknowns fit four wavefronts per SIMD and
-// 32 three (a few registers spill, which costs less than the latency fewer
-// wavefronts leave exposed); both pair two systems per wavefront. 48 unknowns
-// keep two wavefronts, since the spills a third would need cost what it
-// gains; 64 unknowns need the whole register file of one wavefront.
+// Occupancy against registers: 24 unknowns fit four wavefronts per SIMD, 32
+// and 48 three, 64 two (a few hundred bytes spill at 32, 48 and 64, which
+// costs less than the latency fewer wavefronts leave exposed). Up to 32
+// unknowns a wavefront holds two systems.
 template <int NB, int R, int WPE, int SYS>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) void k_rbf(
     const Geo *__restrict__ geo, const double *__restrict__ xs, const double *__restrict__ ys,
     const int32_t *__restrict__ perm, const int32_t *__restrict__ nbr, RhsList L, int n, int K,
     int m, double dx, double *__restrict__ W64, int32_t *__restrict__ dev_err) {
     rbf_solve<NB, R, SYS>(geo, xs, ys, perm, nbr, L, n, K, m, dx, W64, dev_err);
-}
-
-template <int NB, int R>
-__global__ __launch_bounds__(256) void k_rbf_wide(
-    const Geo *__restrict__ geo, const double *__restrict__ xs, const double *__restrict__ ys,
-    const int32_t *__restrict__ perm, const int32_t *__restrict__ nbr, RhsList L, int n, int K,
-    int m, double dx, double *__restrict__ W64, int32_t *__restrict__ dev_err) {
-    rbf_solve<NB, R, 1>(geo, xs, ys, perm, nbr, L, n, K, m, dx, W64, dev_err);
 }
 
 // Owner -> departure-point lists of the paper's stencil rule (CSR): count,
@@ -901,15 +892,11 @@ template <int NB>
 static hipError_t launch_rbf_nb(const Geo *geo, const double *xs, const double *ys,
                                 const int32_t *perm, const int32_t *nbr, RhsList L, int n, int K,
                                 int m, double dx, double *W64, int32_t *dev_err, hipStream_t s) {
-    constexpr int wpe = NB == 24 ? 4 : NB == 32 ? 3 : 2;
+    constexpr int wpe = NB == 24 ? 4 : NB == 64 ? 2 : 3;
     constexpr int sys = NB <= 32 ? 2 : 1;   // systems per wavefront
     dim3 grid(blocks_for(n, 4 * sys)), block(256);
-    if constexpr (NB <= 48)
-        hipLaunchKernelGGL((k_rbf<NB, 8, wpe, sys>), grid, block, 0, s, geo, xs, ys, perm, nbr, L,
-                           n, K, m, dx, W64, dev_err);
-    else
-        hipLaunchKernelGGL((k_rbf_wide<NB, 8>), grid, block, 0, s, geo, xs, ys, perm, nbr, L, n,
-                           K, m, dx, W64, dev_err);
+    hipLaunchKernelGGL((k_rbf<NB, 8, wpe, sys>), grid, block, 0, s, geo, xs, ys, perm, nbr, L, n,
+                       K, m, dx, W64, dev_err);
     return hipGetLastError();
 }
 
