@@ -61,14 +61,16 @@ def test_build_rejects_bad_parameters():
             Plan.build(c.x, c.y, c.period, p)
 
 
-def test_singular_stencil_is_reported():
-    """Nodes on a straight line make every local system singular
-    (the quadratic monomials are not unisolvent)."""
+@pytest.mark.parametrize("K,m", [(12, 2), (30, 4), (48, 4)])
+def test_singular_stencil_is_reported(K, m):
+    """Nodes on a straight line make every local system singular (the
+    monomials of degree >= 2 are not unisolvent), for each solver shape: two
+    systems per wavefront (24 unknowns) and one (48 and 64)."""
     from paper_2306_01525_amd import MLBMError, Params, Plan
-    n = 40
+    n = 61
     x = np.linspace(0.0, 1.0, n)
     y = 2.0 * x + 0.5
-    p = Params(dx=0.01, K=12, degree=2, tau=0.8, stencil_mode=1)
+    p = Params(dx=0.01, K=K, degree=m, tau=0.8, stencil_mode=1)
     with pytest.raises(MLBMError) as ei:
         Plan.build(x, y, (0.0, 0.0), p)
     assert ei.value.status == -2
