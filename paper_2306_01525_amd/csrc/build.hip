@@ -627,7 +627,7 @@ __device__ __forceinline__ void rbf_solve(const Geo *__restrict__ geo,
             }
             store(c0, b);
         }
-        if (singular && live && ll == 0) atomicMin(dev_err, perm[s] + 1);
+        if (singular && count > 0 && ll == 0) atomicMin(dev_err, perm[s] + 1);
         return;
     }
     // elimination, carrying the first group of right-hand sides
@@ -691,7 +691,9 @@ __device__ __forceinline__ void rbf_solve(const Geo *__restrict__ geo,
         }
         store(c0, b);
     }
-    if (singular && live && ll == 0) atomicMin(dev_err, perm[s] + 1);
+    // a system whose weights no departure point uses (count 0, or a group
+    // past the last node) reports nothing, as if it had not been solved
+    if (singular && count > 0 && ll == 0) atomicMin(dev_err, perm[s] + 1);
 }
 
 // Occupancy against registers: 24 unknowns fit four wavefronts per SIMD, 32
