@@ -456,6 +456,81 @@ def summarize_pmc(fetch_dir, write_dir, command):
     print(json.dumps(out, indent=1))
 
 
+def summarize_traffic(fetch_dir, write_dir, out_path, command):
+    """Per-dispatch HBM bytes of every kernel seen in two rocprofv3 --pmc runs
+    (FETCH_SIZE, WRITE_SIZE), scaled by the same counters read on the copy
+    kernel of known size (run with --copy-calibration); written as a text
+    table, largest kernels first."""
+    def per_kernel(rows, counter):
+        acc = {}
+        for r in rows:
+            if r.get("Counter_Name", "") != counter:
+                continue
+            name = r.get("Kernel_Name", "")
+            did = r.get("Dispatch_Id", str(len(acc.get(name, {}))))
+            acc.setdefault(name, {})
+            acc[name][did] = acc[name].get(did, 0.0) + float(r["Counter_Value"])
+        return {k: sorted(v.values()) for k, v in acc.items()}
+
+    fetch = per_kernel(_read_counter_csv(fetch_dir), "FETCH_SIZE")
+    write = per_kernel(_read_counter_csv(write_dir), "WRITE_SIZE")
+    copy = max((k for k in fetch if "elementwise" in k and "mul" in k.lower()),
+               key=lambda k: len(fetch[k]))
+    med = lambda v: v[len(v) // 2]
+    f_scale = (COPY_BYTES / 1024.0) / med(fetch[copy])
+    w_scale = (COPY_BYTES / 1024.0) / med(write[copy])
+    rows = []
+    for k in fetch:
+        if k not in write or "elementwise" in k:
+            continue
+        fb, wb = med(fetch[k]) * 1024.0 * f_scale, med(write[k]) * 1024.0 * w_scale
+        rows.append((fb + wb, len(fetch[k]), fb, wb, k))
+    rows.sort(reverse=True)
+    lines = ["# HBM bytes per dispatch (median over dispatches) from rocprofv3 FETCH_SIZE and",
+             "# WRITE_SIZE, scaled by the copy kernel of %d bytes: FETCH x %.4f, WRITE x %.4f"
+             % (COPY_BYTES, f_scale, w_scale),
+             "# command: " + command,
+             "%-10s %12s %12s %12s  %s" % ("dispatches", "fetch_MB", "write_MB", "total_MB", "kernel")]
+    for tot, nd, fb, wb, k in rows[:30]:
+        lines.append("%-10d %12.1f %12.1f %12.1f  %s" % (nd, fb / 1e6, wb / 1e6, tot / 1e6, k[:110]))
+    with open(out_path, "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
+def summarize_sq(dirs, kernels, out_path, command):
+    """Per-wavefront SQ counters (sum over the dispatch divided by SQ_WAVES,
+    last dispatch of each kernel) of the named kernels, from one or more
+    rocprofv3 --pmc runs; written as a text table."""
+    per = {}
+    for d in dirs:
+        acc = {}
+        for r in _read_counter_csv(d):
+            name = r.get("Kernel_Name", "")
+            if not any(k in name for k in kernels):
+                continue
+            key = (name, r.get("Dispatch_Id", ""))
+            acc.setdefault(key, {})
+            c = r.get("Counter_Name", "")
+            acc[key][c] = acc[key].get(c, 0.0) + float(r["Counter_Value"])
+        last = {}
+        for (name, did), v in acc.items():
+            if name not in last or int(did or 0) > int(last[name][0] or 0):
+                last[name] = (did, v)
+        for name, (_, v) in last.items():
+            per.setdefault(name, {}).update(v)
+    lines = ["# SQ counters per wavefront (last dispatch of each kernel; counter / SQ_WAVES)",
+             "# command: " + command]
+    for name, v in sorted(per.items()):
+        w = v.get("SQ_WAVES", 0.0) or 1.0
+        lines.append(name[:110])
+        lines.append("  waves %d: " % w + ", ".join("%s %.0f" % (c, x / w)
+                                                  for c, x in sorted(v.items()) if c != "SQ_WAVES"))
+    with open(out_path, "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
 PROFILE_TRACE = os.path.join(ROOT, "profiles", "kernels_bench_default.txt")
 
 
@@ -518,11 +593,23 @@ def main():
     ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
                     help="summarise two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE)")
     ap.add_argument("--pmc-command", default="", help="command recorded in the summary")
+    ap.add_argument("--summarize-traffic", nargs=3, metavar=("FETCH_DIR", "WRITE_DIR", "OUT"),
+                    help="HBM bytes per dispatch of every kernel of two --pmc runs")
+    ap.add_argument("--summarize-sq", nargs="+", metavar="DIR",
+                    help="per-wavefront SQ counters of --sq-kernels from --pmc runs")
+    ap.add_argument("--sq-kernels", default="k_rbf,k_knn,k_adj_step")
+    ap.add_argument("--sq-out", default=os.path.join(ROOT, "profiles", "sq_counters.txt"))
     ap.add_argument("--summarize-trace", metavar="TRACE_DIR",
                     help="summarise a rocprofv3 --kernel-trace --stats run")
     args = ap.parse_args()
     if args.summarize_trace:
         summarize_trace(args.summarize_trace, args.pmc_command)
+        return
+    if args.summarize_traffic:
+        summarize_traffic(*args.summarize_traffic, args.pmc_command)
+        return
+    if args.summarize_sq:
+        summarize_sq(args.summarize_sq, args.sq_kernels.split(","), args.sq_out, args.pmc_command)
         return
     if args.summarize_pmc:
         summarize_pmc(args.summarize_pmc[0], args.summarize_pmc[1], args.pmc_command)

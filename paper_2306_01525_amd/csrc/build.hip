@@ -158,60 +158,69 @@ __global__ void k_fill_i32(int32_t *p, int32_t v, int64_t n) {
 // Ordered insertion of (d, u) into the ascending list held in registers. The
 // live entries occupy the tail of the array; the head holds sentinels with
 // distance -1 that nothing displaces, so the worst live entry is always the
-// last element.
+// last element. Branch-free: entry q of the new list is the old entry q-1
+// when the new pair sorts before it, else the new pair when it sorts before
+// the old entry q, else the old entry q (the comparisons are independent, so
+// the list stays in registers).
 template <int KMAX>
 __device__ __forceinline__ void topk_insert(double (&bd)[KMAX], int (&bu)[KMAX], double d,
                                             int u) {
     if (!(d < bd[KMAX - 1] || (d == bd[KMAX - 1] && u < bu[KMAX - 1]))) return;
-    bool placed = false;
+    bool lt[KMAX];
 #pragma unroll
-    for (int q = KMAX - 1; q >= 0; --q) {
-        if (!placed) {
-            bool before = false;
-            if (q > 0) before = d < bd[q - 1] || (d == bd[q - 1] && u < bu[q - 1]);
-            if (before) {
-                bd[q] = bd[q - 1];
-                bu[q] = bu[q - 1];
-            } else {
-                bd[q] = d;
-                bu[q] = u;
-                placed = true;
-            }
-        }
+    for (int q = 0; q < KMAX; ++q) lt[q] = d < bd[q] || (d == bd[q] && u < bu[q]);
+#pragma unroll
+    for (int q = KMAX - 1; q > 0; --q) {
+        const double dq = lt[q - 1] ? bd[q - 1] : (lt[q] ? d : bd[q]);
+        const int uq = lt[q - 1] ? bu[q - 1] : (lt[q] ? u : bu[q]);
+        bd[q] = dq;
+        bu[q] = uq;
+    }
+    if (lt[0]) {
+        bd[0] = d;
+        bu[0] = u;
     }
 }
 
+// Cell of Chebyshev ring r around (cx, cy) number t (0 <= t < 8r, or t = 0 for
+// r = 0): its index, or -1 where an open axis has no such cell. Periodic axes
+// wrap.
+__device__ __forceinline__ int ring_cell(const Geo &g, int cx, int cy, int r, int t) {
+    const int span = 2 * r + 1;
+    int dx, dy;
+    if (r == 0) {
+        dx = 0;
+        dy = 0;
+    } else if (t < span) {        // bottom row
+        dx = t - r;
+        dy = -r;
+    } else if (t < 2 * span) {    // top row
+        dx = t - span - r;
+        dy = r;
+    } else {                      // left and right columns without corners
+        const int v = t - 2 * span;
+        dx = (v & 1) ? r : -r;
+        dy = (v >> 1) - r + 1;
+    }
+    int ix = cx + dx, iy = cy + dy;
+    if (g.Lx > 0.0) ix = (ix % g.gx + g.gx) % g.gx;
+    else if (ix < 0 || ix >= g.gx) return -1;
+    if (g.Ly > 0.0) iy = (iy % g.gy + g.gy) % g.gy;
+    else if (iy < 0 || iy >= g.gy) return -1;
+    return iy * g.gx + ix;
+}
+
 // Scan the cells of Chebyshev ring r around (cx, cy); `body(q)` runs for every
-// node q in those cells. Periodic axes wrap; cells outside open axes are skipped.
+// node q in those cells.
 template <class F>
 __device__ __forceinline__ void for_ring(const Geo &g, const int32_t *__restrict__ cstart,
                                          const int32_t *__restrict__ cend, int cx, int cy,
                                          int r, F &&body) {
-    const int span = 2 * r + 1;
     const int count = r == 0 ? 1 : 8 * r;
     for (int t = 0; t < count; ++t) {
-        int dx, dy;
-        if (r == 0) {
-            dx = 0;
-            dy = 0;
-        } else if (t < span) {        // bottom row
-            dx = t - r;
-            dy = -r;
-        } else if (t < 2 * span) {    // top row
-            dx = t - span - r;
-            dy = r;
-        } else {                      // left and right columns without corners
-            int u = t - 2 * span;
-            dx = (u & 1) ? r : -r;
-            dy = (u >> 1) - r + 1;
-        }
-        int ix = cx + dx, iy = cy + dy;
-        if (g.Lx > 0.0) ix = (ix % g.gx + g.gx) % g.gx;
-        else if (ix < 0 || ix >= g.gx) continue;
-        if (g.Ly > 0.0) iy = (iy % g.gy + g.gy) % g.gy;
-        else if (iy < 0 || iy >= g.gy) continue;
-        int c = iy * g.gx + ix;
-        int e = cend[c];
+        const int c = ring_cell(g, cx, cy, r, t);
+        if (c < 0) continue;
+        const int e = cend[c];
         for (int q = cstart[c]; q < e; ++q) body(q);
     }
 }
@@ -247,17 +256,24 @@ __global__ __launch_bounds__(256) void k_knn(const Geo *__restrict__ geo,
         bool wraps = (g.Lx > 0.0 && 2 * r + 1 > g.gx) || (g.Ly > 0.0 && 2 * r + 1 > g.gy);
         if (wraps) {  // tiny periodic grid: rings would revisit cells, scan all nodes
 #pragma unroll
-            for (int q = first; q < KMAX; ++q) {
-                bd[q] = DBL_MAX;
-                bu[q] = INT_MAX;
+            for (int q = 0; q < KMAX; ++q) {   // static indices keep the list in registers
+                bd[q] = q < first ? bd[q] : DBL_MAX;
+                bu[q] = q < first ? bu[q] : INT_MAX;
             }
             for (int q = 0; q < n; ++q)
                 if (q != p) topk_insert<KMAX>(bd, bu, dist2(px, py, xs[q], ys[q], g.Lx, g.Ly), perm[q]);
             break;
         }
-        for_ring(g, cstart, cend, cx, cy, r, [&](int q) {
-            if (q != p) topk_insert<KMAX>(bd, bu, dist2(px, py, xs[q], ys[q], g.Lx, g.Ly), perm[q]);
-        });
+        // (the ring is walked here rather than through for_ring, whose
+        // closure would take the list's address)
+        const int count = r == 0 ? 1 : 8 * r;
+        for (int t = 0; t < count; ++t) {
+            const int c = ring_cell(g, cx, cy, r, t);
+            if (c < 0) continue;
+            const int e = cend[c];
+            for (int q = cstart[c]; q < e; ++q)
+                if (q != p) topk_insert<KMAX>(bd, bu, dist2(px, py, xs[q], ys[q], g.Lx, g.Ly), perm[q]);
+        }
         double reach = r * cmin;
         if (bd[KMAX - 1] < reach * reach) break;
         if (r > g.gx && r > g.gy) break;
