@@ -443,7 +443,7 @@ __device__ __forceinline__ void wave_lds_sync() {
 // right-hand sides (departure points) are taken R at a time: the first group
 // is eliminated along with the matrix, later groups by replaying the stored
 // multipliers.
-template <int NB, int R, int SYS>
+template <int NB, int R, int SYS, bool REPLAY>
 __device__ __forceinline__ void rbf_solve(const Geo *__restrict__ geo,
                                           const double *__restrict__ xs,
                                           const double *__restrict__ ys,
@@ -471,6 +471,7 @@ __device__ __forceinline__ void rbf_solve(const Geo *__restrict__ geo,
     // stores nothing
     const bool live = s0 + half < n;
     const int s = (int)(live ? s0 + half : s0);
+    // (without REPLAY every owner has at most R departure points)
     const int count = live ? (L.ptr ? L.ptr[s + 1] - L.ptr[s] : 8) : 0;
     int cmax = __builtin_amdgcn_readlane(count, 0);
     if constexpr (SYS == 2) cmax = max(cmax, __builtin_amdgcn_readlane(count, 32));
@@ -632,7 +633,7 @@ __device__ __forceinline__ void rbf_solve(const Geo *__restrict__ geo,
             if (lane != pl) a[k] = l;
         }
         store(0, b);
-        for (int c0 = R; c0 < cmax; c0 += R) {
+        for (int c0 = R; REPLAY && c0 < cmax; c0 += R) {
             load_rhs(c0, b);
 #pragma unroll
             for (int k = 0; k < NB; ++k) {
@@ -690,7 +691,7 @@ __device__ __forceinline__ void rbf_solve(const Geo *__restrict__ geo,
     }
     store(0, b);
     // further groups: replay the stored multipliers
-    for (int c0 = R; c0 < cmax; c0 += R) {
+    for (int c0 = R; REPLAY && c0 < cmax; c0 += R) {
         load_rhs(c0, b);
 #pragma unroll
         for (int k = 0; k < NB; ++k) {
@@ -716,12 +717,12 @@ __device__ __forceinline__ void rbf_solve(const Geo *__restrict__ geo,
 // and 48 three, 64 two (a few hundred bytes spill at 32, 48 and 64, which
 // costs less than the latency fewer wavefronts leave exposed). Up to 32
 // unknowns a wavefront holds two systems.
-template <int NB, int R, int WPE, int SYS>
+template <int NB, int R, int WPE, int SYS, bool REPLAY>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) void k_rbf(
     const Geo *__restrict__ geo, const double *__restrict__ xs, const double *__restrict__ ys,
     const int32_t *__restrict__ perm, const int32_t *__restrict__ nbr, RhsList L, int n, int K,
     int m, double dx, double *__restrict__ W64, int32_t *__restrict__ dev_err) {
-    rbf_solve<NB, R, SYS>(geo, xs, ys, perm, nbr, L, n, K, m, dx, W64, dev_err);
+    rbf_solve<NB, R, SYS, REPLAY>(geo, xs, ys, perm, nbr, L, n, K, m, dx, W64, dev_err);
 }
 
 // Owner -> departure-point lists of the paper's stencil rule (CSR): count,
@@ -913,8 +914,17 @@ static hipError_t launch_rbf_nb(const Geo *geo, const double *xs, const double *
     constexpr int wpe = NB == 24 ? 4 : NB == 64 ? 2 : 3;
     constexpr int sys = NB <= 32 ? 2 : 1;   // systems per wavefront
     dim3 grid(blocks_for(n, 4 * sys)), block(256);
-    hipLaunchKernelGGL((k_rbf<NB, 8, wpe, sys>), grid, block, 0, s, geo, xs, ys, perm, nbr, L, n,
-                       K, m, dx, W64, dev_err);
+    // own-node stencils (exactly 8 departure points per owner) take the
+    // kernel without the replay, which need not keep the multipliers (the
+    // register allocator would park them in scratch memory). Splitting the
+    // paper rule's owners the same way (at most 8 departure points, then the
+    // rest) measured slower: the second launch runs a sparse tail.
+    if (L.ptr)
+        hipLaunchKernelGGL((k_rbf<NB, 8, wpe, sys, true>), grid, block, 0, s, geo, xs, ys, perm,
+                           nbr, L, n, K, m, dx, W64, dev_err);
+    else
+        hipLaunchKernelGGL((k_rbf<NB, 8, wpe, sys, false>), grid, block, 0, s, geo, xs, ys, perm,
+                           nbr, L, n, K, m, dx, W64, dev_err);
     return hipGetLastError();
 }
 
