@@ -922,9 +922,9 @@ static hipError_t launch_rbf_nb(const Geo *geo, const double *xs, const double *
     if (L.ptr)
         hipLaunchKernelGGL((k_rbf<NB, 8, wpe, sys, true>), grid, block, 0, s, geo, xs, ys, perm,
                            nbr, L, n, K, m, dx, W64, dev_err);
-    else
-        hipLaunchKernelGGL((k_rbf<NB, 8, wpe, sys, false>), grid, block, 0, s, geo, xs, ys, perm,
-                           nbr, L, n, K, m, dx, W64, dev_err);
+    else   // fewer registers live: one more wavefront per SIMD from 32 unknowns up
+        hipLaunchKernelGGL((k_rbf<NB, 8, NB == 24 ? 4 : wpe + 1, sys, false>), grid, block, 0, s,
+                           geo, xs, ys, perm, nbr, L, n, K, m, dx, W64, dev_err);
     return hipGetLastError();
 }
 
