@@ -121,15 +121,27 @@ __device__ __forceinline__ int lanes_below(uint64_t mask) {
                                           __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
 }
 
-// Compacted copy of the first lw entries of every sorted CSR row: one lane
-// per node, whole wavefronts per group (lanes past the last node take part
-// in the ballots with hd = 0).
+// Compacted copy of the first lw entries of every sorted CSR row, one
+// wavefront per group of 64 nodes (lanes past the last node take part in the
+// ballots with hd = 0). The wavefront first records, in LDS, the unit of every
+// (slot, node) of its group and writes the padding past each row's end; then,
+// direction by direction, it reads the group's rows (one contiguous CSR
+// segment) with consecutive lanes on consecutive entries, finds each entry's
+// row by a binary search of the row starts, and stores it into its unit.
+constexpr int kEllMaxLw = kMaxK + 4;
 template <class T>
 __global__ __launch_bounds__(256) void k_ell_fill(int n, int lw, const int32_t *__restrict__ ptr,
                                                   const int32_t *__restrict__ col,
                                                   const T *__restrict__ val,
                                                   int32_t *__restrict__ ecol, T *__restrict__ eval) {
-    const int m = blockIdx.x * blockDim.x + threadIdx.x;
+    __shared__ int32_t s_unit[4][kEllMaxLw][64];   // unit of (slot, lane), -1: none
+    __shared__ int32_t s_rb[4][65];                // row starts of one direction
+    const int lane = threadIdx.x & 63;
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int64_t g = (int64_t)blockIdx.x * 4 + wv;
+    const int64_t m0 = g * 64;
+    if (m0 >= n) return;   // uniform across the wavefront
+    const int m = (int)(m0 + lane);
     int b[8], len[8], hd = 0;
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
@@ -141,21 +153,51 @@ __global__ __launch_bounds__(256) void k_ell_fill(int n, int lw, const int32_t *
             hd = max(hd, min(len[k], lw));
         }
     }
-    const int64_t g0 = (int64_t)(m >> 6) * 64 * lw;
+    const int64_t g0 = g * 64 * lw;
     int64_t off = 0;
     for (int e = 0; e < lw; ++e) {
         const bool on = e < hd;
         const uint64_t mask = __ballot(on);
-        if (mask == 0) break;
+        const int64_t u = g0 + off + lanes_below(mask);
+        s_unit[wv][e][lane] = on ? (int32_t)(u - g0) : -1;
         if (on) {
-            const int64_t u = (g0 + off + lanes_below(mask)) * 8;
 #pragma unroll
             for (int k = 0; k < 8; ++k) {
-                ecol[u + k] = e < len[k] ? col[b[k] + e] : (int32_t)m;
-                eval[u + k] = e < len[k] ? val[b[k] + e] : (T)0;
+                if (e >= len[k]) {
+                    ecol[u * 8 + k] = (int32_t)m;
+                    eval[u * 8 + k] = (T)0;
+                }
             }
         }
         off += __popcll(mask);
+    }
+    const int nl = (int)min((int64_t)64, n - m0);   // nodes of this group
+    for (int k = 0; k < 8; ++k) {
+        // row starts of the group's rows in direction k, and the segment end
+        s_rb[wv][lane] = m < n ? b[k] : INT_MAX;
+        const int seg0 = __builtin_amdgcn_readfirstlane(b[k]);
+        const int seg1 = __builtin_amdgcn_readlane(b[k] + len[k], nl - 1);
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        for (int idx = seg0 + lane; idx < seg1; idx += 64) {
+            // last row whose start is <= idx (empty rows share the next start)
+            int lo = 0, hi = nl - 1;
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if (s_rb[wv][mid] <= idx) lo = mid;
+                else hi = mid - 1;
+            }
+            const int e = idx - s_rb[wv][lo];
+            if (e < lw) {
+                const int64_t u = g0 + s_unit[wv][e][lo];
+                ecol[u * 8 + k] = col[idx];
+                eval[u * 8 + k] = val[idx];
+            }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     }
 }
 
@@ -608,6 +650,7 @@ hipError_t launch_transpose(const CloudPlan &cp, int precision, void *tmp, size_
 }
 
 hipError_t launch_ell_fill(const CloudPlan &cp, int precision, hipStream_t s) {
+    if (cp.tr_lw > kEllMaxLw) return hipErrorInvalidValue;
     const dim3 grid(blocks_for(cp.n, 256)), block(256);
     if (precision == MLBM_FP64)
         hipLaunchKernelGGL(k_ell_fill<double>, grid, block, 0, s, cp.n,
