@@ -459,7 +459,8 @@ __global__ __launch_bounds__(256) void k_adj_step(
         const bool onw = 3 * w < hmax;
         const uint64_t mw = __ballot(onw);
         const int64_t uw = gw + (onw ? woff + lanes_below(mw) : 0);
-        const U4 wa = elw[2 * uw], wb = elw[2 * uw + 1];
+        const U4 wa = __builtin_nontemporal_load(elw + 2 * uw);
+        const U4 wb = __builtin_nontemporal_load(elw + 2 * uw + 1);
         tr.wa = onw ? wa : (U4)0;
         tr.wb = onw ? wb : (U4)0;
         woff += __popcll(mw);
@@ -468,7 +469,8 @@ __global__ __launch_bounds__(256) void k_adj_step(
             const bool on = 3 * w + sft < hmax;
             const uint64_t me = __ballot(on);
             const int64_t u = gv + (on ? voff + lanes_below(me) : 0);
-            const T4 va = ev[2 * u], vb = ev[2 * u + 1];
+            const T4 va = __builtin_nontemporal_load(ev + 2 * u);
+            const T4 vb = __builtin_nontemporal_load(ev + 2 * u + 1);
             tr.va[sft] = on ? va : (T4)0;
             tr.vb[sft] = on ? vb : (T4)0;
             voff += __popcll(me);
