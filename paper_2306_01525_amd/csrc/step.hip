@@ -122,6 +122,13 @@ __device__ __forceinline__ float4 load_w(const float4 *p, bool nt) {
     return make_float4(v.x, v.y, v.z, v.w);
 }
 
+// One pair of FP64 weights, non-temporal.
+__device__ __forceinline__ double2 load_w2(const double2 *p) {
+    typedef double f64x2 __attribute__((ext_vector_type(2)));
+    const f64x2 v = __builtin_nontemporal_load(reinterpret_cast<const f64x2 *>(p));
+    return make_double2(v.x, v.y);
+}
+
 template <int MODE, bool FORCE, int WALL, bool REC, int UNROLL, bool NT>
 __device__ __forceinline__ void step32_tile(const Step32Args &a, const float *__restrict__ g,
                                             float *__restrict__ go, int64_t tile,
@@ -344,6 +351,7 @@ __global__ __launch_bounds__(kTile) void k_step64(
             }
             __syncthreads();
             if (tid < cnt) {
+#pragma unroll 2
                 for (int w = 0; w < Kw; ++w) {
                     uint32_t word[4];
 #pragma unroll
@@ -354,8 +362,10 @@ __global__ __launch_bounds__(kTile) void k_step64(
                         const int jj = 3 * w + sft;
                         if (jj < K) {
                             // directions 4 pass + 1 .. 4 pass + 4 as two pairs
-                            const double2 wa = W2[((int64_t)jj * 4 + 2 * pass) * n + p];
-                            const double2 wb = W2[((int64_t)jj * 4 + 2 * pass + 1) * n + p];
+                            // streamed once per step: non-temporal
+                            const double2 wa = load_w2(W2 + ((int64_t)jj * 4 + 2 * pass) * n + p);
+                            const double2 wb =
+                                load_w2(W2 + ((int64_t)jj * 4 + 2 * pass + 1) * n + p);
                             const double wt[4] = {wa.x, wa.y, wb.x, wb.y};
 #pragma unroll
                             for (int dd = 0; dd < 4; ++dd)
