@@ -315,12 +315,12 @@ mlbm_status mlbm_init_adjoint(const mlbm_plan *plan, const double *u0x, const do
 /* ---- tuning --------------------------------------------------------------- */
 
 /* Autotuner of the FP32 step: times every kernel variant (the unroll depth
- * of the stencil loop and non-temporal weight loads) for n_steps steps each,
- * after one warm-up step, on this plan's own cloud, and keeps the fastest for
- * every later step and graph. ms_out (host, may be NULL) receives the measured
- * milliseconds per step of each variant, *n_variants (host, may be NULL) their
- * count. The contents of g_a and g_b are advanced (start again from
- * mlbm_init afterwards). Synchronous. FP64 plans have a single variant. */
+ * of the stencil loop, non-temporal weight loads, one or two lanes per node)
+ * for n_steps steps each, after one warm-up step, on this plan's own cloud,
+ * and keeps the fastest for every later step and graph. ms_out (host, may be
+ * NULL, room for 8 floats) receives the measured milliseconds per step of each
+ * variant, *n_variants (host, may be NULL) their count (8). The contents of
+ * g_a and g_b are advanced (start again from mlbm_init afterwards). Synchronous. FP64 plans have a single variant. */
 mlbm_status mlbm_autotune(mlbm_plan *plan, void *g_a, void *g_b, int32_t n_steps,
                           float *ms_out, int32_t *n_variants, hipStream_t stream);
 

@@ -16,8 +16,10 @@ ARCH = "gfx950"
 COMMON = ["-O3", "--offload-arch=" + ARCH, "-std=c++17", "-fPIC",
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
           "-Wall", "-Wno-unused-result"]
-# the build kernels compare squared distances bitwise: no FMA contraction there
-PER_FILE = {"build.hip": ["-ffp-contract=off"]}
+# the build kernels compare squared distances bitwise, and the step variants
+# must give bitwise the same states: no FMA contraction there (the step's
+# stencil sums are written as explicit fused multiply-adds)
+PER_FILE = {"build.hip": ["-ffp-contract=off"], "step.hip": ["-ffp-contract=off"]}
 
 
 def _hipcc():

@@ -48,7 +48,7 @@ constexpr int kMaxK = 48;       // largest stencil supported
 // room for all 64.
 inline int64_t head_nodes(int n) { return ((int64_t)n + 63) / 64 * 64; }
 constexpr int kTile = 256;      // nodes per workgroup in the step kernels
-constexpr int kStepVariants = 6; // FP32 step tuning variants
+constexpr int kStepVariants = 8; // FP32 step tuning variants
 constexpr int kBuildLanes = 4;   // clouds of one plan built concurrently
 constexpr int kStats = 4;        // build records per cloud (tile tables)
 

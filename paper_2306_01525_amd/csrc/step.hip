@@ -64,16 +64,20 @@ __device__ __forceinline__ void bounce_back(unsigned links, T (&f)[kQ]) {
 // Moments, wall rule, BGK collision with force, and the stores of one node.
 // WALL: 0 none; 1 equilibrium wall nodes (ntype = node types); 2 bounce-back
 // (ntype = the nodes' link masks).
+// Directions k0 <= k < k1 are stored (all of them by default; the two lanes
+// of a node in the split step store one part each).
 template <bool FORCE, int WALL, bool REC>
 __device__ __forceinline__ void collide_store32(int n, int p, float (&f)[kQ],
                                                 float *__restrict__ go,
                                                 const float *__restrict__ force,
                                                 const uint8_t *__restrict__ ntype, float rtau,
                                                 float rho0, float rho_w,
-                                                float *__restrict__ frec) {
+                                                float *__restrict__ frec, int k0 = 0,
+                                                int k1 = kQ) {
     if (WALL == 1 && ntype[p]) {
 #pragma unroll
         for (int k = 0; k < kQ; ++k) {
+            if (k < k0 || k >= k1) continue;
             const float v = wk32(k) * (rho_w - rho0);
             go[(int64_t)k * n + p] = v;
             if (REC) frec[(int64_t)k * n + p] = v;
@@ -98,6 +102,7 @@ __device__ __forceinline__ void collide_store32(int n, int p, float (&f)[kQ],
     }
 #pragma unroll
     for (int k = 0; k < kQ; ++k) {
+        if (k < k0 || k >= k1) continue;
         const float eu = (float)lat_ex(k) * ux + (float)lat_ey(k) * uy;
         const float feq = wk32(k) * (drho + rho * (3.0f * eu + 4.5f * eu * eu - 1.5f * uu));
         float v = f[k] - (f[k] - feq) * rtau;
@@ -181,7 +186,8 @@ __device__ __forceinline__ void step32_tile(const Step32Args &a, const float *__
                     const float wv[8] = {wa.x, wa.y, wa.z, wa.w, wb.x, wb.y, wb.z, wb.w};
 #pragma unroll
                     for (int d = 0; d < 8; ++d)
-                        acc[d] += wv[d] * gl[d * nh + (int)((word[d] >> (10 * sft)) & 1023u)];
+                        acc[d] = __builtin_fmaf(
+                            wv[d], gl[d * nh + (int)((word[d] >> (10 * sft)) & 1023u)], acc[d]);
                 }
             }
         }
@@ -209,12 +215,13 @@ __device__ __forceinline__ void step32_tile(const Step32Args &a, const float *__
         if (MODE == MLBM_STENCIL_OWN) {
             const int q = a.nbr[(int64_t)j * n + p];
 #pragma unroll
-            for (int d = 0; d < 8; ++d) acc[d] += w[d] * g[(int64_t)(d + 1) * n + q];
+            for (int d = 0; d < 8; ++d)
+                acc[d] = __builtin_fmaf(w[d], g[(int64_t)(d + 1) * n + q], acc[d]);
         } else {
 #pragma unroll
             for (int d = 0; d < 8; ++d) {
                 const int q = a.nbr[(int64_t)j * n + s[d]];
-                acc[d] += w[d] * g[(int64_t)(d + 1) * n + q];
+                acc[d] = __builtin_fmaf(w[d], g[(int64_t)(d + 1) * n + q], acc[d]);
             }
         }
     }
@@ -224,6 +231,115 @@ __device__ __forceinline__ void step32_tile(const Step32Args &a, const float *__
     for (int d = 0; d < 8; ++d) f[d + 1] = acc[d];
     collide_store32<FORCE, WALL, REC>(n, p, f, go, a.force, a.ntype, a.rtau, a.rho0, a.rho_w,
                                       a.frec);
+}
+
+// The same tile with two lanes per node (adjacent lanes; 2 kTile threads):
+// lane h of node l interpolates directions 4h+1 .. 4h+4, the pair swaps its
+// four sums with a DPP exchange, and both lanes finish the node identically
+// (same values, same order), lane 0 storing directions 0..4 and lane 1 5..8.
+// The tile's LDS is unchanged, so a compute unit holds twice the wavefronts
+// for the same tiles. Per direction the sums run in the same order as in
+// step32_tile, so the results are bitwise the same.
+__device__ __forceinline__ float swap_pair(float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0xB1, 0xF, 0xF,
+                                                      false));   // quad_perm [1,0,3,2]
+}
+
+template <int MODE, bool FORCE, int WALL, bool REC, bool NT>
+__device__ __forceinline__ void step32_tile_split(const Step32Args &a,
+                                                  const float *__restrict__ g,
+                                                  float *__restrict__ go, int64_t tile,
+                                                  unsigned char *smem) {
+    const int n = a.n, K = a.K;
+    const int base = (int)(tile * kTile);
+    const int cnt = min(kTile, n - base);
+    const int tid = threadIdx.x, l = tid >> 1, h = tid & 1;
+    const int nh = a.tdesc ? a.tdesc[2 * tile + 1] : 0;
+    const float4 *__restrict__ W = a.W;
+    float acc[4];
+#pragma unroll
+    for (int dd = 0; dd < 4; ++dd) acc[dd] = 0.0f;
+
+    if (nh > 0) {
+        const int no = a.tdesc[2 * tile];
+        const int Kw = (K + 2) / 3;
+        float *gl = reinterpret_cast<float *>(smem);                 // [8][nh]
+        uint32_t *nl = reinterpret_cast<uint32_t *>(gl + 8 * nh);    // [no][Kw]
+        const int32_t *hl = a.hlist + tile * (int64_t)a.hcap;
+        for (int i = tid; i < nh; i += 2 * kTile) {
+            int q = hl[i];
+            q = (unsigned)q < (unsigned)n ? q : 0;   // a bad table must not fault
+#pragma unroll
+            for (int d = 0; d < 8; ++d) gl[d * nh + i] = g[(int64_t)(d + 1) * n + q];
+        }
+        const uint32_t *src = a.nbrL + tile * (int64_t)a.ocap * Kw;
+        for (int w = tid; w < no * Kw; w += 2 * kTile) nl[w] = src[w];
+        __syncthreads();
+        if (l >= cnt) return;   // both lanes of a node leave together
+        const int p = base + l;
+        int ol[4];
+#pragma unroll
+        for (int dd = 0; dd < 4; ++dd)
+            ol[dd] = (MODE == MLBM_STENCIL_OWN ? l
+                                               : (int)a.ownerL[(int64_t)(4 * h + dd) * n + p]) * Kw;
+        const float *glh = gl + 4 * h * nh;
+        for (int w = 0; w < Kw; ++w) {
+            uint32_t word[4];
+#pragma unroll
+            for (int dd = 0; dd < 4; ++dd)
+                word[dd] = (MODE == MLBM_STENCIL_OWN && dd > 0) ? word[0] : nl[ol[dd] + w];
+#pragma unroll
+            for (int sft = 0; sft < 3; ++sft) {
+                const int jj = 3 * w + sft;
+                if (jj < K) {
+                    const float4 wv = load_w(W + ((int64_t)jj * 2 + h) * n + p, NT);
+                    const float wt[4] = {wv.x, wv.y, wv.z, wv.w};
+#pragma unroll
+                    for (int dd = 0; dd < 4; ++dd)
+                        acc[dd] = __builtin_fmaf(
+                            wt[dd], glh[dd * nh + (int)((word[dd] >> (10 * sft)) & 1023u)], acc[dd]);
+                }
+            }
+        }
+    } else {
+        if (l >= cnt) return;
+        const int p = base + l;
+        int s[4];
+#pragma unroll
+        for (int dd = 0; dd < 4; ++dd)
+            s[dd] = MODE == MLBM_STENCIL_OWN ? p : a.owner[(int64_t)(4 * h + dd) * n + p];
+        for (int j = 0; j < K; ++j) {
+            const float4 wv = load_w(W + ((int64_t)j * 2 + h) * n + p, NT);
+            const float wt[4] = {wv.x, wv.y, wv.z, wv.w};
+#pragma unroll
+            for (int dd = 0; dd < 4; ++dd) {
+                const int q = a.nbr[(int64_t)j * n + s[dd]];
+                acc[dd] = __builtin_fmaf(wt[dd], g[(int64_t)(4 * h + dd + 1) * n + q], acc[dd]);
+            }
+        }
+    }
+    const int p = base + l;
+    float oth[4];
+#pragma unroll
+    for (int dd = 0; dd < 4; ++dd) oth[dd] = swap_pair(acc[dd]);
+    float f[kQ];
+    f[0] = g[p];
+#pragma unroll
+    for (int dd = 0; dd < 4; ++dd) {
+        f[1 + dd] = h ? oth[dd] : acc[dd];
+        f[5 + dd] = h ? acc[dd] : oth[dd];
+    }
+    collide_store32<FORCE, WALL, REC>(n, p, f, go, a.force, a.ntype, a.rtau, a.rho0, a.rho_w,
+                                      a.frec, h ? 5 : 0, h ? kQ : 5);
+}
+
+template <int MODE, bool FORCE, int WALL, bool REC, bool NT>
+__global__ __launch_bounds__(2 * kTile) void k_step32s(Step32Args a, const float *__restrict__ g,
+                                                       float *__restrict__ go, int64_t nblocks) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int64_t tile = xcd_tile(nblocks);
+    if (tile >= nblocks) return;
+    step32_tile_split<MODE, FORCE, WALL, REC, NT>(a, g, go, tile, smem);
 }
 
 template <int MODE, bool FORCE, int WALL, bool REC, int UNROLL, bool NT>
@@ -250,6 +366,20 @@ __global__ __launch_bounds__(kTile) void k_step32_batch(const Step32Args *__rest
     const Step32Args a = descs[tile2cloud[t]];
     step32_tile<MODE, false, false, false, UNROLL, NT>(a, g + a.soff, go + a.soff,
                                                         t - a.tile_begin, smem);
+}
+
+template <int MODE, bool NT>
+__global__ __launch_bounds__(2 * kTile) void k_step32s_batch(const Step32Args *__restrict__ descs,
+                                                             const int32_t *__restrict__ tile2cloud,
+                                                             const float *__restrict__ g,
+                                                             float *__restrict__ go,
+                                                             int64_t total_tiles) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int64_t t = xcd_tile(total_tiles);
+    if (t >= total_tiles) return;
+    const Step32Args a = descs[tile2cloud[t]];
+    step32_tile_split<MODE, false, false, false, NT>(a, g + a.soff, go + a.soff,
+                                                     t - a.tile_begin, smem);
 }
 
 // Writes one batch descriptor (a kernel, so that graph capture records it).
@@ -369,8 +499,9 @@ __global__ __launch_bounds__(kTile) void k_step64(
                             const double wt[4] = {wa.x, wa.y, wb.x, wb.y};
 #pragma unroll
                             for (int dd = 0; dd < 4; ++dd)
-                                acc[4 * pass + dd] +=
-                                    wt[dd] * gl[dd * nh + (int)((word[dd] >> (10 * sft)) & 1023u)];
+                                acc[4 * pass + dd] = __builtin_fma(
+                                    wt[dd], gl[dd * nh + (int)((word[dd] >> (10 * sft)) & 1023u)],
+                                    acc[4 * pass + dd]);
                         }
                     }
                 }
@@ -389,7 +520,7 @@ __global__ __launch_bounds__(kTile) void k_step64(
             for (int d = 0; d < 8; ++d) {
                 const double w = W[w64_at(d + 1, j, n, p)];
                 const int q = MODE == MLBM_STENCIL_OWN ? qo : nbr[(int64_t)j * n + s[d]];
-                acc[d] += w * g[(int64_t)(d + 1) * n + q];
+                acc[d] = __builtin_fma(w, g[(int64_t)(d + 1) * n + q], acc[d]);
             }
         }
     }
@@ -621,8 +752,10 @@ __global__ void k_collide(int n, const T *__restrict__ f, T *__restrict__ g,
 // Tuning variants of the FP32 step: unroll depth of the stencil loop over
 // index words (1, 2 or 3 words = 3, 6 or 9 weight rows a lane has in flight)
 // and non-temporal weight loads (the weights are streamed once per step and
-// need not displace the halo rows in L2). Variant v: unroll {1, 2, 3}[v / 2],
-// non-temporal v % 2. Tiles without tables unroll their row loop 3x that.
+// need not displace the halo rows in L2). Variant v < 6: one lane per node,
+// unroll {1, 2, 3}[v / 2], non-temporal v % 2. Tiles without tables unroll
+// their row loop 3x that. Variants 6 and 7: two lanes per node (directions
+// split in halves), non-temporal v % 2.
 template <int MODE, bool FORCE, int WALL, bool REC, int UNROLL, bool NT>
 void launch32(const CloudPlan &cp, const void *gin, void *gout, void *frec, int64_t nblocks,
               hipStream_t s) {
@@ -630,6 +763,22 @@ void launch32(const CloudPlan &cp, const void *gin, void *gout, void *frec, int6
     hipLaunchKernelGGL((k_step32<MODE, FORCE, WALL, REC, UNROLL, NT>), dim3(xcd_grid(nblocks)),
                        dim3(kTile), cp.lds_bytes, s, a, (const float *)gin, (float *)gout,
                        nblocks);
+}
+
+template <int MODE, bool FORCE, int WALL, bool REC, bool NT>
+void launch32s(const CloudPlan &cp, const void *gin, void *gout, void *frec, int64_t nblocks,
+               hipStream_t s) {
+    const Step32Args a = step32_args(cp, frec);
+    hipLaunchKernelGGL((k_step32s<MODE, FORCE, WALL, REC, NT>), dim3(xcd_grid(nblocks)),
+                       dim3(2 * kTile), cp.lds_bytes, s, a, (const float *)gin, (float *)gout,
+                       nblocks);
+}
+
+template <int MODE, bool NT>
+void launch32s_batch(const mlbm_plan &plan, const void *gin, void *gout, hipStream_t s) {
+    hipLaunchKernelGGL((k_step32s_batch<MODE, NT>), dim3(xcd_grid(plan.total_tiles)),
+                       dim3(2 * kTile), plan.batch_lds, s, plan.descs, plan.tile2cloud,
+                       (const float *)gin, (float *)gout, plan.total_tiles);
 }
 
 template <int MODE, int UNROLL, bool NT>
@@ -647,6 +796,8 @@ void launch32_batch_v(const mlbm_plan &plan, const void *gin, void *gout, hipStr
         case 3: launch32_batch<MODE, 2, true>(plan, gin, gout, s); break;
         case 4: launch32_batch<MODE, 3, false>(plan, gin, gout, s); break;
         case 5: launch32_batch<MODE, 3, true>(plan, gin, gout, s); break;
+        case 6: launch32s_batch<MODE, false>(plan, gin, gout, s); break;
+        case 7: launch32s_batch<MODE, true>(plan, gin, gout, s); break;
         default: launch32_batch<MODE, 1, false>(plan, gin, gout, s); break;
     }
 }
@@ -664,6 +815,8 @@ void launch32_tuned(const CloudPlan &cp, const void *gin, void *gout, void *frec
         case 3: launch32<MODE, FORCE, WALL, REC, 2, true>(cp, gin, gout, frec, nblocks, s); break;
         case 4: launch32<MODE, FORCE, WALL, REC, 3, false>(cp, gin, gout, frec, nblocks, s); break;
         case 5: launch32<MODE, FORCE, WALL, REC, 3, true>(cp, gin, gout, frec, nblocks, s); break;
+        case 6: launch32s<MODE, FORCE, WALL, REC, false>(cp, gin, gout, frec, nblocks, s); break;
+        case 7: launch32s<MODE, FORCE, WALL, REC, true>(cp, gin, gout, frec, nblocks, s); break;
         default: launch32<MODE, FORCE, WALL, REC, 1, false>(cp, gin, gout, frec, nblocks, s); break;
     }
 }
@@ -764,7 +917,7 @@ __global__ __launch_bounds__(256) void k_interpolate(int n, int K, int mode,
         const int s = mode == MLBM_STENCIL_OWN ? p : owner[(int64_t)(k - 1) * n + p];
         double acc = 0.0;
         for (int j = 0; j < K; ++j)
-            acc += W64[w64_at(k, j, n, p)] * field[perm[nbr[(int64_t)j * n + s]]];
+            acc = __builtin_fma(W64[w64_at(k, j, n, p)], field[perm[nbr[(int64_t)j * n + s]]], acc);
         out[(int64_t)(k - 1) * out_stride + u] = acc;
     }
 }
