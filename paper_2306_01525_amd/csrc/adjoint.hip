@@ -244,19 +244,13 @@ __device__ __forceinline__ void moments_of(const T *f, int n, int p, int dev, do
     uy = jy / rho;
 }
 
-// lam_n = C'(f^n)^T (S^T lam_next); part[block] = sum of (S^T lam).(dC/dtau).
-//   d feq_a / d rho = w_a [1 - 4.5 (e_a.u)^2 + 1.5 u^2]
-//   d feq_a / d j   = w_a [3 e_a + 9 (e_a.u) e_a - 3 u]
-//   C_a = f_a - (f_a - feq_a)/tau, so
-//   lam_b = (1 - 1/tau) lg_b + (1/tau) (A + B . e_b),
-//   A = sum_a lg_a d feq_a / d rho, B = sum_a lg_a d feq_a / d j,
-//   d C_a / d tau = (f_a - feq_a) / tau^2.
 // Inverse halo of a tile of source nodes: every arriving node that the head
 // (first lw entries) of the transposed rows of the tile's nodes reads, sorted
 // (LDS hash set, then a bitonic network), capped at cap. The slot-major
 // columns of those rows are rewritten as positions in that set, three 10-bit
-// fields per word: word w of row k of node m (layout as ell_at) holds slots
-// 3w, 3w+1, 3w+2; fields past the end of the row are 0.
+// fields per word: word w of row k of node m (compacted like the heads, over
+// triples of slots) holds slots 3w, 3w+1, 3w+2; fields past the end of the
+// row are 0.
 constexpr int kAHash = 4096;
 
 __device__ void bitonic_sort_a(int *a, int npow2) {
