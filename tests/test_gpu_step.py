@@ -173,15 +173,20 @@ def test_step_variants_are_bitwise_identical_and_autotune_picks_one():
     c, ux, uy = tgv_case(40, 30, 4, 0)
     plan = Plan.build(c.x, c.y, c.period, _params(c.h, 30, 4, 0, 0, 0.6))
     for pl, vx, vy in ((walled, za, za), (plan, ux, uy)):
-        ref = None
+        ref = rec_ref = None
         for v in range(8):   # 0-5 one lane per node, 6-7 two
             pl.set_variant(v)
             g = pl.init(vx, vy)
             g = pl.step(g, pl.new_state(), 25)
+            # the recording step (pre-collision populations kept for the
+            # adjoint) takes the same variant
+            rec = torch.empty((3, 9, pl.n), dtype=g.dtype, device=g.device)
+            g = pl.step_record(g, pl.new_state(), 3, rec)
             if ref is None:
-                ref = g.clone()
+                ref, rec_ref = g.clone(), rec.clone()
             else:
                 assert torch.equal(g, ref), v
+                assert torch.equal(rec, rec_ref), v
     walled.close()
     a, b = plan.new_state(), plan.new_state()
     ms = plan.autotune(plan.init(ux, uy, g=a), b, 5)
