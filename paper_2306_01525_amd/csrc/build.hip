@@ -626,10 +626,25 @@ __device__ __forceinline__ void rbf_solve(const Geo *__restrict__ geo,
             }
             if (lane == k) plog = pl;
             const double l = lane != pl ? a[k] * pi : 0.0;
+            // (four lane reads ahead of their updates, so that the scalar
+            // results are not waited for one by one)
 #pragma unroll
-            for (int c = k + 1; c < NB; ++c) a[c] = __builtin_fma(-l, readlane_d(a[c], pl), a[c]);
+            for (int c = k + 1; c < NB; c += 4) {
+                const double r0 = readlane_d(a[c], pl);
+                const double r1 = c + 1 < NB ? readlane_d(a[c + 1], pl) : 0.0;
+                const double r2 = c + 2 < NB ? readlane_d(a[c + 2], pl) : 0.0;
+                const double r3 = c + 3 < NB ? readlane_d(a[c + 3], pl) : 0.0;
+                a[c] = __builtin_fma(-l, r0, a[c]);
+                if (c + 1 < NB) a[c + 1] = __builtin_fma(-l, r1, a[c + 1]);
+                if (c + 2 < NB) a[c + 2] = __builtin_fma(-l, r2, a[c + 2]);
+                if (c + 3 < NB) a[c + 3] = __builtin_fma(-l, r3, a[c + 3]);
+            }
 #pragma unroll
-            for (int t = 0; t < R; ++t) b[t] = __builtin_fma(-l, readlane_d(b[t], pl), b[t]);
+            for (int t = 0; t < R; t += 2) {
+                const double r0 = readlane_d(b[t], pl), r1 = readlane_d(b[t + 1], pl);
+                b[t] = __builtin_fma(-l, r0, b[t]);
+                b[t + 1] = __builtin_fma(-l, r1, b[t + 1]);
+            }
             if (lane != pl) a[k] = l;
         }
         store(0, b);
