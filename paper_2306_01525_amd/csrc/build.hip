@@ -610,9 +610,15 @@ __device__ __forceinline__ void rbf_solve(const Geo *__restrict__ geo,
         // compute unit share and which every lane would otherwise read the
         // whole row from. Lane k keeps the pivot lane of step k for the
         // replay of further groups.
+        // Steps from nn on pivot on the identity rows that pad the system
+        // and change nothing, and columns from nn on stay zero in every row
+        // that holds a pivot before (a zero pivot there only happens in a
+        // singular system, which is reported): both are skipped with uniform
+        // branches.
         int plog = 0;
 #pragma unroll
         for (int k = 0; k < NB; ++k) {
+            if (k >= nn) continue;
             const uint32_t key =
                 pstep > k ? ((uint32_t)(__double_as_longlong(a[k]) >> 32) & 0x7FFFFFFFu) | 1u : 0u;
             const double rk = recip(a[k]);
@@ -630,6 +636,7 @@ __device__ __forceinline__ void rbf_solve(const Geo *__restrict__ geo,
             // results are not waited for one by one)
 #pragma unroll
             for (int c = k + 1; c < NB; c += 4) {
+                if (c >= nn) continue;
                 const double r0 = readlane_d(a[c], pl);
                 const double r1 = c + 1 < NB ? readlane_d(a[c + 1], pl) : 0.0;
                 const double r2 = c + 2 < NB ? readlane_d(a[c + 2], pl) : 0.0;
@@ -652,6 +659,7 @@ __device__ __forceinline__ void rbf_solve(const Geo *__restrict__ geo,
             load_rhs(c0, b);
 #pragma unroll
             for (int k = 0; k < NB; ++k) {
+                if (k >= nn) continue;
                 const int pk = __builtin_amdgcn_readlane(plog, k);
                 const double l = lane != pk ? a[k] : 0.0;
 #pragma unroll
