@@ -670,9 +670,11 @@ __device__ __forceinline__ void rbf_solve(const Geo *__restrict__ geo,
         if (singular && count > 0 && ll == 0) atomicMin(dev_err, perm[s] + 1);
         return;
     }
-    // elimination, carrying the first group of right-hand sides
+    // elimination, carrying the first group of right-hand sides (padding
+    // steps and columns skipped as above)
 #pragma unroll
     for (int k = 0; k < NB; ++k) {
+        if (k >= nn) continue;
         const uint32_t key =
             pstep > k ? ((uint32_t)(__double_as_longlong(a[k]) >> 32) & 0x7FFFFFFFu) | 1u : 0u;
         const double rk = recip(a[k]);
@@ -703,9 +705,11 @@ __device__ __forceinline__ void rbf_solve(const Geo *__restrict__ geo,
         // they hold; the updates are explicit fused multiply-adds, since only
         // the distances that decide stencil ties must round like the oracle)
 #pragma unroll
-        for (int c = k + 1; c < NB; ++c) {
-            a[c] = __builtin_fma(-l, row[c], a[c]);
-            if ((c - k) % 16 == 0) __builtin_amdgcn_sched_barrier(0);
+        for (int c0 = k + 1; c0 < NB; c0 += 4) {
+            if (c0 >= nn) continue;
+#pragma unroll
+            for (int c = c0; c < c0 + 4 && c < NB; ++c) a[c] = __builtin_fma(-l, row[c], a[c]);
+            if ((c0 - k + 3) % 16 == 0) __builtin_amdgcn_sched_barrier(0);
         }
 #pragma unroll
         for (int t = 0; t < R; ++t) b[t] = __builtin_fma(-l, row[NB + t], b[t]);
@@ -718,6 +722,7 @@ __device__ __forceinline__ void rbf_solve(const Geo *__restrict__ geo,
         load_rhs(c0, b);
 #pragma unroll
         for (int k = 0; k < NB; ++k) {
+            if (k >= nn) continue;
             if (pstep == k) {
 #pragma unroll
                 for (int t = 0; t < R; ++t) row[NB + t] = b[t];
