@@ -183,9 +183,12 @@ mlbm_status mlbm_plan_get_info(const mlbm_plan *plan, mlbm_plan_info *info);
  *       13 transposed row heads int32 [(K+4) * n64][8], n64 = n rounded up
  *          to a multiple of 64 (internal indices). Nodes are grouped by 64;
  *          hd(m) = max over the 8 rows of node m of min(length, K+4). Group g
- *          starts at unit g*64*(K+4), and its slot e = 0, 1, ... holds one
- *          unit for each node of the group with hd > e, in node order; unit
- *          entry k-1 is entry e of row k-1 of that node (m past the row end).
+ *          starts at unit g*64*(K+4), and its slot e = 0, 1, ... holds a
+ *          block of c units, one for each node of the group with hd > e, in
+ *          node order; unit entry k-1 is entry e of row k-1 of that node (m
+ *          past the row end). A block of c units starting at unit u0 stores
+ *          entries 0-3 of its units first and then entries 4-7: entry k-1 of
+ *          its unit r is element 8 u0 + 4 ((k-1)/4 c + r) + (k-1)%4.
  * Items 4-8 describe the gather tables of the LDS-staged steps and items 9-13
  * those of the adjoint step (internal layout; 9-13 need with_adjoint).
  * Cloud `cloud`; dst_bytes must match exactly. */

@@ -121,6 +121,13 @@ __device__ __forceinline__ int lanes_below(uint64_t mask) {
                                           __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
 }
 
+// Entry k (0..7) of unit r of a block of c units whose first unit is u0. A
+// block is stored as two halves, entries 0-3 of its c units and then entries
+// 4-7, so that a wavefront reads each half as one contiguous run.
+__device__ __forceinline__ int64_t unit_entry(int64_t u0, int c, int r, int k) {
+    return u0 * 8 + (int64_t)((k >> 2) * c + r) * 4 + (k & 3);
+}
+
 // Compacted copy of the first lw entries of every sorted CSR row, one
 // wavefront per group of 64 nodes (lanes past the last node take part in the
 // ballots with hd = 0). The wavefront first records, in LDS, the unit of every
@@ -134,7 +141,8 @@ __global__ __launch_bounds__(256) void k_ell_fill(int n, int lw, const int32_t *
                                                   const int32_t *__restrict__ col,
                                                   const T *__restrict__ val,
                                                   int32_t *__restrict__ ecol, T *__restrict__ eval) {
-    __shared__ int32_t s_unit[4][kEllMaxLw][64];   // unit of (slot, lane), -1: none
+    __shared__ int32_t s_unit[4][kEllMaxLw][64];   // rank of (slot, lane) in its block
+    __shared__ int32_t s_blk[4][kEllMaxLw][2];     // block of a slot: first unit, units
     __shared__ int32_t s_rb[4][65];                // row starts of one direction
     const int lane = threadIdx.x & 63;
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -158,18 +166,20 @@ __global__ __launch_bounds__(256) void k_ell_fill(int n, int lw, const int32_t *
     for (int e = 0; e < lw; ++e) {
         const bool on = e < hd;
         const uint64_t mask = __ballot(on);
-        const int64_t u = g0 + off + lanes_below(mask);
-        s_unit[wv][e][lane] = on ? (int32_t)(u - g0) : -1;
+        const int r = lanes_below(mask), c = __popcll(mask);
+        s_unit[wv][e][lane] = r;
+        if (lane < 2) s_blk[wv][e][lane] = lane ? c : (int32_t)off;
         if (on) {
 #pragma unroll
             for (int k = 0; k < 8; ++k) {
                 if (e >= len[k]) {
-                    ecol[u * 8 + k] = (int32_t)m;
-                    eval[u * 8 + k] = (T)0;
+                    const int64_t at = unit_entry(g0 + off, c, r, k);
+                    ecol[at] = (int32_t)m;
+                    eval[at] = (T)0;
                 }
             }
         }
-        off += __popcll(mask);
+        off += c;
     }
     const int nl = (int)min((int64_t)64, n - m0);   // nodes of this group
     for (int k = 0; k < 8; ++k) {
@@ -190,9 +200,10 @@ __global__ __launch_bounds__(256) void k_ell_fill(int n, int lw, const int32_t *
             }
             const int e = idx - s_rb[wv][lo];
             if (e < lw) {
-                const int64_t u = g0 + s_unit[wv][e][lo];
-                ecol[u * 8 + k] = col[idx];
-                eval[u * 8 + k] = val[idx];
+                const int64_t at =
+                    unit_entry(g0 + s_blk[wv][e][0], s_blk[wv][e][1], s_unit[wv][e][lo], k);
+                ecol[at] = col[idx];
+                eval[at] = val[idx];
             }
         }
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -358,7 +369,7 @@ __global__ __launch_bounds__(1024) void k_adj_tiles(int n, int lw, int hcap, int
                 const uint64_t mask = __ballot(on);
                 if (mask == 0) break;
                 if (on) {
-                    const int64_t u = (g0 + off + lanes_below(mask)) * 8;
+                    const int r = lanes_below(mask), c = __popcll(mask);
                     for (int k = 0; k < 8; ++k) {
                         uint32_t word = 0;
                         for (int sft = 0; sft < 3; ++sft) {
@@ -367,7 +378,7 @@ __global__ __launch_bounds__(1024) void k_adj_tiles(int n, int lw, int hcap, int
                                 word |= (uint32_t)lower_bound_a(hsorted, ni, col[rb[k] + sl])
                                         << (10 * sft);
                         }
-                        elocal[u + k] = word;
+                        elocal[unit_entry(g0 + off, c, r, k)] = word;
                     }
                 }
                 off += __popcll(mask);
@@ -427,8 +438,10 @@ __global__ __launch_bounds__(256) void k_adj_step(
         lg[k + 1] = 0;
     }
     // The heads are compacted per wavefront (64 nodes): slot e holds one unit
-    // for each lane with hmax > e, and a ballot gives this lane's unit; slots
-    // past a row's end hold weight 0. The loads of a triple of slots are
+    // for each lane with hmax > e, stored as two halves (directions 1-4 of
+    // those lanes, then 5-8) so that each load of the wavefront is one
+    // contiguous run, and a ballot gives this lane's unit; slots past a row's
+    // end hold weight 0. The loads of a triple of slots are
     // issued together (fetching one triple ahead, or the first one before the
     // inverse halo is staged, measured slower: it costs a wavefront per SIMD).
     // A lane past its head (or past the last node) reads its group's first
@@ -452,22 +465,24 @@ __global__ __launch_bounds__(256) void k_adj_step(
     auto fetch = [&](int w, Triple &tr) {
         const bool onw = 3 * w < hmax;
         const uint64_t mw = __ballot(onw);
-        const int64_t uw = gw + (onw ? woff + lanes_below(mw) : 0);
-        const U4 wa = __builtin_nontemporal_load(elw + 2 * uw);
-        const U4 wb = __builtin_nontemporal_load(elw + 2 * uw + 1);
+        const int cw = __popcll(mw);
+        const int64_t aw = onw ? 2 * (gw + woff) + lanes_below(mw) : 2 * gw;
+        const U4 wa = __builtin_nontemporal_load(elw + aw);
+        const U4 wb = __builtin_nontemporal_load(elw + aw + (onw ? cw : 0));
         tr.wa = onw ? wa : (U4)0;
         tr.wb = onw ? wb : (U4)0;
-        woff += __popcll(mw);
+        woff += cw;
 #pragma unroll
         for (int sft = 0; sft < 3; ++sft) {
             const bool on = 3 * w + sft < hmax;
             const uint64_t me = __ballot(on);
-            const int64_t u = gv + (on ? voff + lanes_below(me) : 0);
-            const T4 va = __builtin_nontemporal_load(ev + 2 * u);
-            const T4 vb = __builtin_nontemporal_load(ev + 2 * u + 1);
+            const int ce = __popcll(me);
+            const int64_t a = on ? 2 * (gv + voff) + lanes_below(me) : 2 * gv;
+            const T4 va = __builtin_nontemporal_load(ev + a);
+            const T4 vb = __builtin_nontemporal_load(ev + a + (on ? ce : 0));
             tr.va[sft] = on ? va : (T4)0;
             tr.vb[sft] = on ? vb : (T4)0;
-            voff += __popcll(me);
+            voff += ce;
         }
     };
     if (ni > 0) {
@@ -507,9 +522,11 @@ __global__ __launch_bounds__(256) void k_adj_step(
                 const bool on = e < hmax;
                 const uint64_t me = __ballot(on);
                 if (me == 0) break;
-                const int64_t u = on ? gv + voff + lanes_below(me) : gv;
-                const T4 va = on ? ev[2 * u] : (T4)0, vb = on ? ev[2 * u + 1] : (T4)0;
-                const I4 ca = ec[2 * u], cb = ec[2 * u + 1];
+                const int ce = __popcll(me);
+                const int64_t a = on ? 2 * (gv + voff) + lanes_below(me) : 2 * gv;
+                const int64_t b = on ? a + ce : a;
+                const T4 va = on ? ev[a] : (T4)0, vb = on ? ev[b] : (T4)0;
+                const I4 ca = ec[a], cb = ec[b];
                 lg[1] += va.x * lam_next[1 * (int64_t)n + ca.x];
                 lg[2] += va.y * lam_next[2 * (int64_t)n + ca.y];
                 lg[3] += va.z * lam_next[3 * (int64_t)n + ca.z];
@@ -518,7 +535,7 @@ __global__ __launch_bounds__(256) void k_adj_step(
                 lg[6] += vb.y * lam_next[6 * (int64_t)n + cb.y];
                 lg[7] += vb.z * lam_next[7 * (int64_t)n + cb.z];
                 lg[8] += vb.w * lam_next[8 * (int64_t)n + cb.w];
-                voff += __popcll(me);
+                voff += ce;
             }
         }
 #pragma unroll

@@ -120,8 +120,9 @@ def test_tile_tables_are_consistent(mode):
 
 def _uncompact(units, hd, lw, n, fill):
     """Row heads compacted per group of 64 nodes ([units][8]: group g from
-    unit 64 g lw, slot e holding the group's nodes with hd > e in node order)
-    back to [8][lw][n], with `fill` where a node has no unit."""
+    unit 64 g lw, slot e a block of the group's nodes with hd > e in node
+    order, entries 0-3 of the block's units before entries 4-7) back to
+    [8][lw][n], with `fill` where a node has no unit."""
     n64 = (n + 63) // 64 * 64
     G = n64 // 64
     H = np.zeros(n64, dtype=np.int64)
@@ -129,10 +130,14 @@ def _uncompact(units, hd, lw, n, fill):
     act = np.arange(lw)[:, None, None] < H.reshape(G, 64)[None]   # [lw][G][64]
     cnt = act.sum(axis=2)
     start = np.cumsum(cnt, axis=0) - cnt                          # units of earlier slots
-    unit = (np.arange(G) * 64 * lw)[None, :, None] + start[:, :, None] + np.cumsum(act, axis=2) - 1
+    u0 = (np.arange(G) * 64 * lw)[None, :] + start                 # [lw][G] first unit
+    rank = np.cumsum(act, axis=2) - 1
     e, g, l_ = np.nonzero(act)
+    flat = units.reshape(-1)
+    k = np.arange(8)[:, None]
+    at = 8 * u0[e, g][None] + 4 * ((k // 4) * cnt[e, g][None] + rank[e, g, l_][None]) + k % 4
     out = np.full((8, lw, n64), fill, dtype=units.dtype)
-    out[:, e, g * 64 + l_] = units[unit[e, g, l_]].T
+    out[:, e, g * 64 + l_] = flat[at]
     return out[:, :, :n]
 
 
