@@ -212,8 +212,8 @@ __global__ __launch_bounds__(256) void k_ell_fill(int n, int lw, const int32_t *
     }
 }
 
-// Workgroup sum of one double per lane into part[blockIdx.x].
-__device__ __forceinline__ void block_sum_to(double v, double *part) {
+// Workgroup sum of one double per lane into part[at].
+__device__ __forceinline__ void block_sum_to(double v, double *part, int64_t at) {
     __shared__ double sh[256];
     sh[threadIdx.x] = v;
     __syncthreads();
@@ -221,7 +221,7 @@ __device__ __forceinline__ void block_sum_to(double v, double *part) {
         if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
         __syncthreads();
     }
-    if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
+    if (threadIdx.x == 0) part[at] = sh[0];
 }
 
 __global__ __launch_bounds__(256) void k_sum_final(int64_t nparts, const double *__restrict__ part,
@@ -415,7 +415,12 @@ __global__ __launch_bounds__(256) void k_adj_step(
     typedef T T4 __attribute__((ext_vector_type(4)));
     typedef uint32_t U4 __attribute__((ext_vector_type(4)));
     typedef int32_t I4 __attribute__((ext_vector_type(4)));
-    const int t = blockIdx.x, tid = threadIdx.x;
+    // tiles in XCD-contiguous ranges: neighbouring tiles share much of
+    // their inverse halos
+    const int64_t ntiles = ((int64_t)n + kTile - 1) / kTile;
+    const int64_t tt = xcd_tile(ntiles);
+    if (tt >= ntiles) return;
+    const int t = (int)tt, tid = threadIdx.x;
     const int m = t * kTile + tid;
     const int ni = tdescT ? tdescT[t] : 0;
     T *L = reinterpret_cast<T *>(smem);   // [8][ni]
@@ -567,7 +572,7 @@ __global__ __launch_bounds__(256) void k_adj_step(
             lam_n[(int64_t)b * n + m] =
                 ((T)1 - rt) * lg[b] + rt * (A + Bx * (T)lat_ex(b) + By * (T)lat_ey(b));
     }
-    block_sum_to(dt, part);
+    block_sum_to(dt, part, t);
 }
 
 // dJ/df_b for J = 1/2 sum |u - u*|^2: (r . (e_b - u)) / rho, r = u - u*.
@@ -592,7 +597,7 @@ __global__ __launch_bounds__(256) void k_loss_seed(int n, const int32_t *__restr
                 (T)((rx * ((double)lat_ex(b) - (double)ux) + ry * ((double)lat_ey(b) - (double)uy)) /
                     (double)rho);
     }
-    block_sum_to(jl, part);
+    block_sum_to(jl, part, blockIdx.x);
 }
 
 // dJ/du0 = sum_k lam_k d feq_k(rho0, u0) / d u0.
@@ -703,13 +708,15 @@ hipError_t launch_step_adjoint(const CloudPlan &cp, int precision, const void *f
     const unsigned lds = cp.adj_ni ? (unsigned)(8 * cp.adj_ni * esz) : 0;
     const int32_t *td = cp.adj_ni ? cp.tdescT : nullptr;
     if (precision == MLBM_FP64)
-        hipLaunchKernelGGL(k_adj_step<double>, dim3(nb), dim3(256), lds, s, n, (const double *)fn,
+        hipLaunchKernelGGL(k_adj_step<double>, dim3(xcd_grid(nb)), dim3(256), lds, s, n,
+                           (const double *)fn,
                            (const double *)lam_next, (double *)lam_n, cp.tr_ptr, cp.tr_col,
                            (const double *)cp.tr_val, cp.tr_lw, cp.ell_col,
                            (const double *)cp.ell_val, td, cp.ilist, cp.elocal, cp.hcap, rtau,
                            cp.prm.rho0, 0, part);
     else
-        hipLaunchKernelGGL(k_adj_step<float>, dim3(nb), dim3(256), lds, s, n, (const float *)fn,
+        hipLaunchKernelGGL(k_adj_step<float>, dim3(xcd_grid(nb)), dim3(256), lds, s, n,
+                           (const float *)fn,
                            (const float *)lam_next, (float *)lam_n, cp.tr_ptr, cp.tr_col,
                            (const float *)cp.tr_val, cp.tr_lw, cp.ell_col,
                            (const float *)cp.ell_val, td, cp.ilist, cp.elocal, cp.hcap, rtau,

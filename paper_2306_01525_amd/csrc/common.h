@@ -187,6 +187,18 @@ inline unsigned blocks_for(int64_t n, int threads) {
     return static_cast<unsigned>((n + threads - 1) / threads);
 }
 
+// Workgroup -> tile map that gives each XCD a contiguous range of tiles (the
+// hardware deals workgroups round-robin over the 8 XCDs, each with its own
+// L2), so neighbouring tiles, which share stencil members, share an L2. The
+// grid is xcd_grid(nblocks); workgroups mapped past the last tile do nothing.
+__device__ __forceinline__ int64_t xcd_tile(int64_t nblocks) {
+    const int64_t b = blockIdx.x;
+    const int64_t per = (nblocks + 7) / 8;
+    return (b & 7) * per + (b >> 3);
+}
+
+inline unsigned xcd_grid(int64_t nblocks) { return (unsigned)(((nblocks + 7) / 8) * 8); }
+
 // ---- build stages (build.hip) ----
 hipError_t launch_geo_periodic(Geo *geo, double Lx, double Ly, int gx, int gy, int hb,
                                hipStream_t s);

@@ -31,17 +31,6 @@ constexpr float kW0 = 4.0f / 9.0f, kW1 = 1.0f / 9.0f, kW5 = 1.0f / 36.0f;
 
 __device__ __forceinline__ float wk32(int k) { return k == 0 ? kW0 : (k <= 4 ? kW1 : kW5); }
 
-// Workgroup -> tile map that gives each XCD a contiguous range of tiles (the
-// hardware deals workgroups round-robin over the 8 XCDs, each with its own
-// L2), so neighbouring tiles, which share stencil members, share an L2.
-__device__ __forceinline__ int64_t xcd_tile(int64_t nblocks) {
-    const int64_t b = blockIdx.x;
-    const int64_t per = (nblocks + 7) / 8;
-    return (b & 7) * per + (b >> 3);
-}
-
-inline unsigned xcd_grid(int64_t nblocks) { return (unsigned)(((nblocks + 7) / 8) * 8); }
-
 // ------------------------------------------------------------------------
 // FP32, deviation-stored populations
 // ------------------------------------------------------------------------
