@@ -21,17 +21,23 @@ __device__ __forceinline__ int stencil_owner(const int32_t *owner, int mode, int
     return mode == MLBM_STENCIL_OWN ? i : owner[(int64_t)(k - 1) * n + i];
 }
 
+// Row lengths and fill of the transposed operator: one thread per entry
+// (node i along x, direction k and stencil slot j along y), so the entries'
+// atomics overlap instead of queuing behind one thread's chain of 8K.
+__device__ __forceinline__ void tr_entry(int K, int &k, int &j) {
+    k = 1 + (int)blockIdx.y / K;
+    j = (int)blockIdx.y - (k - 1) * K;
+}
+
 __global__ void k_tr_count(int n, int K, int mode, const int32_t *__restrict__ nbr,
                            const int32_t *__restrict__ owner, int32_t *__restrict__ cnt) {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    for (int k = 1; k < kQ; ++k) {
-        const int s = stencil_owner(owner, mode, k, n, i);
-        for (int j = 0; j < K; ++j) {
-            const int m = nbr[(int64_t)j * n + s];
-            atomicAdd(&cnt[(int64_t)(k - 1) * n + m], 1);
-        }
-    }
+    int k, j;
+    tr_entry(K, k, j);
+    const int s = stencil_owner(owner, mode, k, n, i);
+    const int m = nbr[(int64_t)j * n + s];
+    atomicAdd(&cnt[(int64_t)(k - 1) * n + m], 1);
 }
 
 template <class T>
@@ -40,23 +46,21 @@ __global__ void k_tr_fill(int n, int K, int mode, const int32_t *__restrict__ nb
                           const double *__restrict__ W64, const int32_t *__restrict__ ptr,
                           int32_t *__restrict__ cur, int32_t *__restrict__ col,
                           T *__restrict__ val) {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    for (int k = 1; k < kQ; ++k) {
-        const int s = stencil_owner(owner, mode, k, n, i);
-        for (int j = 0; j < K; ++j) {
-            const int m = nbr[(int64_t)j * n + s];
-            const int64_t row = (int64_t)(k - 1) * n + m;
-            const int pos = ptr[row] + atomicAdd(&cur[row], 1);
-            col[pos] = i;
-            T w;
-            if (W64)
-                w = (T)W64[w64_at(k, j, n, i)];
-            else
-                w = (T)W32[(((int64_t)j * 2 + ((k - 1) >> 2)) * n + i) * 4 + ((k - 1) & 3)];
-            val[pos] = w;
-        }
-    }
+    int k, j;
+    tr_entry(K, k, j);
+    const int s = stencil_owner(owner, mode, k, n, i);
+    const int m = nbr[(int64_t)j * n + s];
+    const int64_t row = (int64_t)(k - 1) * n + m;
+    const int pos = ptr[row] + atomicAdd(&cur[row], 1);
+    col[pos] = i;
+    T w;
+    if (W64)
+        w = (T)W64[w64_at(k, j, n, i)];
+    else
+        w = (T)W32[(((int64_t)j * 2 + ((k - 1) >> 2)) * n + i) * 4 + ((k - 1) & 3)];
+    val[pos] = w;
 }
 
 // Sort each CSR row by arriving node. One wavefront per row: an arriving node
@@ -79,7 +83,7 @@ __global__ __launch_bounds__(256) void k_tr_sort(int64_t rows, const int32_t *__
             v = val[b + lane];
         }
         int rank = 0;
-        for (int j = 0; j < 64; ++j) rank += __shfl(c, j, 64) < c;
+        for (int j = 0; j < len; ++j) rank += __shfl(c, j, 64) < c;   // len: uniform
         if (lane < len) {
             col[b + rank] = c;
             val[b + rank] = v;
@@ -639,8 +643,8 @@ hipError_t launch_transpose(const CloudPlan &cp, int precision, void *tmp, size_
     const size_t scan_bytes = tmp_bytes - cnt_bytes;
     hipError_t e = launch_fill_i32(cnt, 0, rows, s);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_tr_count, dim3(blocks_for(n, 256)), dim3(256), 0, s, n, K, mode, cp.nbr,
-                       cp.owner, cnt);
+    const dim3 egrid(blocks_for(n, 256), 8 * K);   // one thread per entry
+    hipLaunchKernelGGL(k_tr_count, egrid, dim3(256), 0, s, n, K, mode, cp.nbr, cp.owner, cnt);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if ((e = exclusive_scan(scan_tmp, scan_bytes, cnt, cp.tr_ptr, (int)rows, s)) != hipSuccess)
         return e;
@@ -649,14 +653,14 @@ hipError_t launch_transpose(const CloudPlan &cp, int precision, void *tmp, size_
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if ((e = launch_fill_i32(cnt, 0, rows, s)) != hipSuccess) return e;
     if (precision == MLBM_FP64) {
-        hipLaunchKernelGGL(k_tr_fill<double>, dim3(blocks_for(n, 256)), dim3(256), 0, s, n, K,
+        hipLaunchKernelGGL(k_tr_fill<double>, egrid, dim3(256), 0, s, n, K,
                            mode, cp.nbr, cp.owner, (const float *)nullptr, cp.W64, cp.tr_ptr, cnt,
                            cp.tr_col, (double *)cp.tr_val);
         if ((e = hipGetLastError()) != hipSuccess) return e;
         hipLaunchKernelGGL(k_tr_sort<double>, dim3(blocks_for(rows, 4)), dim3(256), 0, s, rows,
                            cp.tr_ptr, cp.tr_col, (double *)cp.tr_val);
     } else {
-        hipLaunchKernelGGL(k_tr_fill<float>, dim3(blocks_for(n, 256)), dim3(256), 0, s, n, K,
+        hipLaunchKernelGGL(k_tr_fill<float>, egrid, dim3(256), 0, s, n, K,
                            mode, cp.nbr, cp.owner, cp.W32, (const double *)nullptr, cp.tr_ptr,
                            cnt, cp.tr_col, (float *)cp.tr_val);
         if ((e = hipGetLastError()) != hipSuccess) return e;
