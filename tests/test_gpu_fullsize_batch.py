@@ -1,0 +1,91 @@
+"""The batched workload at full size: 64 Taylor-Green clouds of uneven size
+(10^4 to 2x10^5 nodes, log-uniform, 3.83M nodes in all), each with its own tau
+and degree (K 12/20/30), own-node stencils, FP32, built and stepped in one HIP
+graph with the autotuned variant, as the benchmark runs it. Every cloud of the
+graph's result equals its single-cloud plan bit for bit, and sampled nodes of
+several clouds match the oracle's first step computed node by node."""
+import numpy as np
+import pytest
+
+import oracle
+from gpu_common import say
+from synth import batched_tgv_specs, jittered_lattice, tgv_initial_velocity
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _oracle_first_step(c, K, m, tau, ux, uy, i):
+    """(rho, ux, uy) of node i after one step with own-node stencils (dx = h),
+    from the equilibrium start: stencil of i, shape vectors of the eight
+    departure points, streamed post-collision populations, moments."""
+    ex, ey, _, _ = oracle.tables()
+    L = c.period[0]
+    st = oracle.knn_one(c.x, c.y, c.period, K, i)
+    rx = (c.x[st] - c.x[i] + 0.5 * L) % L - 0.5 * L
+    ry = (c.y[st] - c.y[i] + 0.5 * L) % L - 0.5 * L
+    post = oracle.collide(oracle.equilibrium(np.ones(K), ux[st], uy[st]), tau)
+    f = np.empty(9)
+    f[0] = post[0, 0]                        # st[0] is i itself
+    for k in range(1, 9):
+        w = oracle.shape_vector(rx, ry, -ex[k] * c.h, -ey[k] * c.h, m)
+        f[k] = w @ post[:, k]
+    r, u, v = oracle.moments(f[None, :])
+    return r[0], u[0], v[0]
+
+
+def test_fullsize_batched_graph_sampled():
+    from paper_2306_01525_amd import MLBM_STENCIL_OWN, Params, Plan
+    specs = batched_tgv_specs(64, seed=4)
+    cl, clouds, params, U = [], [], [], []
+    for sp in specs:
+        c = jittered_lattice(sp["n_side"], seed=sp["seed"])
+        a, b = tgv_initial_velocity(c.x, c.y, c.period[0], 0.01)
+        cl.append(c)
+        clouds.append((c.x, c.y, c.period, None))
+        params.append(Params(dx=c.h, K=sp["K"], degree=sp["degree"], tau=sp["tau"],
+                             stencil_mode=MLBM_STENCIL_OWN))
+        U.append((a, b))
+    ux = np.concatenate([a for a, _ in U])
+    uy = np.concatenate([b for _, b in U])
+    say("64 clouds, %d nodes: eager build + autotune" % ux.shape[0])
+    eager = Plan.build_batch(clouds, params)
+    ga, gb = eager.new_state(), eager.new_state()
+    eager.autotune(eager.init(ux, uy, g=ga), gb, 3)
+    variant = int(eager.info.variant)
+    eager.close()
+    del ga, gb
+    say("graph: build + init + 1 step, variant", variant)
+    s = torch.cuda.Stream()
+    plan, _, _, res = Plan.build_graph(clouds, params, ux, uy, 1, s, variant)
+    plan.graph_launch(s)
+    s.synchronize()
+    assert plan.device_error() == 0
+    rho_b, ux_b, uy_b = (t.cpu().numpy() for t in plan.moments(res))
+    torch.cuda.synchronize()
+    for c in range(len(specs)):
+        sp_ = Plan.build(clouds[c][0], clouds[c][1], clouds[c][2], params[c])
+        gs = sp_.step(sp_.init(*U[c]), sp_.new_state(), 1)
+        assert torch.equal(gs, plan.cloud_view(res, c)), c
+        sp_.close()
+    say("every cloud equals its single-cloud plan")
+    rng = np.random.default_rng(11)
+    sizes = np.array([c.n for c in cl])
+    picks = set(rng.choice(len(specs), 6, replace=False).tolist())
+    picks |= {int(sizes.argmin()), int(sizes.argmax())}
+    worst = 0.0
+    for c in sorted(picks):
+        sp = specs[c]
+        off = plan.offsets[c]
+        nodes = np.concatenate([rng.choice(cl[c].n, 16, replace=False), [0, cl[c].n - 1]])
+        for i in nodes:
+            r, u, v = _oracle_first_step(cl[c], sp["K"], sp["degree"], sp["tau"], U[c][0], U[c][1],
+                                         int(i))
+            d = max(abs(r - rho_b[off + i]), abs(u - ux_b[off + i]), abs(v - uy_b[off + i]))
+            worst = max(worst, d)
+            # FP32 deviations (|f - w rho0| <= ~0.03, ulp ~ 2e-9) and FP32
+            # weights (sum |w| <= ~5): one step stays far below 1e-6
+            assert d < 1e-6, (c, i, d)
+    say("sampled %d clouds: max |(rho, u) diff| after one step %.2e" % (len(picks), worst))
+    plan.close()
