@@ -216,12 +216,13 @@ __global__ __launch_bounds__(256) void k_ell_fill(int n, int lw, const int32_t *
     }
 }
 
-// Workgroup sum of one double per lane into part[at].
+// Workgroup sum of one double per lane (NT lanes) into part[at].
+template <int NT = 256>
 __device__ __forceinline__ void block_sum_to(double v, double *part, int64_t at) {
-    __shared__ double sh[256];
+    __shared__ double sh[NT];
     sh[threadIdx.x] = v;
     __syncthreads();
-    for (int w = 128; w > 0; w >>= 1) {
+    for (int w = NT / 2; w > 0; w >>= 1) {
         if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
         __syncthreads();
     }
@@ -407,8 +408,15 @@ __global__ __launch_bounds__(1024) void k_adj_tiles(int n, int lw, int hcap, int
 // lam_next of that halo in LDS and read the row heads through local indices;
 // other tiles (and the rare row tails beyond lw entries) read global memory.
 // Every row is summed in its sorted order, so both paths give identical sums.
+// Two wavefronts per group of 64 source nodes (512 threads per tile):
+// wavefront 2g + h walks group g's units for directions 1-4 (h = 0) or 5-8
+// (h = 1) and loads only its half of each unit (each half is one contiguous
+// run per slot block), which doubles the wavefronts that keep loads in flight.
+// Both take the same ballots (over the longest of the node's eight rows),
+// exchange their four row sums through LDS and finish the node together:
+// h = 0 stores lambda_0..4 and the tau partial, h = 1 stores lambda_5..8.
 template <class T>
-__global__ __launch_bounds__(256) void k_adj_step(
+__global__ __launch_bounds__(2 * kTile) void k_adj_step(
     int n, const T *__restrict__ fn, const T *__restrict__ lam_next, T *__restrict__ lam_n,
     const int32_t *__restrict__ ptr, const int32_t *__restrict__ col, const T *__restrict__ val,
     int lw, const int32_t *__restrict__ ecol, const T *__restrict__ eval,
@@ -416,47 +424,38 @@ __global__ __launch_bounds__(256) void k_adj_step(
     const uint32_t *__restrict__ elocal, int hcap, double rtau, double rho0, int dev,
     double *__restrict__ part) {
     extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ T s_x[kTile / 64][2][4][64];   // row sums exchanged between the halves
     typedef T T4 __attribute__((ext_vector_type(4)));
     typedef uint32_t U4 __attribute__((ext_vector_type(4)));
     typedef int32_t I4 __attribute__((ext_vector_type(4)));
-    // tiles in XCD-contiguous ranges: neighbouring tiles share much of
-    // their inverse halos
     const int64_t ntiles = ((int64_t)n + kTile - 1) / kTile;
     const int64_t tt = xcd_tile(ntiles);
     if (tt >= ntiles) return;
     const int t = (int)tt, tid = threadIdx.x;
-    const int m = t * kTile + tid;
+    const int wv = tid >> 6, lane = tid & 63;
+    const int hv = wv & 1, gq = wv >> 1;    // direction half, group within the tile
+    const int m = t * kTile + gq * 64 + lane;
     const int ni = tdescT ? tdescT[t] : 0;
     T *L = reinterpret_cast<T *>(smem);   // [8][ni]
 
-    // The eight transposed rows of node m are walked together (eight
-    // independent sums keep many loads in flight); each row is summed in its
-    // sorted order: head (zero-weight padding adds nothing), then the CSR
-    // tail of rows longer than lw. Lanes past the last node walk nothing.
-    T lg[kQ];
-    int bk[8], ln[8], hmax = 0;
+    T acc[4] = {0, 0, 0, 0};   // rows 4 hv + i
+    int hmax = 0;
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
-        bk[k] = ln[k] = 0;
         if (m < n) {
             const int64_t row = (int64_t)k * n + m;
-            bk[k] = ptr[row];
-            ln[k] = ptr[row + 1] - bk[k];
-            hmax = max(hmax, min(ln[k], lw));
+            hmax = max(hmax, min(ptr[row + 1] - ptr[row], lw));
         }
-        lg[k + 1] = 0;
     }
-    // The heads are compacted per wavefront (64 nodes): slot e holds one unit
-    // for each lane with hmax > e, stored as two halves (directions 1-4 of
-    // those lanes, then 5-8) so that each load of the wavefront is one
-    // contiguous run, and a ballot gives this lane's unit; slots past a row's
-    // end hold weight 0. The loads of a triple of slots are
-    // issued together (fetching one triple ahead, or the first one before the
-    // inverse halo is staged, measured slower: it costs a wavefront per SIMD).
-    // A lane past its head (or past the last node) reads its group's first
-    // unit instead (a line the group fetches anyway; one shared address for
-    // every such lane of the grid would be a hot spot) and adds nothing: its
-    // weights are zeroed and its local columns point at position 0.
+    // The heads are compacted per group of 64 nodes: slot e holds one unit
+    // for each node with hmax > e (ballot and masked bit count give a lane's
+    // unit), slots past a row's end hold weight 0, and a triple of slots is
+    // loaded together, non-temporal (the heads are streamed once per step and
+    // need not displace the lambda rows from L2); fetching one triple ahead
+    // measured slower. A lane past its head (or past the last node) reads its
+    // group's first unit (a line the group fetches anyway; one shared address
+    // for all such lanes would be a hot spot) and adds nothing: its weights
+    // are zeroed and its local columns point at position 0.
     const T4 *ev = reinterpret_cast<const T4 *>(eval);
     const U4 *elw = reinterpret_cast<const U4 *>(elocal);
     const int lw3 = (lw + 2) / 3;
@@ -467,90 +466,84 @@ __global__ __launch_bounds__(256) void k_adj_step(
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) wmax = max(wmax, __shfl_xor(wmax, off));
     const int ntrip = (wmax + 2) / 3;
-    struct Triple {
-        U4 wa, wb;
-        T4 va[3], vb[3];
-    };
-    auto fetch = [&](int w, Triple &tr) {
-        const bool onw = 3 * w < hmax;
-        const uint64_t mw = __ballot(onw);
-        const int cw = __popcll(mw);
-        const int64_t aw = onw ? 2 * (gw + woff) + lanes_below(mw) : 2 * gw;
-        const U4 wa = __builtin_nontemporal_load(elw + aw);
-        const U4 wb = __builtin_nontemporal_load(elw + aw + (onw ? cw : 0));
-        tr.wa = onw ? wa : (U4)0;
-        tr.wb = onw ? wb : (U4)0;
-        woff += cw;
-#pragma unroll
-        for (int sft = 0; sft < 3; ++sft) {
-            const bool on = 3 * w + sft < hmax;
-            const uint64_t me = __ballot(on);
-            const int ce = __popcll(me);
-            const int64_t a = on ? 2 * (gv + voff) + lanes_below(me) : 2 * gv;
-            const T4 va = __builtin_nontemporal_load(ev + a);
-            const T4 vb = __builtin_nontemporal_load(ev + a + (on ? ce : 0));
-            tr.va[sft] = on ? va : (T4)0;
-            tr.vb[sft] = on ? vb : (T4)0;
-            voff += ce;
-        }
-    };
     if (ni > 0) {
         const int32_t *il = ilist + (int64_t)t * hcap;
-        for (int h = tid; h < ni; h += kTile) {
+        for (int h = tid; h < ni; h += 2 * kTile) {
             int q = il[h];
             q = (unsigned)q < (unsigned)n ? q : 0;   // a bad table must not fault
 #pragma unroll
             for (int k = 1; k < kQ; ++k) L[(k - 1) * ni + h] = lam_next[(int64_t)k * n + q];
         }
         __syncthreads();
+        const T *Lh = L + 4 * hv * ni;
         for (int w = 0; w < ntrip; ++w) {
-            Triple cur;
-            fetch(w, cur);
+            const bool onw = 3 * w < hmax;
+            const uint64_t mw = __ballot(onw);
+            const int cw = __popcll(mw);
+            const int64_t aw = onw ? 2 * (gw + woff) + lanes_below(mw) + hv * cw : 2 * gw;
+            U4 wd = __builtin_nontemporal_load(elw + aw);
+            wd = onw ? wd : (U4)0;
+            woff += cw;
+            T4 v[3];
 #pragma unroll
             for (int sft = 0; sft < 3; ++sft) {
-                const T4 a4 = cur.va[sft], b4 = cur.vb[sft];
-                const U4 wa = cur.wa, wb = cur.wb;
+                const bool on = 3 * w + sft < hmax;
+                const uint64_t me = __ballot(on);
+                const int ce = __popcll(me);
+                const int64_t a = on ? 2 * (gv + voff) + lanes_below(me) + hv * ce : 2 * gv;
+                const T4 va = __builtin_nontemporal_load(ev + a);
+                v[sft] = on ? va : (T4)0;
+                voff += ce;
+            }
+#pragma unroll
+            for (int sft = 0; sft < 3; ++sft) {
                 const int sh = 10 * sft;
-                lg[1] += a4.x * L[0 * ni + ((wa.x >> sh) & 1023u)];
-                lg[2] += a4.y * L[1 * ni + ((wa.y >> sh) & 1023u)];
-                lg[3] += a4.z * L[2 * ni + ((wa.z >> sh) & 1023u)];
-                lg[4] += a4.w * L[3 * ni + ((wa.w >> sh) & 1023u)];
-                lg[5] += b4.x * L[4 * ni + ((wb.x >> sh) & 1023u)];
-                lg[6] += b4.y * L[5 * ni + ((wb.y >> sh) & 1023u)];
-                lg[7] += b4.z * L[6 * ni + ((wb.z >> sh) & 1023u)];
-                lg[8] += b4.w * L[7 * ni + ((wb.w >> sh) & 1023u)];
+                acc[0] += v[sft].x * Lh[0 * ni + ((wd.x >> sh) & 1023u)];
+                acc[1] += v[sft].y * Lh[1 * ni + ((wd.y >> sh) & 1023u)];
+                acc[2] += v[sft].z * Lh[2 * ni + ((wd.z >> sh) & 1023u)];
+                acc[3] += v[sft].w * Lh[3 * ni + ((wd.w >> sh) & 1023u)];
             }
         }
     }
-    double dt = 0.0;
     if (m < n) {
-        lg[0] = lam_next[m];
         if (ni == 0) {
             const I4 *ec = reinterpret_cast<const I4 *>(ecol);
+            const T *lk = lam_next + (int64_t)(1 + 4 * hv) * n;
             for (int e = 0; e < lw; ++e) {
                 const bool on = e < hmax;
                 const uint64_t me = __ballot(on);
                 if (me == 0) break;
                 const int ce = __popcll(me);
-                const int64_t a = on ? 2 * (gv + voff) + lanes_below(me) : 2 * gv;
-                const int64_t b = on ? a + ce : a;
-                const T4 va = on ? ev[a] : (T4)0, vb = on ? ev[b] : (T4)0;
-                const I4 ca = ec[a], cb = ec[b];
-                lg[1] += va.x * lam_next[1 * (int64_t)n + ca.x];
-                lg[2] += va.y * lam_next[2 * (int64_t)n + ca.y];
-                lg[3] += va.z * lam_next[3 * (int64_t)n + ca.z];
-                lg[4] += va.w * lam_next[4 * (int64_t)n + ca.w];
-                lg[5] += vb.x * lam_next[5 * (int64_t)n + cb.x];
-                lg[6] += vb.y * lam_next[6 * (int64_t)n + cb.y];
-                lg[7] += vb.z * lam_next[7 * (int64_t)n + cb.z];
-                lg[8] += vb.w * lam_next[8 * (int64_t)n + cb.w];
+                const int64_t a = on ? 2 * (gv + voff) + lanes_below(me) + hv * ce : 2 * gv;
+                const T4 va = on ? ev[a] : (T4)0;
+                const I4 ca = ec[a];
+                acc[0] += va.x * lk[0 * (int64_t)n + ca.x];
+                acc[1] += va.y * lk[1 * (int64_t)n + ca.y];
+                acc[2] += va.z * lk[2 * (int64_t)n + ca.z];
+                acc[3] += va.w * lk[3 * (int64_t)n + ca.w];
                 voff += ce;
             }
         }
 #pragma unroll
-        for (int k = 0; k < 8; ++k) {
+        for (int i = 0; i < 4; ++i) {
+            const int k = 4 * hv + i;
             const T *lk = lam_next + (int64_t)(k + 1) * n;
-            for (int e = bk[k] + lw; e < bk[k] + ln[k]; ++e) lg[k + 1] += val[e] * lk[col[e]];
+            const int64_t row = (int64_t)k * n + m;
+            const int b0 = ptr[row], b1 = ptr[row + 1];
+            for (int e = b0 + lw; e < b1; ++e) acc[i] += val[e] * lk[col[e]];
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) s_x[gq][hv][i][lane] = acc[i];
+    __syncthreads();
+    double dt = 0.0;
+    if (m < n) {
+        T lg[kQ];
+        lg[0] = lam_next[m];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            lg[1 + i] = hv ? s_x[gq][0][i][lane] : acc[i];
+            lg[5 + i] = hv ? acc[i] : s_x[gq][1][i][lane];
         }
         T fk[kQ], rho, ux, uy, drho;
         moments_of<T>(fn, n, m, dev, rho0, fk, rho, ux, uy, drho);
@@ -569,14 +562,16 @@ __global__ __launch_bounds__(256) void k_adj_step(
                                : fk[a] - w * rho * ((T)1 + poly);
             dtl += (double)lg[a] * (double)fneq;
         }
-        dt = dtl * rtau * rtau;
+        dt = hv ? 0.0 : dtl * rtau * rtau;
         const T rt = (T)rtau;
+        const int b0 = hv ? 5 : 0, b1 = hv ? kQ : 5;
 #pragma unroll
         for (int b = 0; b < kQ; ++b)
-            lam_n[(int64_t)b * n + m] =
-                ((T)1 - rt) * lg[b] + rt * (A + Bx * (T)lat_ex(b) + By * (T)lat_ey(b));
+            if (b >= b0 && b < b1)
+                lam_n[(int64_t)b * n + m] =
+                    ((T)1 - rt) * lg[b] + rt * (A + Bx * (T)lat_ex(b) + By * (T)lat_ey(b));
     }
-    block_sum_to(dt, part, t);
+    block_sum_to<2 * kTile>(dt, part, t);
 }
 
 // dJ/df_b for J = 1/2 sum |u - u*|^2: (r . (e_b - u)) / rho, r = u - u*.
@@ -712,19 +707,17 @@ hipError_t launch_step_adjoint(const CloudPlan &cp, int precision, const void *f
     const unsigned lds = cp.adj_ni ? (unsigned)(8 * cp.adj_ni * esz) : 0;
     const int32_t *td = cp.adj_ni ? cp.tdescT : nullptr;
     if (precision == MLBM_FP64)
-        hipLaunchKernelGGL(k_adj_step<double>, dim3(xcd_grid(nb)), dim3(256), lds, s, n,
-                           (const double *)fn,
-                           (const double *)lam_next, (double *)lam_n, cp.tr_ptr, cp.tr_col,
-                           (const double *)cp.tr_val, cp.tr_lw, cp.ell_col,
-                           (const double *)cp.ell_val, td, cp.ilist, cp.elocal, cp.hcap, rtau,
-                           cp.prm.rho0, 0, part);
+        hipLaunchKernelGGL(k_adj_step<double>, dim3(xcd_grid(nb)), dim3(2 * kTile), lds, s, n,
+                           (const double *)fn, (const double *)lam_next, (double *)lam_n,
+                           cp.tr_ptr, cp.tr_col, (const double *)cp.tr_val, cp.tr_lw,
+                           cp.ell_col, (const double *)cp.ell_val, td, cp.ilist, cp.elocal,
+                           cp.hcap, rtau, cp.prm.rho0, 0, part);
     else
-        hipLaunchKernelGGL(k_adj_step<float>, dim3(xcd_grid(nb)), dim3(256), lds, s, n,
-                           (const float *)fn,
-                           (const float *)lam_next, (float *)lam_n, cp.tr_ptr, cp.tr_col,
-                           (const float *)cp.tr_val, cp.tr_lw, cp.ell_col,
-                           (const float *)cp.ell_val, td, cp.ilist, cp.elocal, cp.hcap, rtau,
-                           cp.prm.rho0, 1, part);
+        hipLaunchKernelGGL(k_adj_step<float>, dim3(xcd_grid(nb)), dim3(2 * kTile), lds, s, n,
+                           (const float *)fn, (const float *)lam_next, (float *)lam_n,
+                           cp.tr_ptr, cp.tr_col, (const float *)cp.tr_val, cp.tr_lw,
+                           cp.ell_col, (const float *)cp.ell_val, td, cp.ilist, cp.elocal,
+                           cp.hcap, rtau, cp.prm.rho0, 1, part);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_sum_final, dim3(1), dim3(256), 0, s, nb, (const double *)part, dtau, 1);
