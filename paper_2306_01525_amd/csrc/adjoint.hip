@@ -414,7 +414,8 @@ __global__ __launch_bounds__(1024) void k_adj_tiles(int n, int lw, int hcap, int
 // run per slot block), which doubles the wavefronts that keep loads in flight.
 // Both take the same ballots (over the longest of the node's eight rows),
 // exchange their four row sums through LDS and finish the node together:
-// h = 0 stores lambda_0..4 and the tau partial, h = 1 stores lambda_5..8.
+// h = 0 reads f^n, passes its moments over and stores lambda_0..4 and the
+// tau partial, h = 1 stores lambda_5..8.
 template <class T>
 __global__ __launch_bounds__(2 * kTile) void k_adj_step(
     int n, const T *__restrict__ fn, const T *__restrict__ lam_next, T *__restrict__ lam_n,
@@ -425,6 +426,8 @@ __global__ __launch_bounds__(2 * kTile) void k_adj_step(
     double *__restrict__ part) {
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ T s_x[kTile / 64][2][4][64];   // row sums exchanged between the halves
+    __shared__ T s_m[kTile / 64][4][64];      // moments of f^n, from half 0 to half 1
+    __shared__ int s_hd[kTile / 64][2][64];   // head length over each half's rows
     typedef T T4 __attribute__((ext_vector_type(4)));
     typedef uint32_t U4 __attribute__((ext_vector_type(4)));
     typedef int32_t I4 __attribute__((ext_vector_type(4)));
@@ -439,14 +442,17 @@ __global__ __launch_bounds__(2 * kTile) void k_adj_step(
     T *L = reinterpret_cast<T *>(smem);   // [8][ni]
 
     T acc[4] = {0, 0, 0, 0};   // rows 4 hv + i
+    // each half reads its own four row lengths; the head length over all
+    // eight is exchanged across the staging barrier
     int hmax = 0;
 #pragma unroll
-    for (int k = 0; k < 8; ++k) {
+    for (int i = 0; i < 4; ++i) {
         if (m < n) {
-            const int64_t row = (int64_t)k * n + m;
+            const int64_t row = (int64_t)(4 * hv + i) * n + m;
             hmax = max(hmax, min(ptr[row + 1] - ptr[row], lw));
         }
     }
+    s_hd[gq][hv][lane] = hmax;
     // The heads are compacted per group of 64 nodes: slot e holds one unit
     // for each node with hmax > e (ballot and masked bit count give a lane's
     // unit), slots past a row's end hold weight 0, and a triple of slots is
@@ -462,10 +468,6 @@ __global__ __launch_bounds__(2 * kTile) void k_adj_step(
     const int64_t grp = min(m, n - 1) >> 6;   // lanes past the last node: its group
     const int64_t gv = grp * 64 * lw, gw = grp * 64 * lw3;
     int64_t voff = 0, woff = 0;
-    int wmax = hmax;
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) wmax = max(wmax, __shfl_xor(wmax, off));
-    const int ntrip = (wmax + 2) / 3;
     if (ni > 0) {
         const int32_t *il = ilist + (int64_t)t * hcap;
         for (int h = tid; h < ni; h += 2 * kTile) {
@@ -474,7 +476,14 @@ __global__ __launch_bounds__(2 * kTile) void k_adj_step(
 #pragma unroll
             for (int k = 1; k < kQ; ++k) L[(k - 1) * ni + h] = lam_next[(int64_t)k * n + q];
         }
-        __syncthreads();
+    }
+    __syncthreads();
+    hmax = max(hmax, s_hd[gq][1 - hv][lane]);
+    int wmax = hmax;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) wmax = max(wmax, __shfl_xor(wmax, off));
+    const int ntrip = (wmax + 2) / 3;
+    if (ni > 0) {
         const T *Lh = L + 4 * hv * ni;
         for (int w = 0; w < ntrip; ++w) {
             const bool onw = 3 * w < hmax;
@@ -535,6 +544,14 @@ __global__ __launch_bounds__(2 * kTile) void k_adj_step(
     }
 #pragma unroll
     for (int i = 0; i < 4; ++i) s_x[gq][hv][i][lane] = acc[i];
+    T fk[kQ], rho = 0, ux = 0, uy = 0, drho = 0;
+    if (hv == 0 && m < n) {
+        moments_of<T>(fn, n, m, dev, rho0, fk, rho, ux, uy, drho);
+        s_m[gq][0][lane] = rho;
+        s_m[gq][1][lane] = ux;
+        s_m[gq][2][lane] = uy;
+        s_m[gq][3][lane] = drho;
+    }
     __syncthreads();
     double dt = 0.0;
     if (m < n) {
@@ -545,8 +562,12 @@ __global__ __launch_bounds__(2 * kTile) void k_adj_step(
             lg[1 + i] = hv ? s_x[gq][0][i][lane] : acc[i];
             lg[5 + i] = hv ? acc[i] : s_x[gq][1][i][lane];
         }
-        T fk[kQ], rho, ux, uy, drho;
-        moments_of<T>(fn, n, m, dev, rho0, fk, rho, ux, uy, drho);
+        if (hv) {
+            rho = s_m[gq][0][lane];
+            ux = s_m[gq][1][lane];
+            uy = s_m[gq][2][lane];
+            drho = s_m[gq][3][lane];
+        }
         const T uu = ux * ux + uy * uy;
         T A = 0, Bx = 0, By = 0;
         double dtl = 0.0;
@@ -557,10 +578,12 @@ __global__ __launch_bounds__(2 * kTile) void k_adj_step(
             A += lg[a] * w * ((T)1 - (T)4.5 * eu * eu + (T)1.5 * uu);
             Bx += lg[a] * w * ((T)3 * ex + (T)9 * eu * ex - (T)3 * ux);
             By += lg[a] * w * ((T)3 * ey + (T)9 * eu * ey - (T)3 * uy);
-            const T poly = (T)3 * eu + (T)4.5 * eu * eu - (T)1.5 * uu;
-            const T fneq = dev ? fk[a] - w * (drho + rho * poly)
-                               : fk[a] - w * rho * ((T)1 + poly);
-            dtl += (double)lg[a] * (double)fneq;
+            if (hv == 0) {   // the tau partial, from the half that holds f^n
+                const T poly = (T)3 * eu + (T)4.5 * eu * eu - (T)1.5 * uu;
+                const T fneq = dev ? fk[a] - w * (drho + rho * poly)
+                                   : fk[a] - w * rho * ((T)1 + poly);
+                dtl += (double)lg[a] * (double)fneq;
+            }
         }
         dt = hv ? 0.0 : dtl * rtau * rtau;
         const T rt = (T)rtau;
