@@ -741,10 +741,10 @@ __device__ __forceinline__ void rbf_solve(const Geo *__restrict__ geo,
     if (singular && count > 0 && ll == 0) atomicMin(dev_err, perm[s] + 1);
 }
 
-// Occupancy against registers: 24 unknowns fit four wavefronts per SIMD, 32
-// and 48 three, 64 two (a few hundred bytes spill at 32, 48 and 64, which
-// costs less than the latency fewer wavefronts leave exposed). Up to 32
-// unknowns a wavefront holds two systems.
+// Occupancy against registers: 24 and 32 unknowns fit four wavefronts per
+// SIMD, 48 three, 64 two (with the replay, nothing spills except at 48
+// without it; a small spill costs less than the latency fewer wavefronts leave
+// exposed). Up to 32 unknowns a wavefront holds two systems.
 template <int NB, int R, int WPE, int SYS, bool REPLAY>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) void k_rbf(
     const Geo *__restrict__ geo, const double *__restrict__ xs, const double *__restrict__ ys,
@@ -939,7 +939,7 @@ template <int NB>
 static hipError_t launch_rbf_nb(const Geo *geo, const double *xs, const double *ys,
                                 const int32_t *perm, const int32_t *nbr, RhsList L, int n, int K,
                                 int m, double dx, double *W64, int32_t *dev_err, hipStream_t s) {
-    constexpr int wpe = NB == 24 ? 4 : NB == 64 ? 2 : 3;
+    constexpr int wpe = NB <= 32 ? 4 : NB == 64 ? 2 : 3;
     constexpr int sys = NB <= 32 ? 2 : 1;   // systems per wavefront
     dim3 grid(blocks_for(n, 4 * sys)), block(256);
     // own-node stencils (exactly 8 departure points per owner) take the
