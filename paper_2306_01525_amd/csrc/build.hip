@@ -919,6 +919,8 @@ hipError_t launch_knn(const Geo *geo, const double *xs, const double *ys,
     dim3 grid(blocks_for(n, 256)), block(256);
     if (K - 1 <= 16)
         hipLaunchKernelGGL(k_knn<16>, grid, block, 0, s, geo, xs, ys, perm, iperm, cstart, cend, n, K, nbr);
+    else if (K - 1 <= 24)   // (the list's cost per candidate grows with its length)
+        hipLaunchKernelGGL(k_knn<24>, grid, block, 0, s, geo, xs, ys, perm, iperm, cstart, cend, n, K, nbr);
     else if (K - 1 <= 32)
         hipLaunchKernelGGL(k_knn<32>, grid, block, 0, s, geo, xs, ys, perm, iperm, cstart, cend, n, K, nbr);
     else
