@@ -301,6 +301,7 @@ __device__ __forceinline__ int lower_bound_a(const int *a, int len, int v) {
 __global__ __launch_bounds__(1024) void k_adj_tiles(int n, int lw, int hcap, int cap,
                                                     const int32_t *__restrict__ ptr,
                                                     const int32_t *__restrict__ col,
+                                                    const int32_t *__restrict__ ecol,
                                                     int32_t *__restrict__ tdescT,
                                                     int32_t *__restrict__ ilist,
                                                     uint32_t *__restrict__ elocal,
@@ -353,38 +354,57 @@ __global__ __launch_bounds__(1024) void k_adj_tiles(int n, int lw, int hcap, int
         bitonic_sort_a(hsorted, np2);
         for (int h = tid; h < ni; h += blockDim.x) ilist[(int64_t)t * hcap + h] = hsorted[h];
         // local columns, one lane per node of the tile (the first four
-        // wavefronts, one per group of 64 nodes)
+        // wavefronts, one per group of 64 nodes): the columns come from the
+        // compacted heads, slot by slot (contiguous over the lanes; the rows
+        // themselves would be read with a stride across the lanes, triple
+        // after triple), and each lane stores its unit's two halves
         if (tid < kTile) {
+            typedef int32_t I4 __attribute__((ext_vector_type(4)));
+            typedef uint32_t U4 __attribute__((ext_vector_type(4)));
             const int m = base + tid;
-            int rb[8], len[8], hd = 0;
+            int len[8], hd = 0;
 #pragma unroll
             for (int k = 0; k < 8; ++k) {
-                rb[k] = len[k] = 0;
+                len[k] = 0;
                 if (m < n) {
                     const int64_t row = (int64_t)k * n + m;
-                    rb[k] = ptr[row];
-                    len[k] = ptr[row + 1] - rb[k];
+                    len[k] = ptr[row + 1] - ptr[row];
                     hd = max(hd, min(len[k], lw));
                 }
             }
-            const int64_t g0 = (int64_t)(m >> 6) * 64 * lw3;
-            int64_t off = 0;
+            const int64_t g0 = (int64_t)(m >> 6) * 64 * lw3;   // words of the group
+            const int64_t gv = (int64_t)(m >> 6) * 64 * lw;    // heads of the group
+            int64_t off = 0, voff = 0;
             for (int w = 0; w < lw3; ++w) {
                 const bool on = 3 * w < hd;
                 const uint64_t mask = __ballot(on);
                 if (mask == 0) break;
+                U4 wa = (U4)0, wb = (U4)0;
+#pragma unroll
+                for (int sft = 0; sft < 3; ++sft) {
+                    const int sl = 3 * w + sft;
+                    const bool ons = sl < hd;
+                    const uint64_t ms = __ballot(ons);
+                    const int cs = __popcll(ms);
+                    if (ons) {
+                        const int rs = lanes_below(ms);
+                        const int32_t *u = ecol + unit_entry(gv + voff, cs, rs, 0);
+                        const I4 ca = *reinterpret_cast<const I4 *>(u);
+                        const I4 cb = *reinterpret_cast<const I4 *>(u + 4 * cs);
+#pragma unroll
+                        for (int k = 0; k < 4; ++k) {
+                            if (sl < len[k])
+                                wa[k] |= (uint32_t)lower_bound_a(hsorted, ni, ca[k]) << (10 * sft);
+                            if (sl < len[k + 4])
+                                wb[k] |= (uint32_t)lower_bound_a(hsorted, ni, cb[k]) << (10 * sft);
+                        }
+                    }
+                    voff += cs;
+                }
                 if (on) {
                     const int r = lanes_below(mask), c = __popcll(mask);
-                    for (int k = 0; k < 8; ++k) {
-                        uint32_t word = 0;
-                        for (int sft = 0; sft < 3; ++sft) {
-                            const int sl = 3 * w + sft;
-                            if (sl < lw && sl < len[k])
-                                word |= (uint32_t)lower_bound_a(hsorted, ni, col[rb[k] + sl])
-                                        << (10 * sft);
-                        }
-                        elocal[unit_entry(g0 + off, c, r, k)] = word;
-                    }
+                    *reinterpret_cast<U4 *>(elocal + unit_entry(g0 + off, c, r, 0)) = wa;
+                    *reinterpret_cast<U4 *>(elocal + unit_entry(g0 + off, c, r, 4)) = wb;
                 }
                 off += __popcll(mask);
             }
@@ -763,7 +783,8 @@ hipError_t launch_init_adjoint(const CloudPlan &cp, int precision, const double 
 hipError_t launch_adj_tiles(const CloudPlan &cp, int32_t *stats, hipStream_t s) {
     const int ntiles = (cp.n + kTile - 1) / kTile;
     hipLaunchKernelGGL(k_adj_tiles, dim3(ntiles), dim3(1024), 0, s, cp.n, cp.tr_lw, cp.hcap,
-                       cp.adj_cap, cp.tr_ptr, cp.tr_col, cp.tdescT, cp.ilist, cp.elocal, stats);
+                       cp.adj_cap, cp.tr_ptr, cp.tr_col, cp.ell_col, cp.tdescT, cp.ilist,
+                       cp.elocal, stats);
     return hipGetLastError();
 }
 
