@@ -12,8 +12,13 @@ Also reported: the same step in plain FP64, the adjoint/forward cost of a
 checkpointed reverse sweep and of one reversed step, L2 errors against the
 analytic decay, the roofline position of the step kernel, the weight-build
 rate, the annular channel (about 490,000 Poisson-disk nodes with walls and
-body force), 64 uneven clouds in one graph, and the FP64 CPU oracle timed on
-the host cores on a bounded sample of the same workload.
+body force), 64 uneven clouds in one graph, and the FP64 CPU oracle run on the
+benchmarked cloud itself: the velocity of the timed FP32 and FP64 states and
+of the 2,000-step states against the oracle's, node by node, and the oracle's
+own rate on the host cores.
+
+Timing: the K timed steps are one HIP graph replayed 5 times; ms_per_step is
+the median replay over K (min and max are reported beside it).
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
 """
@@ -68,26 +73,44 @@ def step_kernel_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def time_steps(plan, g, steps, warmup, stream):
-    """W eager warm-up steps, then K steps replayed from a HIP graph, bracketed
-    by synchronisation and timed with events on the launch stream."""
+TIMING_REPS = 5   # replays of the timed graph; the median is reported
+
+
+def time_steps(plan, g, steps, warmup, stream, reps=TIMING_REPS):
+    """W eager warm-up steps, then a HIP graph of K steps replayed `reps` times,
+    each replay bracketed by synchronisation and timed with events on the
+    launch stream. Returns the per-replay milliseconds (in replay order), the
+    final state and the number of steps taken from g. With K even every replay
+    continues from the last one; with K odd each replay repeats the same K
+    steps from the same input."""
     import torch
     other = plan.new_state()
+    times = []
     with torch.cuda.stream(stream):
         res = plan.step(g, other, warmup, stream=stream)
         if res is other:
             g, other = other, g
         plan.graph_create(g, other, steps, stream)
         torch.cuda.synchronize()
-        e0 = torch.cuda.Event(enable_timing=True)
-        e1 = torch.cuda.Event(enable_timing=True)
-        e0.record(stream)
-        plan.graph_launch(stream)
-        e1.record(stream)
-        torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1)
+        for _ in range(reps):
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            plan.graph_launch(stream)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            times.append(e0.elapsed_time(e1))
     final = other if steps % 2 else g
-    return ms, final
+    taken = warmup + (steps if steps % 2 else steps * reps)
+    return times, final, taken
+
+
+def timing_summary(times, steps):
+    """Median, min and max of the per-replay times, per step."""
+    t = sorted(times)
+    return {"replays": len(t), "steps_per_replay": steps,
+            "ms_per_step_median": t[len(t) // 2] / steps, "ms_per_step_min": t[0] / steps,
+            "ms_per_step_max": t[-1] / steps}
 
 
 def run_gpu(args):
@@ -132,33 +155,48 @@ def run_gpu(args):
     log("autotune ms/step per variant:", " ".join("%.4f" % m for m in tune_ms),
         "-> variant", plan32.info.variant)
     del a, b
-    log("build %.1f ms; timing %d FP32 steps after %d warm-up" % (build_ms, args.steps, args.warmup))
+    log("build %.1f ms; timing %d FP32 steps after %d warm-up, %d replays"
+        % (build_ms, args.steps, args.warmup, TIMING_REPS))
     g = plan32.init(uxt, uyt)
     torch.cuda.synchronize()
-    ms32, g32 = time_steps(plan32, g, args.steps, args.warmup, stream)
-    # accuracy at the workload's full length (2,000 steps): the timed state
-    # is stepped on to that horizon
-    total = max(L2_STEPS, args.steps + args.warmup)
-    g32 = plan32.step(g32, plan32.new_state(), total - args.steps - args.warmup)
+    t32, g32, taken = time_steps(plan32, g, args.steps, args.warmup, stream)
+    out["timing32"] = timing_summary(t32, args.steps)
+    ms32 = out["timing32"]["ms_per_step_median"] * args.steps
+    # velocity of the timed state (kept for the comparison with the oracle),
+    # then the state is stepped on to the workload's full length (2,000 steps)
+    fields = {"fp32": {}, "fp64": {}}
+    _, u, v = plan32.moments(g32)
+    fields["fp32"][taken] = (u.cpu().numpy(), v.cpu().numpy())
+    total = max(L2_STEPS, taken)
+    g32 = plan32.step(g32, plan32.new_state(), total - taken)
     tx, ty = targets.tgv_velocity(c.x, c.y, L, u0, tau, c.h, total)
     tx_t, ty_t = torch.tensor(tx, device=dev), torch.tensor(ty, device=dev)
     l2u32, l2v32 = plan32.l2(g32, tx_t, ty_t)
     _, u32, v32 = plan32.moments(g32)
+    fields["fp32"][total] = (u32.cpu().numpy(), v32.cpu().numpy())
     out.update(ms32=ms32, build_ms=build_ms, build_cold_ms=build_cold_ms, l2_32=(l2u32, l2v32),
-               l2_steps=total)
-    log("FP32: %.3f ms/step, L2(u) vs analytic %.3e" % (ms32 / args.steps, l2u32))
+               l2_steps=total, timed_state_steps=taken, fields=fields, cloud=c,
+               velocity0=(ux, uy), tau=tau, degree=m)
+    log("FP32: %.4f ms/step (median of %d replays; min %.4f, max %.4f), L2(u) vs analytic %.3e"
+        % (ms32 / args.steps, TIMING_REPS, out["timing32"]["ms_per_step_min"],
+           out["timing32"]["ms_per_step_max"], l2u32))
 
     # FP64 plain form, same number of steps
     if not args.skip_fp64:
         plan64, build64_ms = build(MLBM_FP64)
         g = plan64.init(uxt, uyt)
-        ms64, g64 = time_steps(plan64, g, args.steps, args.warmup, stream)
-        g64 = plan64.step(g64, plan64.new_state(), total - args.steps - args.warmup)
+        t64, g64, taken64 = time_steps(plan64, g, args.steps, args.warmup, stream)
+        out["timing64"] = timing_summary(t64, args.steps)
+        ms64 = out["timing64"]["ms_per_step_median"] * args.steps
+        _, u, v = plan64.moments(g64)
+        fields["fp64"][taken64] = (u.cpu().numpy(), v.cpu().numpy())
+        g64 = plan64.step(g64, plan64.new_state(), total - taken64)
         l2u64, l2v64 = plan64.l2(g64, tx_t, ty_t)
         _, u64, v64 = plan64.moments(g64)
+        fields["fp64"][total] = (u64.cpu().numpy(), v64.cpu().numpy())
         d = torch.sqrt(((u32 - u64) ** 2 + (v32 - v64) ** 2).sum() / (u64 ** 2 + v64 ** 2).sum())
         out.update(ms64=ms64, l2_64=(l2u64, l2v64), fp32_vs_fp64=float(d))
-        log("FP64: %.3f ms/step, L2(u) vs analytic %.3e, FP32 vs FP64 %.3e"
+        log("FP64: %.4f ms/step, L2(u) vs analytic %.3e, FP32 vs FP64 %.3e"
             % (ms64 / args.steps, l2u64, float(d)))
         plan64.close()
         del plan64
@@ -234,12 +272,13 @@ def run_annulus(steps: int, warmup: int):
     tune = plan.autotune(plan.init(zeros, zeros), plan.new_state(), 20)
     log("annulus: autotune ms/step per variant:", " ".join("%.4f" % t for t in tune),
         "-> variant", plan.info.variant)
-    ms, g = time_steps(plan, plan.init(zeros, zeros), steps, warmup, stream)
+    times, g, _ = time_steps(plan, plan.init(zeros, zeros), steps, warmup, stream)
+    timing = timing_summary(times, steps)
     _, u, v = plan.moments(g)
     bpu = bytes_per_update(K, "f32", True)
-    per = ms / steps
+    per = timing["ms_per_step_median"]
     out = {"nodes": c.n, "K": K, "degree": 3, "steps": steps, "ms_per_step": per,
-           "value": c.n / (per / 1e3), "bytes_per_update": bpu,
+           "value": c.n / (per / 1e3), "bytes_per_update": bpu, "timing": timing,
            "roofline_frac": bpu * c.n / (per / 1e3) / 1e9 / HBM_PEAK_GBS,
            "build_ms": build_ms, "fallback_tiles": int(plan.info.fallback_tiles),
            "autotune_ms_per_step": tune, "variant": int(plan.info.variant),
@@ -367,28 +406,64 @@ def run_batched(steps: int):
             "variant": variant, "autotune_ms_per_step": tune, "device_error": err}
 
 
-def cpu_baseline(budget_s: float):
-    """The FP64 CPU oracle on a bounded sample of the same workload: a
-    128 x 128 cloud of the same kind (16,384 nodes, same jitter, K, degree,
-    tau, stencil rule), stepped until about budget_s seconds of CPU time."""
+def field_error(u, v, uo, vo):
+    """Relative L2 of the velocity against the oracle's, and the largest
+    per-node error |u - u_o| over the largest oracle speed."""
+    import numpy as np
+    du = np.hypot(u - uo, v - vo)
+    return {"rel_l2": float(np.sqrt((du ** 2).sum() / (uo ** 2 + vo ** 2).sum())),
+            "max_node_rel": float(du.max() / np.hypot(uo, vo).max())}
+
+
+def oracle_leg(r):
+    """The FP64 CPU oracle on the benchmarked cloud itself (the 262,144-node
+    Taylor-Green cloud, same K, degree, tau and stencil rule): its stencils,
+    owners (k-d tree candidates, exact selection) and shape vectors, then the
+    time loop to every step count at which the GPU states were kept. Returns
+    the error of each GPU state against the oracle's and the oracle's own
+    rates: all host threads over the whole run, and one thread over 3 steps."""
     import numpy as np
     import oracle
-    from synth import jittered_lattice, tgv_initial_velocity
-    c = jittered_lattice(128, seed=2)
-    nbr, own, W = oracle.build_plan(c, c.h, 30, 4, mode=0)
-    ux, uy = tgv_initial_velocity(c.x, c.y, c.period[0], 0.01)
-    f = oracle.equilibrium(np.ones(c.n), ux, uy)
-    f = oracle.run(f, nbr, own, W, 0.6, 2)    # warm
-    steps = 0
+    c = r["cloud"]
+    ux, uy = r["velocity0"]
+    tau, K, m = r["tau"], r["K"], r["degree"]
+    threads = oracle.threads()
     t0 = time.perf_counter()
-    while time.perf_counter() - t0 < budget_s:
-        f = oracle.run(f, nbr, own, W, 0.6, 10)
-        steps += 10
-    dt = time.perf_counter() - t0
-    return {"value": c.n * steps / dt, "unit": "node-updates/s", "cores": oracle.threads(),
+    nbr, own, W = oracle.build_plan(c, c.h, K, m, mode=0, search="tree")
+    build_s = time.perf_counter() - t0
+    log("oracle: built stencils, owners and shape vectors in %.1f s on %d threads"
+        % (build_s, threads))
+    f = oracle.equilibrium(np.ones(c.n), ux, uy)
+    marks = sorted({s for flds in r["fields"].values() for s in flds})
+    errs = {prec: {} for prec in r["fields"]}
+    done, step_s = 0, 0.0
+    for s in marks:
+        t0 = time.perf_counter()
+        f = oracle.run(f, nbr, own, W, tau, s - done)
+        step_s += time.perf_counter() - t0
+        done = s
+        _, uo, vo = oracle.moments(f)
+        for prec, flds in r["fields"].items():
+            if s in flds:
+                errs[prec][str(s)] = field_error(flds[s][0], flds[s][1], uo, vo)
+        log("oracle: step %d after %.1f s; " % (s, step_s) +
+            ", ".join("%s rel L2 %.3e, max node %.3e" % (p, e[str(s)]["rel_l2"],
+                                                         e[str(s)]["max_node_rel"])
+                      for p, e in errs.items() if str(s) in e))
+    oracle.set_threads(1)
+    t0 = time.perf_counter()
+    oracle.run(f, nbr, own, W, tau, 3)
+    one_s = time.perf_counter() - t0
+    oracle.set_threads(threads)
+    base = {"value": c.n * done / step_s, "unit": "node-updates/s", "cores": threads,
             "kind": "oracle",
-            "sample": "FP64 oracle on a 128x128 jittered TGV cloud (16,384 nodes, K 30, degree 4, "
-                      "tau 0.6, paper stencils), %d steps in %.1f s after setup" % (steps, dt)}
+            "sample": "FP64 oracle on the benchmarked TGV-512 cloud itself (262,144 nodes, K 30, "
+                      "degree 4, tau 0.6, paper stencils): %d steps in %.1f s on %d threads after "
+                      "a %.1f s build of stencils, owners and shape vectors"
+                      % (done, step_s, threads, build_s),
+            "build_s": build_s, "one_thread_value": c.n * 3 / one_s,
+            "search_fallbacks": dict(oracle.last_fallbacks)}
+    return errs, base
 
 
 COPY_BYTES = 256 << 20
@@ -587,7 +662,6 @@ def main():
     ap.add_argument("--skip-annulus", action="store_true")
     ap.add_argument("--skip-lbm", action="store_true")
     ap.add_argument("--batched-steps", type=int, default=500)
-    ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a copy of known size (for HBM counter scaling)")
     ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
@@ -639,6 +713,7 @@ def main():
         "steps": steps,
         "warmup": args.warmup,
         "ms_per_step": ms_step,
+        "timing": r["timing32"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -658,11 +733,13 @@ def main():
         },
         "l2_vs_analytic": {"steps": r["l2_steps"], "fp32_u": r["l2_32"][0],
                            "fp32_vec": r["l2_32"][1]},
+        "timed_state_steps": r["timed_state_steps"],
         "build_ms": r["build_ms"],
     }
     if "ms64" in r:
         line["fp64"] = {
             "value": n * steps / (r["ms64"] / 1e3), "ms_per_step": r["ms64"] / steps,
+            "timing": r["timing64"],
             "roofline_frac": bytes_per_update(K, "f64", True) * n / (r["ms64"] / steps / 1e3)
             / 1e9 / HBM_PEAK_GBS,
             "l2_vs_analytic_u": r["l2_64"][0],
@@ -690,8 +767,18 @@ def main():
     if not args.skip_batched:
         line["batched_64_clouds"] = run_batched(args.batched_steps)
     if not args.no_cpu_baseline:
-        log("timing the CPU oracle (%.0f s budget)" % args.cpu_budget)
-        line["cpu_baseline"] = cpu_baseline(args.cpu_budget)
+        log("running the FP64 oracle on the benchmarked cloud")
+        errs, base = oracle_leg(r)
+        line["l2_vs_oracle"] = errs
+        line["l2_vs_oracle"]["note"] = (
+            "velocity of the GPU state against the FP64 CPU oracle's after the same steps on "
+            "the same cloud: relative L2 over all nodes and the largest per-node error over "
+            "the largest oracle speed; keys are step counts (the timed state, then the full "
+            "run)")
+        e32 = errs.get("fp32", {}).get(str(r["l2_steps"]))
+        if e32:
+            line["l2_vs_oracle"]["fp32_over_method_error"] = e32["rel_l2"] / r["l2_32"][1]
+        line["cpu_baseline"] = base
     print(json.dumps(line), flush=True)
 
 

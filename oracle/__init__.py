@@ -48,10 +48,13 @@ _D = ctypes.c_double
 _SIGS = {
     "orc_tables": (None, [_P, _P, _P, _P]),
     "orc_threads": (_I, []),
+    "orc_set_threads": (None, [_I]),
     "orc_knn_one": (None, [_I, _P, _P, _D, _D, _I, _I, _P]),
     "orc_knn": (None, [_I, _P, _P, _D, _D, _I, _P]),
     "orc_nearest": (_I, [_I, _P, _P, _D, _D, _D, _D]),
     "orc_owners": (None, [_I, _P, _P, _D, _D, _D, _I, _P]),
+    "orc_knn_cand": (_I, [_I, _P, _P, _D, _D, _I, _I, _P, _P]),
+    "orc_owners_cand": (_I, [_I, _P, _P, _D, _D, _D, _I, _P, _P]),
     "orc_poly_count": (_I, [_I]),
     "orc_local_system": (_I, [_I, _I, _P, _P, _D, _D, _P, _P]),
     "orc_lu_solve": (_I, [_I, _P, _P, _P]),
@@ -117,6 +120,10 @@ def threads() -> int:
     return int(lib().orc_threads())
 
 
+def set_threads(t: int) -> None:
+    lib().orc_set_threads(int(t))
+
+
 # --------------------------------------------------------------------------
 # geometry
 # --------------------------------------------------------------------------
@@ -149,6 +156,65 @@ def owners(x, y, period, dx, mode):
     own = np.empty((n, 9), dtype=np.int32)
     lib().orc_owners(n, _p(x), _p(y), float(period[0]), float(period[1]), float(dx),
                      int(mode), _p(own))
+    return own
+
+
+# Candidate lists for large clouds: scipy's k-d tree reports the C nearest
+# nodes of every query point; the C functions take the exact answer from them
+# (or fall back to brute force where the list cannot be shown to hold it).
+KNN_EXTRA = 8        # candidates beyond K per stencil query
+OWNER_CAND = 4       # candidates per departure point
+
+last_fallbacks = {"knn": 0, "owners": 0}
+
+
+def _tree(x, y, period):
+    from scipy.spatial import cKDTree
+    pts = np.stack([x, y], axis=1)
+    periodic = period[0] > 0 and period[1] > 0
+    return cKDTree(pts, boxsize=(period[0], period[1]) if periodic else None), periodic
+
+
+def _wrap_query(px, py, period, periodic):
+    if periodic:
+        px = np.mod(px, period[0])
+        py = np.mod(py, period[1])
+        px[px >= period[0]] = 0.0
+        py[py >= period[1]] = 0.0
+    return np.stack([px, py], axis=1)
+
+
+def knn_tree(x, y, period, K):
+    """Same result as knn(), from k-d tree candidate lists."""
+    x, y = _f64(x), _f64(y)
+    n = x.shape[0]
+    C = min(n, K + KNN_EXTRA)
+    tree, periodic = _tree(x, y, period)
+    _, cand = tree.query(_wrap_query(x.copy(), y.copy(), period, periodic), k=C,
+                         workers=threads())
+    cand = _i32(np.asarray(cand).reshape(n, C))
+    nbr = np.empty((n, K), dtype=np.int32)
+    last_fallbacks["knn"] = int(lib().orc_knn_cand(n, _p(x), _p(y), float(period[0]),
+                                                   float(period[1]), K, C, _p(cand), _p(nbr)))
+    return nbr
+
+
+def owners_tree(x, y, period, dx, mode):
+    """Same result as owners(), from k-d tree candidate lists (mode 0)."""
+    if mode != 0:
+        return owners(x, y, period, dx, mode)
+    x, y = _f64(x), _f64(y)
+    n = x.shape[0]
+    ex, ey, _, _ = tables()
+    px = (x[:, None] - ex[None, 1:] * dx).ravel()
+    py = (y[:, None] - ey[None, 1:] * dx).ravel()
+    C = min(n, OWNER_CAND)
+    tree, periodic = _tree(x, y, period)
+    _, cand = tree.query(_wrap_query(px, py, period, periodic), k=C, workers=threads())
+    cand = _i32(np.asarray(cand).reshape(n * 8, C))
+    own = np.empty((n, 9), dtype=np.int32)
+    last_fallbacks["owners"] = int(lib().orc_owners_cand(
+        n, _p(x), _p(y), float(period[0]), float(period[1]), float(dx), C, _p(cand), _p(own)))
     return own
 
 
@@ -346,9 +412,15 @@ def adjoint(nbr, own, W, tau, steps, rho0, u0x, u0y, tx, ty):
 # whole-setup helpers
 # --------------------------------------------------------------------------
 
-def build_plan(cloud, dx, K, m, mode=0):
-    """Stencils, owners and shape vectors of a cloud (Appendix A, init loop)."""
-    nbr = knn(cloud.x, cloud.y, cloud.period, K)
-    own = owners(cloud.x, cloud.y, cloud.period, dx, mode)
+def build_plan(cloud, dx, K, m, mode=0, search="brute"):
+    """Stencils, owners and shape vectors of a cloud (Appendix A, init loop).
+    search: "brute" scans every node per query; "tree" takes the same answers
+    from k-d tree candidate lists (for clouds of 10^5 nodes and more)."""
+    if search == "tree":
+        nbr = knn_tree(cloud.x, cloud.y, cloud.period, K)
+        own = owners_tree(cloud.x, cloud.y, cloud.period, dx, mode)
+    else:
+        nbr = knn(cloud.x, cloud.y, cloud.period, K)
+        own = owners(cloud.x, cloud.y, cloud.period, dx, mode)
     W = weights(cloud.x, cloud.y, cloud.period, dx, K, m, nbr, own)
     return nbr, own, W

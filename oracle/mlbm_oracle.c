@@ -73,6 +73,15 @@ int orc_threads(void) {
 #endif
 }
 
+/* Thread count of later parallel loops (results do not depend on it). */
+void orc_set_threads(int t) {
+#ifdef _OPENMP
+    if (t > 0) omp_set_num_threads(t);
+#else
+    (void)t;
+#endif
+}
+
 /* ------------------------------------------------------------------------ */
 /* Geometry: periodic minimum image, stencils, closest Eulerian node         */
 /* ------------------------------------------------------------------------ */
@@ -162,6 +171,93 @@ void orc_owners(int n, const double *x, const double *y, double Lx, double Ly, d
             }
         }
     }
+}
+
+/* The same two searches for large clouds, from candidate lists that a spatial
+ * search library (a k-d tree) produced: cand[q][0..C-1] are C distinct nodes
+ * that it reports as the C nearest to query point q. The answer is taken from
+ * the candidates by the exact rule above (squared distance as written here,
+ * then index). It is provably the brute-force answer when every chosen
+ * distance is clearly below the farthest candidate's, since no node outside
+ * the list is nearer than that one (the margin 1e-9 covers the library's own
+ * rounding); otherwise that query falls back to the brute-force search. Each
+ * function returns how many queries fell back. */
+static const double CAND_MARGIN = 1.0 - 1e-9;
+
+int orc_knn_cand(int n, const double *x, const double *y, double Lx, double Ly, int K, int C,
+                 const int *cand, int *nbr) {
+    int fallbacks = 0;
+#pragma omp parallel for schedule(dynamic, 256) reduction(+ : fallbacks)
+    for (int c = 0; c < n; ++c) {
+        const int *cq = cand + (size_t)c * C;
+        double bd[K];
+        int bj[K];
+        int have = 0, self = 0;
+        double dmax = 0.0;
+        int *out = nbr + (size_t)c * K;
+        out[0] = c;
+        for (int e = 0; e < C; ++e) {
+            int j = cq[e];
+            double d = dist2(x[c], y[c], x[j], y[j], Lx, Ly);
+            if (d > dmax) dmax = d;
+            if (j == c) {
+                self = 1;
+                continue;
+            }
+            if (have == K - 1) {
+                if (d > bd[K - 1] || (d == bd[K - 1] && j > bj[K - 1])) continue;
+                have--;
+            }
+            int pos = have + 1;
+            while (pos > 1 && (bd[pos - 1] > d || (bd[pos - 1] == d && bj[pos - 1] > j))) {
+                bd[pos] = bd[pos - 1];
+                bj[pos] = bj[pos - 1];
+                pos--;
+            }
+            bd[pos] = d;
+            bj[pos] = j;
+            have++;
+        }
+        if (self && have == K - 1 && bd[K - 1] < dmax * CAND_MARGIN) {
+            for (int q = 1; q < K; ++q) out[q] = bj[q];
+        } else {
+            orc_knn_one(n, x, y, Lx, Ly, K, c, out);
+            fallbacks++;
+        }
+    }
+    return fallbacks;
+}
+
+/* Owners of the departure points (mode 0 of orc_owners) from candidate lists
+ * of the points x_i - e_k dx, k = 1..8: cand[(i * 8 + k - 1)][0..C-1]. */
+int orc_owners_cand(int n, const double *x, const double *y, double Lx, double Ly, double dx,
+                    int C, const int *cand, int *owner) {
+    int fallbacks = 0;
+#pragma omp parallel for schedule(dynamic, 256) reduction(+ : fallbacks)
+    for (int i = 0; i < n; ++i) {
+        owner[(size_t)i * Q] = i;
+        for (int k = 1; k < Q; ++k) {
+            double px = x[i] - EX[k] * dx, py = y[i] - EY[k] * dx;
+            const int *cq = cand + ((size_t)i * 8 + (k - 1)) * C;
+            int best = -1;
+            double bd = INFINITY, dmax = 0.0;
+            for (int e = 0; e < C; ++e) {
+                int j = cq[e];
+                double d = dist2(px, py, x[j], y[j], Lx, Ly);
+                if (d > dmax) dmax = d;
+                if (d < bd || (d == bd && j < best)) {
+                    bd = d;
+                    best = j;
+                }
+            }
+            if (!(best >= 0 && bd < dmax * CAND_MARGIN)) {
+                best = orc_nearest(n, x, y, Lx, Ly, px, py);
+                fallbacks++;
+            }
+            owner[(size_t)i * Q + k] = best;
+        }
+    }
+    return fallbacks;
 }
 
 /* ------------------------------------------------------------------------ */

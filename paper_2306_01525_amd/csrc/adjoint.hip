@@ -593,15 +593,16 @@ __global__ __launch_bounds__(2 * kTile) void k_adj_step(
         double dtl = 0.0;
 #pragma unroll
         for (int a = 0; a < kQ; ++a) {
-            const T ex = (T)lat_ex(a), ey = (T)lat_ey(a), w = (T)lat_w(a);
+            const T ex = (T)lat_ex(a), ey = (T)lat_ey(a);
             const T eu = ex * ux + ey * uy;
-            A += lg[a] * w * ((T)1 - (T)4.5 * eu * eu + (T)1.5 * uu);
-            Bx += lg[a] * w * ((T)3 * ex + (T)9 * eu * ex - (T)3 * ux);
-            By += lg[a] * w * ((T)3 * ey + (T)9 * eu * ey - (T)3 * uy);
+            const T wl = lat_wmul(a, lg[a]);
+            A += wl * ((T)1 - (T)4.5 * eu * eu + (T)1.5 * uu);
+            Bx += wl * ((T)3 * ex + (T)9 * eu * ex - (T)3 * ux);
+            By += wl * ((T)3 * ey + (T)9 * eu * ey - (T)3 * uy);
             if (hv == 0) {   // the tau partial, from the half that holds f^n
                 const T poly = (T)3 * eu + (T)4.5 * eu * eu - (T)1.5 * uu;
-                const T fneq = dev ? fk[a] - w * (drho + rho * poly)
-                                   : fk[a] - w * rho * ((T)1 + poly);
+                const T fneq = dev ? fk[a] - lat_wmul(a, drho + rho * poly)
+                                   : fk[a] - lat_wmul(a, rho * ((T)1 + poly));
                 dtl += (double)lg[a] * (double)fneq;
             }
         }

@@ -36,6 +36,24 @@ static_assert(lat_opp(1) == 3 && lat_opp(2) == 4 && lat_opp(3) == 1 && lat_opp(4
 
 constexpr int kQ = 9;
 
+// w_k x for a lattice weight w_k. 4/9, 1/9 and 1/36 are not binary fractions,
+// and their FP32 roundings are all high by the same relative 7.5e-9: an FP32
+// equilibrium built on them carries that much excess mass and momentum, which
+// every collision feeds back (a gain of 7.5e-9/tau per step that accumulates
+// linearly in time). In FP32 the weight is therefore applied as two FP32 parts
+// whose sum is w_k to 48 bits, so the product is rounded once from a nearly
+// exact value.
+template <class T>
+__device__ __forceinline__ T lat_wmul(int k, T x) {
+    return (T)lat_w(k) * x;
+}
+template <>
+__device__ __forceinline__ float lat_wmul<float>(int k, float x) {
+    const float hi = (float)lat_w(k);
+    const float lo = (float)(lat_w(k) - (double)hi);
+    return __builtin_fmaf(hi, x, lo * x);
+}
+
 // FP64 shape vectors, layout [K][4][n][2]: slot j of directions (1,2), (3,4),
 // (5,6), (7,8) of node p form one 16-byte pair, so a lane reads two directions
 // per load and a wavefront reads 1 KiB of consecutive memory.

@@ -27,10 +27,6 @@
 namespace mlbm {
 namespace {
 
-constexpr float kW0 = 4.0f / 9.0f, kW1 = 1.0f / 9.0f, kW5 = 1.0f / 36.0f;
-
-__device__ __forceinline__ float wk32(int k) { return k == 0 ? kW0 : (k <= 4 ? kW1 : kW5); }
-
 // ------------------------------------------------------------------------
 // FP32, deviation-stored populations
 // ------------------------------------------------------------------------
@@ -67,7 +63,7 @@ __device__ __forceinline__ void collide_store32(int n, int p, float (&f)[kQ],
 #pragma unroll
         for (int k = 0; k < kQ; ++k) {
             if (k < k0 || k >= k1) continue;
-            const float v = wk32(k) * (rho_w - rho0);
+            const float v = lat_wmul(k, rho_w - rho0);
             go[(int64_t)k * n + p] = v;
             if (REC) frec[(int64_t)k * n + p] = v;
         }
@@ -93,9 +89,9 @@ __device__ __forceinline__ void collide_store32(int n, int p, float (&f)[kQ],
     for (int k = 0; k < kQ; ++k) {
         if (k < k0 || k >= k1) continue;
         const float eu = (float)lat_ex(k) * ux + (float)lat_ey(k) * uy;
-        const float feq = wk32(k) * (drho + rho * (3.0f * eu + 4.5f * eu * eu - 1.5f * uu));
+        const float feq = lat_wmul(k, drho + rho * (3.0f * eu + 4.5f * eu * eu - 1.5f * uu));
         float v = f[k] - (f[k] - feq) * rtau;
-        if (FORCE) v += 3.0f * wk32(k) * ((float)lat_ex(k) * ax + (float)lat_ey(k) * ay);
+        if (FORCE) v += lat_wmul(k, 3.0f * ((float)lat_ex(k) * ax + (float)lat_ey(k) * ay));
         go[(int64_t)k * n + p] = v;
         if (REC) frec[(int64_t)k * n + p] = f[k];
     }
@@ -728,9 +724,8 @@ __global__ void k_collide(int n, const T *__restrict__ f, T *__restrict__ g,
     const T ux = jx / rho, uy = jy / rho, uu = ux * ux + uy * uy;
     for (int k = 0; k < kQ; ++k) {
         const T eu = (T)lat_ex(k) * ux + (T)lat_ey(k) * uy;
-        const T w = (T)lat_w(k);
         const T poly = (T)3 * eu + (T)4.5 * eu * eu - (T)1.5 * uu;
-        const T feq = dev ? w * (drho + rho * poly) : w * rho * ((T)1 + poly);
+        const T feq = dev ? lat_wmul(k, drho + rho * poly) : lat_wmul(k, rho * ((T)1 + poly));
         T v = fk[k] - (fk[k] - feq) * (T)rtau;
         if (force)
             v += (T)(3.0 * lat_w(k) * (lat_ex(k) * force[p] + lat_ey(k) * force[n + p]));

@@ -68,6 +68,21 @@ def first_step_rounding_bounds(nbr, own, W, f0, eps):
     return 8.0 * eps * b
 
 
+# FP64 GPU vs FP64 oracle after up to 2,000 steps of the full-size workload.
+TOL_FP64_FULL = 1e-10
+
+
+def tol_fp32_node(steps: int) -> float:
+    """Bound on the largest per-node velocity error of the FP32 path over the
+    largest oracle speed."""
+    return 4.0 * tol_fp32(steps)
+
+
+# Largest FP32 error against the oracle, as a share of the method's own
+# error against the analytic solution after the same steps.
+FP32_SHARE_OF_METHOD_ERROR = 0.25
+
+
 def tol_fp32(steps: int) -> float:
     """Relative L2 bound on the velocity of the FP32 deviation path against
     the FP64 oracle. Each step adds rounding of the stored deviations and of

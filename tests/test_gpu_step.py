@@ -34,14 +34,17 @@ def _gpu_run(plan, ux, uy, steps_list, rho=None):
     return out
 
 
-def _compare(ref, got, tol, label):
+def _compare(ref, got, tol, label, node_factor=4.0):
     for s in sorted(ref):
         r_o, u_o, v_o = ref[s]
         r_g, u_g, v_g = got[s]
         eu = rel_l2(np.stack([u_g, v_g]), np.stack([u_o, v_o]))
+        en = float(np.hypot(u_g - u_o, v_g - v_o).max() / np.hypot(u_o, v_o).max())
         er = float(np.abs(r_g - r_o).max())
-        say("  %s step %d: rel L2 velocity %.3e, max |drho| %.3e (tol %.1e)" % (label, s, eu, er, tol(s)))
+        say("  %s step %d: rel L2 velocity %.3e, max node %.3e, max |drho| %.3e (tol %.1e)"
+            % (label, s, eu, en, er, tol(s)))
         assert eu < tol(s), (label, s, eu)
+        assert en < node_factor * tol(s), (label, s, en)
         assert er < tol(s), (label, s, er)
 
 

@@ -73,3 +73,37 @@ def test_periodic_wrap_is_minimum_image():
     assert nbr[0, 1] == 1 and nbr[1, 1] == 0
     nbr_open = oracle.knn(x, y, (0.0, 0.0), 2)
     assert nbr_open[0, 1] == 3
+
+
+@pytest.mark.parametrize("kind", ["periodic", "annulus", "lattice"])
+def test_tree_candidates_give_the_bruteforce_answers(kind, monkeypatch):
+    """The k-d tree candidate path used for full-size clouds returns exactly
+    the brute-force stencils and owners, including exact lattice ties; with no
+    spare candidates the ties at the cut cannot be settled from the list and
+    the fallback to brute force must still give the same answers."""
+    if kind == "periodic":
+        c = jittered_lattice(21, length=1.0, seed=5, ny=17, length_y=0.81)
+    elif kind == "annulus":
+        c = annulus_poisson(1.0, 2.0, 0.12, seed=4)
+    else:
+        c = jittered_lattice(10, length=10.0, jitter=0.0)
+    for extra in (8, 0):
+        monkeypatch.setattr(oracle, "KNN_EXTRA", extra)
+        monkeypatch.setattr(oracle, "OWNER_CAND", 4 if extra else 1)
+        for K in (6, 13, 20):
+            np.testing.assert_array_equal(oracle.knn_tree(c.x, c.y, c.period, K),
+                                          oracle.knn(c.x, c.y, c.period, K))
+            if extra == 0:
+                assert oracle.last_fallbacks["knn"] > 0
+        dx = 0.9 * c.h
+        np.testing.assert_array_equal(oracle.owners_tree(c.x, c.y, c.period, dx, 0),
+                                      oracle.owners(c.x, c.y, c.period, dx, 0))
+        if extra == 0:
+            assert oracle.last_fallbacks["owners"] == 8 * c.n
+    if kind == "lattice":
+        # on the lattice every departure point sits on a node: the list of one
+        # candidate holds the owner but cannot prove it, the others can
+        monkeypatch.setattr(oracle, "OWNER_CAND", 4)
+        np.testing.assert_array_equal(oracle.owners_tree(c.x, c.y, c.period, c.h, 0),
+                                      oracle.owners(c.x, c.y, c.period, c.h, 0))
+        assert oracle.last_fallbacks["owners"] == 0
