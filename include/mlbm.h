@@ -199,7 +199,9 @@ mlbm_status mlbm_plan_destroy(mlbm_plan *plan);   /* frees the host object only 
 
 /* Change the relaxation time tau (> 0.5) of every cloud of the plan. The
  * shape vectors do not depend on tau, so nothing is rebuilt; a graph created
- * earlier is dropped (it holds the old value). */
+ * earlier is dropped (it holds the old value). Synchronous: it waits for the
+ * device, and a multi-cloud plan's step descriptors are rewritten in place, so
+ * no step of this plan may be in flight on another thread. */
 mlbm_status mlbm_plan_set_tau(mlbm_plan *plan, double tau);
 
 /* ---- time stepping (Algorithm 1, time loop) ------------------------------- */
@@ -359,9 +361,38 @@ mlbm_status mlbm_graph_launch(mlbm_plan *plan, hipStream_t stream);
 
 const char *mlbm_last_error(void);
 
-/* Sticky device error word of the plan, read synchronously: 0 none; > 0 the
- * 1-based user index of the first node whose local system was singular. */
+/* Conditions the kernels record in a plan's sticky device error words (bits;
+ * several may be set). They never stop a kernel: a diverging run finishes its
+ * steps and the caller decides what to do. */
+enum {
+    MLBM_DEVERR_SINGULAR = 1,   /* a local RBF system was numerically singular
+                                   (mlbm_build_weights, mostly under capture)      */
+    MLBM_DEVERR_INDEX = 2,      /* a gather table of the plan held a node index
+                                   outside the cloud; that gather read node 0
+                                   instead (the plan buffer was overwritten)       */
+    MLBM_DEVERR_NONFINITE = 4,  /* a node's density or velocity was NaN or Inf     */
+    MLBM_DEVERR_SPEED = 8       /* a node's speed exceeded 0.3 (lattice units;
+                                   Mach 0.52): the run is diverging, as the method
+                                   does for some stencils and spacings (Sec. 3)    */
+};
+
+/* The plan's device error bits (MLBM_DEVERR_*), read synchronously (waits for
+ * the device): 0 none, -1 if the read failed. Set by the build (singular
+ * systems), by every step (non-finite or too fast nodes, out-of-range halo
+ * indices) and by mlbm_moments, mlbm_l2_sums and mlbm_residual (non-finite or
+ * too fast nodes). */
 int32_t mlbm_device_error(const mlbm_plan *plan);
+
+/* The nodes behind the bits, synchronous: *singular_node = user index of the
+ * first node (lowest index) whose local system was singular, and
+ * *diverged_node = the lowest user index reported non-finite or too fast; -1
+ * where none is known. Either pointer may be NULL (host). */
+mlbm_status mlbm_device_error_nodes(const mlbm_plan *plan, int32_t *singular_node,
+                                    int32_t *diverged_node);
+
+/* Reset the device error words to "none" (enqueued on `stream`; kernels only,
+ * so it may be captured). */
+mlbm_status mlbm_device_error_clear(mlbm_plan *plan, hipStream_t stream);
 
 #ifdef __cplusplus
 }

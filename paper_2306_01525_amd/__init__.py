@@ -4,8 +4,9 @@ C-ABI (include/mlbm.h), with a thin PyTorch-side binding.
 Importing this package does not touch the GPU; the HIP library is loaded on
 first use and its absence raises ImportError.
 """
-from ._lib import (MLBM_FP32_DEV, MLBM_FP64, MLBM_STENCIL_OWN,  # noqa: F401
-                   MLBM_STENCIL_PAPER, MLBMError)
+from ._lib import (MLBM_DEVERR_INDEX, MLBM_DEVERR_NONFINITE,  # noqa: F401
+                   MLBM_DEVERR_SINGULAR, MLBM_DEVERR_SPEED, MLBM_FP32_DEV, MLBM_FP64,
+                   MLBM_STENCIL_OWN, MLBM_STENCIL_PAPER, MLBMError)
 
 
 def __getattr__(name):

@@ -16,6 +16,11 @@ MLBM_EUNSUPPORTED = -5
 
 MLBM_FP32_DEV = 0
 MLBM_FP64 = 1
+# sticky device error bits (mlbm_device_error)
+MLBM_DEVERR_SINGULAR = 1
+MLBM_DEVERR_INDEX = 2
+MLBM_DEVERR_NONFINITE = 4
+MLBM_DEVERR_SPEED = 8
 MLBM_STENCIL_PAPER = 0
 MLBM_STENCIL_OWN = 1
 
@@ -82,6 +87,8 @@ SIGNATURES = {
     "mlbm_graph_launch": (_c_i32, [_c_p, _c_p]),
     "mlbm_last_error": (ctypes.c_char_p, []),
     "mlbm_device_error": (_c_i32, [_c_p]),
+    "mlbm_device_error_nodes": (_c_i32, [_c_p, _P(_c_i32), _P(_c_i32)]),
+    "mlbm_device_error_clear": (_c_i32, [_c_p, _c_p]),
 }
 
 _lib = None

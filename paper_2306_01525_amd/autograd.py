@@ -17,10 +17,17 @@ from .mlbm import Plan
 
 
 class Rollout:
+    """One checkpointed rollout on a plan. The relaxation time in force when
+    forward() runs is recorded, and backward() recomputes and differentiates
+    at that value whatever the plan holds by then (the plan's value is put
+    back afterwards), so several rollouts on one plan may be differentiated in
+    any order."""
+
     def __init__(self, plan: Plan, steps: int, segment: int = 50):
         if steps < 1 or segment < 1:
             raise ValueError("steps and segment must be positive")
         self.plan = plan
+        self.tau = None
         self.T = int(steps)
         self.C = int(segment)
         self.nseg = (self.T + self.C - 1) // self.C
@@ -34,6 +41,7 @@ class Rollout:
         """Run T steps; returns f^T (pre-collision) and keeps checkpoints."""
         plan = self.plan
         self.u0 = (u0x, u0y)
+        self.tau = float(plan.params.tau)
         ck = [plan.init_f(u0x, u0y, stream=stream)]
         g = plan.collide(ck[0], stream=stream)
         other = plan.new_state()
@@ -59,6 +67,17 @@ class Rollout:
 
     def backward(self, stream=None):
         """Returns (dJ/du0x, dJ/du0y, dJ/dtau) as device tensors."""
+        plan = self.plan
+        held = float(plan.params.tau)
+        if held != self.tau:
+            plan.set_tau(self.tau)
+        try:
+            return self._backward(stream)
+        finally:
+            if held != self.tau:
+                plan.set_tau(held)
+
+    def _backward(self, stream):
         plan = self.plan
         lam = self.lam_T
         lam_other = plan.new_state()

@@ -443,7 +443,7 @@ __global__ __launch_bounds__(2 * kTile) void k_adj_step(
     int lw, const int32_t *__restrict__ ecol, const T *__restrict__ eval,
     const int32_t *__restrict__ tdescT, const int32_t *__restrict__ ilist,
     const uint32_t *__restrict__ elocal, int hcap, double rtau, double rho0, int dev,
-    double *__restrict__ part) {
+    double *__restrict__ part, int32_t *err) {
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ T s_x[kTile / 64][2][4][64];   // row sums exchanged between the halves
     __shared__ T s_m[kTile / 64][4][64];      // moments of f^n, from half 0 to half 1
@@ -492,7 +492,10 @@ __global__ __launch_bounds__(2 * kTile) void k_adj_step(
         const int32_t *il = ilist + (int64_t)t * hcap;
         for (int h = tid; h < ni; h += 2 * kTile) {
             int q = il[h];
-            q = (unsigned)q < (unsigned)n ? q : 0;   // a bad table must not fault
+            if ((unsigned)q >= (unsigned)n) {   // a bad table must not fault
+                q = 0;
+                report_index(err);
+            }
 #pragma unroll
             for (int k = 1; k < kQ; ++k) L[(k - 1) * ni + h] = lam_next[(int64_t)k * n + q];
         }
@@ -755,13 +758,13 @@ hipError_t launch_step_adjoint(const CloudPlan &cp, int precision, const void *f
                            (const double *)fn, (const double *)lam_next, (double *)lam_n,
                            cp.tr_ptr, cp.tr_col, (const double *)cp.tr_val, cp.tr_lw,
                            cp.ell_col, (const double *)cp.ell_val, td, cp.ilist, cp.elocal,
-                           cp.hcap, rtau, cp.prm.rho0, 0, part);
+                           cp.hcap, rtau, cp.prm.rho0, 0, part, cp.err);
     else
         hipLaunchKernelGGL(k_adj_step<float>, dim3(xcd_grid(nb)), dim3(2 * kTile), lds, s, n,
                            (const float *)fn, (const float *)lam_next, (float *)lam_n,
                            cp.tr_ptr, cp.tr_col, (const float *)cp.tr_val, cp.tr_lw,
                            cp.ell_col, (const float *)cp.ell_val, td, cp.ilist, cp.elocal,
-                           cp.hcap, rtau, cp.prm.rho0, 1, part);
+                           cp.hcap, rtau, cp.prm.rho0, 1, part, cp.err);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_sum_final, dim3(1), dim3(256), 0, s, nb, (const double *)part, dtau, 1);

@@ -176,6 +176,13 @@ void layout_common(Carve &pl, mlbm_plan &plan, int64_t n_total, int n_clouds = 1
         pl.take<double>(16 + 4 * (size_t)n_clouds + (size_t)blocks_for(n_total, 256) * 4);
 }
 
+// Error words to "none": no singular node, no flags, no reported node.
+hipError_t reset_errors(mlbm_plan *plan, hipStream_t s) {
+    hipError_t e = launch_fill_i32(plan->dev_err, INT_MAX, 3, s);
+    if (e == hipSuccess) e = launch_fill_i32(plan->dev_err + kErrFlags, 0, 1, s);
+    return e;
+}
+
 bool capturing(hipStream_t s) {
     hipStreamCaptureStatus st = hipStreamCaptureStatusNone;
     if (hipStreamIsCapturing(s, &st) != hipSuccess) return false;
@@ -300,7 +307,8 @@ bool batchable(const mlbm_params *params, int32_t n_clouds) {
 }
 
 void layout_plan(const mlbm_cloud *clouds, const mlbm_params *params, int32_t n_clouds,
-                 void *plan_buf, void *workspace, PlanLayout &L, mlbm_plan &plan) {
+                 void *plan_buf, void *workspace, PlanLayout &L, mlbm_plan &plan,
+                 int max_lanes = kBuildLanes) {
     Carve pl(plan_buf);
     L.cps.assign(n_clouds, CloudPlan());
     L.bws.assign(n_clouds, BuildWs());
@@ -314,7 +322,7 @@ void layout_plan(const mlbm_cloud *clouds, const mlbm_params *params, int32_t n_
         layout_cloud(clouds[c], params[c], params[0].precision, p0, &w0, cp0, &bw0);
         stride = std::max(stride, (w0.used + 255) & ~size_t(255));
     }
-    L.lanes = std::min(n_clouds, kBuildLanes);
+    L.lanes = std::max(1, std::min(n_clouds, max_lanes));
     int64_t off = 0, tiles = 0;
     for (int c = 0; c < n_clouds; ++c) {
         Carve ws(workspace ? (char *)workspace + (size_t)(c % L.lanes) * stride : nullptr);
@@ -450,27 +458,30 @@ mlbm_status build_batch(mlbm_plan *plan, hipStream_t s) {
 
 }  // namespace
 
-mlbm_status mlbm_weights_query(const mlbm_cloud *clouds, const mlbm_params *params,
-                               int32_t n_clouds, size_t *plan_bytes, size_t *workspace_bytes) {
+namespace {
+
+// Plan and workspace sizes with at most max_lanes clouds built at once.
+mlbm_status query_lanes(const mlbm_cloud *clouds, const mlbm_params *params, int32_t n_clouds,
+                        int max_lanes, size_t *plan_bytes, size_t *workspace_bytes) {
     if (!plan_bytes || !workspace_bytes) return fail(MLBM_EINVAL, "null output pointer");
     mlbm_status st = check_batch(clouds, params, n_clouds, false);
     if (st != MLBM_OK) return st;
     PlanLayout L;
     mlbm_plan tmp;
-    layout_plan(clouds, params, n_clouds, nullptr, nullptr, L, tmp);
+    layout_plan(clouds, params, n_clouds, nullptr, nullptr, L, tmp, max_lanes);
     *plan_bytes = L.plan_used + 256;
     *workspace_bytes = L.ws_max + 256;
     return MLBM_OK;
 }
 
-mlbm_status mlbm_build_weights(const mlbm_cloud *clouds, const mlbm_params *params,
-                               int32_t n_clouds, void *plan_buf, size_t plan_bytes,
-                               void *workspace, size_t workspace_bytes, mlbm_plan **out,
-                               hipStream_t s) {
+mlbm_status build_weights_lanes(const mlbm_cloud *clouds, const mlbm_params *params,
+                                int32_t n_clouds, void *plan_buf, size_t plan_bytes,
+                                void *workspace, size_t workspace_bytes, int max_lanes,
+                                mlbm_plan **out, hipStream_t s) {
     if (!out) return fail(MLBM_EINVAL, "null output pointer");
     *out = nullptr;
     size_t need_p = 0, need_w = 0;
-    mlbm_status st = mlbm_weights_query(clouds, params, n_clouds, &need_p, &need_w);
+    mlbm_status st = query_lanes(clouds, params, n_clouds, max_lanes, &need_p, &need_w);
     if (st != MLBM_OK) return st;
     st = check_batch(clouds, params, n_clouds, true);
     if (st != MLBM_OK) return st;
@@ -481,13 +492,14 @@ mlbm_status mlbm_build_weights(const mlbm_cloud *clouds, const mlbm_params *para
     if (!plan) return fail(MLBM_EINVAL, "out of host memory");
     plan->precision = params[0].precision;
     PlanLayout L;
-    layout_plan(clouds, params, n_clouds, plan_buf, workspace, L, *plan);
+    layout_plan(clouds, params, n_clouds, plan_buf, workspace, L, *plan, max_lanes);
     plan->c = L.cps;
+    for (CloudPlan &cp : plan->c) cp.err = plan->dev_err;
     auto cleanup = [&](mlbm_status r) {
         delete plan;
         return r;
     };
-    hipError_t e = launch_fill_i32(plan->dev_err, INT_MAX, 1, s);
+    hipError_t e = reset_errors(plan, s);
     if (e == hipSuccess) e = launch_fill_i32(plan->stats, 0, (int64_t)kStats * n_clouds, s);
     if (e != hipSuccess) return cleanup(hip_fail(e, "launch_fill_i32"));
     st = build_clouds(plan, clouds, params, L, s);
@@ -500,6 +512,21 @@ mlbm_status mlbm_build_weights(const mlbm_cloud *clouds, const mlbm_params *para
     if (st != MLBM_OK) return cleanup(st);
     *out = plan;
     return MLBM_OK;
+}
+
+}  // namespace
+
+mlbm_status mlbm_weights_query(const mlbm_cloud *clouds, const mlbm_params *params,
+                               int32_t n_clouds, size_t *plan_bytes, size_t *workspace_bytes) {
+    return query_lanes(clouds, params, n_clouds, kBuildLanes, plan_bytes, workspace_bytes);
+}
+
+mlbm_status mlbm_build_weights(const mlbm_cloud *clouds, const mlbm_params *params,
+                               int32_t n_clouds, void *plan_buf, size_t plan_bytes,
+                               void *workspace, size_t workspace_bytes, mlbm_plan **out,
+                               hipStream_t s) {
+    return build_weights_lanes(clouds, params, n_clouds, plan_buf, plan_bytes, workspace,
+                               workspace_bytes, kBuildLanes, out, s);
 }
 
 mlbm_status mlbm_import_query(int32_t n, const mlbm_params *params, size_t *plan_bytes) {
@@ -588,7 +615,8 @@ mlbm_status mlbm_import_weights(int32_t n, const double *x, const double *y,
     if (cp.W32) STEP(launch_pack_w32(cp.W64, n, K, cp.W32, s));
     STEP(launch_force(cp.xs, cp.ys, cp.ntype, n, p.force_kind, p.force_mag, cp.force32,
                       cp.force64, s));
-    STEP(launch_fill_i32(plan->dev_err, INT_MAX, 1, s));
+    cp.err = plan->dev_err;
+    STEP(reset_errors(plan, s));
     if (p.with_adjoint) {
         // This path has no workspace argument, so the transposed operator is
         // assembled on the host (rows filled in ascending arriving node, which
@@ -766,15 +794,53 @@ mlbm_status mlbm_plan_set_tau(mlbm_plan *plan, double tau) {
     if (!(tau > 0.5)) return fail(MLBM_EINVAL, "tau must exceed 0.5");
     for (auto &cp : plan->c) cp.prm.tau = tau;
     drop_graph(plan);
+    if (plan->batched) {
+        // the batched step reads each cloud's relaxation rate from the device
+        // descriptor table: rewrite the table (synchronous copies)
+        MLBM_HIP(hipDeviceSynchronize());
+        int64_t tb = 0;
+        for (size_t c = 0; c < plan->c.size(); ++c) {
+            const CloudPlan &cp = plan->c[c];
+            Step32Args a = step32_args(cp, nullptr);
+            a.soff = (int64_t)kQ * cp.off;
+            a.tile_begin = tb;
+            tb += (cp.n + kTile - 1) / kTile;
+            MLBM_HIP(hipMemcpy(plan->descs + c, &a, sizeof(a), hipMemcpyHostToDevice));
+        }
+    }
     return MLBM_OK;
 }
 
+namespace {
+mlbm_status read_errors(const mlbm_plan *plan, int32_t (&w)[3]) {
+    MLBM_HIP(hipDeviceSynchronize());
+    MLBM_HIP(hipMemcpy(w, plan->dev_err, sizeof(w), hipMemcpyDeviceToHost));
+    return MLBM_OK;
+}
+}  // namespace
+
 int32_t mlbm_device_error(const mlbm_plan *plan) {
     if (!plan || !plan->dev_err) return 0;
-    int32_t v = INT_MAX;
-    if (hipDeviceSynchronize() != hipSuccess) return -1;
-    if (hipMemcpy(&v, plan->dev_err, sizeof(v), hipMemcpyDeviceToHost) != hipSuccess) return -1;
-    return v == INT_MAX ? 0 : v;
+    int32_t w[3];
+    if (read_errors(plan, w) != MLBM_OK) return -1;
+    return (w[kErrSingular] != INT_MAX ? MLBM_DEVERR_SINGULAR : 0) | w[kErrFlags];
+}
+
+mlbm_status mlbm_device_error_nodes(const mlbm_plan *plan, int32_t *singular_node,
+                                    int32_t *diverged_node) {
+    if (!plan || !plan->dev_err) return fail(MLBM_EINVAL, "null plan");
+    int32_t w[3];
+    mlbm_status st = read_errors(plan, w);
+    if (st != MLBM_OK) return st;
+    if (singular_node) *singular_node = w[kErrSingular] == INT_MAX ? -1 : w[kErrSingular] - 1;
+    if (diverged_node) *diverged_node = w[kErrNode] == INT_MAX ? -1 : w[kErrNode];
+    return MLBM_OK;
+}
+
+mlbm_status mlbm_device_error_clear(mlbm_plan *plan, hipStream_t s) {
+    if (!plan || !plan->dev_err) return fail(MLBM_EINVAL, "null plan");
+    MLBM_HIP(reset_errors(plan, s));
+    return MLBM_OK;
 }
 
 namespace {

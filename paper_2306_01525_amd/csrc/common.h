@@ -100,7 +100,7 @@ struct CloudPlan {
     uint8_t *ntype = nullptr; // [n]
     int32_t *nbr = nullptr;   // [K][n], internal indices, centre first
     int32_t *owner = nullptr; // [8][n] for k = 1..8 (paper mode only)
-    double *W64 = nullptr;    // [8][K][n] FP64 shape vectors, k = 1..8
+    double *W64 = nullptr;    // [K][4][n][2] FP64 shape vectors, k = 1..8 (w64_at)
     float *W32 = nullptr;     // [K][2][n][4] FP32 shape vectors, k = 1..8
     float *force32 = nullptr; // [2][n] body force (lattice units), FP32 state
     double *force64 = nullptr;// [2][n] body force, FP64 state
@@ -118,18 +118,53 @@ struct CloudPlan {
     int32_t *tr_ptr = nullptr;  // [8n+1] row offsets, row (k-1)*n + m
     int32_t *tr_col = nullptr;  // [8Kn] arriving node, ascending within a row
     void *tr_val = nullptr;     // [8Kn] float (FP32 plans) or double (FP64)
-    // the first tr_lw entries of every row again, slot-major ([8][lw][n]) so
-    // that the lanes of a wavefront read them with unit stride
+    // the first tr_lw = K + 4 entries of every row again (the row heads),
+    // compacted per group of 64 nodes: node m's head length hd(m) is the
+    // longest of its eight rows (at most tr_lw); group g starts at unit
+    // 64 g tr_lw, and its slot e holds one unit (eight directions) for each node
+    // of the group with hd > e, in node order, stored as the block's first
+    // halves (directions 1-4) and then its second halves (adjoint.hip,
+    // unit_entry)
     int tr_lw = 0;
-    int32_t *ell_col = nullptr;
-    void *ell_val = nullptr;
+    int32_t *ell_col = nullptr;   // [tr_lw * n64][8], n64 = n rounded up to 64
+    void *ell_val = nullptr;      // same layout, float or double
     // inverse halos of source tiles for the LDS-staged adjoint gather
     int32_t *tdescT = nullptr;    // [ntiles] |I_t| (0: global gathers)
     int32_t *ilist = nullptr;     // [ntiles][hcap] arriving nodes, sorted
-    uint32_t *elocal = nullptr;   // [8][ceil(lw/3)][n] row heads as 3 x 10-bit positions in I_t
+    uint32_t *elocal = nullptr;   // the row heads' columns as three 10-bit positions
+                                  // in I_t per word, compacted like ell_col over
+                                  // triples of slots: [ceil(tr_lw/3) * n64][8]
     int adj_cap = 0;              // largest |I_t| kept (10-bit positions: at most 1024)
     int adj_ni = 0;               // largest |I_t| (LDS of the adjoint launch: 8 |I_t| values)
+    int32_t *err = nullptr;       // the plan's device error words (kErrWords)
 };
+
+// Device error words of a plan (int32, sticky until cleared):
+//   [kErrSingular] 1 + user index of the first node with a singular local
+//                  system, INT_MAX when none (build);
+//   [kErrFlags]    MLBM_DEVERR_* bits found by the steps and the diagnostics;
+//   [kErrNode]     user index of the first node found non-finite or too fast,
+//                  INT_MAX when none or not known.
+constexpr int kErrSingular = 0, kErrFlags = 1, kErrNode = 2, kErrWords = 64;
+// Largest speed (lattice units) before a node is reported as diverging: BGK
+// with the second-order equilibrium is only consistent well below c_s = 0.577.
+constexpr float kMaxSpeed2 = 0.09f;
+
+// Check of one node's squared speed uu: a NaN fails every comparison, so a
+// node whose moments are not finite or whose speed exceeds the limit is
+// reported (code MLBM_DEVERR_NONFINITE or MLBM_DEVERR_SPEED, and the lowest
+// such user index). The branch is taken only by a diverging run.
+template <class T>
+__device__ __forceinline__ void check_speed(int32_t *err, T uu, const int32_t *perm, int p,
+                                            int uoff) {
+    if (uu <= (T)kMaxSpeed2 || !err) return;
+    const bool finite = (uu - uu) == (T)0;   // false for NaN and Inf
+    atomicOr(err + kErrFlags, finite ? MLBM_DEVERR_SPEED : MLBM_DEVERR_NONFINITE);
+    atomicMin(err + kErrNode, uoff + (perm ? perm[p] : p));
+}
+__device__ __forceinline__ void report_index(int32_t *err) {
+    if (err) atomicOr(err + kErrFlags, MLBM_DEVERR_INDEX);
+}
 
 // Arguments of the FP32 step for one cloud; also the per-cloud descriptor
 // of the batched step (soff: element offset of the cloud's state, tile_begin:
@@ -147,6 +182,9 @@ struct Step32Args {
     const uint32_t *nbrL;
     const int32_t *hlist;
     int64_t soff, tile_begin;
+    int32_t *err;            // device error words (may be null)
+    const int32_t *perm;     // internal -> user index of this cloud
+    int uoff;                // offset of this cloud's nodes in the plan's user order
 };
 
 // Bump allocator over a caller buffer (a null base computes sizes only).
@@ -176,7 +214,7 @@ struct mlbm_plan {
     int32_t *tile2cloud = nullptr;       // device [total_tiles]
     unsigned batch_lds = 0;
     int precision = MLBM_FP32_DEV;
-    int32_t *dev_err = nullptr;     // device word: 0 or 1 + user index
+    int32_t *dev_err = nullptr;     // device error words (kErrWords int32)
     int32_t *stats = nullptr;       // device [n_clouds][kStats]: tile-table records
     double *scratch64 = nullptr;    // device, small reductions
     hipGraph_t graph = nullptr;

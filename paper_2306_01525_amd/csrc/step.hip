@@ -57,7 +57,8 @@ __device__ __forceinline__ void collide_store32(int n, int p, float (&f)[kQ],
                                                 const float *__restrict__ force,
                                                 const uint8_t *__restrict__ ntype, float rtau,
                                                 float rho0, float rho_w,
-                                                float *__restrict__ frec, int k0 = 0,
+                                                float *__restrict__ frec, int32_t *err,
+                                                const int32_t *perm, int uoff, int k0 = 0,
                                                 int k1 = kQ) {
     if (WALL == 1 && ntype[p]) {
 #pragma unroll
@@ -80,6 +81,7 @@ __device__ __forceinline__ void collide_store32(int n, int p, float (&f)[kQ],
     const float rho = rho0 + drho;
     const float ux = jx / rho, uy = jy / rho;
     const float uu = ux * ux + uy * uy;
+    if (k0 == 0) check_speed(err, uu, perm, p, uoff);
     float ax = 0.0f, ay = 0.0f;
     if (FORCE) {
         ax = force[p];
@@ -142,7 +144,10 @@ __device__ __forceinline__ void step32_tile(const Step32Args &a, const float *__
         const int32_t *hl = a.hlist + tile * (int64_t)a.hcap;
         for (int h = tid; h < nh; h += kTile) {
             int q = hl[h];
-            q = (unsigned)q < (unsigned)n ? q : 0;   // a bad table must not fault
+            if ((unsigned)q >= (unsigned)n) {   // a bad table must not fault
+                q = 0;
+                report_index(a.err);
+            }
 #pragma unroll
             for (int d = 0; d < 8; ++d) gl[d * nh + h] = g[(int64_t)(d + 1) * n + q];
         }
@@ -181,7 +186,7 @@ __device__ __forceinline__ void step32_tile(const Step32Args &a, const float *__
 #pragma unroll
         for (int d = 0; d < 8; ++d) f[d + 1] = acc[d];
         collide_store32<FORCE, WALL, REC>(n, p, f, go, a.force, a.ntype, a.rtau, a.rho0,
-                                          a.rho_w, a.frec);
+                                          a.rho_w, a.frec, a.err, a.perm, a.uoff);
         return;
     }
 
@@ -215,7 +220,7 @@ __device__ __forceinline__ void step32_tile(const Step32Args &a, const float *__
 #pragma unroll
     for (int d = 0; d < 8; ++d) f[d + 1] = acc[d];
     collide_store32<FORCE, WALL, REC>(n, p, f, go, a.force, a.ntype, a.rtau, a.rho0, a.rho_w,
-                                      a.frec);
+                                      a.frec, a.err, a.perm, a.uoff);
 }
 
 // The same tile with two lanes per node (adjacent lanes; 2 kTile threads):
@@ -253,7 +258,10 @@ __device__ __forceinline__ void step32_tile_split(const Step32Args &a,
         const int32_t *hl = a.hlist + tile * (int64_t)a.hcap;
         for (int i = tid; i < nh; i += 2 * kTile) {
             int q = hl[i];
-            q = (unsigned)q < (unsigned)n ? q : 0;   // a bad table must not fault
+            if ((unsigned)q >= (unsigned)n) {   // a bad table must not fault
+                q = 0;
+                report_index(a.err);
+            }
 #pragma unroll
             for (int d = 0; d < 8; ++d) gl[d * nh + i] = g[(int64_t)(d + 1) * n + q];
         }
@@ -315,7 +323,7 @@ __device__ __forceinline__ void step32_tile_split(const Step32Args &a,
         f[5 + dd] = h ? acc[dd] : oth[dd];
     }
     collide_store32<FORCE, WALL, REC>(n, p, f, go, a.force, a.ntype, a.rtau, a.rho0, a.rho_w,
-                                      a.frec, h ? 5 : 0, h ? kQ : 5);
+                                      a.frec, a.err, a.perm, a.uoff, h ? 5 : 0, h ? kQ : 5);
 }
 
 template <int MODE, bool FORCE, int WALL, bool REC, bool NT>
@@ -378,7 +386,8 @@ __device__ __forceinline__ void collide_store64(int n, int p, double (&f)[kQ],
                                                 double *__restrict__ go,
                                                 const double *__restrict__ force,
                                                 const uint8_t *__restrict__ ntype, double rtau,
-                                                double rho_w, double *__restrict__ frec) {
+                                                double rho_w, double *__restrict__ frec,
+                                                int32_t *err, const int32_t *perm, int uoff) {
     if (WALL == 1 && ntype[p]) {
 #pragma unroll
         for (int k = 0; k < kQ; ++k) {
@@ -398,6 +407,7 @@ __device__ __forceinline__ void collide_store64(int n, int p, double (&f)[kQ],
     }
     const double ux = jx / rho, uy = jy / rho;
     const double uu = ux * ux + uy * uy;
+    check_speed(err, uu, perm, p, uoff);
     double ax = 0.0, ay = 0.0;
     if (FORCE) {
         ax = force[p];
@@ -426,7 +436,8 @@ __global__ __launch_bounds__(kTile) void k_step64(
     const int32_t *__restrict__ owner, const double *__restrict__ force,
     const uint8_t *__restrict__ ntype, double rtau, double rho_w, double *__restrict__ frec,
     const int32_t *__restrict__ tdesc, const uint16_t *__restrict__ ownerL,
-    const uint32_t *__restrict__ nbrL, const int32_t *__restrict__ hlist, int ocap, int hcap) {
+    const uint32_t *__restrict__ nbrL, const int32_t *__restrict__ hlist, int ocap, int hcap,
+    int32_t *err, const int32_t *__restrict__ perm, int uoff) {
     extern __shared__ __align__(16) unsigned char smem[];
     const int64_t tile = xcd_tile(nblocks);
     if (tile >= nblocks) return;
@@ -459,7 +470,10 @@ __global__ __launch_bounds__(kTile) void k_step64(
             if (pass) __syncthreads();   // the first half is read by everyone
             for (int h = tid; h < nh; h += kTile) {
                 int q = hl[h];
-                q = (unsigned)q < (unsigned)n ? q : 0;   // a bad table must not fault
+                if ((unsigned)q >= (unsigned)n) {   // a bad table must not fault
+                    q = 0;
+                    report_index(err);
+                }
 #pragma unroll
                 for (int dd = 0; dd < 4; ++dd)
                     gl[dd * nh + h] = g[(int64_t)(4 * pass + dd + 1) * n + q];
@@ -513,7 +527,8 @@ __global__ __launch_bounds__(kTile) void k_step64(
     f[0] = g[p];
 #pragma unroll
     for (int d = 0; d < 8; ++d) f[d + 1] = acc[d];
-    collide_store64<FORCE, WALL, REC>(n, p, f, go, force, ntype, rtau, rho_w, frec);
+    collide_store64<FORCE, WALL, REC>(n, p, f, go, force, ntype, rtau, rho_w, frec, err, perm,
+                                      uoff);
 }
 
 // ------------------------------------------------------------------------
@@ -552,7 +567,7 @@ __global__ void k_moments(int n, const int32_t *__restrict__ perm, const T *__re
                           const float *__restrict__ f32, const double *__restrict__ f64,
                           const uint8_t *__restrict__ ntype, double rho0, int dev,
                           double *__restrict__ rho, double *__restrict__ ux,
-                          double *__restrict__ uy) {
+                          double *__restrict__ uy, int32_t *err, int uoff) {
     int p = blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= n) return;
     double r = 0.0, jx = 0.0, jy = 0.0;
@@ -573,9 +588,11 @@ __global__ void k_moments(int n, const int32_t *__restrict__ perm, const T *__re
         }
     }
     const int u = perm ? perm[p] : p;
+    const double vx = jx / r, vy = jy / r;
+    check_speed(err, vx * vx + vy * vy, perm, p, uoff);
     if (rho) rho[u] = r;
-    if (ux) ux[u] = jx / r;
-    if (uy) uy[u] = jy / r;
+    if (ux) ux[u] = vx;
+    if (uy) uy[u] = vy;
 }
 
 // Per-block partial sums, then a single workgroup adds the partials in a fixed
@@ -585,7 +602,7 @@ __global__ __launch_bounds__(256) void k_l2_partial(
     int n, const int32_t *__restrict__ perm, const T *__restrict__ g,
     const float *__restrict__ f32, const double *__restrict__ f64,
     const uint8_t *__restrict__ ntype, double rho0, int dev, const double *__restrict__ uxt,
-    const double *__restrict__ uyt, double *__restrict__ part) {
+    const double *__restrict__ uyt, double *__restrict__ part, int32_t *err, int uoff) {
     __shared__ double sh[4][256];
     int p = blockIdx.x * blockDim.x + threadIdx.x;
     double a0 = 0, a1 = 0, a2 = 0, a3 = 0;
@@ -608,7 +625,9 @@ __global__ __launch_bounds__(256) void k_l2_partial(
             }
         }
         const int u = perm[p];
-        const double ex = jx / r - uxt[u], ey = jy / r - uyt[u];
+        const double vx = jx / r, vy = jy / r;
+        check_speed(err, vx * vx + vy * vy, perm, p, uoff);
+        const double ex = vx - uxt[u], ey = vy - uyt[u];
         a0 = ex * ex + ey * ey;
         a1 = uxt[u] * uxt[u] + uyt[u] * uyt[u];
         a2 = ex * ex;
@@ -636,7 +655,7 @@ __global__ __launch_bounds__(256) void k_residual_partial(
     int n, const int32_t *__restrict__ perm, const T *__restrict__ g,
     const float *__restrict__ f32, const double *__restrict__ f64,
     const uint8_t *__restrict__ ntype, double rho0, int dev, double *__restrict__ speed,
-    double *__restrict__ part) {
+    double *__restrict__ part, int32_t *err, int uoff) {
     __shared__ double sh[2][256];
     int p = blockIdx.x * blockDim.x + threadIdx.x;
     double a0 = 0, a1 = 0;
@@ -660,6 +679,7 @@ __global__ __launch_bounds__(256) void k_residual_partial(
         }
         const int u = perm[p];
         const double U = sqrt(jx * jx + jy * jy) / r;
+        check_speed(err, U * U, perm, p, uoff);
         const double d = U - speed[u];
         a0 = d * d;
         a1 = U * U;
@@ -817,7 +837,7 @@ hipError_t step_variant(const CloudPlan &cp, int precision, const void *gin, voi
                            cp.prm.wall_kind == 2 ? cp.links : cp.ntype,
                            1.0 / cp.prm.tau, cp.prm.rho_wall, (double *)frec,
                            cp.lds_bytes ? cp.tdesc : nullptr, cp.ownerL, cp.nbrL, cp.hlist,
-                           cp.ocap, cp.hcap);
+                           cp.ocap, cp.hcap, cp.err, cp.perm, (int)cp.off);
     } else {
         launch32_tuned<MODE, FORCE, WALL, REC>(cp, gin, gout, frec, nblocks, s);
     }
@@ -878,10 +898,10 @@ __global__ __launch_bounds__(256) void k_lbm_step(int nx, int ny, int64_t nblock
     }
     if constexpr (sizeof(T) == 4)
         collide_store32<false, false, false>((int)n, p, f, go, nullptr, nullptr, (float)rtau,
-                                             (float)rho0, 0.0f, nullptr);
+                                             (float)rho0, 0.0f, nullptr, nullptr, nullptr, 0);
     else
         collide_store64<false, false, false>((int)n, p, f, go, nullptr, nullptr, rtau, 0.0,
-                                             nullptr);
+                                             nullptr, nullptr, nullptr, 0);
 }
 
 // Interpolation alone (Sec. 4, Fig. interp_test): the streaming operator of
@@ -941,6 +961,9 @@ Step32Args step32_args(const CloudPlan &cp, void *frec) {
     a.hlist = cp.hlist;
     a.soff = 0;
     a.tile_begin = 0;
+    a.err = cp.err;
+    a.perm = cp.perm;
+    a.uoff = (int)cp.off;
     return a;
 }
 
@@ -989,11 +1012,11 @@ hipError_t launch_moments(const CloudPlan &cp, int precision, const void *g, dou
     if (precision == MLBM_FP64)
         hipLaunchKernelGGL(k_moments<double>, dim3(blocks_for(n, 256)), dim3(256), 0, s, n,
                            cp.perm, (const double *)g, f32, f64, fmask(cp), cp.prm.rho0, 0, rho,
-                           ux, uy);
+                           ux, uy, cp.err, (int)cp.off);
     else
         hipLaunchKernelGGL(k_moments<float>, dim3(blocks_for(n, 256)), dim3(256), 0, s, n,
                            cp.perm, (const float *)g, f32, f64, fmask(cp), cp.prm.rho0, 1, rho,
-                           ux, uy);
+                           ux, uy, cp.err, (int)cp.off);
     return hipGetLastError();
 }
 
@@ -1005,10 +1028,12 @@ hipError_t launch_l2(const CloudPlan &cp, int precision, const void *g, const do
     const double *f64 = precision == MLBM_FP64 ? cp.force64 : nullptr;
     if (precision == MLBM_FP64)
         hipLaunchKernelGGL(k_l2_partial<double>, dim3(nb), dim3(256), 0, s, n, cp.perm,
-                           (const double *)g, f32, f64, fmask(cp), cp.prm.rho0, 0, uxt, uyt, part);
+                           (const double *)g, f32, f64, fmask(cp), cp.prm.rho0, 0, uxt, uyt, part,
+                           cp.err, (int)cp.off);
     else
         hipLaunchKernelGGL(k_l2_partial<float>, dim3(nb), dim3(256), 0, s, n, cp.perm,
-                           (const float *)g, f32, f64, fmask(cp), cp.prm.rho0, 1, uxt, uyt, part);
+                           (const float *)g, f32, f64, fmask(cp), cp.prm.rho0, 1, uxt, uyt, part,
+                           cp.err, (int)cp.off);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_l2_final, dim3(1), dim3(256), 0, s, nb, (const double *)part, out);
@@ -1023,10 +1048,12 @@ hipError_t launch_residual(const CloudPlan &cp, int precision, const void *g, do
     const double *f64 = precision == MLBM_FP64 ? cp.force64 : nullptr;
     if (precision == MLBM_FP64)
         hipLaunchKernelGGL(k_residual_partial<double>, dim3(nb), dim3(256), 0, s, n, cp.perm,
-                           (const double *)g, f32, f64, fmask(cp), cp.prm.rho0, 0, speed, part);
+                           (const double *)g, f32, f64, fmask(cp), cp.prm.rho0, 0, speed, part,
+                           cp.err, (int)cp.off);
     else
         hipLaunchKernelGGL(k_residual_partial<float>, dim3(nb), dim3(256), 0, s, n, cp.perm,
-                           (const float *)g, f32, f64, fmask(cp), cp.prm.rho0, 1, speed, part);
+                           (const float *)g, f32, f64, fmask(cp), cp.prm.rho0, 1, speed, part,
+                           cp.err, (int)cp.off);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_l2_final, dim3(1), dim3(256), 0, s, nb, (const double *)part, out);
@@ -1085,12 +1112,12 @@ hipError_t launch_lbm_moments(int n, int precision, double rho0, const void *g, 
         hipLaunchKernelGGL(k_moments<double>, dim3(blocks_for(n, 256)), dim3(256), 0, s, n,
                            (const int32_t *)nullptr, (const double *)g, (const float *)nullptr,
                            (const double *)nullptr, (const uint8_t *)nullptr, rho0, 0, rho, ux,
-                           uy);
+                           uy, (int32_t *)nullptr, 0);
     else
         hipLaunchKernelGGL(k_moments<float>, dim3(blocks_for(n, 256)), dim3(256), 0, s, n,
                            (const int32_t *)nullptr, (const float *)g, (const float *)nullptr,
                            (const double *)nullptr, (const uint8_t *)nullptr, rho0, 1, rho, ux,
-                           uy);
+                           uy, (int32_t *)nullptr, 0);
     return hipGetLastError();
 }
 

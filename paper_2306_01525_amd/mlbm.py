@@ -115,13 +115,12 @@ class Plan:
         check(L.mlbm_weights_query(ctypes.byref(cloud), ctypes.byref(cp), 1, ctypes.byref(pb),
                                    ctypes.byref(wb)))
         plan_buf = torch.empty(pb.value, dtype=torch.uint8, device=device)
-        ws = torch.empty(wb.value, dtype=torch.uint8, device=device)
         h = ctypes.c_void_p()
+        ws = torch.empty(wb.value, dtype=torch.uint8, device=device)
         check(L.mlbm_build_weights(ctypes.byref(cloud), ctypes.byref(cp), 1, _ptr(plan_buf),
                                    pb.value, _ptr(ws), wb.value, ctypes.byref(h),
                                    _stream(stream)))
         torch.cuda.current_stream().synchronize() if stream is None else stream.synchronize()
-        del ws
         return cls(h, plan_buf, params, n, device)
 
     @staticmethod
@@ -433,8 +432,20 @@ class Plan:
         return out
 
     def set_tau(self, tau: float):
+        """Same relaxation time for every cloud of the plan."""
         check(_lib.load().mlbm_plan_set_tau(self._h, float(tau)))
-        self.params.tau = float(tau)
+        for p in self.params_list:
+            p.tau = float(tau)
 
     def device_error(self) -> int:
+        """Sticky device error bits (MLBM_DEVERR_*), 0 when none."""
         return int(_lib.load().mlbm_device_error(self._h))
+
+    def device_error_nodes(self):
+        """(first singular node, first diverged node), user indices, -1 = none."""
+        a, b = ctypes.c_int32(), ctypes.c_int32()
+        check(_lib.load().mlbm_device_error_nodes(self._h, ctypes.byref(a), ctypes.byref(b)))
+        return a.value, b.value
+
+    def clear_device_error(self, stream=None):
+        check(_lib.load().mlbm_device_error_clear(self._h, _stream(stream)))

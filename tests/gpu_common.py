@@ -14,11 +14,10 @@ EPS32 = 2.0 ** -24
 
 # FP64 GPU path vs FP64 oracle: both evaluate the same formulas in double
 # precision; they differ in summation order and in the local solver (pivoted
-# elimination with implicit row order vs explicit row swaps). Per step the
-# relative difference of the populations is a few ulps times the Lebesgue
-# constant of the stencil (sum |w| <= ~5), so after n steps it stays below
-# n * 1e-14 with a margin; 1e-11 covers the 200-step runs here.
-TOL_FP64 = 1e-11
+# elimination with implicit row order vs explicit row swaps). Measured relative
+# L2 of the velocity over every small case here (1 to 400 steps, walls, force,
+# bounce-back, K 12 to 48): at most 8.8e-13; the bound is about 4x that.
+TOL_FP64 = 4e-12
 # Shape vectors: the local systems have condition numbers up to ~1e7 after
 # scaling, so the FP64 solutions agree to about 1e-16 * cond.
 TOL_W = 1e-9
@@ -68,29 +67,35 @@ def first_step_rounding_bounds(nbr, own, W, f0, eps):
     return 8.0 * eps * b
 
 
-# FP64 GPU vs FP64 oracle after up to 2,000 steps of the full-size workload.
-TOL_FP64_FULL = 1e-10
+# FP64 GPU vs FP64 oracle on the full 262,144-node Taylor-Green workload, up
+# to 2,000 steps: measured 9.3e-13 relative L2 and 2.0e-12 at the worst node.
+TOL_FP64_FULL = 8e-12
 
 
 def tol_fp32_node(steps: int) -> float:
     """Bound on the largest per-node velocity error of the FP32 path over the
-    largest oracle speed."""
-    return 4.0 * tol_fp32(steps)
+    largest oracle speed: the worst node sits 2.6-5x above the field-wide
+    relative L2 in every measured case."""
+    return 3.0 * tol_fp32(steps)
 
 
-# Largest FP32 error against the oracle, as a share of the method's own
-# error against the analytic solution after the same steps.
-FP32_SHARE_OF_METHOD_ERROR = 0.25
+# Largest FP32 error against the oracle, as a share of the method's own error
+# against the analytic solution after the same steps: at most 1 %, so the FP32
+# form never changes the stated accuracy (measured 0.34 % after 2,000 steps of
+# the full-size Taylor-Green workload).
+FP32_SHARE_OF_METHOD_ERROR = 0.01
 
 
 def tol_fp32(steps: int) -> float:
     """Relative L2 bound on the velocity of the FP32 deviation path against
-    the FP64 oracle. Each step adds rounding of the stored deviations and of
-    the FP32 weights, at most ~8 ulps of FP32 relative to the velocity scale
-    (sum |w| <= 5 times a few operations); errors add linearly in the worst
-    case: 8 * 2^-24 * steps, plus a floor of 64 ulps for the initial
-    rounding."""
-    return 8.0 * EPS32 * steps + 64 * EPS32
+    the FP64 oracle after `steps` steps. The FP32 step rounds the stored
+    deviations, the FP32 shape vectors and its own arithmetic; with the
+    lattice weights applied exactly in the collision those roundings carry no
+    bias, so the difference grows like a random walk. Every case measured (1
+    to 2,000 steps, clouds of 289 to 262,144 nodes, K 12 to 48, walls, force)
+    lies below (2.5 + 0.57 sqrt(steps)) units of 2^-24; the bound is 2.5x that
+    envelope, at most 4x the largest value measured at each step count."""
+    return (6.0 + 1.5 * math.sqrt(steps)) * EPS32
 
 
 def say(*a):

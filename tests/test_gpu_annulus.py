@@ -10,7 +10,7 @@ import numpy as np
 import pytest
 
 import oracle
-from gpu_common import TOL_W, rel_l2, say, tol_fp32
+from gpu_common import TOL_FP64, TOL_W, rel_l2, say, tol_fp32
 from oracle import analytic
 from synth.clouds import annulus_h_for_count, annulus_poisson
 
@@ -115,11 +115,11 @@ def test_fullsize_fp32_vs_fp64(c3):
         plan.close()
     d = rel_l2(np.stack(res[0][1:]), np.stack(res[1][1:]))
     wall = c.node_type == 1
-    say("fp32 vs fp64 after 200 steps %.2e (bound %.2e)" % (d, 4 * tol_fp32(200)))
+    say("fp32 vs fp64 after 200 steps %.2e (bound %.2e)" % (d, tol_fp32(200)))
     for prec in (0, 1):
         assert np.isfinite(res[prec][1]).all()
         assert np.abs(res[prec][1][wall]).max() < 1e-6
-    assert d < 4 * tol_fp32(200)
+    assert d < tol_fp32(200)
 
 
 def _steady(c, h, precision, tau, g=G):
@@ -159,7 +159,9 @@ def test_steady_state_matches_oracle_and_analytic(precision):
     _, uo, vo = oracle.moments(f)
     d = rel_l2(np.stack([u, v]), np.stack([uo, vo]))
     say("h 0.05 n %d steps %d: GPU vs oracle at steady state %.2e" % (c.n, steps, d))
-    assert d < (1e-9 if precision == 1 else 1e-3)
+    # measured 2.5e-12 (FP64) and 1.2e-6 (FP32): the steady field forgets the
+    # rounding of the transient, so the FP32 bound is a constant
+    assert d < (1e-11 if precision == 1 else 5e-6)
 
     nu = (TAU - 0.5) / 3.0
     errs = []
@@ -253,7 +255,7 @@ def test_bounce_back_walls_match_oracle(tau):
         f = oracle.run(f, nbr, own, W, tau, s_ - done, ax, ay, links=links)
         done = s_
         ref[s_] = oracle.moments(f)
-    for prec, tol in ((1, lambda s: 1e-11), (0, lambda s: 4 * tol_fp32(s))):
+    for prec, tol in ((1, lambda s: TOL_FP64), (0, tol_fp32)):
         p = Params(dx=dx, K=K, degree=m, tau=tau, stencil_mode=0, precision=prec,
                    force_kind=1, force_mag=g, wall_kind=2)
         plan = Plan.build(c.x, c.y, c.period, p, node_type=c.node_type, normals=(nx, ny))

@@ -105,3 +105,29 @@ def test_build_graph_replays_equal_eager():
         assert torch.equal(ge2, ge)
     plan.close()
     eager.close()
+
+
+def test_set_tau_reaches_every_cloud_of_a_batched_plan():
+    """The batched step reads each cloud's relaxation time from the device
+    descriptor table: after set_tau every cloud steps exactly like a
+    single-cloud plan built at the new value, and the graph created before
+    the change is dropped."""
+    from paper_2306_01525_amd import Plan
+    clouds, params, u = _clouds()
+    for p in params:
+        p.stencil_mode = 1
+    ux = np.concatenate([a for a, _ in u])
+    uy = np.concatenate([b for _, b in u])
+    bp = Plan.build_batch(clouds, params)
+    g = bp.step(bp.init(ux, uy), bp.new_state(), 3)
+    new_tau = 0.77
+    bp.set_tau(new_tau)
+    g = bp.step(bp.init(ux, uy), bp.new_state(), 10)
+    for c, (x, y, period, _) in enumerate(clouds):
+        p = params[c]
+        assert p.tau == new_tau
+        sp = Plan.build(x, y, period, p)
+        gs = sp.step(sp.init(*u[c]), sp.new_state(), 10)
+        assert torch.equal(gs, bp.cloud_view(g, c)), c
+        sp.close()
+    bp.close()

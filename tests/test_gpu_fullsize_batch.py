@@ -84,8 +84,9 @@ def test_fullsize_batched_graph_sampled():
                                          int(i))
             d = max(abs(r - rho_b[off + i]), abs(u - ux_b[off + i]), abs(v - uy_b[off + i]))
             worst = max(worst, d)
-            # FP32 deviations (|f - w rho0| <= ~0.03, ulp ~ 2e-9) and FP32
-            # weights (sum |w| <= ~5): one step stays far below 1e-6
-            assert d < 1e-6, (c, i, d)
+            # FP32 deviations (|f - w rho0| <= ~0.03: half an ulp is 1.9e-9)
+            # and FP32 weights: one step is a few half-ulps off (1.9e-9
+            # measured); the bound is about 4x that
+            assert d < 8e-9, (c, i, d)
     say("sampled %d clouds: max |(rho, u) diff| after one step %.2e" % (len(picks), worst))
     plan.close()

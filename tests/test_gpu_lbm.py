@@ -40,7 +40,10 @@ def test_lbm_matches_oracle(nx, ny):
         g = lat.init(ux, uy, rho=rho)
         g = lat.step(g, lat.new_state(), steps)
         r_g, u_g, v_g = (a.cpu().numpy() for a in lat.moments(g))
-        e = rel_l2(np.stack([u_g, v_g]), np.stack([u_o, v_o]))
+        # relative to the initial field: on the one-column lattice the flow
+        # decays by e^-47 in 150 steps, and only rounding-level noise is left
+        e = float(np.linalg.norm(np.stack([u_g - u_o, v_g - v_o])) /
+                  np.linalg.norm(np.stack([ux, uy])))
         er = float(np.abs(r_g - r_o).max())
         say("lattice %dx%d precision %d: rel L2 velocity %.2e, max |drho| %.2e" % (nx, ny, prec, e, er))
         assert e < tol and er < tol
