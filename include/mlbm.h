@@ -147,6 +147,22 @@ mlbm_status mlbm_build_weights(const mlbm_cloud *clouds, const mlbm_params *para
                                void *workspace, size_t workspace_bytes, mlbm_plan **out,
                                hipStream_t stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, serving loops, harnesses that forbid allocation): the build of
+ * mlbm_build_weights with no workspace argument. Its temporary arrays live in
+ * a fixed 32 MiB array inside the library, one per GPU, held until the process
+ * ends; clouds are built one after another on `stream`. That covers one cloud
+ * of about 550,000 nodes (K 30, degree 4), 350,000 with the adjoint tables;
+ * a build whose one-cloud-at-a-time workspace (compare mlbm_weights_query)
+ * exceeds it returns MLBM_EUNSUPPORTED before any device work. plan_buf and
+ * plan_bytes as for mlbm_build_weights (same size); the results are the same.
+ * Calls on one GPU share the array, so calls whose work overlaps on that GPU
+ * (other streams, other threads) race: order them. Allocates no device
+ * memory; the host plan object is released by mlbm_plan_destroy. */
+mlbm_status mlbm_build_weights_static(const mlbm_cloud *clouds, const mlbm_params *params,
+                                      int32_t n_clouds, void *plan_buf, size_t plan_bytes,
+                                      mlbm_plan **out, hipStream_t stream);
+
 /* Test hook: a plan built from host arrays instead of the GPU build, for one
  * periodic or open cloud. x, y: host [n]; nbr: host int32 [n][K] stencils in
  * user indices (centre first); owner: host int32 [n][9] owner node per

@@ -87,6 +87,8 @@ SIGNATURES = {
     "mlbm_graph_launch": (_c_i32, [_c_p, _c_p]),
     "mlbm_last_error": (ctypes.c_char_p, []),
     "mlbm_device_error": (_c_i32, [_c_p]),
+    "mlbm_build_weights_static": (_c_i32, [_P(Cloud), _P(Params), _c_i32, _c_p, _c_sz, _P(_c_p),
+                                           _c_p]),
     "mlbm_device_error_nodes": (_c_i32, [_c_p, _P(_c_i32), _P(_c_i32)]),
     "mlbm_device_error_clear": (_c_i32, [_c_p, _c_p]),
 }

@@ -263,6 +263,34 @@ const CloudPlan *single(const mlbm_plan *plan) {
 
 using namespace mlbm;
 
+// Workspace of mlbm_build_weights_static: a fixed array in device memory, one
+// per GPU the library runs on, held until the process ends. In host code the
+// array's name only stands in for it; kernels get its device address, which
+// hipGetSymbolAddress gives once per device (each GPU holds its own copy at
+// its own address). Every call on one GPU shares it; the build clears what it
+// needs (cell ranges, counters) with its own fill kernels before use.
+namespace {
+constexpr size_t kStaticWorkspaceBytes = size_t(32) << 20;
+static __device__ __align__(256) unsigned char scratch[kStaticWorkspaceBytes];
+
+mlbm_status static_workspace(void **out) {
+    static std::mutex mu;
+    static std::map<int, void *> addr;
+    int dev = 0;
+    MLBM_HIP(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lock(mu);
+    auto it = addr.find(dev);
+    if (it == addr.end()) {
+        void *p = nullptr;
+        MLBM_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!p) return fail(MLBM_EHIP, "hipGetSymbolAddress returned a null workspace");
+        it = addr.emplace(dev, p).first;
+    }
+    *out = it->second;
+    return MLBM_OK;
+}
+}  // namespace
+
 extern "C" {
 
 const char *mlbm_last_error(void) { return g_error.c_str(); }
@@ -527,6 +555,27 @@ mlbm_status mlbm_build_weights(const mlbm_cloud *clouds, const mlbm_params *para
                                hipStream_t s) {
     return build_weights_lanes(clouds, params, n_clouds, plan_buf, plan_bytes, workspace,
                                workspace_bytes, kBuildLanes, out, s);
+}
+
+mlbm_status mlbm_build_weights_static(const mlbm_cloud *clouds, const mlbm_params *params,
+                                      int32_t n_clouds, void *plan_buf, size_t plan_bytes,
+                                      mlbm_plan **out, hipStream_t s) {
+    if (!out) return fail(MLBM_EINVAL, "null output pointer");
+    *out = nullptr;
+    size_t need_p = 0, need_w = 0;
+    mlbm_status st = query_lanes(clouds, params, n_clouds, 1, &need_p, &need_w);
+    if (st != MLBM_OK) return st;
+    if (need_w > kStaticWorkspaceBytes)
+        return fail(MLBM_EUNSUPPORTED,
+                    "the build needs a workspace of " + std::to_string(need_w) +
+                        " bytes, more than the library's static workspace of " +
+                        std::to_string(kStaticWorkspaceBytes) +
+                        " bytes: use mlbm_build_weights with a caller workspace");
+    void *ws = nullptr;
+    st = static_workspace(&ws);
+    if (st != MLBM_OK) return st;
+    return build_weights_lanes(clouds, params, n_clouds, plan_buf, plan_bytes, ws,
+                               kStaticWorkspaceBytes, 1, out, s);
 }
 
 mlbm_status mlbm_import_query(int32_t n, const mlbm_params *params, size_t *plan_bytes) {

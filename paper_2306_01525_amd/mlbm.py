@@ -94,9 +94,11 @@ class Plan:
     # ---- construction ----------------------------------------------------
     @classmethod
     def build(cls, x, y, period, params: Params, node_type=None, device="cuda",
-              stream=None, normals=None):
+              stream=None, normals=None, static_workspace=False):
         """normals: (nx, ny), the outward normal of the fluid domain at wall
-        nodes (user order); needed by bounce-back walls (wall_kind 2)."""
+        nodes (user order); needed by bounce-back walls (wall_kind 2).
+        static_workspace: build through mlbm_build_weights_static (the
+        library's own fixed workspace; no temporary device buffer)."""
         L = _lib.load()
         x = _f64(x, device)
         y = _f64(y, device)
@@ -116,10 +118,15 @@ class Plan:
                                    ctypes.byref(wb)))
         plan_buf = torch.empty(pb.value, dtype=torch.uint8, device=device)
         h = ctypes.c_void_p()
-        ws = torch.empty(wb.value, dtype=torch.uint8, device=device)
-        check(L.mlbm_build_weights(ctypes.byref(cloud), ctypes.byref(cp), 1, _ptr(plan_buf),
-                                   pb.value, _ptr(ws), wb.value, ctypes.byref(h),
-                                   _stream(stream)))
+        if static_workspace:
+            check(L.mlbm_build_weights_static(ctypes.byref(cloud), ctypes.byref(cp), 1,
+                                              _ptr(plan_buf), pb.value, ctypes.byref(h),
+                                              _stream(stream)))
+        else:
+            ws = torch.empty(wb.value, dtype=torch.uint8, device=device)
+            check(L.mlbm_build_weights(ctypes.byref(cloud), ctypes.byref(cp), 1, _ptr(plan_buf),
+                                       pb.value, _ptr(ws), wb.value, ctypes.byref(h),
+                                       _stream(stream)))
         torch.cuda.current_stream().synchronize() if stream is None else stream.synchronize()
         return cls(h, plan_buf, params, n, device)
 
