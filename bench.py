@@ -242,6 +242,32 @@ def run_gpu(args):
             torch.cuda.synchronize()
         out["adj_step_ms"] = e0.elapsed_time(e1) / reps
         log("adjoint step alone: %.4f ms" % out["adj_step_ms"])
+        # the whole adjoint workload: 500 steps checkpointed every 50
+        # (forward with checkpoints + loss, then recompute + reverse sweep)
+        T = 500
+        with torch.cuda.stream(stream):
+            del fn, lam_a, lam_b
+            torch.cuda.synchronize()
+            torch.cuda.reset_peak_memory_stats()
+            base_mem = torch.cuda.memory_allocated()
+            ro = Rollout(planA, T, C)
+            e = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+            e[0].record(stream)
+            ro.forward(uxt, uyt, stream=stream)
+            ro.loss(tx_t, ty_t, stream=stream)
+            e[1].record(stream)
+            ro.backward(stream=stream)
+            e[2].record(stream)
+            torch.cuda.synchronize()
+        out["rollout"] = {"steps": T, "segment": C, "forward_loss_ms": e[0].elapsed_time(e[1]),
+                          "backward_ms": e[1].elapsed_time(e[2]),
+                          "ratio": e[1].elapsed_time(e[2]) / e[0].elapsed_time(e[1]),
+                          "peak_extra_bytes": torch.cuda.max_memory_allocated() - base_mem,
+                          "plan_bytes": int(planA._buf.numel())}
+        log("rollout of %d steps: forward+loss %.1f ms, backward %.1f ms, peak extra memory "
+            "%.2f GB" % (T, out["rollout"]["forward_loss_ms"], out["rollout"]["backward_ms"],
+                          out["rollout"]["peak_extra_bytes"] / 1e9))
+        del ro
         planA.close()
     out["n"] = c.n
     out["K"] = K
@@ -249,18 +275,72 @@ def run_gpu(args):
     return out
 
 
+def run_tgv40():
+    """The small Taylor-Green workload: 40 x 40 jittered lattice (seed 1),
+    1,600 nodes, K = 12, degree 2, own-node stencils (the paper's rule
+    diverges at K = 12 with degree 2 on these clouds), tau = 0.8, u0 = 0.01,
+    200 steps; FP32 and FP64 steps timed as for the headline, L2 against the
+    analytic decay and against the oracle after the 200 steps, and the oracle's
+    own rate on the host (all threads and one). The whole cloud sits in L2, so
+    this is a latency figure, not a roofline point."""
+    import numpy as np
+    import torch
+    import oracle
+    from paper_2306_01525_amd import MLBM_FP32_DEV, MLBM_FP64, MLBM_STENCIL_OWN, Params, Plan
+    from paper_2306_01525_amd import targets
+    from synth import jittered_lattice, tgv_initial_velocity
+    steps, K, m, tau, u0 = 200, 12, 2, 0.8, 0.01
+    c = jittered_lattice(40, seed=1)
+    ux, uy = tgv_initial_velocity(c.x, c.y, c.period[0], u0)
+    tx, ty = targets.tgv_velocity(c.x, c.y, c.period[0], u0, tau, c.h, steps)
+    nbr, own, W = oracle.build_plan(c, c.h, K, m, mode=1)
+    f0 = oracle.equilibrium(np.ones(c.n), ux, uy)
+    threads = oracle.threads()
+    t0 = time.perf_counter()
+    f = oracle.run(f0, nbr, own, W, tau, steps)
+    t_all = time.perf_counter() - t0
+    oracle.set_threads(1)
+    t0 = time.perf_counter()
+    oracle.run(f0, nbr, own, W, tau, steps)
+    t_one = time.perf_counter() - t0
+    oracle.set_threads(threads)
+    _, uo, vo = oracle.moments(f)
+    out = {"nodes": c.n, "K": K, "degree": m, "tau": tau, "steps": steps, "stencil": "own",
+           "oracle": {"value_all_threads": c.n * steps / t_all, "threads": threads,
+                      "value_one_thread": c.n * steps / t_one}}
+    stream = torch.cuda.Stream()
+    for prec, name in ((MLBM_FP32_DEV, "fp32"), (MLBM_FP64, "fp64")):
+        p = Params(dx=c.h, K=K, degree=m, tau=tau, stencil_mode=MLBM_STENCIL_OWN, precision=prec)
+        plan = Plan.build(c.x, c.y, c.period, p)
+        times, _, _ = time_steps(plan, plan.init(ux, uy), steps, 0, stream)
+        g = plan.step(plan.init(ux, uy), plan.new_state(), steps)
+        _, u, v = (a.cpu().numpy() for a in plan.moments(g))
+        t = timing_summary(times, steps)
+        out[name] = {"ms_per_step": t["ms_per_step_median"], "timing": t,
+                     "value": c.n / (t["ms_per_step_median"] / 1e3),
+                     "l2_vs_analytic_u": float(np.linalg.norm(u - tx) / np.linalg.norm(tx)),
+                     "l2_vs_oracle": field_error(u, v, uo, vo)}
+        plan.close()
+    log("TGV-40: FP32 %.4f ms/step, L2 vs oracle %.2e; FP64 %.4f ms/step"
+        % (out["fp32"]["ms_per_step"], out["fp32"]["l2_vs_oracle"]["rel_l2"],
+           out["fp64"]["ms_per_step"]))
+    return out
+
+
 def run_annulus(steps: int, warmup: int):
     """The annular channel at about 490,000 Poisson-disk nodes (R1 = 1, R2 = 2,
     seed 3): K = 20, degree 3, paper stencils, dx = h, tau = 0.7, equilibrium
-    walls, azimuthal force 1e-6. FP32 steps timed as for the headline."""
+    walls, azimuthal force of the paper's flow (g = 1e-6 at dx_ML = 1/160
+    carried to dx = h under diffusive scaling). FP32 steps timed as for the
+    headline."""
     import numpy as np
     import torch
     from paper_2306_01525_amd import Params, Plan
-    from synth.clouds import annulus_h_for_count, annulus_poisson
+    from synth.clouds import annulus_force, annulus_h_for_count, annulus_poisson
     c = annulus_poisson(1.0, 2.0, annulus_h_for_count(1.0, 2.0, 500_000), seed=3)
     K = 20
-    p = Params(dx=c.h, K=K, degree=3, tau=0.7, stencil_mode=0, force_kind=1, force_mag=1e-6,
-               wall_kind=1, rho_wall=1.0)
+    p = Params(dx=c.h, K=K, degree=3, tau=0.7, stencil_mode=0, force_kind=1,
+               force_mag=annulus_force(c.h), wall_kind=1, rho_wall=1.0)
     log("annulus: n = %d, h = %.3e; building" % (c.n, c.h))
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -345,13 +425,13 @@ def run_lbm(steps: int, warmup: int, l2_steps: int, ml_l2: float, ml_ms: float):
 def run_batched(steps: int):
     """64 Taylor-Green clouds of uneven size (10^4 to 2x10^5 nodes,
     log-uniform, seed 4), each with its own tau in [0.55, 1] and degree 2-4
-    (K 12/20/30), own-node stencils (one stencil rule for the whole batch),
-    FP32. One HIP graph holds the weight build of all clouds, the initial state
-    and `steps` steps; it is launched once and timed, and the steps alone are
-    timed from a second graph."""
+    (K 20/25/30), the paper's stencil rule, FP32. One HIP graph holds the
+    weight build of all clouds, the initial state and `steps` steps; it is
+    launched once and timed, and the steps alone are timed from a second
+    graph."""
     import numpy as np
     import torch
-    from paper_2306_01525_amd import MLBM_STENCIL_OWN, Params, Plan
+    from paper_2306_01525_amd import MLBM_STENCIL_PAPER, Params, Plan
     from synth import batched_tgv_specs, jittered_lattice, tgv_initial_velocity
     specs = batched_tgv_specs(64, seed=4)
     clouds, params, ux, uy = [], [], [], []
@@ -360,7 +440,7 @@ def run_batched(steps: int):
         a, b = tgv_initial_velocity(c.x, c.y, c.period[0], 0.01)
         clouds.append((c.x, c.y, c.period, None))
         params.append(Params(dx=c.h, K=sp["K"], degree=sp["degree"], tau=sp["tau"],
-                             stencil_mode=MLBM_STENCIL_OWN))
+                             stencil_mode=MLBM_STENCIL_PAPER))
         ux.append(a)
         uy.append(b)
     ux, uy = np.concatenate(ux), np.concatenate(uy)
@@ -661,6 +741,7 @@ def main():
     ap.add_argument("--skip-batched", action="store_true")
     ap.add_argument("--skip-annulus", action="store_true")
     ap.add_argument("--skip-lbm", action="store_true")
+    ap.add_argument("--skip-tgv40", action="store_true")
     ap.add_argument("--batched-steps", type=int, default=500)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a copy of known size (for HBM counter scaling)")
@@ -752,6 +833,7 @@ def main():
         ach = abpu * n / (r["adj_step_ms"] / 1e3) / 1e9
         line["adjoint_step"] = {"ms": r["adj_step_ms"], "bytes_per_update": abpu,
                                 "achieved": ach, "unit": "GB/s", "frac": ach / HBM_PEAK_GBS}
+        line["adjoint_rollout_500"] = r["rollout"]
     # local solves: n = K + M unknowns (M = 15 monomials of degree <= 4), LU-class
     # elimination 2n^3/3 plus 8 right-hand sides at 2n^2 each, per node
     nn = K + 15
@@ -762,6 +844,8 @@ def main():
     line["autotune"] = r["tune"]
     if not args.skip_lbm:
         line["lbm"] = run_lbm(args.steps, args.warmup, r["l2_steps"], r["l2_32"][0], ms_step)
+    if not args.skip_tgv40:
+        line["tgv40"] = run_tgv40()
     if not args.skip_annulus:
         line["annulus_490k"] = run_annulus(args.steps, args.warmup)
     if not args.skip_batched:

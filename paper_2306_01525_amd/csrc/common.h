@@ -154,16 +154,23 @@ constexpr float kMaxSpeed2 = 0.09f;
 // node whose moments are not finite or whose speed exceeds the limit is
 // reported (code MLBM_DEVERR_NONFINITE or MLBM_DEVERR_SPEED, and the lowest
 // such user index). The branch is taken only by a diverging run.
+// A diverging run fails at most of its nodes every step, so the words are
+// read first and written only when that adds a bit or lowers the node: the
+// atomics stay rare instead of serialising every lane on one address.
 template <class T>
 __device__ __forceinline__ void check_speed(int32_t *err, T uu, const int32_t *perm, int p,
                                             int uoff) {
     if (uu <= (T)kMaxSpeed2 || !err) return;
     const bool finite = (uu - uu) == (T)0;   // false for NaN and Inf
-    atomicOr(err + kErrFlags, finite ? MLBM_DEVERR_SPEED : MLBM_DEVERR_NONFINITE);
-    atomicMin(err + kErrNode, uoff + (perm ? perm[p] : p));
+    const int code = finite ? MLBM_DEVERR_SPEED : MLBM_DEVERR_NONFINITE;
+    const int user = uoff + (perm ? perm[p] : p);
+    if ((__atomic_load_n(err + kErrFlags, __ATOMIC_RELAXED) & code) != code)
+        atomicOr(err + kErrFlags, code);
+    if (user < __atomic_load_n(err + kErrNode, __ATOMIC_RELAXED)) atomicMin(err + kErrNode, user);
 }
 __device__ __forceinline__ void report_index(int32_t *err) {
-    if (err) atomicOr(err + kErrFlags, MLBM_DEVERR_INDEX);
+    if (err && !(__atomic_load_n(err + kErrFlags, __ATOMIC_RELAXED) & MLBM_DEVERR_INDEX))
+        atomicOr(err + kErrFlags, MLBM_DEVERR_INDEX);
 }
 
 // Arguments of the FP32 step for one cloud; also the per-cloud descriptor

@@ -10,6 +10,8 @@
   cloud.
 * `annulus_convergence`: the annular channel of Sec. 3 (Fig. bch_conv) with
   the paper's bounce-back walls and settings, run to the steady state.
+* `annulus_workload_steady`: the ~490,000-node annular workload (equilibrium
+  walls, tau = 0.7, K = 20, degree 3) from rest to the steady state.
 
 Flow and scaling follow Sec. 3: the unit periodic square, u = U0 cos 2 pi x
 sin 2 pi y, v = -U0 sin 2 pi x cos 2 pi y decaying as exp(-2 nu k^2 t) with
@@ -178,6 +180,64 @@ def annulus_convergence(hs=(1 / 10, 1 / 20, 1 / 40, 1 / 55, 1 / 80, 1 / 110), dx
                     "l2_speed": float(np.linalg.norm(U - exact) / np.linalg.norm(exact)),
                     "wall_speed_max": float(U[c.node_type == 1].max() / exact.max())})
     return out
+
+
+def annulus_workload_steady(precision: int = 0, n_target: int = 500_000, tau: float = 0.7,
+                            g: float | None = None, K: int = 20, degree: int = 3,
+                            tol: float = 1e-8, max_steps: int = 500_000, plateau: int = 10,
+                            check_every: int = 100, fixed_steps: int | None = None,
+                            seed: int = 3, device="cuda"):
+    """The annular-channel workload at full size run from rest to the steady
+    state (Sec. 3, with the workload's walls and threshold): about 490,000
+    Poisson-disk nodes between r = 1 and r = 2 (h chosen for n_target), dx =
+    h, K = 20 with degree 3, the paper's stencil rule, tau = 0.7, equilibrium
+    wall nodes, azimuthal acceleration g in lattice units (default: the
+    paper's g = 1e-6 at dx_ML = 1/160 under diffusive scaling to h). Stops
+    when the residual between checks `check_every` steps apart falls below
+    `tol`, after `plateau` checks without a new minimum, or at max_steps; with
+    fixed_steps, runs exactly that many steps instead. Returns the stop
+    record, the L2 errors of the azimuthal velocity and of the speed against
+    eq. bch_solution, the largest radial over the largest azimuthal speed, the
+    wall speed, and the velocity field (user order) for comparisons."""
+    import time as _time
+    import torch
+    from .mlbm import Params, Plan
+    from .targets import annulus_azimuthal
+    from synth.clouds import annulus_force, annulus_h_for_count, annulus_poisson
+    c = annulus_poisson(1.0, 2.0, annulus_h_for_count(1.0, 2.0, n_target), seed=seed)
+    g = annulus_force(c.h) if g is None else g
+    p = Params(dx=c.h, K=K, degree=degree, tau=tau, stencil_mode=0, precision=precision,
+               force_kind=1, force_mag=g, wall_kind=1, rho_wall=1.0)
+    plan = Plan.build(c.x, c.y, c.period, p, node_type=c.node_type, device=device)
+    zeros = np.zeros(c.n)
+    torch.cuda.synchronize()
+    t0 = _time.perf_counter()
+    if fixed_steps is None:
+        gs, steps, res, why = plan.run_to_steady(plan.init(zeros, zeros), tol=tol,
+                                                 check_every=check_every, max_steps=max_steps,
+                                                 plateau=plateau)
+    else:
+        gs = plan.step(plan.init(zeros, zeros), plan.new_state(), fixed_steps)
+        steps, res, why = fixed_steps, float("nan"), "fixed"
+    torch.cuda.synchronize()
+    wall_s = _time.perf_counter() - t0
+    _, u, v = (a.cpu().numpy() for a in plan.moments(gs))
+    err = plan.device_error()
+    plan.close()
+    r = np.hypot(c.x, c.y)
+    ut = (-u * c.y + v * c.x) / r
+    ur = (u * c.x + v * c.y) / r
+    exact = annulus_azimuthal(r, 1.0, 2.0, c.h, g, tau)
+    fluid = c.node_type == 0
+    return {"precision": precision, "nodes": c.n, "h": c.h, "g": g,
+            "u_max_analytic": float(np.abs(exact).max()), "steps": steps, "stop": why,
+            "residual": res, "seconds": wall_s, "device_error": err,
+            "l2_u_phi": float(np.linalg.norm(ut - exact) / np.linalg.norm(exact)),
+            "l2_speed": float(np.linalg.norm(np.hypot(u, v) - np.abs(exact)) /
+                              np.linalg.norm(exact)),
+            "max_radial_over_azimuthal": float(np.abs(ur[fluid]).max() / np.abs(exact).max()),
+            "wall_speed_max": float(np.hypot(u, v)[~fluid].max()),
+            "u": u, "v": v}
 
 
 def main():

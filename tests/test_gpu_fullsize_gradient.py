@@ -6,7 +6,8 @@ a vortex 10 % weaker than the initial one, so the misfit is not a near
 cancellation of the two fields.
 
 FP64: the adjoint gradient against central differences of the FP64 forward
-along a smooth direction of u0 and in tau. FP32 (the benchmarked path):
+along a smooth direction of u0 and in tau, and against the FP64 oracle's
+complex-step derivatives on the same cloud. FP32 (the benchmarked path):
 against the FP64 gradient, within the FP32 rounding bound carried through the
 misfit."""
 import math
@@ -14,6 +15,7 @@ import math
 import numpy as np
 import pytest
 
+import oracle
 from gpu_common import rel_l2, say, tol_fp32
 from synth import jittered_lattice, tgv_initial_velocity
 
@@ -80,6 +82,28 @@ def test_fullsize_gradient_fd_and_fp32():
     # central differences: O(eps^2) truncation, rounding of J ~ 1e-16 J / eps
     assert abs(D - fd) <= 1e-6 * abs(D) + 1e-9 * J64
     assert abs(gt64 - fdt) <= 1e-6 * abs(gt64) + 1e-9 * J64
+
+    # the FP64 oracle on the same cloud: its loss and its complex-step
+    # derivatives J(u0 + i h d) and J(tau + i h) (exact to rounding, no
+    # cancellation) along the same direction and in tau
+    say("oracle: build and complex-step rollouts on the whole cloud")
+    nbr, own, W = oracle.build_plan(c, c.h, K, M_DEG, 0, search="tree")
+    hcs = 1e-30
+    Jo, Jd = oracle.loss_cs(nbr, own, W, TAU, STEPS, 1.0, u0x, u0y, tx, ty,
+                            u0x_im=hcs * dx, u0y_im=hcs * dy)
+    _, Jt = oracle.loss_cs(nbr, own, W, TAU, STEPS, 1.0, u0x, u0y, tx, ty, tau_im=hcs)
+    del nbr, own, W
+    Dcs, Tcs = Jd / hcs, Jt / hcs
+    say("oracle: J %.12e vs GPU %.12e; direction %.12e vs GPU %.12e; tau %.12e vs GPU %.12e"
+        % (Jo, J64, Dcs, D, Tcs, gt64))
+    # the gradient carries rounding relative to its own size; the direction
+    # is nearly orthogonal to it, so the directional derivative is compared
+    # on the scale |grad| |d| (measured 7.7e-13 relative in J, 1.7e-12 in tau)
+    scale = math.sqrt(float(gx64 @ gx64 + gy64 @ gy64) * float(dx @ dx + dy @ dy))
+    say("oracle: |D - D_cs| / (|grad| |d|) %.2e" % (abs(D - Dcs) / scale))
+    assert abs(J64 - Jo) <= 4e-12 * Jo
+    assert abs(D - Dcs) <= 1e-10 * scale
+    assert abs(gt64 - Tcs) <= 1e-11 * abs(Tcs)
 
     say("FP32 rollout + adjoint")
     p32 = _plan(c, 0)
