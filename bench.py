@@ -588,7 +588,10 @@ def summarize_pmc(fetch_dir, write_dir, command):
 
     fetch = per_kernel(_read_counter_csv(fetch_dir), "FETCH_SIZE")
     write = per_kernel(_read_counter_csv(write_dir), "WRITE_SIZE")
-    steps = [k for k in fetch if "k_step32" in k]
+    # the headline kernel: the TGV step (paper stencils, no force, no walls,
+    # no recording) in whichever variant the autotuner kept
+    steps = [k for k in fetch if ("k_step32s<0, false, 0, false" in k or
+                                  "k_step32<0, false, 0, false" in k)]
     step = max(steps, key=lambda k: len(fetch[k]))
     copy = [k for k in fetch if "elementwise" in k and "mul" in k.lower()]
     copy = max(copy, key=lambda k: len(fetch[k]))
@@ -689,7 +692,7 @@ def summarize_sq(dirs, kernels, out_path, command):
 PROFILE_TRACE = os.path.join(ROOT, "profiles", "kernels_bench_default.txt")
 
 
-def summarize_trace(trace_dir, command):
+def summarize_trace(trace_dir, command, out_path=None):
     """Text summary of a rocprofv3 --kernel-trace --stats run (kernel_stats.csv):
     per kernel calls, mean and total duration, for profiles/."""
     import csv
@@ -711,8 +714,9 @@ def summarize_trace(trace_dir, command):
         lines.append("%-8s %12.2f %12.1f %7s  %s" % (r["Calls"], float(r["AverageNs"]) / 1e3,
                                                      float(r["TotalDurationNs"]) / 1e3,
                                                      r["Percentage"][:6], name))
-    os.makedirs(os.path.dirname(PROFILE_TRACE), exist_ok=True)
-    with open(PROFILE_TRACE, "w") as fh:
+    out_path = out_path or PROFILE_TRACE
+    os.makedirs(os.path.dirname(out_path), exist_ok=True)
+    with open(out_path, "w") as fh:
         fh.write("\n".join(lines) + "\n")
     print("\n".join(lines))
 
@@ -756,9 +760,10 @@ def main():
     ap.add_argument("--sq-out", default=os.path.join(ROOT, "profiles", "sq_counters.txt"))
     ap.add_argument("--summarize-trace", metavar="TRACE_DIR",
                     help="summarise a rocprofv3 --kernel-trace --stats run")
+    ap.add_argument("--trace-out", default=None, help="where the trace summary goes")
     args = ap.parse_args()
     if args.summarize_trace:
-        summarize_trace(args.summarize_trace, args.pmc_command)
+        summarize_trace(args.summarize_trace, args.pmc_command, args.trace_out)
         return
     if args.summarize_traffic:
         summarize_traffic(*args.summarize_traffic, args.pmc_command)

@@ -54,6 +54,7 @@ typedef enum {
 } mlbm_status;
 
 enum { MLBM_FP32_DEV = 0, MLBM_FP64 = 1 };          /* mlbm_params.precision    */
+enum { MLBM_STEP_VARIANTS = 10 };   /* FP32 step variants (mlbm_autotune)           */
 enum { MLBM_STENCIL_PAPER = 0, MLBM_STENCIL_OWN = 1 }; /* mlbm_params.stencil_mode */
 
 /* One point cloud (Sec. 2.2: the set X of Eulerian nodes). */
@@ -339,8 +340,8 @@ mlbm_status mlbm_init_adjoint(const mlbm_plan *plan, const double *u0x, const do
  * of the stencil loop, non-temporal weight loads, one or two lanes per node)
  * for n_steps steps each, after one warm-up step, on this plan's own cloud,
  * and keeps the fastest for every later step and graph. ms_out (host, may be
- * NULL, room for 8 floats) receives the measured milliseconds per step of each
- * variant, *n_variants (host, may be NULL) their count (8). The contents of
+ * NULL, room for MLBM_STEP_VARIANTS floats) receives the measured milliseconds
+ * per step of each variant, *n_variants (host, may be NULL) their count. The contents of
  * g_a and g_b are advanced (start again from mlbm_init afterwards). Synchronous. FP64 plans have a single variant. */
 mlbm_status mlbm_autotune(mlbm_plan *plan, void *g_a, void *g_b, int32_t n_steps,
                           float *ms_out, int32_t *n_variants, hipStream_t stream);

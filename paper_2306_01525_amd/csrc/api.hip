@@ -125,7 +125,7 @@ void layout_cloud(const mlbm_cloud &c, const mlbm_params &p, int precision, Carv
     }
     {   // gather tables of the LDS-staged steps (both precisions)
         const int ntiles = (n + kTile - 1) / kTile;
-        cp.hcap = 1024;
+        cp.hcap = kHaloCap;
         cp.ocap = std::min(512, (65536 - 8 * cp.hcap * 4) / (4 * ((K + 2) / 3)));
         cp.tdesc = pl.take<int32_t>((size_t)2 * ntiles);
         if (p.stencil_mode == MLBM_STENCIL_PAPER) cp.ownerL = pl.take<uint16_t>((size_t)8 * n);

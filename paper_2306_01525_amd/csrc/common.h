@@ -66,7 +66,8 @@ constexpr int kMaxK = 48;       // largest stencil supported
 // room for all 64.
 inline int64_t head_nodes(int n) { return ((int64_t)n + 63) / 64 * 64; }
 constexpr int kTile = 256;      // nodes per workgroup in the step kernels
-constexpr int kStepVariants = 8; // FP32 step tuning variants
+constexpr int kHaloCap = 1024;  // largest halo a tile stages (10-bit positions)
+constexpr int kStepVariants = MLBM_STEP_VARIANTS; // FP32 step tuning variants
 constexpr int kBuildLanes = 4;   // clouds of one plan built concurrently
 constexpr int kStats = 4;        // build records per cloud (tile tables)
 

@@ -121,6 +121,62 @@ __device__ __forceinline__ double2 load_w2(const double2 *p) {
     return make_double2(v.x, v.y);
 }
 
+// Staging of a tile (before its barrier), NTH threads. Every load of a lane
+// is issued before the first LDS store, so the L2 round trips overlap
+// instead of following one another: the halo populations (a halo holds at
+// most kHaloCap nodes, so at most kHaloCap / NTH per lane) and the index
+// words (in batches of four per lane).
+template <int NTH>
+__device__ __forceinline__ void stage_halo32(const float *__restrict__ g, int n,
+                                             const int32_t *__restrict__ hl, int nh,
+                                             float *__restrict__ gl, int32_t *err, int tid) {
+    constexpr int U = (kHaloCap + NTH - 1) / NTH;
+    int q[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const int h = tid + u * NTH;
+        int v = h < nh ? hl[h] : 0;
+        if ((unsigned)v >= (unsigned)n) {   // a bad table must not fault
+            v = 0;
+            report_index(err);
+        }
+        q[u] = v;
+    }
+    float v[U][8];
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+#pragma unroll
+        for (int d = 0; d < 8; ++d)
+            v[u][d] = tid + u * NTH < nh ? g[(int64_t)(d + 1) * n + q[u]] : 0.0f;
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const int h = tid + u * NTH;
+        if (h < nh) {
+#pragma unroll
+            for (int d = 0; d < 8; ++d) gl[d * nh + h] = v[u][d];
+        }
+    }
+}
+
+template <int NTH>
+__device__ __forceinline__ void stage_words(uint32_t *__restrict__ dst,
+                                            const uint32_t *__restrict__ src, int count,
+                                            int tid) {
+    for (int b = 0; b < count; b += 4 * NTH) {
+        uint32_t v[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int w = b + tid + u * NTH;
+            v[u] = w < count ? src[w] : 0u;
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int w = b + tid + u * NTH;
+            if (w < count) dst[w] = v[u];
+        }
+    }
+}
+
 template <int MODE, bool FORCE, int WALL, bool REC, int UNROLL, bool NT>
 __device__ __forceinline__ void step32_tile(const Step32Args &a, const float *__restrict__ g,
                                             float *__restrict__ go, int64_t tile,
@@ -142,17 +198,8 @@ __device__ __forceinline__ void step32_tile(const Step32Args &a, const float *__
         float *gl = reinterpret_cast<float *>(smem);                 // [8][nh]
         uint32_t *nl = reinterpret_cast<uint32_t *>(gl + 8 * nh);    // [no][Kw]
         const int32_t *hl = a.hlist + tile * (int64_t)a.hcap;
-        for (int h = tid; h < nh; h += kTile) {
-            int q = hl[h];
-            if ((unsigned)q >= (unsigned)n) {   // a bad table must not fault
-                q = 0;
-                report_index(a.err);
-            }
-#pragma unroll
-            for (int d = 0; d < 8; ++d) gl[d * nh + h] = g[(int64_t)(d + 1) * n + q];
-        }
-        const uint32_t *src = a.nbrL + tile * (int64_t)a.ocap * Kw;
-        for (int w = tid; w < no * Kw; w += kTile) nl[w] = src[w];
+        stage_halo32<kTile>(g, n, hl, nh, gl, a.err, tid);
+        stage_words<kTile>(nl, a.nbrL + tile * (int64_t)a.ocap * Kw, no * Kw, tid);
         __syncthreads();
         if (tid >= cnt) return;
         const int p = base + tid;
@@ -235,7 +282,7 @@ __device__ __forceinline__ float swap_pair(float v) {
                                                       false));   // quad_perm [1,0,3,2]
 }
 
-template <int MODE, bool FORCE, int WALL, bool REC, bool NT>
+template <int MODE, bool FORCE, int WALL, bool REC, bool NT, int UNROLL>
 __device__ __forceinline__ void step32_tile_split(const Step32Args &a,
                                                   const float *__restrict__ g,
                                                   float *__restrict__ go, int64_t tile,
@@ -256,17 +303,8 @@ __device__ __forceinline__ void step32_tile_split(const Step32Args &a,
         float *gl = reinterpret_cast<float *>(smem);                 // [8][nh]
         uint32_t *nl = reinterpret_cast<uint32_t *>(gl + 8 * nh);    // [no][Kw]
         const int32_t *hl = a.hlist + tile * (int64_t)a.hcap;
-        for (int i = tid; i < nh; i += 2 * kTile) {
-            int q = hl[i];
-            if ((unsigned)q >= (unsigned)n) {   // a bad table must not fault
-                q = 0;
-                report_index(a.err);
-            }
-#pragma unroll
-            for (int d = 0; d < 8; ++d) gl[d * nh + i] = g[(int64_t)(d + 1) * n + q];
-        }
-        const uint32_t *src = a.nbrL + tile * (int64_t)a.ocap * Kw;
-        for (int w = tid; w < no * Kw; w += 2 * kTile) nl[w] = src[w];
+        stage_halo32<2 * kTile>(g, n, hl, nh, gl, a.err, tid);
+        stage_words<2 * kTile>(nl, a.nbrL + tile * (int64_t)a.ocap * Kw, no * Kw, tid);
         __syncthreads();
         if (l >= cnt) return;   // both lanes of a node leave together
         const int p = base + l;
@@ -276,6 +314,7 @@ __device__ __forceinline__ void step32_tile_split(const Step32Args &a,
             ol[dd] = (MODE == MLBM_STENCIL_OWN ? l
                                                : (int)a.ownerL[(int64_t)(4 * h + dd) * n + p]) * Kw;
         const float *glh = gl + 4 * h * nh;
+#pragma unroll UNROLL
         for (int w = 0; w < Kw; ++w) {
             uint32_t word[4];
 #pragma unroll
@@ -326,13 +365,13 @@ __device__ __forceinline__ void step32_tile_split(const Step32Args &a,
                                       a.frec, a.err, a.perm, a.uoff, h ? 5 : 0, h ? kQ : 5);
 }
 
-template <int MODE, bool FORCE, int WALL, bool REC, bool NT>
+template <int MODE, bool FORCE, int WALL, bool REC, bool NT, int UNROLL>
 __global__ __launch_bounds__(2 * kTile) void k_step32s(Step32Args a, const float *__restrict__ g,
                                                        float *__restrict__ go, int64_t nblocks) {
     extern __shared__ __align__(16) unsigned char smem[];
     const int64_t tile = xcd_tile(nblocks);
     if (tile >= nblocks) return;
-    step32_tile_split<MODE, FORCE, WALL, REC, NT>(a, g, go, tile, smem);
+    step32_tile_split<MODE, FORCE, WALL, REC, NT, UNROLL>(a, g, go, tile, smem);
 }
 
 template <int MODE, bool FORCE, int WALL, bool REC, int UNROLL, bool NT>
@@ -361,7 +400,7 @@ __global__ __launch_bounds__(kTile) void k_step32_batch(const Step32Args *__rest
                                                         t - a.tile_begin, smem);
 }
 
-template <int MODE, bool NT>
+template <int MODE, bool NT, int UNROLL>
 __global__ __launch_bounds__(2 * kTile) void k_step32s_batch(const Step32Args *__restrict__ descs,
                                                              const int32_t *__restrict__ tile2cloud,
                                                              const float *__restrict__ g,
@@ -371,8 +410,8 @@ __global__ __launch_bounds__(2 * kTile) void k_step32s_batch(const Step32Args *_
     const int64_t t = xcd_tile(total_tiles);
     if (t >= total_tiles) return;
     const Step32Args a = descs[tile2cloud[t]];
-    step32_tile_split<MODE, false, false, false, NT>(a, g + a.soff, go + a.soff,
-                                                     t - a.tile_begin, smem);
+    step32_tile_split<MODE, false, false, false, NT, UNROLL>(a, g + a.soff, go + a.soff,
+                                                             t - a.tile_begin, smem);
 }
 
 // Writes one batch descriptor (a kernel, so that graph capture records it).
@@ -758,8 +797,8 @@ __global__ void k_collide(int n, const T *__restrict__ f, T *__restrict__ g,
 // and non-temporal weight loads (the weights are streamed once per step and
 // need not displace the halo rows in L2). Variant v < 6: one lane per node,
 // unroll {1, 2, 3}[v / 2], non-temporal v % 2. Tiles without tables unroll
-// their row loop 3x that. Variants 6 and 7: two lanes per node (directions
-// split in halves), non-temporal v % 2.
+// their row loop 3x that. Variants 6-9: two lanes per node (directions split
+// in halves), non-temporal v % 2, the index-word loop unrolled 2x from 8 on.
 template <int MODE, bool FORCE, int WALL, bool REC, int UNROLL, bool NT>
 void launch32(const CloudPlan &cp, const void *gin, void *gout, void *frec, int64_t nblocks,
               hipStream_t s) {
@@ -769,18 +808,18 @@ void launch32(const CloudPlan &cp, const void *gin, void *gout, void *frec, int6
                        nblocks);
 }
 
-template <int MODE, bool FORCE, int WALL, bool REC, bool NT>
+template <int MODE, bool FORCE, int WALL, bool REC, bool NT, int UNROLL = 1>
 void launch32s(const CloudPlan &cp, const void *gin, void *gout, void *frec, int64_t nblocks,
                hipStream_t s) {
     const Step32Args a = step32_args(cp, frec);
-    hipLaunchKernelGGL((k_step32s<MODE, FORCE, WALL, REC, NT>), dim3(xcd_grid(nblocks)),
+    hipLaunchKernelGGL((k_step32s<MODE, FORCE, WALL, REC, NT, UNROLL>), dim3(xcd_grid(nblocks)),
                        dim3(2 * kTile), cp.lds_bytes, s, a, (const float *)gin, (float *)gout,
                        nblocks);
 }
 
-template <int MODE, bool NT>
+template <int MODE, bool NT, int UNROLL = 1>
 void launch32s_batch(const mlbm_plan &plan, const void *gin, void *gout, hipStream_t s) {
-    hipLaunchKernelGGL((k_step32s_batch<MODE, NT>), dim3(xcd_grid(plan.total_tiles)),
+    hipLaunchKernelGGL((k_step32s_batch<MODE, NT, UNROLL>), dim3(xcd_grid(plan.total_tiles)),
                        dim3(2 * kTile), plan.batch_lds, s, plan.descs, plan.tile2cloud,
                        (const float *)gin, (float *)gout, plan.total_tiles);
 }
@@ -802,6 +841,8 @@ void launch32_batch_v(const mlbm_plan &plan, const void *gin, void *gout, hipStr
         case 5: launch32_batch<MODE, 3, true>(plan, gin, gout, s); break;
         case 6: launch32s_batch<MODE, false>(plan, gin, gout, s); break;
         case 7: launch32s_batch<MODE, true>(plan, gin, gout, s); break;
+        case 8: launch32s_batch<MODE, false, 2>(plan, gin, gout, s); break;
+        case 9: launch32s_batch<MODE, true, 2>(plan, gin, gout, s); break;
         default: launch32_batch<MODE, 1, false>(plan, gin, gout, s); break;
     }
 }
@@ -821,6 +862,8 @@ void launch32_tuned(const CloudPlan &cp, const void *gin, void *gout, void *frec
         case 5: launch32<MODE, FORCE, WALL, REC, 3, true>(cp, gin, gout, frec, nblocks, s); break;
         case 6: launch32s<MODE, FORCE, WALL, REC, false>(cp, gin, gout, frec, nblocks, s); break;
         case 7: launch32s<MODE, FORCE, WALL, REC, true>(cp, gin, gout, frec, nblocks, s); break;
+        case 8: launch32s<MODE, FORCE, WALL, REC, false, 2>(cp, gin, gout, frec, nblocks, s); break;
+        case 9: launch32s<MODE, FORCE, WALL, REC, true, 2>(cp, gin, gout, frec, nblocks, s); break;
         default: launch32<MODE, FORCE, WALL, REC, 1, false>(cp, gin, gout, frec, nblocks, s); break;
     }
 }

@@ -177,7 +177,7 @@ def test_step_variants_are_bitwise_identical_and_autotune_picks_one():
     plan = Plan.build(c.x, c.y, c.period, _params(c.h, 30, 4, 0, 0, 0.6))
     for pl, vx, vy in ((walled, za, za), (plan, ux, uy)):
         ref = rec_ref = None
-        for v in range(8):   # 0-5 one lane per node, 6-7 two
+        for v in range(10):   # 0-5 one lane per node, 6-9 two
             pl.set_variant(v)
             g = pl.init(vx, vy)
             g = pl.step(g, pl.new_state(), 25)
@@ -194,7 +194,7 @@ def test_step_variants_are_bitwise_identical_and_autotune_picks_one():
     a, b = plan.new_state(), plan.new_state()
     ms = plan.autotune(plan.init(ux, uy, g=a), b, 5)
     say("variant ms/step", ["%.4f" % m for m in ms], "chosen", plan.info.variant)
-    assert len(ms) == 8 and all(m > 0 for m in ms)
+    assert len(ms) == 10 and all(m > 0 for m in ms)
     assert ms[plan.info.variant] == min(ms)
     plan.close()
 
