@@ -753,6 +753,324 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) void
     rbf_solve<NB, R, SYS, REPLAY>(geo, xs, ys, perm, nbr, L, n, K, m, dx, W64, dev_err);
 }
 
+// ---- the same solve with the FP64 matrix cores ------------------------------
+// The systems and the elimination of rbf_solve (Gauss-Jordan, partial
+// pivoting on the upper 32 bits of |a_k|, ties to the lowest row, rows never
+// moved, pivot rows left unscaled), taken four pivot columns at a time so that
+// the bulk of the arithmetic runs on v_mfma_f64_16x16x4:
+//  - the augmented matrix [Phi | b_0 .. b_15] (NB = 16 RT unknowns, up to 16
+//    departure points) lives in the registers of one wavefront as RT x (RT+1)
+//    tiles of 16 x 16 in the result layout of that instruction (register i of
+//    lane l holds row l / 16 + 4 i, column l % 16 of its tile);
+//  - a panel of four columns is copied to LDS and eliminated with one row per
+//    lane, pivot search and row reads as in rbf_solve but on four columns. Its
+//    four steps E_j = I - l_j e_{p_j}^T (l_j the multipliers, zero at the pivot
+//    row p_j) multiply to I - Lt S^T, S^T selecting the pivot rows; the new
+//    column of Lt is the step's multipliers and the earlier ones are reduced
+//    by the step like matrix columns;
+//  - every column right of the panel, right-hand sides included, then takes
+//    the rank-4 product -Lt U, U the four pivot rows as they stood before the
+//    panel: RT x (tiles right of the panel) matrix-core products, with Lt in
+//    the A layout (lane 16 k + r holds row r, column k) and U in the B layout
+//    (lane 16 k + c holds row k, column c).
+// The pivot row of step j ends as d_j e_j on the matrix part, so unknown j is
+// its right-hand-side entry times 1/d_j. Owners with more than 16 departure
+// points solve again for each further group of 16. Each lane assembles its own
+// tile entries (monomials from a per-member table in LDS).
+// The FP64 matrix-core rate of gfx950 equals its FP64 vector rate: what the
+// products save is issue slots (108 products a system at 48 unknowns against
+// about 2,700 vector FMAs). The pivot steps (reduction, lane reads) stay
+// serial and dominate what remains.
+typedef double dbl4 __attribute__((ext_vector_type(4)));
+
+// v from the lane CTRL names (a DPP row pattern), both halves of a double
+template <int CTRL> __device__ __forceinline__ double dpp_d(double v) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffll), CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, false);
+    return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+
+template <int RT>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(RT == 3 ? 3 : 2))) void k_rbf_mfma(
+    const Geo *__restrict__ geo, const double *__restrict__ xs, const double *__restrict__ ys,
+    const int32_t *__restrict__ perm, const int32_t *__restrict__ nbr, RhsList L, int n, int K,
+    int m, double dx, double *__restrict__ W64, int32_t *__restrict__ dev_err) {
+    constexpr int NB = 16 * RT, CT = RT + 1, NC = 16 * CT;
+    __shared__ double2 s_c[64];          // scaled stencil members
+    __shared__ double2 s_q[16];          // scaled departure points of the group
+    __shared__ int2 s_pk[16];            // their (node, direction)
+    __shared__ double s_pan[4][NB];      // panel columns
+    __shared__ double s_L[4][NB];        // Lt, column-major
+    __shared__ double s_U[4][NC][4];     // the row groups that hold the pivot rows
+    __shared__ int s_step[NB];
+    __shared__ double s_pinv[NB];
+    static_assert(48 * 15 + 16 * 15 <= 4 * NC * 4, "the monomial tables fit in s_U");
+    const int lane = threadIdx.x;
+    const int s = blockIdx.x;
+    if (s >= n) return;
+    const int count = L.ptr ? L.ptr[s + 1] - L.ptr[s] : 8;
+    if (count == 0) return;
+    const Geo g = *geo;
+    const int M = (m + 1) * (m + 2) / 2;
+    const int nn = K + M;
+
+    double rx = 0.0, ry = 0.0;
+    if (lane < K) {
+        const int q = nbr[(int64_t)lane * n + s];
+        rx = min_image(xs[q] - xs[s], g.Lx);
+        ry = min_image(ys[q] - ys[s], g.Ly);
+    }
+    double rad = sqrt(rx * rx + ry * ry);
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) rad = fmax(rad, __shfl_xor(rad, off));
+    if (!(rad > 0.0)) rad = 1.0;
+    const double sx = rx / rad, sy = ry / rad, irad = 1.0 / rad;
+    s_c[lane] = make_double2(sx, sy);
+    bool singular = false;
+
+    for (int c0 = 0; c0 < count; c0 += 16) {
+        const int cnt = min(16, count - c0);
+        if (lane < 16) {
+            double qx = 0.0, qy = 0.0;
+            int p = 0, k = 1;
+            if (lane < cnt) {
+                rhs_point(L, s, c0 + lane, p, k);
+                qx = (L.ptr ? min_image(xs[p] - lat_ex(k) * dx - xs[s], g.Lx) : -lat_ex(k) * dx) *
+                     irad;
+                qy = (L.ptr ? min_image(ys[p] - lat_ey(k) * dx - ys[s], g.Ly) : -lat_ey(k) * dx) *
+                     irad;
+            }
+            s_q[lane] = make_double2(qx, qy);
+            s_pk[lane] = make_int2(p, k);
+        }
+        wave_lds_sync();
+
+        // monomials of the stencil members (lanes below K) and of the group's
+        // departure points (lanes 48 + t), row stride 15, in the space that
+        // the elimination uses for U; powers first, then each product
+        double *tab = &s_U[0][0][0];
+        // the lane index again, opaque to the compiler: what depends on it is
+        // recomputed for each group rather than kept live from the first
+        int lid = lane;
+        __asm__ volatile("" : "+v"(lid));
+        const int g4 = lid >> 4, cl = lid & 15;
+        {
+            const int t = lid - 48;
+            const bool mem = lid < K, dep = t >= 0 && t < cnt;
+            double px = sx, py = sy;
+            if (dep) {
+                const double2 q = s_q[t];
+                px = q.x;
+                py = q.y;
+            }
+            double xp[5], yp[5];
+            xp[0] = yp[0] = 1.0;
+#pragma unroll
+            for (int e = 1; e < 5; ++e) {
+                xp[e] = xp[e - 1] * px;
+                yp[e] = yp[e - 1] * py;
+            }
+            double *row = tab + (mem ? lid * 15 : 720 + (dep ? t : 0) * 15);
+            if (mem || dep) {
+#pragma unroll
+                for (int d = 0, q = 0; d <= 4; ++d)
+#pragma unroll
+                    for (int ey = 0; ey <= d; ++ey, ++q)
+                        if (q < M) row[q] = xp[d - ey] * yp[ey];
+            }
+        }
+        wave_lds_sync();
+
+        // assembly: every lane computes its own entries of the tiles; the
+        // branches on a tile's place against K are uniform
+        dbl4 T[RT][CT];
+        double rsum[RT][4];
+#pragma unroll
+        for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int r = 16 * rt + g4 + 4 * i;
+                const double2 xr = s_c[r];
+                const bool rr = r < K, pr = r >= K && r < nn;
+                double acc = 0.0;
+#pragma unroll
+                for (int ct = 0; ct < RT; ++ct) {
+                    const int c = 16 * ct + cl;
+                    const bool rc = c < K, pc = c >= K && c < nn;
+                    double r3 = 0.0;
+                    if (16 * rt < K && 16 * ct < K) {
+                        const double2 xc = s_c[c];
+                        r3 = cube_dist(xr.x, xr.y, xc.x, xc.y);
+                    }
+                    const int ti = rr && pc ? r * 15 + (c - K) : pr && rc ? c * 15 + (r - K) : 0;
+                    const double tv = tab[ti];
+                    const double a = rr ? (rc ? r3 : (pc ? tv : 0.0))
+                                        : pr ? (rc ? tv : 0.0) : (r == c ? 1.0 : 0.0);
+                    T[rt][ct][i] = a;
+                    acc += fabs(a);
+                }
+                rsum[rt][i] = acc;
+                {
+                    const int t = cl;
+                    double r3 = 0.0;
+                    if (16 * rt < K) {
+                        const double2 q = s_q[t];
+                        r3 = cube_dist(xr.x, xr.y, q.x, q.y);
+                    }
+                    const double tv = tab[pr ? 720 + t * 15 + (r - K) : 0];
+                    T[rt][RT][i] = t < cnt ? (rr ? r3 : (pr ? tv : 0.0)) : 0.0;
+                }
+                // one row at a time: keeps the compiler from hoisting every
+                // row's table reads (and their registers) to the start
+                __asm__ volatile("" ::: "memory");
+            }
+        // infinity norm of the matrix: row sums over the sixteen lanes that
+        // share a row group, then the largest row
+        double rs = 0.0;
+#pragma unroll
+        for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                double v = rsum[rt][i];
+                v += dpp_d<0x128>(v);
+                v += dpp_d<0x124>(v);
+                v += dpp_d<0x122>(v);
+                v += dpp_d<0x121>(v);
+                rs = fmax(rs, v);
+            }
+        rs = fmax(fmax(readlane_d(rs, 0), readlane_d(rs, 16)),
+                  fmax(readlane_d(rs, 32), readlane_d(rs, 48)));
+        const double tiny = 1e3 * DBL_EPSILON * rs;
+        wave_lds_sync();   // the table's space is U's from here on
+
+        int pstep = lane < NB ? NB : -1;
+        double pinv = 1.0;
+        // panels: the column tile of the panel is unrolled (register tiles
+        // take compile-time indices), the four panels inside it are not; the
+        // products cover the panel's own tile too (for its last panel only
+        // finished columns change there)
+#pragma unroll
+        for (int ctp = 0; ctp < RT; ++ctp) {
+#pragma unroll 1
+            for (int cp0 = 0; cp0 < 16; cp0 += 4) {
+                const int k0 = 16 * ctp + cp0;
+                if (k0 >= nn) break;                  // uniform
+                if (cl >= cp0 && cl < cp0 + 4) {
+#pragma unroll
+                    for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+                        for (int i = 0; i < 4; ++i)
+                            s_pan[cl - cp0][16 * rt + g4 + 4 * i] = T[rt][ctp][i];
+                }
+                wave_lds_sync();
+                double pv[4] = {0.0, 0.0, 0.0, 0.0}, Lt[4] = {0.0, 0.0, 0.0, 0.0};
+                if (lane < NB) {
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) pv[j] = s_pan[j][lane];
+                }
+                int plist[4];
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const int k = k0 + j;
+                    plist[j] = -1;
+                    if (k >= nn) continue;            // uniform
+                    const uint32_t key =
+                        pstep > k
+                            ? ((uint32_t)(__double_as_longlong(pv[j]) >> 32) & 0x7FFFFFFFu) | 1u
+                            : 0u;
+                    const double rk = recip(pv[j]);
+                    const uint32_t km = group_max_u32<1>(key, 0);
+                    const int pl =
+                        __builtin_amdgcn_readfirstlane(__builtin_ctzll(__ballot(key == km)));
+                    const double pvv = readlane_d(pv[j], pl), pi = readlane_d(rk, pl);
+                    if (!(fabs(pvv) > tiny)) singular = true;
+                    if (lane == pl) {
+                        pstep = k;
+                        pinv = pi;
+                    }
+                    const double l = lane != pl ? pv[j] * pi : 0.0;
+#pragma unroll
+                    for (int jj = j + 1; jj < 4; ++jj)
+                        pv[jj] = __builtin_fma(-l, readlane_d(pv[jj], pl), pv[jj]);
+#pragma unroll
+                    for (int jj = 0; jj < j; ++jj)
+                        Lt[jj] = __builtin_fma(-l, readlane_d(Lt[jj], pl), Lt[jj]);
+                    Lt[j] = l;
+                    plist[j] = pl;
+                }
+                if (lane < NB) {
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) s_L[j][lane] = Lt[j];
+                }
+                // U: the row group of each pivot row writes its four rows of
+                // every tile from the panel's on; a step past nn gives a zero row
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const int p = plist[j];
+                    if (p < 0) {
+                        if (g4 == 0) {
+#pragma unroll
+                            for (int ct = ctp; ct < CT; ++ct)
+                                *reinterpret_cast<dbl4 *>(&s_U[j][16 * ct + cl][0]) =
+                                    dbl4{0.0, 0.0, 0.0, 0.0};
+                        }
+                        continue;
+                    }
+                    const int rtp = p >> 4, gp = p & 3;
+                    // one branch per row tile (uniform); the empty asm keeps
+                    // the compiler from merging the stores into one store of
+                    // a value selected across every tile
+#pragma unroll
+                    for (int rt = 0; rt < RT; ++rt) {
+                        if (rt == rtp) {
+                            __asm__ volatile("" ::: "memory");
+                            if (g4 == gp) {
+#pragma unroll
+                                for (int ct = ctp; ct < CT; ++ct)
+                                    *reinterpret_cast<dbl4 *>(&s_U[j][16 * ct + cl][0]) =
+                                        T[rt][ct];
+                            }
+                        }
+                    }
+                }
+                wave_lds_sync();
+                const int pk =
+                    g4 == 0 ? plist[0] : g4 == 1 ? plist[1] : g4 == 2 ? plist[2] : plist[3];
+                const int ik = pk < 0 ? 0 : ((pk & 15) >> 2);
+#pragma unroll
+                for (int rt = 0; rt < RT; ++rt) {
+                    const double a = -s_L[g4][16 * rt + cl];
+#pragma unroll
+                    for (int ct = ctp; ct < CT; ++ct) {
+                        const double b = s_U[g4][16 * ct + cl][ik];
+                        T[rt][ct] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, T[rt][ct], 0, 0, 0);
+                    }
+                }
+                wave_lds_sync();
+            }
+        }
+        if (lane < NB) {
+            s_step[lane] = pstep;
+            s_pinv[lane] = pinv;
+        }
+        wave_lds_sync();
+        if (cl < cnt) {
+            const int2 pk = s_pk[cl];
+#pragma unroll
+            for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const int r = 16 * rt + g4 + 4 * i;
+                    const int j = s_step[r];
+                    if (j < K) W64[w64_at(pk.y, j, n, pk.x)] = T[rt][RT][i] * s_pinv[r];
+                }
+        }
+        wave_lds_sync();
+    }
+    if (singular && lane == 0) atomicMin(dev_err, perm[s] + 1);
+}
+
 // Owner -> departure-point lists of the paper's stencil rule (CSR): count,
 // then fill (the order inside a list does not affect the solved weights).
 __global__ void k_owned_count(int n, const int32_t *__restrict__ owner, int32_t *__restrict__ cnt) {
@@ -941,6 +1259,14 @@ template <int NB>
 static hipError_t launch_rbf_nb(const Geo *geo, const double *xs, const double *ys,
                                 const int32_t *perm, const int32_t *nbr, RhsList L, int n, int K,
                                 int m, double dx, double *W64, int32_t *dev_err, hipStream_t s) {
+    // 48 unknowns: the matrix-core solver (measured 10 % faster on the
+    // 262,144-node lattice, K 30, degree 4); at 64 unknowns the register
+    // tiles leave two wavefronts per SIMD and the row-per-lane solver is faster
+    if constexpr (NB == 48) {
+        hipLaunchKernelGGL((k_rbf_mfma<NB / 16>), dim3(n), dim3(64), 0, s, geo, xs, ys, perm, nbr,
+                           L, n, K, m, dx, W64, dev_err);
+        return hipGetLastError();
+    }
     constexpr int wpe = NB <= 32 ? 4 : NB == 64 ? 2 : 3;
     constexpr int sys = NB <= 32 ? 2 : 1;   // systems per wavefront
     dim3 grid(blocks_for(n, 4 * sys)), block(256);

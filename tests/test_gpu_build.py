@@ -23,6 +23,8 @@ CASES = [
     ("tgv37x41-K30-m4-paper", lambda: tgv_case(37, 30, 4, 0, ny=41, length_y=7.0)[0], 1.0, 30, 4, 0),
     ("tgv23-K20-m3-own", lambda: tgv_case(23, 20, 3, 1, seed=7)[0], 0.7, 20, 3, 1),
     ("annulus-h0.1-K15-m2-paper", lambda: annulus_case(0.1), None, 15, 2, 0),
+    ("tgv30-K47-m4-own", lambda: tgv_case(30, 47, 4, 1, seed=3)[0], 1.0, 47, 4, 1),
+    ("tgv32-K40-m3-paper", lambda: tgv_case(32, 40, 3, 0, seed=5)[0], 1.0, 40, 3, 0),
     ("lattice16-K12-m2-paper", lambda: tgv_case(16, 12, 2, 0, jitter=0.0, length=16.0)[0], 1.0, 12, 2, 0),
 ]
 
