@@ -21,60 +21,208 @@ __device__ __forceinline__ int stencil_owner(const int32_t *owner, int mode, int
     return mode == MLBM_STENCIL_OWN ? i : owner[(int64_t)(k - 1) * n + i];
 }
 
-// Row lengths and fill of the transposed operator: one thread per entry
-// (node i along x, direction k and stencil slot j along y), so the entries'
-// atomics overlap instead of queuing behind one thread's chain of 8K.
-__device__ __forceinline__ void tr_entry(int K, int &k, int &j) {
-    k = 1 + (int)blockIdx.y / K;
-    j = (int)blockIdx.y - (k - 1) * K;
+// Row lengths and fill of the transposed operator. Entries (arriving node i,
+// direction k, stencil slot j) are gathered by row (k, source node m) in an
+// LDS hash table per tile of arriving nodes, so that a tile adds to a row, or
+// claims a run of it, with a single atomic. Keys that find no slot within
+// kTrProbe probes (an unusually wide tile) fall back to one atomic per entry;
+// k_tr_sort orders every row afterwards.
+constexpr int kTrHash = 4096;    // counts: keys of four directions
+constexpr int kTrHashF = 1024;   // fill: keys of one direction
+constexpr int kTrProbe = 32;
+constexpr uint32_t kTrEmpty = 0xFFFFFFFFu;
+
+template <int HS = kTrHash>
+__device__ __forceinline__ int tr_slot(uint32_t *hkey, uint32_t key, bool insert) {
+    static_assert((HS & (HS - 1)) == 0, "power of two");
+    const uint32_t h = (key * 2654435761u) >> (32 - __builtin_ctz(HS));
+    for (int p = 0; p < kTrProbe; ++p) {
+        const int sl = (int)((h + p) & (HS - 1));
+        const uint32_t cur = hkey[sl];
+        if (cur == key) return sl;
+        if (cur == kTrEmpty) {
+            if (!insert) return -1;
+            const uint32_t prev = atomicCAS(&hkey[sl], kTrEmpty, key);
+            if (prev == kTrEmpty || prev == key) return sl;
+        }
+    }
+    return -1;
 }
 
-__global__ void k_tr_count(int n, int K, int mode, const int32_t *__restrict__ nbr,
-                           const int32_t *__restrict__ owner, int32_t *__restrict__ cnt) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+// Source node m of entry (i, direction 4 h + kk + 1, slot j).
+__device__ __forceinline__ int tr_source(const int32_t *nbr, const int32_t *owner, int mode,
+                                         int n, int h, int kk, int j, int i) {
+    const int s = stencil_owner(owner, mode, 4 * h + kk + 1, n, i);
+    return nbr[(int64_t)j * n + s];
+}
+
+// Pass over the workgroup's entries: per-key counts in hcnt; entries without
+// a slot add to cnt_direct[row] directly (when it is given).
+__device__ __forceinline__ void tr_count_tile(int n, int K, int mode, int h, int i,
+                                              const int32_t *nbr, const int32_t *owner,
+                                              uint32_t *hkey, int32_t *hcnt,
+                                              int32_t *cnt_direct) {
     if (i >= n) return;
-    int k, j;
-    tr_entry(K, k, j);
-    const int s = stencil_owner(owner, mode, k, n, i);
-    const int m = nbr[(int64_t)j * n + s];
-    atomicAdd(&cnt[(int64_t)(k - 1) * n + m], 1);
+    for (int j = 0; j < K; ++j) {
+#pragma unroll
+        for (int kk = 0; kk < 4; ++kk) {
+            const int m = tr_source(nbr, owner, mode, n, h, kk, j, i);
+            const int sl = tr_slot(hkey, (uint32_t)(kk * n + m), true);
+            if (sl >= 0)
+                atomicAdd(&hcnt[sl], 1);
+            else if (cnt_direct)
+                atomicAdd(&cnt_direct[(int64_t)(4 * h + kk) * n + m], 1);
+        }
+    }
 }
 
-template <class T>
-__global__ void k_tr_fill(int n, int K, int mode, const int32_t *__restrict__ nbr,
-                          const int32_t *__restrict__ owner, const float *__restrict__ W32,
-                          const double *__restrict__ W64, const int32_t *__restrict__ ptr,
-                          int32_t *__restrict__ cur, int32_t *__restrict__ col,
-                          T *__restrict__ val) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    int k, j;
-    tr_entry(K, k, j);
-    const int s = stencil_owner(owner, mode, k, n, i);
-    const int m = nbr[(int64_t)j * n + s];
-    const int64_t row = (int64_t)(k - 1) * n + m;
-    const int pos = ptr[row] + atomicAdd(&cur[row], 1);
-    col[pos] = i;
-    T w;
-    if (W64)
-        w = (T)W64[w64_at(k, j, n, i)];
-    else
-        w = (T)W32[(((int64_t)j * 2 + ((k - 1) >> 2)) * n + i) * 4 + ((k - 1) & 3)];
-    val[pos] = w;
+__device__ __forceinline__ void tr_hash_clear(uint32_t *hkey, int32_t *hcnt) {
+    for (int t = threadIdx.x; t < kTrHash; t += blockDim.x) {
+        hkey[t] = kTrEmpty;
+        hcnt[t] = 0;
+    }
 }
 
-// Sort each CSR row by arriving node. One wavefront per row: an arriving node
-// appears at most once in a row, so the rank of an entry (how many entries of
-// the row have a smaller column) is its sorted position. Rows longer than a
-// wavefront (not met with K <= 48 on clouds of even spacing) take an insertion
-// sort by one lane.
+__device__ __forceinline__ int64_t tr_key_row(uint32_t key, int n, int h) {
+    const int kk = (int)(key / (uint32_t)n), m = (int)(key - (uint32_t)kk * n);
+    return (int64_t)(4 * h + kk) * n + m;
+}
+
+// Counts: a workgroup per tile of 256 arriving nodes and half of the
+// directions (1-4 or 5-8), keys (k - 1 - 4 h) n + m.
+__global__ __launch_bounds__(256) void k_tr_count(int n, int K, int mode,
+                                                  const int32_t *__restrict__ nbr,
+                                                  const int32_t *__restrict__ owner,
+                                                  int32_t *__restrict__ cnt) {
+    __shared__ uint32_t hkey[kTrHash];
+    __shared__ int32_t hcnt[kTrHash];
+    const int64_t nt = ((int64_t)n + 255) / 256, t = xcd_tile(nt);
+    if (t >= nt) return;   // uniform
+    const int h = blockIdx.y, i = (int)(t * 256) + (int)threadIdx.x;
+    tr_hash_clear(hkey, hcnt);
+    __syncthreads();
+    tr_count_tile(n, K, mode, h, i, nbr, owner, hkey, hcnt, cnt);
+    __syncthreads();
+    for (int t = threadIdx.x; t < kTrHash; t += blockDim.x)
+        if (hkey[t] != kTrEmpty) atomicAdd(&cnt[tr_key_row(hkey[t], n, h)], hcnt[t]);
+}
+
+// Fill: a workgroup of kTrJs TT threads takes a tile of TT arriving nodes
+// (kTrJs threads a node, each on every kTrJs-th stencil slot: the LDS the
+// tile needs leaves room for few workgroups, so each brings many wavefronts)
+// and a half of the directions, one direction after another. For each it counts the
+// tile's entries per row, claims one run of each row, gathers the entries in
+// LDS run by run with their places, and then writes the runs out with
+// consecutive lanes on consecutive places. The LDS holds TT K entries (the
+// host picks TT so that they fit).
+constexpr int kTrJs = 4;
+template <class T, int TT>
+__global__ __launch_bounds__(kTrJs * TT) void k_tr_fill(int n, int K, int mode,
+                                                const int32_t *__restrict__ nbr,
+                                                const int32_t *__restrict__ owner,
+                                                const float *__restrict__ W32,
+                                                const double *__restrict__ W64,
+                                                const int32_t *__restrict__ ptr,
+                                                int32_t *__restrict__ cur,
+                                                int32_t *__restrict__ col, T *__restrict__ val) {
+    extern __shared__ __align__(16) unsigned char s_stage[];
+    __shared__ uint32_t hkey[kTrHashF];
+    __shared__ int32_t hcnt[kTrHashF];
+    __shared__ int32_t hbase[kTrHashF];
+    __shared__ int32_t hloc[kTrHashF];
+    constexpr int NT = kTrJs * TT;
+    __shared__ int32_t s_part[NT];
+    constexpr int SPT = kTrHashF / NT;   // hash slots per thread in the scan
+    static_assert(kTrHashF % NT == 0, "whole slots per thread");
+    const int64_t nt = ((int64_t)n + TT - 1) / TT, t = xcd_tile(nt);
+    if (t >= nt) return;   // uniform
+    const int h = blockIdx.y, tid = threadIdx.x;
+    const int i = (int)(t * TT) + tid % TT, j0 = tid / TT;
+    const size_t words = ((size_t)TT * K * sizeof(int32_t) + 15) & ~size_t(15);
+    int32_t *scol = reinterpret_cast<int32_t *>(s_stage);
+    int32_t *spos = reinterpret_cast<int32_t *>(s_stage + words);
+    T *sval = reinterpret_cast<T *>(s_stage + 2 * words);
+    for (int kk = 0; kk < 4; ++kk) {
+        const int k = 4 * h + kk + 1;
+        for (int q = tid; q < kTrHashF; q += NT) {
+            hkey[q] = kTrEmpty;
+            hcnt[q] = 0;
+        }
+        __syncthreads();
+        const int s = i < n ? stencil_owner(owner, mode, k, n, i) : 0;
+        if (i < n) {
+            for (int j = j0; j < K; j += kTrJs) {
+                const int sl = tr_slot<kTrHashF>(hkey, (uint32_t)nbr[(int64_t)j * n + s], true);
+                if (sl >= 0) atomicAdd(&hcnt[sl], 1);
+            }
+        }
+        __syncthreads();
+        // local run starts in slot order (exclusive scan), the rows' runs
+        int mine = 0;
+#pragma unroll
+        for (int q = 0; q < SPT; ++q) mine += hcnt[tid * SPT + q];
+        s_part[tid] = mine;
+        __syncthreads();
+        for (int w = 1; w < NT; w <<= 1) {
+            const int add = tid >= w ? s_part[tid - w] : 0;
+            __syncthreads();
+            s_part[tid] += add;
+            __syncthreads();
+        }
+        int run = s_part[tid] - mine;
+        const int total = s_part[NT - 1];
+#pragma unroll
+        for (int q = 0; q < SPT; ++q) {
+            const int sl = tid * SPT + q;
+            const int c = hcnt[sl];
+            hloc[sl] = run;
+            run += c;
+            if (c > 0) {
+                const int64_t row = (int64_t)(k - 1) * n + hkey[sl];
+                hbase[sl] = ptr[row] + atomicAdd(&cur[row], c);
+            }
+            hcnt[sl] = 0;
+        }
+        __syncthreads();
+        if (i < n) {
+            for (int j = j0; j < K; j += kTrJs) {
+                const int m = nbr[(int64_t)j * n + s];
+                const int sl = tr_slot<kTrHashF>(hkey, (uint32_t)m, false);
+                const T w = W64 ? (T)W64[w64_at(k, j, n, i)]
+                                : (T)W32[(((int64_t)j * 2 + ((k - 1) >> 2)) * n + i) * 4 +
+                                         ((k - 1) & 3)];
+                if (sl >= 0) {
+                    const int r = atomicAdd(&hcnt[sl], 1), q = hloc[sl] + r;
+                    scol[q] = i;
+                    spos[q] = hbase[sl] + r;
+                    sval[q] = w;
+                } else {   // no slot: a place of its own
+                    const int64_t row = (int64_t)(k - 1) * n + m;
+                    const int pos = ptr[row] + atomicAdd(&cur[row], 1);
+                    col[pos] = i;
+                    val[pos] = w;
+                }
+            }
+        }
+        __syncthreads();
+        for (int q = tid; q < total; q += NT) {
+            const int pos = spos[q];
+            col[pos] = scol[q];
+            val[pos] = sval[q];
+        }
+        __syncthreads();
+    }
+}
+
+// Sort each CSR row by arriving node. An arriving node appears at most once
+// in a row, so the rank of an entry (how many entries of the row have a
+// smaller column) is its sorted position. A wavefront takes two rows: when
+// both have at most 32 entries, each half of the wavefront ranks one;
+// otherwise the whole wavefront ranks one row after the other, and a row
+// longer than a wavefront (not met with K <= 48 on clouds of even spacing)
+// takes an insertion sort by one lane.
 template <class T>
-__global__ __launch_bounds__(256) void k_tr_sort(int64_t rows, const int32_t *__restrict__ ptr,
-                                                 int32_t *__restrict__ col, T *__restrict__ val) {
-    const int lane = threadIdx.x & 63;
-    const int64_t r = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (r >= rows) return;   // uniform across the wavefront
-    const int b = ptr[r], len = ptr[r + 1] - b;
+__device__ __forceinline__ void tr_sort_row_wave(int lane, int b, int len, int32_t *col, T *val) {
     if (len <= 64) {
         int c = INT_MAX;
         T v = 0;
@@ -103,6 +251,37 @@ __global__ __launch_bounds__(256) void k_tr_sort(int64_t rows, const int32_t *__
         col[q + 1] = c;
         val[q + 1] = v;
     }
+}
+
+template <class T>
+__global__ __launch_bounds__(256) void k_tr_sort(int64_t rows, const int32_t *__restrict__ ptr,
+                                                 int32_t *__restrict__ col, T *__restrict__ val) {
+    const int lane = threadIdx.x & 63;
+    const int64_t r0 = ((int64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * 2;
+    if (r0 >= rows) return;   // uniform across the wavefront
+    const int half = lane >> 5, hl = lane & 31;
+    const int64_t r = r0 + half;
+    const int b = r < rows ? ptr[r] : 0;
+    const int len = r < rows ? ptr[r + 1] - b : 0;
+    const int len0 = __builtin_amdgcn_readlane(len, 0), len1 = __builtin_amdgcn_readlane(len, 32);
+    const int lmax = max(len0, len1);
+    if (lmax <= 32) {
+        int c = INT_MAX;
+        T v = 0;
+        if (hl < len) {
+            c = col[b + hl];
+            v = val[b + hl];
+        }
+        int rank = 0;
+        for (int j = 0; j < lmax; ++j) rank += __shfl(c, j, 32) < c;   // pads hold INT_MAX
+        if (hl < len) {
+            col[b + rank] = c;
+            val[b + rank] = v;
+        }
+        return;
+    }
+    tr_sort_row_wave(lane, __builtin_amdgcn_readlane(b, 0), len0, col, val);
+    if (r0 + 1 < rows) tr_sort_row_wave(lane, __builtin_amdgcn_readlane(b, 32), len1, col, val);
 }
 
 __global__ void k_set_i32(int32_t *p, int32_t v) { *p = v; }
@@ -134,23 +313,27 @@ __device__ __forceinline__ int64_t unit_entry(int64_t u0, int c, int r, int k) {
 
 // Compacted copy of the first lw entries of every sorted CSR row, one
 // wavefront per group of 64 nodes (lanes past the last node take part in the
-// ballots with hd = 0). The wavefront first records, in LDS, the unit of every
-// (slot, node) of its group and writes the padding past each row's end; then,
-// direction by direction, it reads the group's rows (one contiguous CSR
-// segment) with consecutive lanes on consecutive entries, finds each entry's
-// row by a binary search of the row starts, and stores it into its unit.
+// ballots with hd = 0). Slot by slot, each lane of a node with hd > e builds
+// its unit: the eight rows' entry e, padded with (m, 0) past a row's end, and
+// stores it as two 16-byte column vectors and two weight vectors. Consecutive
+// active lanes hold consecutive units, so the stores are coalesced. A lane
+// reads kEllChunk consecutive entries of a row back to back, so that the
+// lines they share are used while they are still in the cache (one slot at a
+// time, with every wavefront of a CU walking its own rows, they were not).
 constexpr int kEllMaxLw = kMaxK + 4;
+constexpr int kEllChunk = 8;
+template <class T> struct Vec4;
+template <> struct Vec4<float> { typedef float4 type; };
+template <> struct Vec4<double> { typedef double __attribute__((ext_vector_type(4))) type; };
+
 template <class T>
 __global__ __launch_bounds__(256) void k_ell_fill(int n, int lw, const int32_t *__restrict__ ptr,
                                                   const int32_t *__restrict__ col,
                                                   const T *__restrict__ val,
                                                   int32_t *__restrict__ ecol, T *__restrict__ eval) {
-    __shared__ int32_t s_unit[4][kEllMaxLw][64];   // rank of (slot, lane) in its block
-    __shared__ int32_t s_blk[4][kEllMaxLw][2];     // block of a slot: first unit, units
-    __shared__ int32_t s_rb[4][65];                // row starts of one direction
+    typedef typename Vec4<T>::type V4;
     const int lane = threadIdx.x & 63;
-    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int64_t g = (int64_t)blockIdx.x * 4 + wv;
+    const int64_t g = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
     const int64_t m0 = g * 64;
     if (m0 >= n) return;   // uniform across the wavefront
     const int m = (int)(m0 + lane);
@@ -167,52 +350,52 @@ __global__ __launch_bounds__(256) void k_ell_fill(int n, int lw, const int32_t *
     }
     const int64_t g0 = g * 64 * lw;
     int64_t off = 0;
-    for (int e = 0; e < lw; ++e) {
-        const bool on = e < hd;
-        const uint64_t mask = __ballot(on);
-        const int r = lanes_below(mask), c = __popcll(mask);
-        s_unit[wv][e][lane] = r;
-        if (lane < 2) s_blk[wv][e][lane] = lane ? c : (int32_t)off;
-        if (on) {
+    for (int e0 = 0; e0 < lw; e0 += kEllChunk) {
+        if (__ballot(e0 < hd) == 0) break;   // hd is fixed: no later slot has a unit
+        int rk[kEllChunk], ck[kEllChunk];
 #pragma unroll
-            for (int k = 0; k < 8; ++k) {
-                if (e >= len[k]) {
-                    const int64_t at = unit_entry(g0 + off, c, r, k);
-                    ecol[at] = (int32_t)m;
-                    eval[at] = (T)0;
+        for (int t = 0; t < kEllChunk; ++t) {
+            const uint64_t mask = __ballot(e0 + t < hd);
+            rk[t] = lanes_below(mask);
+            ck[t] = __popcll(mask);
+        }
+#pragma unroll
+        for (int hh = 0; hh < 2; ++hh) {
+            // the chunk's entries of the half's four rows, read row by row
+            int cv[4][kEllChunk];
+            T wv[4][kEllChunk];
+#pragma unroll
+            for (int kk = 0; kk < 4; ++kk) {
+                const int k = 4 * hh + kk;
+#pragma unroll
+                for (int t = 0; t < kEllChunk; ++t) {
+                    cv[kk][t] = m;
+                    wv[kk][t] = (T)0;
+                    if (e0 + t < len[k]) {
+                        cv[kk][t] = col[b[k] + e0 + t];
+                        wv[kk][t] = val[b[k] + e0 + t];
+                    }
                 }
             }
-        }
-        off += c;
-    }
-    const int nl = (int)min((int64_t)64, n - m0);   // nodes of this group
-    for (int k = 0; k < 8; ++k) {
-        // row starts of the group's rows in direction k, and the segment end
-        s_rb[wv][lane] = m < n ? b[k] : INT_MAX;
-        const int seg0 = __builtin_amdgcn_readfirstlane(b[k]);
-        const int seg1 = __builtin_amdgcn_readlane(b[k] + len[k], nl - 1);
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        for (int idx = seg0 + lane; idx < seg1; idx += 64) {
-            // last row whose start is <= idx (empty rows share the next start)
-            int lo = 0, hi = nl - 1;
-            while (lo < hi) {
-                const int mid = (lo + hi + 1) >> 1;
-                if (s_rb[wv][mid] <= idx) lo = mid;
-                else hi = mid - 1;
-            }
-            const int e = idx - s_rb[wv][lo];
-            if (e < lw) {
-                const int64_t at =
-                    unit_entry(g0 + s_blk[wv][e][0], s_blk[wv][e][1], s_unit[wv][e][lo], k);
-                ecol[at] = col[idx];
-                eval[at] = val[idx];
+            int64_t u = off;
+#pragma unroll
+            for (int t = 0; t < kEllChunk; ++t) {
+                if (e0 + t < hd) {
+                    const int64_t at = unit_entry(g0 + u, ck[t], rk[t], 4 * hh);
+                    *reinterpret_cast<int4 *>(ecol + at) =
+                        make_int4(cv[0][t], cv[1][t], cv[2][t], cv[3][t]);
+                    V4 vv;
+                    vv[0] = wv[0][t];
+                    vv[1] = wv[1][t];
+                    vv[2] = wv[2][t];
+                    vv[3] = wv[3][t];
+                    *reinterpret_cast<V4 *>(eval + at) = vv;
+                }
+                u += ck[t];
             }
         }
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+#pragma unroll
+        for (int t = 0; t < kEllChunk; ++t) off += ck[t];
     }
 }
 
@@ -685,7 +868,10 @@ hipError_t launch_transpose(const CloudPlan &cp, int precision, void *tmp, size_
     const size_t scan_bytes = tmp_bytes - cnt_bytes;
     hipError_t e = launch_fill_i32(cnt, 0, rows, s);
     if (e != hipSuccess) return e;
-    const dim3 egrid(blocks_for(n, 256), 8 * K);   // one thread per entry
+    if (n >= (1 << 29)) return hipErrorInvalidValue;   // hash keys 4 n + m in 32 bits
+    // tiles of 256 arriving nodes (neighbouring tiles on one XCD, whose L2
+    // then merges the runs they write into shared rows) x half of the directions
+    const dim3 egrid(xcd_grid(blocks_for(n, 256)), 2);
     hipLaunchKernelGGL(k_tr_count, egrid, dim3(256), 0, s, n, K, mode, cp.nbr, cp.owner, cnt);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if ((e = exclusive_scan(scan_tmp, scan_bytes, cnt, cp.tr_ptr, (int)rows, s)) != hipSuccess)
@@ -694,19 +880,39 @@ hipError_t launch_transpose(const CloudPlan &cp, int precision, void *tmp, size_
                        (int32_t)(rows * K));
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if ((e = launch_fill_i32(cnt, 0, rows, s)) != hipSuccess) return e;
+    // staging of the fill: TT K entries of a tile (column, place, weight),
+    // 128 nodes a tile while they take at most 46 KiB (with the hash table,
+    // under 64 KiB), else 64
+    const size_t esz = precision == MLBM_FP64 ? sizeof(double) : sizeof(float);
+    auto stage_bytes = [&](int tt) {
+        return 2 * (((size_t)tt * K * 4 + 15) & ~size_t(15)) + (size_t)tt * K * esz;
+    };
+    const bool wide = stage_bytes(128) <= 46 * 1024;
+    const unsigned lds = (unsigned)stage_bytes(wide ? 128 : 64);
+    const dim3 fgrid(xcd_grid(blocks_for(n, wide ? 128 : 64)), 2);
     if (precision == MLBM_FP64) {
-        hipLaunchKernelGGL(k_tr_fill<double>, egrid, dim3(256), 0, s, n, K,
-                           mode, cp.nbr, cp.owner, (const float *)nullptr, cp.W64, cp.tr_ptr, cnt,
-                           cp.tr_col, (double *)cp.tr_val);
+        if (wide)
+            hipLaunchKernelGGL((k_tr_fill<double, 128>), fgrid, dim3(kTrJs * 128), lds, s, n, K, mode,
+                               cp.nbr, cp.owner, (const float *)nullptr, cp.W64, cp.tr_ptr, cnt,
+                               cp.tr_col, (double *)cp.tr_val);
+        else
+            hipLaunchKernelGGL((k_tr_fill<double, 64>), fgrid, dim3(kTrJs * 64), lds, s, n, K, mode,
+                               cp.nbr, cp.owner, (const float *)nullptr, cp.W64, cp.tr_ptr, cnt,
+                               cp.tr_col, (double *)cp.tr_val);
         if ((e = hipGetLastError()) != hipSuccess) return e;
-        hipLaunchKernelGGL(k_tr_sort<double>, dim3(blocks_for(rows, 4)), dim3(256), 0, s, rows,
+        hipLaunchKernelGGL(k_tr_sort<double>, dim3(blocks_for(rows, 8)), dim3(256), 0, s, rows,
                            cp.tr_ptr, cp.tr_col, (double *)cp.tr_val);
     } else {
-        hipLaunchKernelGGL(k_tr_fill<float>, egrid, dim3(256), 0, s, n, K,
-                           mode, cp.nbr, cp.owner, cp.W32, (const double *)nullptr, cp.tr_ptr,
-                           cnt, cp.tr_col, (float *)cp.tr_val);
+        if (wide)
+            hipLaunchKernelGGL((k_tr_fill<float, 128>), fgrid, dim3(kTrJs * 128), lds, s, n, K, mode,
+                               cp.nbr, cp.owner, cp.W32, (const double *)nullptr, cp.tr_ptr, cnt,
+                               cp.tr_col, (float *)cp.tr_val);
+        else
+            hipLaunchKernelGGL((k_tr_fill<float, 64>), fgrid, dim3(kTrJs * 64), lds, s, n, K, mode,
+                               cp.nbr, cp.owner, cp.W32, (const double *)nullptr, cp.tr_ptr, cnt,
+                               cp.tr_col, (float *)cp.tr_val);
         if ((e = hipGetLastError()) != hipSuccess) return e;
-        hipLaunchKernelGGL(k_tr_sort<float>, dim3(blocks_for(rows, 4)), dim3(256), 0, s, rows,
+        hipLaunchKernelGGL(k_tr_sort<float>, dim3(blocks_for(rows, 8)), dim3(256), 0, s, rows,
                            cp.tr_ptr, cp.tr_col, (float *)cp.tr_val);
     }
     if ((e = hipGetLastError()) != hipSuccess) return e;
