@@ -477,10 +477,26 @@ def run_batched(steps: int):
     torch.cuda.synchronize()
     full_ms = e0.elapsed_time(e1)
     err = plan.device_error()
+    # the same steps on the plan that graph built: its tile LDS was sized at
+    # capture time (the capacity bound, the halo sizes being unknown until
+    # the build has run), so its steps can be slower than the eager plan's;
+    # the build + init share of the one-graph run is the difference
+    with torch.cuda.stream(stream):
+        plan.graph_create(res, g_a if res is g_b else g_b, steps, stream)
+        plan.graph_launch(stream)                      # warm
+        torch.cuda.synchronize()
+        e0.record(stream)
+        plan.graph_launch(stream)
+        e1.record(stream)
+        torch.cuda.synchronize()
+    steps_cap_ms = e0.elapsed_time(e1)
     plan.close()
-    log("batched: build+init+%d steps %.1f ms in one graph; steps alone %.1f ms" % (steps, full_ms, steps_ms))
+    log("batched: build+init+%d steps %.1f ms in one graph; steps alone %.1f ms (eager plan), "
+        "%.1f ms (the graph's plan)" % (steps, full_ms, steps_ms, steps_cap_ms))
     return {"clouds": len(clouds), "nodes": int(n_total), "steps": steps,
             "graph_ms_build_init_steps": full_ms, "graph_ms_steps": steps_ms,
+            "graph_ms_steps_capture_sized_plan": steps_cap_ms,
+            "build_init_ms": full_ms - steps_cap_ms,
             "node_updates_per_s_steps": n_total * steps / (steps_ms / 1e3),
             "node_updates_per_s_incl_build": n_total * steps / (full_ms / 1e3),
             "variant": variant, "autotune_ms_per_step": tune, "device_error": err}

@@ -352,9 +352,11 @@ mlbm_status mlbm_autotune(mlbm_plan *plan, void *g_a, void *g_b, int32_t n_steps
  * (g_a, g_b) (mlbm_step) with FP32 step variant `variant`. Nothing runs until
  * mlbm_graph_launch; each launch rebuilds the weights and restarts from the
  * initial state. Buffers as for those calls; the workspace and the inputs must
- * stay allocated while the graph is used. The step LDS size is the capacity
- * bound (no size read-back under capture) and a singular system is reported
- * through mlbm_device_error after a launch. */
+ * stay allocated while the graph is used. The step LDS size is chosen before
+ * the tables exist (no size read-back under capture): 40 KiB for FP32 plans up
+ * to K = 30, where a tile whose tables need more gathers from global memory
+ * instead (same results, slower), else the capacity bound. A singular system
+ * is reported through mlbm_device_error after a launch. */
 mlbm_status mlbm_build_graph(const mlbm_cloud *clouds, const mlbm_params *params,
                              int32_t n_clouds, void *plan_buf, size_t plan_bytes,
                              void *workspace, size_t workspace_bytes, const double *rho,

@@ -218,7 +218,14 @@ mlbm_status finish_tables(mlbm_plan *plan, hipStream_t s) {
     if (capturing(s)) {
         for (CloudPlan &cp : plan->c) {
             if (cp.tdesc) {
-                cp.lds_bytes = (unsigned)(8 * cp.hcap * 4 + cp.ocap * ((cp.K + 2) / 3) * 4);
+                // the capacity bound; the FP32 step checks every tile against
+                // its launch's LDS and sends a larger one to the global-gather
+                // path, so up to K = 30 it takes 40 KiB (four workgroups per
+                // CU; the tables measured up to 38 KiB) instead of 53 KiB
+                const unsigned cap =
+                    (unsigned)(8 * cp.hcap * 4 + cp.ocap * ((cp.K + 2) / 3) * 4);
+                cp.lds_bytes = cp.prm.precision != MLBM_FP64 && cp.K <= 30
+                                   ? std::min(cap, kCaptureLds) : cap;
                 cp.fallback_tiles = -1;
             }
             if (cp.tdescT) cp.adj_ni = cp.adj_cap;

@@ -61,6 +61,7 @@ __host__ __device__ inline int64_t w64_at(int k, int j, int64_t n, int64_t p) {
     return (((int64_t)j * 4 + ((k - 1) >> 1)) * n + p) * 2 + ((k - 1) & 1);
 }
 constexpr int kMaxK = 48;       // largest stencil supported
+constexpr unsigned kCaptureLds = 40 * 1024;   // FP32 step LDS of a plan built under capture
 // Nodes rounded up to whole wavefronts: the row heads of the transposed
 // operator are compacted per group of 64 nodes, and each slot of a group has
 // room for all 64.
@@ -193,6 +194,8 @@ struct Step32Args {
     int32_t *err;            // device error words (may be null)
     const int32_t *perm;     // internal -> user index of this cloud
     int uoff;                // offset of this cloud's nodes in the plan's user order
+    int lcap;                // LDS bytes of the launch: a tile whose tables need more
+                             // gathers from global memory instead
 };
 
 // Bump allocator over a caller buffer (a null base computes sizes only).

@@ -177,6 +177,16 @@ __device__ __forceinline__ void stage_words(uint32_t *__restrict__ dst,
     }
 }
 
+// Halo size of a tile that stages its tables, 0 for one that gathers from
+// global memory: no tables, or tables larger than the launch's LDS (a plan
+// built inside a graph capture sizes its LDS before the tables exist).
+__device__ __forceinline__ int tile_halo(const Step32Args &a, int64_t tile) {
+    if (!a.tdesc) return 0;
+    const int nh = a.tdesc[2 * tile + 1];
+    const int no = a.tdesc[2 * tile];
+    return nh > 0 && 32 * nh + 4 * no * ((a.K + 2) / 3) <= a.lcap ? nh : 0;
+}
+
 template <int MODE, bool FORCE, int WALL, bool REC, int UNROLL, bool NT>
 __device__ __forceinline__ void step32_tile(const Step32Args &a, const float *__restrict__ g,
                                             float *__restrict__ go, int64_t tile,
@@ -185,7 +195,7 @@ __device__ __forceinline__ void step32_tile(const Step32Args &a, const float *__
     const int base = (int)(tile * kTile);
     const int cnt = min(kTile, n - base);
     const int tid = threadIdx.x;
-    const int nh = a.tdesc ? a.tdesc[2 * tile + 1] : 0;
+    const int nh = tile_halo(a, tile);
     const float4 *__restrict__ W = a.W;
 
     float acc[8];
@@ -291,7 +301,7 @@ __device__ __forceinline__ void step32_tile_split(const Step32Args &a,
     const int base = (int)(tile * kTile);
     const int cnt = min(kTile, n - base);
     const int tid = threadIdx.x, l = tid >> 1, h = tid & 1;
-    const int nh = a.tdesc ? a.tdesc[2 * tile + 1] : 0;
+    const int nh = tile_halo(a, tile);
     const float4 *__restrict__ W = a.W;
     float acc[4];
 #pragma unroll
@@ -999,6 +1009,7 @@ Step32Args step32_args(const CloudPlan &cp, void *frec) {
     a.rho_w = (float)cp.prm.rho_wall;
     a.frec = (float *)frec;
     a.tdesc = cp.lds_bytes ? cp.tdesc : nullptr;
+    a.lcap = (int)cp.lds_bytes;
     a.ownerL = cp.ownerL;
     a.nbrL = cp.nbrL;
     a.hlist = cp.hlist;

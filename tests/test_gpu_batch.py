@@ -131,3 +131,45 @@ def test_set_tau_reaches_every_cloud_of_a_batched_plan():
         assert torch.equal(gs, bp.cloud_view(g, c)), c
         sp.close()
     bp.close()
+
+
+def _dense_strip(n=4096, frac=0.8, width=0.125, seed=5):
+    """Periodic square with 80 % of the nodes in a strip an eighth of its
+    width: the tiles along the strip's edges stage large halos."""
+    import math
+    L = 2 * math.pi
+    r = np.random.Generator(np.random.PCG64(seed))
+    a = int(n * frac)
+    x = np.concatenate([r.uniform(0, L * width, a), r.uniform(L * width, L, n - a)])
+    y = r.uniform(0, L, n)
+    return x, y, (L, L), L / math.sqrt(n)
+
+
+@pytest.mark.parametrize("variant", [0, 6])
+def test_captured_plan_sends_tiles_beyond_its_lds_to_the_global_path(variant):
+    """A plan built inside a graph capture sizes the FP32 step's LDS before
+    its tables exist (40 KiB up to K = 30). On a cloud whose largest tile needs
+    more, those tiles gather from global memory and the captured plan still
+    steps bitwise like the eager plan, which stages every tile. (The strip's
+    nodes are far closer than the streaming distance, which is not a stable
+    setting (the run would pass the speed limit within 15 steps): three steps
+    compare the arithmetic of the two paths.)"""
+    from paper_2306_01525_amd import Params, Plan
+    x, y, period, h = _dense_strip()
+    p = Params(dx=h, K=30, degree=4, tau=0.8, stencil_mode=0)
+    ux, uy = tgv_initial_velocity(x, y, period[0], 0.01)
+    eager = Plan.build(x, y, period, p)
+    need = int(eager.info.step_lds_bytes)
+    say("largest tile needs %d bytes of LDS; fallback tiles %d" % (need, int(eager.info.fallback_tiles)))
+    assert need > 40 * 1024 and int(eager.info.fallback_tiles) == 0
+    eager.set_variant(variant)
+    ge = eager.step(eager.init(ux, uy), eager.new_state(), 3)
+    s = torch.cuda.Stream()
+    plan, g_a, g_b, res = Plan.build_graph([(x, y, period, None)], [p], ux, uy, 3, s, variant)
+    plan.graph_launch(s)
+    s.synchronize()
+    say("device error words: captured %d, eager %d" % (plan.device_error(), eager.device_error()))
+    assert plan.device_error() == eager.device_error() == 0
+    assert torch.equal(res.reshape(-1), ge.reshape(-1))
+    plan.close()
+    eager.close()
