@@ -723,7 +723,7 @@ def summarize_trace(trace_dir, command, out_path=None):
              "# command: " + command,
              "# step kernel source hash: " + step_kernel_hash(),
              "%-8s %12s %12s %7s  %s" % ("calls", "mean_us", "total_us", "pct", "kernel")]
-    for r in rows[:25]:
+    for r in rows[:40]:
         name = r["Name"]
         if len(name) > 110:
             name = name[:110] + "..."
