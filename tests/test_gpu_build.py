@@ -143,15 +143,16 @@ def _uncompact(units, hd, lw, n, fill):
     return out[:, :, :n]
 
 
-@pytest.mark.parametrize("mode,precision", [(0, 0), (1, 1)])
-def test_adjoint_tables_are_consistent(mode, precision):
+@pytest.mark.parametrize("mode,precision,K,m", [(0, 0, 30, 4), (1, 1, 30, 4), (1, 0, 48, 4),
+                                                (0, 0, 12, 2)])
+def test_adjoint_tables_are_consistent(mode, precision, K, m):
     """Transposed stencil operator and the gather tables of the adjoint step,
     checked on the CPU before any adjoint step uses them: row lengths and row
     heads match the transpose of the forward stencils (rows sorted by arriving
     node), inverse halo lists are sorted, unique and in range, and the local
-    columns map back to the row heads."""
+    columns map back to the row heads. The fill stages 128-node tiles up to
+    K = 30 in FP32 and 64-node tiles for FP64 or larger K."""
     from paper_2306_01525_amd import Params, Plan
-    K, m = 30, 4
     c, _, _ = tgv_case(61, K, m, mode, seed=9)   # 3,721 nodes: a partial last group of 64
     p = Params(dx=c.h, K=K, degree=m, tau=0.8, stencil_mode=mode, precision=precision,
                with_adjoint=1)
