@@ -791,6 +791,8 @@ template <int CTRL> __device__ __forceinline__ double dpp_d(double v) {
     return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
 }
 
+// Three wavefronts per SIMD at 48 unknowns (167 VGPRs, a 20-byte spill);
+// without the hint the compiler keeps the tiles in 460 registers and runs one.
 template <int RT>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(RT == 3 ? 3 : 2))) void k_rbf_mfma(
     const Geo *__restrict__ geo, const double *__restrict__ xs, const double *__restrict__ ys,
