@@ -98,6 +98,19 @@ def tol_fp32(steps: int) -> float:
     return (6.0 + 1.5 * math.sqrt(steps)) * EPS32
 
 
+def dense_strip(n=4096, frac=0.8, width=0.125, seed=5):
+    """Periodic square [0, 2pi)^2 with a share `frac` of the n nodes uniform
+    in a strip `width` of its side wide and the rest uniform outside:
+    (x, y, period, mean spacing). Tiles along the strip's edges stage large
+    halos, and nodes just outside it own many departure points."""
+    L = 2 * math.pi
+    r = np.random.Generator(np.random.PCG64(seed))
+    a = int(n * frac)
+    x = np.concatenate([r.uniform(0, L * width, a), r.uniform(L * width, L, n - a)])
+    y = r.uniform(0, L, n)
+    return x, y, (L, L), L / math.sqrt(n)
+
+
 def say(*a):
     print(*a, flush=True)
     sys.stdout.flush()

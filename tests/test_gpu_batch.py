@@ -3,7 +3,7 @@ clouds, and the whole workload (build + init + steps) as one HIP graph."""
 import numpy as np
 import pytest
 
-from gpu_common import oracle_run, rel_l2, say, tgv_case, tol_fp32
+from gpu_common import dense_strip, oracle_run, rel_l2, say, tgv_case, tol_fp32
 from synth import annulus_poisson, jittered_lattice, tgv_initial_velocity
 
 pytestmark = pytest.mark.gpu
@@ -133,18 +133,6 @@ def test_set_tau_reaches_every_cloud_of_a_batched_plan():
     bp.close()
 
 
-def _dense_strip(n=4096, frac=0.8, width=0.125, seed=5):
-    """Periodic square with 80 % of the nodes in a strip an eighth of its
-    width: the tiles along the strip's edges stage large halos."""
-    import math
-    L = 2 * math.pi
-    r = np.random.Generator(np.random.PCG64(seed))
-    a = int(n * frac)
-    x = np.concatenate([r.uniform(0, L * width, a), r.uniform(L * width, L, n - a)])
-    y = r.uniform(0, L, n)
-    return x, y, (L, L), L / math.sqrt(n)
-
-
 @pytest.mark.parametrize("variant", [0, 6])
 def test_captured_plan_sends_tiles_beyond_its_lds_to_the_global_path(variant):
     """A plan built inside a graph capture sizes the FP32 step's LDS before
@@ -155,7 +143,7 @@ def test_captured_plan_sends_tiles_beyond_its_lds_to_the_global_path(variant):
     setting (the run would pass the speed limit within 15 steps): three steps
     compare the arithmetic of the two paths.)"""
     from paper_2306_01525_amd import Params, Plan
-    x, y, period, h = _dense_strip()
+    x, y, period, h = dense_strip()
     p = Params(dx=h, K=30, degree=4, tau=0.8, stencil_mode=0)
     ux, uy = tgv_initial_velocity(x, y, period[0], 0.01)
     eager = Plan.build(x, y, period, p)

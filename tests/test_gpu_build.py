@@ -3,7 +3,7 @@ import numpy as np
 import pytest
 
 import oracle
-from gpu_common import TOL_W, annulus_case, say, tgv_case
+from gpu_common import TOL_W, annulus_case, dense_strip, say, tgv_case, weight_bounds
 
 pytestmark = pytest.mark.gpu
 
@@ -50,6 +50,38 @@ def test_build_matches_oracle(label, make, dxf, K, m, mode):
     assert err < TOL_W
     # k = 0 is the identity on both sides
     np.testing.assert_allclose(W_o[:, 0, 0], 1.0, atol=1e-10)
+    plan.close()
+
+
+def test_build_with_crowded_owners_matches_oracle():
+    """Weights on the dense-strip cloud, where nodes beside the strip own
+    more than 16 departure points: the 48-unknown matrix-core solver solves
+    them in groups of 16 (K 30, degree 4, paper rule)."""
+    from paper_2306_01525_amd import Params, Plan
+    x, y, period, h = dense_strip()
+    K, m = 30, 4
+    p = Params(dx=h, K=K, degree=m, tau=0.8, stencil_mode=0)
+    plan = Plan.build(x, y, period, p)
+    nbr_o = oracle.knn(x, y, period, K)
+    own_o = oracle.owners(x, y, period, h, 0)
+    counts = np.bincount(own_o[:, 1:].ravel(), minlength=x.shape[0])
+    say("largest number of departure points of one owner:", counts.max())
+    assert counts.max() > 16
+    np.testing.assert_array_equal(plan.export("nbr"), nbr_o)
+    np.testing.assert_array_equal(plan.export("owner"), own_o)
+    W_o = oracle.weights(x, y, period, h, K, m, nbr_o, own_o)
+    d = np.abs(plan.export("W") - W_o).max(axis=2)[:, 1:]            # [n][8]
+    # the stencils at the strip's edges are lopsided and their systems far
+    # worse conditioned than on the lattices: each (node, direction) is held
+    # to the backward-error bound of its owner's system
+    from types import SimpleNamespace
+    c = SimpleNamespace(x=x, y=y, period=period, n=x.shape[0])
+    b = weight_bounds(c, nbr_o, own_o, W_o, K, m)[:, 1:]
+    worst = np.unravel_index(np.argmax(d / b), d.shape)
+    say("max |W_gpu - W_oracle| = %.2e; worst against its bound: %.2e of %.2e (owner of %d points)"
+        % (d.max(), d[worst], b[worst], counts[own_o[worst[0], worst[1] + 1]]))
+    assert (d <= np.maximum(b, TOL_W)).all()
+    assert plan.device_error() == 0
     plan.close()
 
 
