@@ -209,6 +209,8 @@ def run_gpu(args):
         % ms_cold)
     planB.close()
     del pair
+    out["copy_bw"] = copy_bandwidth()
+    log("torch device copy of 1 GiB: %.0f GB/s" % out["copy_bw"]["achieved"])
 
     # FP64 plain form, same number of steps
     if not args.skip_fp64:
@@ -580,6 +582,17 @@ def oracle_leg(r):
     oracle.run(f, nbr, own, W, tau, 3)
     one_s = time.perf_counter() - t0
     oracle.set_threads(threads)
+    # one segment of the adjoint workload: 50 steps forward (kept), then 50
+    # reversed steps of the discrete adjoint, on all threads
+    from paper_2306_01525_amd import targets
+    seg = 50
+    tx, ty = targets.tgv_velocity(c.x, c.y, c.period[0], 0.01, tau, c.h, seg)
+    t0 = time.perf_counter()
+    oracle.adjoint(nbr, own, W, tau, seg, 1.0, ux, uy, tx, ty)
+    adj_s = time.perf_counter() - t0
+    fwd_s = step_s / done * seg
+    log("oracle: %d forward + %d reversed steps in %.2f s (forward alone %.2f s)"
+        % (seg, seg, adj_s, fwd_s))
     base = {"value": c.n * done / step_s, "unit": "node-updates/s", "cores": threads,
             "kind": "oracle",
             "sample": "FP64 oracle on the benchmarked TGV-512 cloud itself (262,144 nodes, K 30, "
@@ -587,11 +600,34 @@ def oracle_leg(r):
                       "a %.1f s build of stencils, owners and shape vectors"
                       % (done, step_s, threads, build_s),
             "build_s": build_s, "one_thread_value": c.n * 3 / one_s,
+            "adjoint_segment": {"steps": seg, "forward_and_reverse_s": adj_s,
+                                "forward_s": fwd_s,
+                                "reverse_over_forward": (adj_s - fwd_s) / fwd_s},
             "search_fallbacks": dict(oracle.last_fallbacks)}
     return errs, base
 
 
 COPY_BYTES = 256 << 20
+
+
+def copy_bandwidth(reps=5):
+    """HBM bandwidth of torch's device copy of 1 GiB (read and write), the
+    median of `reps` copies: a plain streaming kernel beside the roofline."""
+    import torch
+    x = torch.ones((1 << 30) // 4, device="cuda")
+    y = torch.empty_like(x)
+    y.copy_(x)
+    ts = []
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        y.copy_(x)
+        e1.record()
+        torch.cuda.synchronize()
+        ts.append(e0.elapsed_time(e1))
+    ms = sorted(ts)[reps // 2]
+    del x, y
+    return {"bytes": 2 << 30, "ms": ms, "achieved": (2 << 30) / (ms * 1e-3) / 1e9, "unit": "GB/s"}
 
 
 def copy_calibration():
@@ -867,6 +903,9 @@ def main():
         "timed_state_steps": r["timed_state_steps"],
         "build_ms": r["build_ms"],
     }
+    if "copy_bw" in r:
+        line["copy_bandwidth"] = dict(r["copy_bw"], note="torch's device copy of 1 GiB (read "
+                                      "and write): a plain streaming kernel on the same part")
     if "ms_cold" in r:
         ach_cold = bpu * n / (r["ms_cold"] / 1e3) / 1e9
         line["roofline_cache_cold"] = {
