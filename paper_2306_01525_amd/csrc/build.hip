@@ -1280,8 +1280,9 @@ static hipError_t launch_rbf_nb(const Geo *geo, const double *xs, const double *
     if (L.ptr)
         hipLaunchKernelGGL((k_rbf<NB, 8, wpe, sys, true>), grid, block, 0, s, geo, xs, ys, perm,
                            nbr, L, n, K, m, dx, W64, dev_err);
-    else   // fewer registers live: one more wavefront per SIMD from 32 unknowns up
-        hipLaunchKernelGGL((k_rbf<NB, 8, NB == 24 ? 4 : wpe + 1, sys, false>), grid, block, 0, s,
+    else   // fewer registers live: one more wavefront per SIMD at 64 unknowns (at 24
+           // and 32 four is the most the registers allow either way)
+        hipLaunchKernelGGL((k_rbf<NB, 8, NB <= 32 ? 4 : wpe + 1, sys, false>), grid, block, 0, s,
                            geo, xs, ys, perm, nbr, L, n, K, m, dx, W64, dev_err);
     return hipGetLastError();
 }

@@ -7,11 +7,15 @@
 
 namespace mlbm {
 
+// Temporary storage of the library calls (a failed size query gives 0: the
+// call itself then reports the error).
 size_t sort_pairs_temp_bytes(int n) {
     size_t bytes = 0;
-    hipcub::DeviceRadixSort::SortPairs(nullptr, bytes, (const uint32_t *)nullptr,
-                                       (uint32_t *)nullptr, (const int32_t *)nullptr,
-                                       (int32_t *)nullptr, n, 0, 32, (hipStream_t)0);
+    if (hipcub::DeviceRadixSort::SortPairs(nullptr, bytes, (const uint32_t *)nullptr,
+                                           (uint32_t *)nullptr, (const int32_t *)nullptr,
+                                           (int32_t *)nullptr, n, 0, 32,
+                                           (hipStream_t)0) != hipSuccess)
+        return 0;
     return bytes;
 }
 
@@ -24,8 +28,9 @@ hipError_t sort_pairs(void *tmp, size_t tmp_bytes, const uint32_t *kin, uint32_t
 
 size_t scan_temp_bytes(int n) {
     size_t bytes = 0;
-    hipcub::DeviceScan::ExclusiveSum(nullptr, bytes, (const int32_t *)nullptr,
-                                     (int32_t *)nullptr, n, (hipStream_t)0);
+    if (hipcub::DeviceScan::ExclusiveSum(nullptr, bytes, (const int32_t *)nullptr,
+                                         (int32_t *)nullptr, n, (hipStream_t)0) != hipSuccess)
+        return 0;
     return bytes;
 }
 
