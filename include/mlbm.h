@@ -59,7 +59,7 @@ enum { MLBM_STENCIL_PAPER = 0, MLBM_STENCIL_OWN = 1 }; /* mlbm_params.stencil_mo
 
 /* One point cloud (Sec. 2.2: the set X of Eulerian nodes). */
 typedef struct {
-    int32_t n;                  /* number of nodes, >= K                          */
+    int32_t n;                  /* number of nodes, K <= n <= 268,435,455         */
     const double *x, *y;        /* device, [n] coordinates, user order            */
     const uint8_t *node_type;   /* device, [n]: 0 fluid, 1 wall; NULL = all fluid */
     double period_x, period_y;  /* > 0: periodic with that period, coordinates in
@@ -98,7 +98,8 @@ typedef struct {
                                not available through mlbm_import_weights       */
     double rho_wall;
     int32_t with_adjoint;   /* 1: also build the transposed streaming operator
-                               used by mlbm_step_adjoint (8K entries per node)     */
+                               used by mlbm_step_adjoint (8K entries per node;
+                               8 K n above 2^31 - 1 is MLBM_EUNSUPPORTED)          */
 } mlbm_params;
 
 typedef struct mlbm_plan mlbm_plan;  /* opaque host object; refers to the

@@ -54,6 +54,9 @@ void choose_grid(int n, double Lx, double Ly, int &gx, int &gy, int &hb) {
 
 mlbm_status check_params(const mlbm_cloud &c, const mlbm_params &p, bool device_cloud) {
     if (c.n <= 0) return fail(MLBM_EINVAL, "cloud has no nodes");
+    // the departure points (8 per node) are listed per owner with 32-bit offsets
+    if ((int64_t)8 * c.n > (int64_t)INT32_MAX)
+        return fail(MLBM_EUNSUPPORTED, "clouds above 268,435,455 nodes are not supported");
     if (device_cloud && (!c.x || !c.y)) return fail(MLBM_EINVAL, "cloud coordinates are null");
     if (p.degree < 2 || p.degree > 4)
         return fail(MLBM_EINVAL, "polynomial degree must be 2, 3 or 4");
@@ -80,6 +83,9 @@ mlbm_status check_params(const mlbm_cloud &c, const mlbm_params &p, bool device_
     if (p.wall_kind == 1 && !(p.rho_wall > 0.0)) return fail(MLBM_EINVAL, "rho_wall must be positive");
     if (p.with_adjoint && (p.force_kind != 0 || p.wall_kind != 0))
         return fail(MLBM_EUNSUPPORTED, "the adjoint supports periodic clouds without walls or force");
+    // the transposed operator's rows are indexed with 32-bit offsets
+    if (p.with_adjoint && (int64_t)8 * p.K * c.n > (int64_t)INT32_MAX)
+        return fail(MLBM_EUNSUPPORTED, "the adjoint tables of this cloud exceed 2^31 entries");
     return MLBM_OK;
 }
 

@@ -56,6 +56,7 @@ def test_query_sizes_grow_with_problem():
     (dict(tau=0.5), -1), (dict(dx=0.0), -1), (dict(dx=0.6), -1), (dict(precision=7), -1),
     (dict(stencil_mode=3), -1), (dict(K=49), -1), (dict(n=10), -1),
     (dict(with_adjoint=1, force_kind=1), -5),
+    (dict(with_adjoint=1, K=48, degree=4, n=5_600_000), -5), (dict(K=6, n=268_435_456), -5),
 ])
 def test_query_rejects_invalid(kw, code):
     st, _, _ = _query(**kw)
