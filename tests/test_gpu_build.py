@@ -53,6 +53,32 @@ def test_build_matches_oracle(label, make, dxf, K, m, mode):
     plan.close()
 
 
+# K and degree whose K + M unknowns (33 to 48) take the 48-unknown matrix-core
+# solver: every remainder of K + M modulo 4 (the last panel of four pivot
+# columns only partly used) and both ends of the range.
+MFMA_RANGE = [(18, 4, 0), (24, 3, 1), (30, 2, 0), (24, 4, 1), (32, 3, 0), (32, 4, 1),
+              (33, 4, 0), (38, 3, 1)]
+
+
+@pytest.mark.parametrize("K,m,mode", MFMA_RANGE,
+                         ids=["K%d-m%d-n%d" % (K, m, K + (m + 1) * (m + 2) // 2)
+                              for K, m, _ in MFMA_RANGE])
+def test_48_unknown_solver_over_its_range(K, m, mode):
+    c, _, _ = tgv_case(20, K, m, mode, seed=11)
+    plan = _build(c, c.h, K, m, mode)
+    nbr_o = oracle.knn(c.x, c.y, c.period, K)
+    own_o = oracle.owners(c.x, c.y, c.period, c.h, mode)
+    np.testing.assert_array_equal(plan.export("nbr"), nbr_o)
+    np.testing.assert_array_equal(plan.export("owner"), own_o)
+    W_o = oracle.weights(c.x, c.y, c.period, c.h, K, m, nbr_o, own_o)
+    err = np.abs(plan.export("W")[:, 1:, :] - W_o[:, 1:, :]).max()
+    say("K %d degree %d (%d unknowns), mode %d: max |W_gpu - W_oracle| = %.2e"
+        % (K, m, K + oracle.poly_count(m), mode, err))
+    assert err < TOL_W
+    assert plan.device_error() == 0
+    plan.close()
+
+
 def test_build_with_crowded_owners_matches_oracle():
     """Weights on the dense-strip cloud, where nodes beside the strip own
     more than 16 departure points: the 48-unknown matrix-core solver solves
