@@ -807,7 +807,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(RT == 3 ? 3 
     __shared__ double s_U[4][NC][4];     // the row groups that hold the pivot rows
     __shared__ int s_step[NB];
     __shared__ double s_pinv[NB];
-    static_assert(48 * 15 + 16 * 15 <= 4 * NC * 4, "the monomial tables fit in s_U");
+    constexpr int PQ = NB * 15;          // the departure points' monomials follow the members'
+    static_assert(PQ + 16 * 15 <= 4 * NC * 4, "the monomial tables fit in s_U");
     const int lane = threadIdx.x;
     const int s = blockIdx.x;
     if (s >= n) return;
@@ -873,7 +874,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(RT == 3 ? 3 
                 xp[e] = xp[e - 1] * px;
                 yp[e] = yp[e - 1] * py;
             }
-            double *row = tab + (mem ? lid * 15 : 720 + (dep ? t : 0) * 15);
+            double *row = tab + (mem ? lid * 15 : PQ + (dep ? t : 0) * 15);
             if (mem || dep) {
 #pragma unroll
                 for (int d = 0, q = 0; d <= 4; ++d)
@@ -920,7 +921,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(RT == 3 ? 3 
                         const double2 q = s_q[t];
                         r3 = cube_dist(xr.x, xr.y, q.x, q.y);
                     }
-                    const double tv = tab[pr ? 720 + t * 15 + (r - K) : 0];
+                    const double tv = tab[pr ? PQ + t * 15 + (r - K) : 0];
                     T[rt][RT][i] = t < cnt ? (rr ? r3 : (pr ? tv : 0.0)) : 0.0;
                 }
                 // one row at a time: keeps the compiler from hoisting every
