@@ -9,6 +9,7 @@
 #include <memory>
 #include <mutex>
 #include <new>
+#include <numeric>
 #include <string>
 #include <utility>
 #include <vector>
@@ -478,22 +479,74 @@ mlbm_status build_clouds(mlbm_plan *plan, const mlbm_cloud *clouds, const mlbm_p
     return st;
 }
 
+// Order in which the batched step lays out the clouds' tiles: by stencil
+// size, then as given. The states keep the caller's order; only the launch's
+// sequence of tiles changes. Clouds of one K next to each other measured 1.6 %
+// faster than a random mix on a 64-cloud workload of K 20, 25 and 30 (0.710
+// against 0.722 ms per step, with the split below in both).
+std::vector<int> tile_order(const mlbm_plan &plan) {
+    std::vector<int> o(plan.c.size());
+    std::iota(o.begin(), o.end(), 0);
+    std::stable_sort(o.begin(), o.end(),
+                     [&](int a, int b) { return plan.c[a].prm.K < plan.c[b].prm.K; });
+    return o;
+}
+
+// The batched step's descriptor of a cloud whose tiles start at tile_begin.
+Step32Args batch_desc(const CloudPlan &cp, int64_t tile_begin) {
+    Step32Args a = step32_args(cp, nullptr);
+    a.soff = (int64_t)kQ * cp.off;
+    a.tile_begin = tile_begin;
+    return a;
+}
+
+// Splits the batch's tiles into eight contiguous ranges of about equal cost,
+// one per XCD. A node-update costs its algorithmic bytes, 4 (9K + 18) + 32
+// with the paper's stencils, plus about 170 bytes' worth of work that does not
+// grow with K (staging, collision, stores): a linear fit to the batched step's
+// time per node over clouds of K = 20, 25 and 30. The tile that crosses a
+// boundary goes to the earlier XCD.
+void split_xcds(mlbm_plan &plan, const std::vector<int> &order) {
+    auto node_cost = [&](const CloudPlan &cp) {
+        return 4.0 * (9 * cp.prm.K + 18) + (plan.batch_mode == MLBM_STENCIL_PAPER ? 32 : 0) +
+               170.0;
+    };
+    double total = 0.0;
+    for (const CloudPlan &cp : plan.c) total += node_cost(cp) * cp.n;
+    XcdSplit &r = plan.xcd;
+    r.begin[0] = 0;
+    int x = 1;
+    int64_t t = 0;
+    double acc = 0.0;
+    for (int c : order) {
+        const CloudPlan &cp = plan.c[c];
+        const double w = node_cost(cp);
+        for (int64_t p = 0; p < cp.n; p += kTile, ++t) {
+            acc += w * (double)std::min<int64_t>(kTile, cp.n - p);
+            while (x < 8 && acc >= total * x / 8.0) r.begin[x++] = t + 1;
+        }
+    }
+    while (x < 9) r.begin[x++] = plan.total_tiles;
+    plan.xcd_longest = 0;
+    for (int i = 0; i < 8; ++i)
+        plan.xcd_longest = std::max(plan.xcd_longest, r.begin[i + 1] - r.begin[i]);
+}
+
 mlbm_status build_batch(mlbm_plan *plan, hipStream_t s) {
     if (!plan->batched) return MLBM_OK;
+    const std::vector<int> order = tile_order(*plan);
     int64_t tb = 0;
     unsigned lds = 0;
-    for (size_t c = 0; c < plan->c.size(); ++c) {
-        CloudPlan &cp = plan->c[c];
-        Step32Args a = step32_args(cp, nullptr);
-        a.soff = (int64_t)kQ * cp.off;
-        a.tile_begin = tb;
+    for (int c : order) {
+        const CloudPlan &cp = plan->c[c];
         const int64_t nt = (cp.n + kTile - 1) / kTile;
-        MLBM_HIP(launch_set_desc(plan->descs + c, a, s));
+        MLBM_HIP(launch_set_desc(plan->descs + c, batch_desc(cp, tb), s));
         MLBM_HIP(launch_fill_i32(plan->tile2cloud + tb, (int32_t)c, nt, s));
         tb += nt;
         lds = std::max(lds, cp.lds_bytes);
     }
     plan->batch_lds = lds;
+    split_xcds(*plan, order);
     return MLBM_OK;
 }
 
@@ -861,11 +914,9 @@ mlbm_status mlbm_plan_set_tau(mlbm_plan *plan, double tau) {
         // descriptor table: rewrite the table (synchronous copies)
         MLBM_HIP(hipDeviceSynchronize());
         int64_t tb = 0;
-        for (size_t c = 0; c < plan->c.size(); ++c) {
+        for (int c : tile_order(*plan)) {
             const CloudPlan &cp = plan->c[c];
-            Step32Args a = step32_args(cp, nullptr);
-            a.soff = (int64_t)kQ * cp.off;
-            a.tile_begin = tb;
+            const Step32Args a = batch_desc(cp, tb);
             tb += (cp.n + kTile - 1) / kTile;
             MLBM_HIP(hipMemcpy(plan->descs + c, &a, sizeof(a), hipMemcpyHostToDevice));
         }

@@ -198,6 +198,14 @@ struct Step32Args {
                              // gathers from global memory instead
 };
 
+// Tile ranges of the eight XCDs in a launch over several clouds: XCD x takes
+// tiles [begin[x], begin[x + 1]). The ranges are contiguous and carry about
+// equal work rather than equal tile counts, tiles of clouds with larger
+// stencils costing more; the grid is 8 * the longest range.
+struct XcdSplit {
+    int64_t begin[9];
+};
+
 // Bump allocator over a caller buffer (a null base computes sizes only).
 struct Carve {
     char *base;
@@ -224,6 +232,8 @@ struct mlbm_plan {
     mlbm::Step32Args *descs = nullptr;   // device [n_clouds]
     int32_t *tile2cloud = nullptr;       // device [total_tiles]
     unsigned batch_lds = 0;
+    mlbm::XcdSplit xcd{};                // tile ranges of the XCDs
+    int64_t xcd_longest = 0;             // longest of those ranges
     int precision = MLBM_FP32_DEV;
     int32_t *dev_err = nullptr;     // device error words (kErrWords int32)
     int32_t *stats = nullptr;       // device [n_clouds][kStats]: tile-table records
@@ -265,6 +275,21 @@ __device__ __forceinline__ int64_t xcd_tile(int64_t nblocks) {
 }
 
 inline unsigned xcd_grid(int64_t nblocks) { return (unsigned)(((nblocks + 7) / 8) * 8); }
+
+
+// This workgroup's tile under an XcdSplit, or -1 past the end of its XCD's range.
+__device__ __forceinline__ int64_t xcd_split_tile(const XcdSplit &r) {
+    const int x = blockIdx.x & 7;
+    int64_t b = r.begin[0], e = r.begin[1];
+#pragma unroll
+    for (int i = 1; i < 8; ++i)
+        if (x == i) {
+            b = r.begin[i];
+            e = r.begin[i + 1];
+        }
+    const int64_t t = b + (blockIdx.x >> 3);
+    return t < e ? t : -1;
+}
 
 // ---- build stages (build.hip) ----
 hipError_t launch_geo_periodic(Geo *geo, double Lx, double Ly, int gx, int gy, int hb,

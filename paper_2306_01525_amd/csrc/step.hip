@@ -401,10 +401,10 @@ __global__ __launch_bounds__(kTile) void k_step32_batch(const Step32Args *__rest
                                                         const int32_t *__restrict__ tile2cloud,
                                                         const float *__restrict__ g,
                                                         float *__restrict__ go,
-                                                        int64_t total_tiles) {
+                                                        XcdSplit xs) {
     extern __shared__ __align__(16) unsigned char smem[];
-    const int64_t t = xcd_tile(total_tiles);
-    if (t >= total_tiles) return;
+    const int64_t t = xcd_split_tile(xs);
+    if (t < 0) return;
     const Step32Args a = descs[tile2cloud[t]];
     step32_tile<MODE, false, false, false, UNROLL, NT>(a, g + a.soff, go + a.soff,
                                                         t - a.tile_begin, smem);
@@ -415,10 +415,10 @@ __global__ __launch_bounds__(2 * kTile) void k_step32s_batch(const Step32Args *_
                                                              const int32_t *__restrict__ tile2cloud,
                                                              const float *__restrict__ g,
                                                              float *__restrict__ go,
-                                                             int64_t total_tiles) {
+                                                             XcdSplit xs) {
     extern __shared__ __align__(16) unsigned char smem[];
-    const int64_t t = xcd_tile(total_tiles);
-    if (t >= total_tiles) return;
+    const int64_t t = xcd_split_tile(xs);
+    if (t < 0) return;
     const Step32Args a = descs[tile2cloud[t]];
     step32_tile_split<MODE, false, false, false, NT, UNROLL>(a, g + a.soff, go + a.soff,
                                                              t - a.tile_begin, smem);
@@ -829,16 +829,16 @@ void launch32s(const CloudPlan &cp, const void *gin, void *gout, void *frec, int
 
 template <int MODE, bool NT, int UNROLL = 1>
 void launch32s_batch(const mlbm_plan &plan, const void *gin, void *gout, hipStream_t s) {
-    hipLaunchKernelGGL((k_step32s_batch<MODE, NT, UNROLL>), dim3(xcd_grid(plan.total_tiles)),
+    hipLaunchKernelGGL((k_step32s_batch<MODE, NT, UNROLL>), dim3(8 * plan.xcd_longest),
                        dim3(2 * kTile), plan.batch_lds, s, plan.descs, plan.tile2cloud,
-                       (const float *)gin, (float *)gout, plan.total_tiles);
+                       (const float *)gin, (float *)gout, plan.xcd);
 }
 
 template <int MODE, int UNROLL, bool NT>
 void launch32_batch(const mlbm_plan &plan, const void *gin, void *gout, hipStream_t s) {
-    hipLaunchKernelGGL((k_step32_batch<MODE, UNROLL, NT>), dim3(xcd_grid(plan.total_tiles)),
+    hipLaunchKernelGGL((k_step32_batch<MODE, UNROLL, NT>), dim3(8 * plan.xcd_longest),
                        dim3(kTile), plan.batch_lds, s, plan.descs, plan.tile2cloud,
-                       (const float *)gin, (float *)gout, plan.total_tiles);
+                       (const float *)gin, (float *)gout, plan.xcd);
 }
 
 template <int MODE>
