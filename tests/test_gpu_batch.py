@@ -58,6 +58,31 @@ def test_batched_plan_equals_single_plans_and_oracle():
     bp.close()
 
 
+def test_batch_with_fewer_tiles_than_xcds_and_clouds_out_of_k_order():
+    """Four tiles over eight XCD ranges (some ranges empty), clouds passed with
+    K falling (the launch lays their tiles out by K): every cloud still steps
+    bitwise like its single-cloud plan."""
+    from paper_2306_01525_amd import Params, Plan
+    specs = [(12, 30, 4, 0.8, 21), (10, 20, 3, 0.7, 22), (17, 12, 2, 0.9, 23)]  # 144, 100, 289 nodes
+    clouds, params, u = [], [], []
+    for n_side, K, m, tau, seed in specs:
+        c = jittered_lattice(n_side, seed=seed)
+        clouds.append((c.x, c.y, c.period, None))
+        params.append(Params(dx=c.h, K=K, degree=m, tau=tau, stencil_mode=1))
+        u.append(tgv_initial_velocity(c.x, c.y, c.period[0], 0.01))
+    ux = np.concatenate([a for a, _ in u])
+    uy = np.concatenate([b for _, b in u])
+    bp = Plan.build_batch(clouds, params)
+    g = bp.step(bp.init(ux, uy), bp.new_state(), 7)
+    for c, ((x, y, period, _), p) in enumerate(zip(clouds, params)):
+        sp = Plan.build(x, y, period, p)
+        gs = sp.step(sp.init(*u[c]), sp.new_state(), 7)
+        assert torch.equal(gs, bp.cloud_view(g, c)), c
+        sp.close()
+    assert bp.device_error() == 0
+    bp.close()
+
+
 def test_mixed_batch_falls_back_to_per_cloud_launches():
     """An annulus with walls and force next to a periodic cloud: no common
     batched kernel, each cloud is stepped by its own launch."""
