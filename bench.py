@@ -844,6 +844,8 @@ def main():
     ap.add_argument("--skip-lbm", action="store_true")
     ap.add_argument("--skip-tgv40", action="store_true")
     ap.add_argument("--batched-steps", type=int, default=500)
+    ap.add_argument("--batched-only", action="store_true",
+                    help="run only the 64-cloud batched leg and print its figures")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a copy of known size (for HBM counter scaling)")
     ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
@@ -881,6 +883,9 @@ def main():
 
     if args.copy_calibration:
         copy_calibration()
+    if args.batched_only:
+        print(json.dumps({"batched_64_clouds": run_batched(args.batched_steps)}), flush=True)
+        return
     r = run_gpu(args)
     n, K, steps = r["n"], r["K"], args.steps
     ms_step = r["ms32"] / steps
