@@ -76,6 +76,10 @@ E2E_CASES = [
     ("c1-own", 40, 12, 2, 1, 0.8, 200),
     ("paper-K30-m4", 48, 30, 4, 0, 0.6, 100),
     ("ragged-rect-paper-K20-m3", None, 20, 3, 0, 0.7, 50),
+    # the smallest cloud the boundary accepts, n = K: every stencil is the
+    # whole cloud, one partial tile
+    ("n-equals-K-paper", 4, 16, 2, 0, 0.8, 20),
+    ("n-equals-K-own", 4, 16, 2, 1, 0.8, 20),
 ]
 
 
