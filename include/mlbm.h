@@ -100,6 +100,15 @@ typedef struct {
     int32_t with_adjoint;   /* 1: also build the transposed streaming operator
                                used by mlbm_step_adjoint (8K entries per node;
                                8 K n above 2^31 - 1 is MLBM_EUNSUPPORTED)          */
+    int32_t fp32_weights_only;  /* 0: the plan keeps the FP64 shape vectors beside
+                               the FP32 ones. 1 (MLBM_FP32_DEV only, else
+                               MLBM_EINVAL): the FP64 ones are solved into the
+                               workspace and dropped after the build, which takes
+                               64 K bytes per node off the plan (about 60 % of a
+                               K = 30 plan) and adds them to the workspace; then
+                               mlbm_plan_export of item 3 and mlbm_interpolate
+                               return MLBM_EUNSUPPORTED, and mlbm_import_weights
+                               does not take it. Steps are bitwise the same     */
 } mlbm_params;
 
 typedef struct mlbm_plan mlbm_plan;  /* opaque host object; refers to the
@@ -184,7 +193,8 @@ mlbm_status mlbm_plan_get_info(const mlbm_plan *plan, mlbm_plan_info *info);
  * what = 0 perm int32 [n] (internal position -> user index),
  *        1 nbr int32 [n][K] (user indices, node-major, user order),
  *        2 owner int32 [n][9] (user indices, user order),
- *        3 W FP64 [n][9][K] (user order; k = 0 is the identity),
+ *        3 W FP64 [n][9][K] (user order; k = 0 is the identity; not with
+ *          fp32_weights_only),
  *        4 tile descriptors int32 [ntiles][2] (|O_t|, |H_t|; 0 = global path),
  *        5 halo lists int32 [ntiles][hcap] (internal indices),
  *        6 local stencils uint32 [ntiles][ocap][ceil(K/3)]: halo positions of
@@ -259,7 +269,8 @@ mlbm_status mlbm_l2_sums(const mlbm_plan *plan, const void *g, const double *ux_
  * out[k-1][i] = sum_j w_{i,k,j} field[stencil member j of the stencil that
  * serves departure point x_i - e_k dx], k = 1..8. field: device FP64
  * [n_total], user order; out: device FP64 [8][n_total], user order (clouds of
- * a multi-cloud plan at their offsets). */
+ * a multi-cloud plan at their offsets). MLBM_EUNSUPPORTED for a plan built
+ * with fp32_weights_only, which has no FP64 shape vectors. */
 mlbm_status mlbm_interpolate(const mlbm_plan *plan, const double *field, double *out,
                              hipStream_t stream);
 

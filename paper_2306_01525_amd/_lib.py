@@ -40,7 +40,7 @@ class Params(ctypes.Structure):
     _fields_ = [("dx", _c_d), ("K", _c_i32), ("degree", _c_i32), ("stencil_mode", _c_i32),
                 ("precision", _c_i32), ("tau", _c_d), ("rho0", _c_d), ("force_kind", _c_i32),
                 ("force_mag", _c_d), ("wall_kind", _c_i32), ("rho_wall", _c_d),
-                ("with_adjoint", _c_i32)]
+                ("with_adjoint", _c_i32), ("fp32_weights_only", _c_i32)]
 
 
 class PlanInfo(ctypes.Structure):

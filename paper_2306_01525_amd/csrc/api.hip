@@ -87,6 +87,10 @@ mlbm_status check_params(const mlbm_cloud &c, const mlbm_params &p, bool device_
     // the transposed operator's rows are indexed with 32-bit offsets
     if (p.with_adjoint && (int64_t)8 * p.K * c.n > (int64_t)INT32_MAX)
         return fail(MLBM_EUNSUPPORTED, "the adjoint tables of this cloud exceed 2^31 entries");
+    if (p.fp32_weights_only != 0 && p.fp32_weights_only != 1)
+        return fail(MLBM_EINVAL, "fp32_weights_only must be 0 or 1");
+    if (p.fp32_weights_only && p.precision != MLBM_FP32_DEV)
+        return fail(MLBM_EINVAL, "fp32_weights_only needs the FP32 state");
     return MLBM_OK;
 }
 
@@ -124,8 +128,13 @@ void layout_cloud(const mlbm_cloud &c, const mlbm_params &p, int precision, Carv
     cp.links = p.wall_kind == 2 ? pl.take<uint8_t>(n) : nullptr;
     cp.nbr = pl.take<int32_t>((size_t)K * n);
     cp.owner = p.stencil_mode == MLBM_STENCIL_PAPER ? pl.take<int32_t>((size_t)8 * n) : nullptr;
-    cp.W64 = pl.take<double>((size_t)8 * K * n);
+    // FP64 shape vectors: in the plan, or with fp32_weights_only in the
+    // workspace, where only the build uses them (solve, then FP32 packing)
     cp.W32 = precision == MLBM_FP32_DEV ? pl.take<float>((size_t)8 * K * n) : nullptr;
+    if (p.fp32_weights_only && precision == MLBM_FP32_DEV)
+        cp.W64 = ws ? ws->take<double>((size_t)8 * K * n) : nullptr;
+    else
+        cp.W64 = pl.take<double>((size_t)8 * K * n);
     if (p.force_kind) {
         cp.force64 = pl.take<double>((size_t)2 * n);
         cp.force32 = precision == MLBM_FP32_DEV ? pl.take<float>((size_t)2 * n) : nullptr;
@@ -407,6 +416,8 @@ mlbm_status build_cloud(mlbm_plan *plan, CloudPlan &cp, const mlbm_cloud &c,
     MLBM_HIP(launch_rbf(cp.geo, cp.xs, cp.ys, cp.perm, cp.nbr, cp.owner, n, p.K, p.degree, p.dx,
                         p.stencil_mode, bw.rbf_tmp, bw.rbf_bytes, cp.W64, plan->dev_err, s));
     if (cp.W32) MLBM_HIP(launch_pack_w32(cp.W64, n, p.K, cp.W32, s));
+    // with fp32_weights_only the FP64 shape vectors were workspace, used up here
+    if (p.fp32_weights_only) cp.W64 = nullptr;
     // equilibrium wall nodes receive no force; with bounce-back every node does
     MLBM_HIP(launch_force(cp.xs, cp.ys, p.wall_kind == 1 ? cp.ntype : nullptr, n, p.force_kind,
                           p.force_mag, cp.force32, cp.force64, s));
@@ -650,6 +661,8 @@ mlbm_status mlbm_import_query(int32_t n, const mlbm_params *params, size_t *plan
     c.n = n;
     mlbm_status st = check_params(c, *params, false);
     if (st != MLBM_OK) return st;
+    if (params->fp32_weights_only)
+        return fail(MLBM_EUNSUPPORTED, "imported plans keep their FP64 shape vectors");
     Carve pl(nullptr);
     CloudPlan cp;
     mlbm_plan tmp;
@@ -832,6 +845,8 @@ mlbm_status mlbm_plan_export(const mlbm_plan *plan, int32_t cloud, int32_t what,
     if (what >= 9 && !cp.tdescT) return fail(MLBM_EINVAL, "plan was built without with_adjoint");
     if (what >= 4 && what <= 6 && !cp.tdesc) return fail(MLBM_EINVAL, "plan has no tile tables");
     if (what == 7 && !cp.ownerL) return fail(MLBM_EINVAL, "plan has no local owners");
+    if (what == 3 && !cp.W64)
+        return fail(MLBM_EUNSUPPORTED, "plan was built with fp32_weights_only: no FP64 shape vectors");
     if (dst_bytes != need) return fail(MLBM_ESMALLBUF, "export size mismatch");
     MLBM_HIP(hipDeviceSynchronize());
     if (what == 8) {
@@ -1049,6 +1064,9 @@ mlbm_status mlbm_moments(const mlbm_plan *plan, const void *g, double *rho, doub
 mlbm_status mlbm_interpolate(const mlbm_plan *plan, const double *field, double *out,
                              hipStream_t s) {
     if (!single(plan) || !field || !out) return fail(MLBM_EINVAL, "null argument");
+    for (const CloudPlan &cp : plan->c)
+        if (!cp.W64)
+            return fail(MLBM_EUNSUPPORTED, "plan was built with fp32_weights_only: no FP64 shape vectors");
     for (const CloudPlan &cp : plan->c)
         MLBM_HIP(launch_interpolate(cp, node_at(field, cp), plan->n_total, out_at(out, cp), s));
     return MLBM_OK;

@@ -66,11 +66,13 @@ class Params:
     wall_kind: int = 0
     rho_wall: float = 1.0
     with_adjoint: int = 0
+    fp32_weights_only: int = 0
 
     def to_c(self) -> _lib.Params:
         return _lib.Params(self.dx, self.K, self.degree, self.stencil_mode, self.precision,
                            self.tau, self.rho0, self.force_kind, self.force_mag,
-                           self.wall_kind, self.rho_wall, self.with_adjoint)
+                           self.wall_kind, self.rho_wall, self.with_adjoint,
+                           self.fp32_weights_only)
 
 
 class Plan:

@@ -57,12 +57,29 @@ def test_query_sizes_grow_with_problem():
     (dict(stencil_mode=3), -1), (dict(K=49), -1), (dict(n=10), -1),
     (dict(with_adjoint=1, force_kind=1), -5),
     (dict(with_adjoint=1, K=48, degree=4, n=5_600_000), -5), (dict(K=6, n=268_435_456), -5),
+    (dict(fp32_weights_only=1, precision=1), -1), (dict(fp32_weights_only=2), -1),
 ])
 def test_query_rejects_invalid(kw, code):
     st, _, _ = _query(**kw)
     assert st == code
     from paper_2306_01525_amd import _lib
     assert len(_lib.load().mlbm_last_error()) > 0
+
+
+def test_fp32_weights_only_moves_the_fp64_shape_vectors_to_the_workspace():
+    """The FP64 shape vectors (8 directions x K doubles per node) leave the
+    plan for the workspace; imported plans keep them and refuse the flag."""
+    import ctypes
+    from paper_2306_01525_amd import _lib
+    n, K = 1000, 12
+    st0, pb0, wb0 = _query(n=n, K=K)
+    st1, pb1, wb1 = _query(n=n, K=K, fp32_weights_only=1)
+    assert st0 == st1 == 0
+    assert pb0 - pb1 >= 8 * K * n * 8 and wb1 - wb0 >= 8 * K * n * 8
+    p = _lib.Params(dx=0.1, K=K, degree=2, stencil_mode=0, precision=0, tau=0.8, rho0=1.0,
+                    fp32_weights_only=1)
+    size = ctypes.c_size_t()
+    assert _lib.load().mlbm_import_query(n, ctypes.byref(p), ctypes.byref(size)) == -5
 
 
 def test_missing_library_fails_loudly(monkeypatch, tmp_path):

@@ -263,3 +263,64 @@ def test_adjoint_tables_are_consistent(mode, precision, K, m):
             mask = np.arange(lw)[:, None] < hl[None, :]
             np.testing.assert_array_equal(I[el[k][:, ms][mask]], ecol[k][:, ms][mask])
     plan.close()
+
+
+def test_fp32_weights_only_plan_steps_like_the_full_plan():
+    """A plan built with fp32_weights_only holds no FP64 shape vectors: its
+    buffer is smaller by 64 K bytes per node; its steps (one cloud, a batch,
+    the static-workspace build) and its gradient are bitwise those of the full
+    plan; the calls that need the FP64 vectors refuse."""
+    from paper_2306_01525_amd import MLBMError, Params, Plan
+    from paper_2306_01525_amd.autograd import rollout_loss
+    from synth import jittered_lattice, tgv_initial_velocity
+    c, ux, uy = tgv_case(48, 30, 4, 0, seed=4)
+    ux, uy = tgv_initial_velocity(c.x, c.y, c.period[0], 0.01)
+
+    def prm(lean, K=30, m=4, **kw):
+        return Params(dx=c.h, K=K, degree=m, tau=0.8, stencil_mode=0,
+                      fp32_weights_only=int(lean), **kw)
+
+    full = Plan.build(c.x, c.y, c.period, prm(False))
+    lean = Plan.build(c.x, c.y, c.period, prm(True))
+    stat = Plan.build(c.x, c.y, c.period, prm(True), static_workspace=True)
+    saved = full._buf.numel() - lean._buf.numel()
+    say("plan bytes per node: full %.0f, fp32_weights_only %.0f"
+        % (full._buf.numel() / c.n, lean._buf.numel() / c.n))
+    assert saved >= 64 * 30 * c.n
+    g_full = full.step(full.init(ux, uy), full.new_state(), 20)
+    for q in (lean, stat):
+        assert torch.equal(q.step(q.init(ux, uy), q.new_state(), 20), g_full)
+        assert q.device_error() == 0
+    for call in (lambda: lean.export("W"), lambda: lean.interpolate(np.zeros(c.n))):
+        with pytest.raises(MLBMError) as ei:
+            call()
+        assert ei.value.status == -5
+    for q in (full, lean, stat):
+        q.close()
+
+    # a batch of two clouds
+    c2 = jittered_lattice(30, seed=8)
+    u2x, u2y = tgv_initial_velocity(c2.x, c2.y, c2.period[0], 0.01)
+    clouds = [(c.x, c.y, c.period, None), (c2.x, c2.y, c2.period, None)]
+    bx, by = np.concatenate([ux, u2x]), np.concatenate([uy, u2y])
+    states = []
+    for lean_flag in (False, True):
+        b = Plan.build_batch(clouds, [prm(lean_flag), prm(lean_flag, K=20, m=3)])
+        states.append(b.step(b.init(bx, by), b.new_state(), 10))
+        b.close()
+    assert torch.equal(states[0], states[1])
+
+    # the gradient of a short checkpointed rollout
+    tx, ty = (torch.tensor(a, device="cuda") for a in (ux, uy))
+    grads = []
+    for lean_flag in (False, True):
+        q = Plan.build(c.x, c.y, c.period, prm(lean_flag, with_adjoint=1))
+        u0x = torch.tensor(ux, device="cuda", requires_grad=True)
+        u0y = torch.tensor(uy, device="cuda", requires_grad=True)
+        tau = torch.tensor(0.8, dtype=torch.float64, device="cuda", requires_grad=True)
+        J = rollout_loss(q, u0x, u0y, tau, 6, 0.5 * tx, 0.5 * ty, 3)
+        J.backward()
+        grads.append((J.detach(), u0x.grad, u0y.grad, tau.grad))
+        q.close()
+    for a, b in zip(*grads):
+        assert torch.equal(a, b)
