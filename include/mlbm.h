@@ -163,7 +163,8 @@ mlbm_status mlbm_build_weights(const mlbm_cloud *clouds, const mlbm_params *para
  * mlbm_build_weights with no workspace argument. Its temporary arrays live in
  * a fixed 32 MiB array inside the library, one per GPU, held until the process
  * ends; clouds are built one after another on `stream`. That covers one cloud
- * of about 550,000 nodes (K 30, degree 4), 350,000 with the adjoint tables;
+ * of about 550,000 nodes (K 30, degree 4), 350,000 with the adjoint tables,
+ * 16,000 with fp32_weights_only (whose FP64 shape vectors then live in it);
  * a build whose one-cloud-at-a-time workspace (compare mlbm_weights_query)
  * exceeds it returns MLBM_EUNSUPPORTED before any device work. plan_buf and
  * plan_bytes as for mlbm_build_weights (same size); the results are the same.
