@@ -297,6 +297,15 @@ def test_fp32_weights_only_plan_steps_like_the_full_plan():
         assert ei.value.status == -5
     for q in (full, lean, stat):
         q.close()
+    # built, initialised and stepped inside one captured graph, replayed twice
+    s = torch.cuda.Stream()
+    gp, _, _, res = Plan.build_graph([(c.x, c.y, c.period, None)], [prm(True)], ux, uy, 20, s)
+    for _ in range(2):
+        gp.graph_launch(s)
+        s.synchronize()
+        assert torch.equal(res.reshape(-1), g_full.reshape(-1))
+    assert gp.device_error() == 0
+    gp.close()
 
     # a batch of two clouds
     c2 = jittered_lattice(30, seed=8)
