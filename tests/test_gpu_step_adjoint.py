@@ -4,7 +4,7 @@ import numpy as np
 import pytest
 
 import oracle
-from gpu_common import rel_l2, say
+from gpu_common import rel_l2, say, tol_fp32
 from synth import jittered_lattice, tgv_initial_velocity
 
 pytestmark = pytest.mark.gpu
@@ -121,4 +121,53 @@ def test_two_rollouts_at_different_tau_each_differentiate_at_their_own():
         assert eg < 1e-10
         assert abs(tt.grad.item() - gt_o) < 1e-10 * abs(gt_o)
         assert plan.params.tau == 0.95
+    plan.close()
+
+
+def _adjoint_draw(count=8, seed=77):
+    r = np.random.Generator(np.random.PCG64(seed))
+    out = []
+    for _ in range(count):
+        m = int(r.integers(2, 5))
+        M = (m + 1) * (m + 2) // 2
+        n_side = int(r.integers(8, 17))
+        K = int(r.integers(M + 6, min(48, 64 - M, n_side * n_side - 1) + 1))
+        out.append(dict(n_side=n_side, K=K, m=m, mode=int(r.integers(0, 2)),
+                        tau=float(r.uniform(0.55, 1.2)), steps=int(r.integers(6, 15)),
+                        seg=int(r.integers(2, 6)), seed=int(r.integers(1, 10_000))))
+    return out
+
+
+ADJ_CASES = _adjoint_draw()
+
+
+@pytest.mark.parametrize("case", ADJ_CASES, ids=["n%d-K%d-m%d-mode%d-s%d" % (
+    c["n_side"], c["K"], c["m"], c["mode"], c["steps"]) for c in ADJ_CASES])
+@pytest.mark.parametrize("precision", [1, 0])
+def test_adjoint_sweep_against_oracle(case, precision):
+    """Seeded random stencil sizes, degrees, rules, relaxation times, step
+    counts and checkpoint intervals, on the oracle's weights: FP64 to 1e-10.
+    In FP32, J and its gradient come from the misfit u(T) - u*, so the
+    rounding of u is amplified by |u*| / |u(T) - u*| (from 2 to 84 here); the
+    bound is tol_fp32(steps) times that ratio plus one (measured: at most 0.28
+    of it, 1e-7 to 2e-7 per unit of the ratio)."""
+    from paper_2306_01525_amd import Params, Plan
+    c, u0x, u0y, tx, ty, K, m, mode = _setup(n_side=case["n_side"], K=case["K"], m=case["m"],
+                                             mode=case["mode"], seed=case["seed"])
+    tau, steps, seg = case["tau"], case["steps"], case["seg"]
+    nbr, own, W = oracle.build_plan(c, 1.0, K, m, mode)
+    J_o, gx_o, gy_o, gt_o = oracle.adjoint(nbr, own, W, tau, steps, 1.0, u0x, u0y, tx, ty)
+    p = Params(dx=1.0, K=K, degree=m, tau=tau, stencil_mode=mode, precision=precision,
+               with_adjoint=1)
+    plan = Plan.from_arrays(c.x, c.y, nbr, own, W, p)
+    J, gx, gy, gt = _gpu_grad(plan, u0x, u0y, tx, ty, steps, seg)
+    ratio = float(np.sqrt((tx ** 2 + ty ** 2).sum() / (2.0 * J_o)))
+    tol = 1e-10 if precision == 1 else tol_fp32(steps) * (ratio + 1.0)
+    eg = rel_l2(np.concatenate([gx, gy]), np.concatenate([gx_o, gy_o]))
+    say("%s prec %d: J rel %.2e, grad u0 rel %.2e, dtau rel %.2e (misfit ratio %.1f, tol %.1e)"
+        % (case, precision, abs(J - J_o) / abs(J_o), eg, abs(gt - gt_o) / abs(gt_o), ratio, tol))
+    assert abs(J - J_o) <= tol * abs(J_o)
+    assert eg < tol
+    assert abs(gt - gt_o) <= tol * abs(gt_o)
+    assert plan.device_error() == 0
     plan.close()
