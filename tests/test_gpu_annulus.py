@@ -376,3 +376,69 @@ def test_annulus_study_with_the_papers_settings():
     assert e[0] > e[1] > e[2]
     assert order > 1.5
     assert e[2] < 5e-4
+
+
+def _annulus_draw(count=8, seed=404):
+    r = np.random.Generator(np.random.PCG64(seed))
+    out = []
+    for _ in range(count):
+        m = int(r.integers(2, 4))
+        M = (m + 1) * (m + 2) // 2
+        h = float(r.choice([0.08, 0.1, 0.12]))
+        out.append(dict(h=h, dx=float(h * r.uniform(0.5, 1.0)), K=int(r.integers(M + 6, 31)), m=m,
+                        mode=int(r.integers(0, 2)), tau=float(r.uniform(0.6, 1.2)),
+                        g=float(10 ** r.uniform(-5, -4)), wall=int(r.integers(1, 3)),
+                        seed=int(r.integers(1, 1000))))
+    return out
+
+
+ANN_CASES = _annulus_draw()
+
+
+@pytest.mark.parametrize("case", ANN_CASES, ids=["h%.2f-K%d-m%d-mode%d-wall%d" % (
+    c["h"], c["K"], c["m"], c["mode"], c["wall"]) for c in ANN_CASES])
+def test_annulus_sweep_matches_oracle(case):
+    """Seeded random annuli: spacing, streaming distance (dx <= h), stencil
+    size, degree, stencil rule, relaxation time, force and wall rule
+    (equilibrium or bounce-back), both precisions against the oracle after 1
+    and 30 steps from a swirl."""
+    from paper_2306_01525_amd import Params, Plan
+    c = annulus_poisson(R1, R2, case["h"], seed=case["seed"])
+    dx, K, m, mode, tau, g = case["dx"], case["K"], case["m"], case["mode"], case["tau"], case["g"]
+    nbr, own, W = oracle.build_plan(c, dx, K, m, mode)
+    ux, uy = _swirl(c, 1e-3)
+    if case["wall"] == 2:
+        nx, ny = _normals(c)
+        links = oracle.bounce_links(nx, ny, c.node_type)
+        ax, ay = oracle.azimuthal_force(c.x, c.y, g, None)
+        kw = dict(links=links)
+        extra = dict(normals=(nx, ny))
+    else:
+        ax, ay = oracle.azimuthal_force(c.x, c.y, g, c.node_type)
+        kw = dict(node_type=c.node_type, rho_w=1.0)
+        extra = {}
+    f = oracle.equilibrium(np.ones(c.n), ux, uy)
+    ref, done = {}, 0
+    for s_ in (1, 30):
+        f = oracle.run(f, nbr, own, W, tau, s_ - done, ax, ay, **kw)
+        done = s_
+        ref[s_] = oracle.moments(f)
+    for prec, tol in ((1, lambda s: TOL_FP64), (0, tol_fp32)):
+        p = Params(dx=dx, K=K, degree=m, tau=tau, stencil_mode=mode, precision=prec,
+                   force_kind=1, force_mag=g, wall_kind=case["wall"], rho_wall=1.0)
+        plan = Plan.build(c.x, c.y, c.period, p, node_type=c.node_type, **extra)
+        gst, other, done = plan.init(ux, uy), plan.new_state(), 0
+        for s_ in (1, 30):
+            res = plan.step(gst, other, s_ - done)
+            if res is other:
+                gst, other = other, gst
+            done = s_
+            r_g, u_g, v_g = (a.cpu().numpy() for a in plan.moments(gst))
+            r_o, u_o, v_o = ref[s_]
+            e = rel_l2(np.stack([u_g, v_g]), np.stack([u_o, v_o]))
+            er = float(np.abs(r_g - r_o).max())
+            say("%s prec %d step %d: rel L2 %.2e, max |drho| %.2e (tol %.1e)"
+                % (case, prec, s_, e, er, tol(s_)))
+            assert e < tol(s_) and er < tol(s_)
+        assert plan.device_error() == 0
+        plan.close()
