@@ -186,3 +186,45 @@ def test_captured_plan_sends_tiles_beyond_its_lds_to_the_global_path(variant):
     assert torch.equal(res.reshape(-1), ge.reshape(-1))
     plan.close()
     eager.close()
+
+
+def _batch_draw(count=4, seed=99):
+    r = np.random.Generator(np.random.PCG64(seed))
+    out = []
+    for _ in range(count):
+        mode = int(r.integers(0, 2))
+        clouds = []
+        for _ in range(int(r.integers(2, 8))):
+            m = int(r.integers(2, 5))
+            K = {2: 20, 3: 25, 4: 30}[m] if mode == 0 else int(r.integers(12, 41))
+            clouds.append(dict(n_side=int(r.integers(8, 70)), K=max(K, (m + 1) * (m + 2) // 2 + 2),
+                               m=m, tau=float(r.uniform(0.55, 1.0)), seed=int(r.integers(1, 9999))))
+        out.append(dict(mode=mode, clouds=clouds))
+    return out
+
+
+@pytest.mark.parametrize("batch", _batch_draw(), ids=lambda b: "mode%d-%dclouds" % (
+    b["mode"], len(b["clouds"])))
+def test_random_batches_equal_single_plans(batch):
+    """Seeded random batches (2-7 clouds of 64 to 4,761 nodes, their own K,
+    degree and tau, one stencil rule): every cloud of the batched plan steps
+    bitwise like its own single-cloud plan."""
+    from paper_2306_01525_amd import Params, Plan
+    clouds, params, u = [], [], []
+    for s in batch["clouds"]:
+        c = jittered_lattice(s["n_side"], seed=s["seed"])
+        clouds.append((c.x, c.y, c.period, None))
+        params.append(Params(dx=c.h, K=min(s["K"], c.n), degree=s["m"], tau=s["tau"],
+                             stencil_mode=batch["mode"]))
+        u.append(tgv_initial_velocity(c.x, c.y, c.period[0], 0.01))
+    ux = np.concatenate([a for a, _ in u])
+    uy = np.concatenate([b for _, b in u])
+    bp = Plan.build_batch(clouds, params)
+    g = bp.step(bp.init(ux, uy), bp.new_state(), 9)
+    for c, ((x, y, period, _), p) in enumerate(zip(clouds, params)):
+        sp = Plan.build(x, y, period, p)
+        gs = sp.step(sp.init(*u[c]), sp.new_state(), 9)
+        assert torch.equal(gs, bp.cloud_view(g, c)), c
+        sp.close()
+    assert bp.device_error() == 0
+    bp.close()
