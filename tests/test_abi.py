@@ -82,6 +82,48 @@ def test_fp32_weights_only_moves_the_fp64_shape_vectors_to_the_workspace():
     assert _lib.load().mlbm_import_query(n, ctypes.byref(p), ctypes.byref(size)) == -5
 
 
+PLAN_CALLS = {   # entry point -> its arguments after the plan (pointers null)
+    "mlbm_plan_get_info": [None],
+    "mlbm_plan_export": [0, 0, None, 0],
+    "mlbm_plan_set_tau": [0.8],
+    "mlbm_plan_set_variant": [1],
+    "mlbm_init": [None, None, None, None, None],
+    "mlbm_init_f": [None, None, None, None, None],
+    "mlbm_collide": [None, None, None],
+    "mlbm_step": [None, None, 1, None, None],
+    "mlbm_step_record": [None, None, 1, None, None, None],
+    "mlbm_moments": [None, None, None, None, None],
+    "mlbm_l2_sums": [None, None, None, None, None],
+    "mlbm_interpolate": [None, None, None],
+    "mlbm_residual": [None, None, None, None],
+    "mlbm_loss_seed": [None, None, None, None, None, None],
+    "mlbm_step_adjoint": [None, None, None, None, None],
+    "mlbm_init_adjoint": [None, None, None, None, None, None],
+    "mlbm_autotune": [None, None, 1, None, None, None],
+    "mlbm_graph_create": [None, None, 1, None],
+    "mlbm_graph_launch": [None],
+    "mlbm_device_error_nodes": [None, None],
+    "mlbm_device_error_clear": [None],
+}
+
+
+@pytest.mark.parametrize("name", sorted(PLAN_CALLS))
+def test_plan_calls_reject_a_null_plan(name):
+    """Every entry point that takes a plan returns MLBM_EINVAL for a null one
+    (checked before any device work), with a message."""
+    from paper_2306_01525_amd import _lib
+    L = _lib.load()
+    assert getattr(L, name)(None, *PLAN_CALLS[name]) == -1
+    assert len(L.mlbm_last_error()) > 0
+
+
+def test_null_plan_device_error_and_destroy():
+    from paper_2306_01525_amd import _lib
+    L = _lib.load()
+    assert L.mlbm_device_error(None) == 0
+    assert L.mlbm_plan_destroy(None) == 0
+
+
 def test_missing_library_fails_loudly(monkeypatch, tmp_path):
     from paper_2306_01525_amd import _lib
     monkeypatch.setattr(_lib, "_lib", None)
