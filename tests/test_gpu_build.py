@@ -137,6 +137,21 @@ def test_singular_stencil_is_reported(K, m):
 
 
 @pytest.mark.parametrize("mode", [0, 1])
+def test_duplicate_node_is_reported_singular(mode):
+    """Two nodes at the same place: every stencil that holds both has two
+    equal rows (and columns) in its local system, which is singular; the
+    build reports it (the lower-index twin owns the departure points near it
+    in the paper's rule, and every node owns its own in the other)."""
+    from paper_2306_01525_amd import MLBMError, Params, Plan
+    c, _, _ = tgv_case(20, 20, 3, mode, seed=13)
+    x, y = c.x.copy(), c.y.copy()
+    x[150], y[150] = x[77], y[77]
+    with pytest.raises(MLBMError) as ei:
+        Plan.build(x, y, c.period, Params(dx=c.h, K=20, degree=3, tau=0.8, stencil_mode=mode))
+    assert ei.value.status == -2
+
+
+@pytest.mark.parametrize("mode", [0, 1])
 def test_tile_tables_are_consistent(mode):
     """Gather tables of the FP32 step, checked on the CPU before any step
     uses them: halo lists sorted, unique and in range; local owners and
