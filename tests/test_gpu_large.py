@@ -1,7 +1,8 @@
-"""A cloud of 12.25M nodes (3,500 x 3,500 jittered lattice, K = 30, degree 4,
-paper stencils), where the FP64 shape vectors hold 8 K n = 2.9e9 values, past
-2^31: the first step at sampled nodes, half of them among the last internal
-(Hilbert) positions, against the oracle formed node by node."""
+"""Clouds at the size limits. A cloud of 12.25M nodes (3,500 x 3,500 jittered
+lattice, K = 30, degree 4, paper stencils), where the FP64 shape vectors hold
+8 K n = 2.9e9 values, past 2^31: the first step at sampled nodes, half of
+them among the last internal (Hilbert) positions, against the oracle formed
+node by node. And the adjoint at the largest cloud its tables allow."""
 import numpy as np
 import pytest
 
@@ -98,3 +99,42 @@ def test_large_cloud_first_step_at_sampled_nodes():
     # per-node bound after one step (measured 1.9e-7)
     assert emax64 < 1e-10
     assert emax32 < tol_fp32_node(1)
+
+
+def test_adjoint_at_the_table_limit_satisfies_the_dot_product_identity():
+    """2,991^2 = 8,946,081 nodes at K = 30: the transposed operator holds
+    8 K n = 2,147,059,440 entries, just below the 2^31 - 1 the row pointers
+    allow. For the one-step map F(f) = S(C(f)) and seeded random directions,
+    <lam, J df> (central difference of the GPU forward, FP64) equals
+    <J^T lam, df> (one reversed step)."""
+    from paper_2306_01525_amd import Params, Plan
+    n_side = 2991
+    c = jittered_lattice(n_side, seed=8)
+    assert 2 ** 31 - 1_000_000 < 8 * K * c.n <= 2 ** 31 - 1
+    ux, uy = tgv_initial_velocity(c.x, c.y, c.period[0], U0)
+    p = Params(dx=c.h, K=K, degree=M_DEG, tau=TAU, stencil_mode=0, precision=1, with_adjoint=1)
+    say("building FP64 plan with the adjoint tables, n = %d" % c.n)
+    plan = Plan.build(c.x, c.y, c.period, p)
+    f0 = plan.init_f(ux, uy)
+    gen = torch.Generator(device="cuda").manual_seed(11)
+    df = torch.randn(f0.shape, generator=gen, device="cuda", dtype=torch.float64)
+    lam = torch.randn(f0.shape, generator=gen, device="cuda", dtype=torch.float64)
+    eps = 1e-7
+
+    def F(f):
+        rec = plan.new_state()
+        plan.step_record(plan.collide(f), plan.new_state(), 1, rec)
+        return rec
+
+    jdf = (F(f0 + eps * df) - F(f0 - eps * df)) / (2 * eps)
+    lam_n = plan.new_state()
+    dtau = torch.zeros(1, dtype=torch.float64, device="cuda")
+    plan.step_adjoint(f0, lam, lam_n, dtau)
+    a = float(torch.dot(lam.reshape(-1), jdf.reshape(-1)))
+    b = float(torch.dot(lam_n.reshape(-1), df.reshape(-1)))
+    say("<lam, J df> %.12e, <J^T lam, df> %.12e, relative difference %.2e" % (a, b, abs(a - b) / abs(b)))
+    assert plan.device_error() == 0
+    # measured 1.8e-11: the central difference's truncation is O(eps^2) and its
+    # rounding about 1e-16 |F| / eps per entry, averaged over 80M entries
+    assert abs(a - b) <= 1e-10 * abs(b)
+    plan.close()
