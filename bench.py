@@ -804,7 +804,10 @@ def summarize_trace(trace_dir, command, out_path=None):
              "# command: " + command,
              "# step kernel source hash: " + step_kernel_hash(),
              "%-8s %12s %12s %7s  %s" % ("calls", "mean_us", "total_us", "pct", "kernel")]
-    for r in rows[:40]:
+    # the 40 largest, then every other step-kernel instance (the autotuner's
+    # variants that lost run only its timing launches and would drop out)
+    keep = rows[:40] + [r for r in rows[40:] if "k_step" in r["Name"] or "k_adj_step" in r["Name"]]
+    for r in keep:
         name = r["Name"]
         if len(name) > 110:
             name = name[:110] + "..."
