@@ -86,6 +86,7 @@ def step_kernel_hash() -> str:
 
 
 TIMING_REPS = 5   # replays of the timed graph; the median is reported
+BUILD_REPS = 3    # warm weight builds; the median is reported
 
 
 def time_steps(plan, g, steps, warmup, stream, reps=TIMING_REPS):
@@ -155,12 +156,16 @@ def run_gpu(args):
         return plan, (time.perf_counter() - t0) * 1e3
 
     # FP32 deviation form: the headline. The first build of the process also
-    # pays one-time costs (code objects, library set-up): a second build is
-    # the build time reported.
+    # pays one-time costs (code objects, library set-up); the build time
+    # reported is the median of the three builds after it.
     log("building FP32 plan, N =", c.n)
     plan32, build_cold_ms = build(MLBM_FP32_DEV)
-    plan32.close()
-    plan32, build_ms = build(MLBM_FP32_DEV)
+    build_warm = []
+    for _ in range(BUILD_REPS):
+        plan32.close()
+        plan32, t = build(MLBM_FP32_DEV)
+        build_warm.append(t)
+    build_ms = float(np.median(build_warm))
     a, b = plan32.new_state(), plan32.new_state()
     tune_ms = plan32.autotune(plan32.init(uxt, uyt, g=a), b, 20)
     out["tune"] = {"ms_per_step": tune_ms, "chosen": int(plan32.info.variant)}
@@ -186,7 +191,8 @@ def run_gpu(args):
     l2u32, l2v32 = plan32.l2(g32, tx_t, ty_t)
     _, u32, v32 = plan32.moments(g32)
     fields["fp32"][total] = (u32.cpu().numpy(), v32.cpu().numpy())
-    out.update(ms32=ms32, build_ms=build_ms, build_cold_ms=build_cold_ms, l2_32=(l2u32, l2v32),
+    out.update(ms32=ms32, build_ms=build_ms, build_cold_ms=build_cold_ms,
+               build_warm_ms=build_warm, l2_32=(l2u32, l2v32),
                l2_steps=total, timed_state_steps=taken, fields=fields, cloud=c,
                velocity0=(ux, uy), tau=tau, degree=m)
     log("FP32: %.4f ms/step (median of %d replays; min %.4f, max %.4f), L2(u) vs analytic %.3e"
@@ -961,7 +967,8 @@ def main():
     # elimination 2n^3/3 plus 8 right-hand sides at 2n^2 each, per node
     nn = K + 15
     flop = n * (2.0 * nn ** 3 / 3.0 + 16.0 * nn ** 2)
-    line["build"] = {"ms": r["build_ms"], "first_build_ms": r["build_cold_ms"],
+    line["build"] = {"ms": r["build_ms"], "warm_builds_ms": r["build_warm_ms"],
+                     "first_build_ms": r["build_cold_ms"],
                      "fp64_flop_algorithmic": flop,
                      "tflops": flop / (r["build_ms"] / 1e3) / 1e12}
     line["autotune"] = r["tune"]
