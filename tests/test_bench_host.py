@@ -1,7 +1,7 @@
 """Host logic of bench.py, on the CPU: the algorithmic byte counts, the
 timing summary, the kernel names it reports for the autotuner's variants (as
-the step source dispatches them), the HBM counter summary on synthetic
-rocprofv3 files, and the one-GPU guard."""
+the step source dispatches them), the HBM counter and kernel-trace summaries
+on synthetic rocprofv3 files, and the one-GPU guard."""
 import csv
 import json
 import os
@@ -92,6 +92,28 @@ def test_counter_summary_scales_by_the_copy_kernel(tmp_path, monkeypatch):
     d["kernel_hash"] = "0" * 16
     out.write_text(json.dumps(d))
     assert bench.load_traffic(1, 1) is None
+
+
+def test_trace_summary_keeps_every_step_kernel(tmp_path):
+    """The trace summary lists the 40 longest kernels and then every further
+    step-kernel instance (the autotuner's losing variants), nothing else."""
+    rows = [dict(Name="k_other_%d(x)" % i, Calls="1", AverageNs=str(1e6 - i),
+                 TotalDurationNs=str(1e6 - i), Percentage="1.0") for i in range(45)]
+    rows += [dict(Name="void k_step32s<0, false, 0, false, true, 2>(x)", Calls="21",
+                  AverageNs="46000", TotalDurationNs="966000", Percentage="0.03"),
+             dict(Name="void k_adj_step<float>(x)", Calls="3", AverageNs="66000",
+                  TotalDurationNs="198000", Percentage="0.01")]
+    os.makedirs(tmp_path / "trace")
+    with open(tmp_path / "trace" / "run_kernel_stats.csv", "w", newline="") as fh:
+        w = csv.DictWriter(fh, fieldnames=list(rows[0]))
+        w.writeheader()
+        w.writerows(rows)
+    out = tmp_path / "trace.txt"
+    bench.summarize_trace(str(tmp_path / "trace"), "cmd", str(out))
+    text = out.read_text()
+    assert "k_other_39(" in text and "k_other_40(" not in text
+    assert "k_step32s<0, false, 0, false, true, 2>" in text and "k_adj_step<float>" in text
+    assert re.search(r"^21\s+46\.00\s", text, re.M)
 
 
 def test_more_than_one_gpu_is_refused_with_a_message():
