@@ -321,6 +321,33 @@ def run_gpu(args):
             "%.2f GB" % (T, out["rollout"]["forward_loss_ms"], out["rollout"]["backward_ms"],
                           out["rollout"]["peak_extra_bytes"] / 1e9))
         del ro
+        # the same 500 steps with every pre-collision state kept by the
+        # forward (T + 1 states, 4.7 GB): the backward is the reversed steps
+        # alone. One untimed run first, so that the timed one reuses the
+        # allocator's blocks.
+        with torch.cuda.stream(stream):
+            for timed in (False, True):
+                torch.cuda.synchronize()
+                torch.cuda.reset_peak_memory_stats()
+                base_mem = torch.cuda.memory_allocated()
+                ro = Rollout(planA, T, C, store_all=True)
+                e = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+                e[0].record(stream)
+                ro.forward(uxt, uyt, stream=stream)
+                ro.loss(tx_t, ty_t, stream=stream)
+                e[1].record(stream)
+                ro.backward(stream=stream)
+                e[2].record(stream)
+                torch.cuda.synchronize()
+                peak = torch.cuda.max_memory_allocated() - base_mem
+                del ro
+        out["rollout_stored"] = {"steps": T, "forward_loss_ms": e[0].elapsed_time(e[1]),
+                                 "backward_ms": e[1].elapsed_time(e[2]),
+                                 "ratio": e[1].elapsed_time(e[2]) / e[0].elapsed_time(e[1]),
+                                 "peak_extra_bytes": peak}
+        log("rollout of %d steps, every state stored: forward+loss %.1f ms, backward %.1f ms, "
+            "peak extra memory %.2f GB" % (T, out["rollout_stored"]["forward_loss_ms"],
+                                           out["rollout_stored"]["backward_ms"], peak / 1e9))
         planA.close()
     out["n"] = c.n
     out["K"] = K
@@ -963,6 +990,7 @@ def main():
         line["adjoint_step"] = {"ms": r["adj_step_ms"], "bytes_per_update": abpu,
                                 "achieved": ach, "unit": "GB/s", "frac": ach / HBM_PEAK_GBS}
         line["adjoint_rollout_500"] = r["rollout"]
+        line["adjoint_rollout_500_stored"] = r["rollout_stored"]
     # local solves: n = K + M unknowns (M = 15 monomials of degree <= 4), LU-class
     # elimination 2n^3/3 plus 8 right-hand sides at 2n^2 each, per node
     nn = K + 15

@@ -9,7 +9,7 @@ FP64: the adjoint gradient against central differences of the FP64 forward
 along a smooth direction of u0 and in tau, and against the FP64 oracle's
 complex-step derivatives on the same cloud. FP32 (the benchmarked path):
 against the FP64 gradient, within the FP32 rounding bound carried through the
-misfit."""
+misfit, and the rollout that stores every state against the checkpointed one."""
 import math
 
 import numpy as np
@@ -40,9 +40,9 @@ def _loss(plan, u0x, u0y, tx, ty):
     return float(ro.loss(tx, ty).item())
 
 
-def _grad(plan, u0x, u0y, tx, ty):
+def _grad(plan, u0x, u0y, tx, ty, store_all=False):
     from paper_2306_01525_amd.autograd import Rollout
-    ro = Rollout(plan, STEPS, SEG)
+    ro = Rollout(plan, STEPS, SEG, store_all)
     ro.forward(u0x, u0y)
     J = float(ro.loss(tx, ty).item())
     gx, gy, gt = ro.backward()
@@ -108,7 +108,16 @@ def test_fullsize_gradient_fd_and_fp32():
     say("FP32 rollout + adjoint")
     p32 = _plan(c, 0)
     J32, gx32, gy32, gt32 = _grad(p32, u0x, u0y, tx_t, ty_t)
+    # every state stored by the forward (501 states, 4.7 GB) instead of the
+    # checkpoints: the same reversed steps on the same recorded states
+    Js, gxs, gys, gts = _grad(p32, u0x, u0y, tx_t, ty_t, store_all=True)
     p32.close()
+    ds = max(np.abs(gxs - gx32).max(), np.abs(gys - gy32).max()) / np.abs(
+        np.concatenate([gx32, gy32])).max()
+    say("FP32 stored vs checkpointed: J diff %.2e, grad u0 max diff %.2e, dtau diff %.2e"
+        % (abs(Js - J32), ds, abs(gts - gt32)))
+    assert abs(Js - J32) <= 1e-14 * J32
+    assert ds <= 1e-6 and abs(gts - gt32) <= 1e-6 * abs(gt32)
     # the FP32 state is within tol_fp32(T) of the FP64 one relative to |u|; the
     # misfit e = u(T) - u* is 10x smaller than u, and the reverse sweep adds
     # its own rounding of the same order

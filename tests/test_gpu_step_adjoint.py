@@ -19,9 +19,9 @@ def _setup(n_side=10, K=20, m=3, mode=0, seed=21):
     return c, u0x, u0y, tx, ty, K, m, mode
 
 
-def _gpu_grad(plan, u0x, u0y, tx, ty, steps, segment):
+def _gpu_grad(plan, u0x, u0y, tx, ty, steps, segment, store_all=False):
     from paper_2306_01525_amd.autograd import Rollout
-    ro = Rollout(plan, steps, segment)
+    ro = Rollout(plan, steps, segment, store_all)
     ro.forward(u0x, u0y)
     J = ro.loss(tx, ty)
     gx, gy, gt = ro.backward()
@@ -52,6 +52,40 @@ def test_adjoint_on_imported_weights(mode, precision):
     plan.close()
 
 
+@pytest.mark.parametrize("precision", [1, 0])
+def test_stored_rollout_equals_checkpointed_and_oracle(precision):
+    """store_all (every pre-collision state kept by the forward, nothing
+    recomputed) against the oracle's discrete adjoint within the bounds of
+    the imported-weights test, and against checkpointed rollouts of segment
+    lengths 1, 5 (ragged: 13 = 5 + 5 + 3) and 13."""
+    from paper_2306_01525_amd import Params, Plan
+    c, u0x, u0y, tx, ty, K, m, mode = _setup(seed=31)
+    tau, steps = 0.75, 13
+    nbr, own, W = oracle.build_plan(c, 1.0, K, m, mode)
+    J_o, gx_o, gy_o, gt_o = oracle.adjoint(nbr, own, W, tau, steps, 1.0, u0x, u0y, tx, ty)
+    p = Params(dx=1.0, K=K, degree=m, tau=tau, stencil_mode=mode, precision=precision,
+               with_adjoint=1)
+    plan = Plan.from_arrays(c.x, c.y, nbr, own, W, p)
+    J, gx, gy, gt = _gpu_grad(plan, u0x, u0y, tx, ty, steps, 1, store_all=True)
+    tol = 1e-10 if precision == 1 else 2e-6
+    eg = rel_l2(np.concatenate([gx, gy]), np.concatenate([gx_o, gy_o]))
+    say("stored, prec %d: J %.6e vs %.6e, grad u0 rel %.2e, dtau %.6e vs %.6e"
+        % (precision, J, J_o, eg, gt, gt_o))
+    assert abs(J - J_o) <= tol * abs(J_o)
+    assert eg < tol
+    assert abs(gt - gt_o) <= tol * abs(gt_o)
+    for seg in (1, 5, steps):
+        Jc, gxc, gyc, gtc = _gpu_grad(plan, u0x, u0y, tx, ty, steps, seg)
+        d = max(np.abs(gx - gxc).max(), np.abs(gy - gyc).max()) / np.abs(
+            np.concatenate([gx, gy])).max()
+        say("segment %d: J diff %.2e, grad u0 max diff %.2e, dtau diff %.2e"
+            % (seg, abs(J - Jc), d, abs(gt - gtc)))
+        assert abs(J - Jc) <= 1e-14 * abs(J)
+        assert d <= (1e-13 if precision == 1 else 1e-6)
+        assert abs(gt - gtc) <= (1e-13 if precision == 1 else 1e-6) * abs(gt)
+    plan.close()
+
+
 def test_adjoint_end_to_end_gpu_build_and_autograd():
     """GPU-built weights, autograd.Function, against the oracle gradient and
     central finite differences of the GPU forward in FP64."""
@@ -77,6 +111,13 @@ def test_adjoint_end_to_end_gpu_build_and_autograd():
     assert abs(J.item() - J_o) < 1e-8 * abs(J_o)
     assert eg < 1e-7
     assert abs(tau.grad.item() - gt_o) < 1e-7 * abs(gt_o)
+    # the same through the autograd function with every state stored
+    ux2 = torch.tensor(u0x, device=dev, requires_grad=True)
+    uy2 = torch.tensor(u0y, device=dev, requires_grad=True)
+    tau2 = torch.tensor(0.8, dtype=torch.float64, device=dev, requires_grad=True)
+    rollout_loss(plan, ux2, uy2, tau2, steps, txt, tyt, seg, store_all=True).backward()
+    for a, b in ((ux2.grad, ux.grad), (uy2.grad, uy.grad), (tau2.grad, tau.grad)):
+        assert float((a - b).abs().max()) <= 1e-13 * float(b.abs().max())
     # central finite difference of the GPU forward with respect to tau
     h = 1e-5
     with torch.no_grad():
