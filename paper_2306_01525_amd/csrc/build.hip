@@ -465,7 +465,11 @@ __device__ __forceinline__ void rbf_solve(const Geo *__restrict__ geo,
     const int half = SYS == 2 ? lane >> 5 : 0;     // this lane's system
     const int ll = lane & (LW - 1);                // row within it
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int64_t s0 = ((int64_t)blockIdx.x * 4 + wv) * SYS;
+    // each XCD takes a contiguous range of owners: the shape vectors they
+    // store land at neighbouring nodes, so the L2 of one XCD collects whole
+    // lines of them (grid xcd_grid of the workgroup count)
+    const int64_t blk = xcd_tile(((int64_t)n + 4 * SYS - 1) / (4 * SYS));
+    const int64_t s0 = (blk * 4 + wv) * SYS;
     if (s0 >= n) return;   // uniform across the wavefront
     // a group past the last node solves its neighbour's system again and
     // stores nothing
@@ -815,8 +819,10 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(RT == 3 ? 3 
     constexpr int PQ = NB * 15;          // the departure points' monomials follow the members'
     static_assert(PQ + 16 * 15 <= 4 * NC * 4, "the monomial tables fit in s_U");
     const int lane = threadIdx.x;
-    const int s = blockIdx.x;
-    if (s >= n) return;
+    // owners in XCD-contiguous ranges, as in k_rbf (grid xcd_grid(n))
+    const int64_t so = xcd_tile(n);
+    if (so >= n) return;
+    const int s = (int)so;
     const int count = L.ptr ? L.ptr[s + 1] - L.ptr[s] : 8;
     if (count == 0) return;
     const Geo g = *geo;
@@ -1272,13 +1278,13 @@ static hipError_t launch_rbf_nb(const Geo *geo, const double *xs, const double *
     // 262,144-node lattice, K 30, degree 4); at 64 unknowns the register
     // tiles leave two wavefronts per SIMD and the row-per-lane solver is faster
     if constexpr (NB == 48) {
-        hipLaunchKernelGGL((k_rbf_mfma<NB / 16>), dim3(n), dim3(64), 0, s, geo, xs, ys, perm, nbr,
-                           L, n, K, m, dx, W64, dev_err);
+        hipLaunchKernelGGL((k_rbf_mfma<NB / 16>), dim3(xcd_grid(n)), dim3(64), 0, s, geo, xs, ys,
+                           perm, nbr, L, n, K, m, dx, W64, dev_err);
         return hipGetLastError();
     }
     constexpr int wpe = NB <= 32 ? 4 : NB == 64 ? 2 : 3;
     constexpr int sys = NB <= 32 ? 2 : 1;   // systems per wavefront
-    dim3 grid(blocks_for(n, 4 * sys)), block(256);
+    dim3 grid(xcd_grid(blocks_for(n, 4 * sys))), block(256);
     // own-node stencils (exactly 8 departure points per owner) take the
     // kernel without the replay, which need not keep the multipliers (the
     // register allocator would park them in scratch memory). Splitting the
