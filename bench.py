@@ -748,7 +748,7 @@ def summarize_traffic(fetch_dir, write_dir, out_path, command):
     """Per-dispatch HBM bytes of every kernel seen in two rocprofv3 --pmc runs
     (FETCH_SIZE, WRITE_SIZE), scaled by the same counters read on the copy
     kernel of known size (run with --copy-calibration); written as a text
-    table, largest kernels first."""
+    table of every kernel, largest first."""
     def per_kernel(rows, counter):
         acc = {}
         for r in rows:
@@ -779,7 +779,7 @@ def summarize_traffic(fetch_dir, write_dir, out_path, command):
              % (COPY_BYTES, f_scale, w_scale),
              "# command: " + command,
              "%-10s %12s %12s %12s  %s" % ("dispatches", "fetch_MB", "write_MB", "total_MB", "kernel")]
-    for tot, nd, fb, wb, k in rows[:30]:
+    for tot, nd, fb, wb, k in rows:
         lines.append("%-10d %12.1f %12.1f %12.1f  %s" % (nd, fb / 1e6, wb / 1e6, tot / 1e6, k[:110]))
     with open(out_path, "w") as fh:
         fh.write("\n".join(lines) + "\n")
