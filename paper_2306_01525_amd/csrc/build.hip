@@ -1112,8 +1112,12 @@ __global__ void k_set_last(int32_t *ptr, int n, int32_t v) { ptr[n] = v; }
 // FP64) is added to one weight, the smallest in magnitude among those at least
 // 64 times larger than the defect, so the rounded weights keep the partition
 // of unity that the deviation-stored populations rely on. One thread per
-// (node, direction), numbered like the inner [4][n][2] part of the FP64
-// layout so that each of its K loads is coalesced; the weights stay in
+// (node, direction), numbered like the FP32 layout: four consecutive lanes
+// fill one node's float4, so a wavefront stores whole lines of each member
+// plane (numbered like the FP64 layout instead, two far-apart workgroups each
+// wrote half of every float4, and the partly written lines doubled the
+// writes). Its loads are two 256-byte runs per wavefront and member, one in
+// each direction pair's plane of the FP64 layout. The weights stay in
 // registers between the three passes.
 template <int KB>
 __global__ __launch_bounds__(256) void k_pack_w32(const double *__restrict__ W64, int n, int K,
@@ -1121,16 +1125,17 @@ __global__ __launch_bounds__(256) void k_pack_w32(const double *__restrict__ W64
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= (int64_t)8 * n) return;
     const int64_t plane = (int64_t)8 * n;   // distance between members j and j+1
-    const int h = (int)(t & 1);
-    const int64_t pk = t >> 1;
-    const int kk = (int)(pk / n);
-    const int p = (int)(pk - (int64_t)kk * n);
-    const int k = 2 * kk + h + 1;
+    const int c = (int)(t & 3);              // direction within the half
+    const int64_t hp = t >> 2;
+    const int hh = (int)(hp / n);            // half: directions 1-4 or 5-8
+    const int p = (int)(hp - (int64_t)hh * n);
+    const int k = 4 * hh + c + 1;
+    const int64_t src = w64_at(k, 0, n, p);
     double w[KB];
     double sum = 0.0;
 #pragma unroll
     for (int j = 0; j < KB; ++j) {
-        w[j] = j < K ? W64[j * plane + t] : 0.0;
+        w[j] = j < K ? W64[j * plane + src] : 0.0;
         sum += (double)(float)w[j];
     }
     const double defect = 1.0 - sum;
@@ -1144,7 +1149,6 @@ __global__ __launch_bounds__(256) void k_pack_w32(const double *__restrict__ W64
             jstar = j;
         }
     }
-    const int hh = (k - 1) >> 2, c = (k - 1) & 3;
     float *out = W32 + ((int64_t)hh * n + p) * 4 + c;
 #pragma unroll
     for (int j = 0; j < KB; ++j) {
